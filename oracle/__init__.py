@@ -1,0 +1,283 @@
+"""ctypes binding of the plain FP64 CPU oracle (``oracle/*.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the package smoke check
+and by the benchmark's CPU-baseline leg.  The GPU product path never imports
+it.  ``build()`` compiles the C sources with gcc into ``oracle/liboracle.so``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from pathlib import Path
+
+import numpy as np
+
+_DIR = Path(__file__).resolve().parent
+_LIB_PATH = _DIR / "liboracle.so"
+_SOURCES = ["mesh.c", "fem.c", "krylov.c", "cgp.c", "learn.c"]
+_lib = None
+
+ERRORS = {0: "ok", 1: "bad argument", 2: "invalid mesh", 3: "no convergence", 4: "non-finite value"}
+
+
+def build(openmp: bool = False) -> Path:
+    """Compile the oracle with gcc (plain C99, -O2, no fast-math)."""
+    srcs = [str(_DIR / s) for s in _SOURCES if (_DIR / s).exists()]
+    cmd = ["gcc", "-O2", "-std=c99", "-D_POSIX_C_SOURCE=200809L", "-fPIC", "-shared", "-Wall",
+           "-Wno-unused-function", "-o", str(_LIB_PATH) + ".tmp"] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(str(_LIB_PATH) + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not _LIB_PATH.exists():
+            build()
+        _lib = C.CDLL(str(_LIB_PATH))
+        _declare(_lib)
+    return _lib
+
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    return a.ctypes.data_as(_ip)
+
+
+class Stats(C.Structure):
+    _fields_ = [("mom_iters", C.c_int * 2), ("p_iters", C.c_int), ("mass_iters", C.c_int * 2),
+                ("mom_relres", C.c_double * 2), ("p_relres", C.c_double), ("mass_relres", C.c_double * 2)]
+
+    def asdict(self):
+        return {"mom_iters": list(self.mom_iters), "p_iters": self.p_iters, "mass_iters": list(self.mass_iters),
+                "mom_relres": list(self.mom_relres), "p_relres": self.p_relres,
+                "mass_relres": list(self.mass_relres)}
+
+
+def _declare(L):
+    L.orc_check_mesh.restype = C.c_int
+    L.orc_check_mesh.argtypes = [C.c_int, _dp, C.c_int, _ip, C.c_int, _ip, _ip]
+    L.orc_create.restype = C.c_void_p
+    L.orc_create.argtypes = [C.c_int, _dp, C.c_int, _ip, C.c_int, _ip, _ip, C.c_int, _ip]
+    L.orc_free.argtypes = [C.c_void_p]
+    L.orc_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+    L.orc_export.restype = C.c_int
+    L.orc_export.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p]
+    L.orc_priority.restype = C.c_uint64
+    L.orc_priority.argtypes = [C.c_uint64]
+    L.orc_element.argtypes = [_dp, _dp, C.c_double, _dp, _dp, _dp, _dp, _dp]
+    L.orc_assemble.restype = C.c_int
+    L.orc_assemble.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int]
+    L.orc_export_values.restype = C.c_int
+    L.orc_export_values.argtypes = [C.c_void_p, C.c_int, _dp]
+    L.orc_step.restype = C.c_int
+    L.orc_step.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_int,
+                           C.c_int, C.POINTER(Stats)]
+    L.orc_projection_step.restype = C.c_int
+    L.orc_projection_step.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
+                                      C.c_int, C.POINTER(Stats)]
+    L.orc_momentum.restype = C.c_int
+    L.orc_momentum.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, C.c_double, C.c_int, C.POINTER(Stats)]
+    L.orc_restrict.restype = C.c_int
+    L.orc_restrict.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
+    L.orc_prolong.argtypes = [C.c_void_p, _dp, _dp]
+    L.orc_poisson_solve.restype = C.c_int
+    L.orc_poisson_solve.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_int, _ip, _dp]
+    L.orc_dense_solve.restype = C.c_int
+    L.orc_dense_solve.argtypes = [C.c_int, _dp, _dp, _dp]
+    for name in ("orc_pcg", "orc_bicgstab"):
+        f = getattr(L, name)
+        f.restype = C.c_int
+        f.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double, C.c_int, _ip, _dp]
+    L.orc_spmv.argtypes = [C.c_void_p, _dp, _dp, _dp]
+    if hasattr(L, "orc_mlp_forward"):
+        _declare_learn(L)
+
+
+class _CSR(C.Structure):
+    _fields_ = [("n", C.c_int), ("nnz", C.c_int), ("rp", _ip), ("col", _ip)]
+
+
+def _csr(rp, col):
+    rp = np.ascontiguousarray(rp, np.int32)
+    col = np.ascontiguousarray(col, np.int32)
+    s = _CSR(len(rp) - 1, len(col), _i(rp), _i(col))
+    return s, (rp, col)
+
+
+def priority(t: int) -> int:
+    return int(lib().orc_priority(C.c_uint64(t)))
+
+
+def element(xy3, u3=None, rho=1.0):
+    """P1 element matrices (M, K, Dx, Dy, N) of one triangle."""
+    xy3 = np.ascontiguousarray(xy3, np.float64).reshape(6)
+    out = [np.zeros(9) for _ in range(5)]
+    u = np.ascontiguousarray(u3, np.float64).reshape(6) if u3 is not None else None
+    lib().orc_element(_d(xy3), _d(u) if u is not None else None, rho, *[_d(o) for o in out])
+    return [o.reshape(3, 3) for o in out]
+
+
+def check_mesh(mesh) -> int:
+    return lib().orc_check_mesh(mesh.n_nodes, _d(mesh.xy), mesh.n_tris, _i(mesh.tri), len(mesh.bedge),
+                                _i(mesh.bedge), _i(mesh.bkind))
+
+
+def pcg(rp, col, val, b, x0=None, tol=1e-12, maxit=100000, method="cg"):
+    s, keep = _csr(rp, col)
+    val = np.ascontiguousarray(val, np.float64)
+    b = np.ascontiguousarray(b, np.float64)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, np.float64)
+    it, rr = C.c_int(), C.c_double()
+    f = lib().orc_pcg if method == "cg" else lib().orc_bicgstab
+    st = f(C.byref(s), _d(val), _d(b), _d(x), tol, maxit, C.byref(it), C.byref(rr))
+    return x, st, it.value, rr.value
+
+
+def spmv(rp, col, val, x):
+    s, keep = _csr(rp, col)
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.zeros(len(rp) - 1)
+    lib().orc_spmv(C.byref(s), _d(np.ascontiguousarray(val, np.float64)), _d(x), _d(y))
+    return y
+
+
+def dense_solve(A, b):
+    A = np.array(A, np.float64, order="C")
+    b = np.array(b, np.float64)
+    x = np.zeros_like(b)
+    st = lib().orc_dense_solve(len(b), _d(A), _d(b), _d(x))
+    if st:
+        raise RuntimeError("singular matrix")
+    return x
+
+
+class Problem:
+    """A coarse mesh refined ``levels`` times, with the CGP operators of the oracle."""
+
+    INFO = ("n_f", "t_f", "n_c", "t_c", "nnz_f", "nnz_c", "ncol_f", "ncol_c", "nb_f", "nb_c", "levels", "n_pdir")
+
+    def __init__(self, mesh, levels: int):
+        st = C.c_int()
+        self._h = lib().orc_create(mesh.n_nodes, _d(mesh.xy), mesh.n_tris, _i(mesh.tri), len(mesh.bedge),
+                                   _i(mesh.bedge), _i(mesh.bkind), levels, C.byref(st))
+        if not self._h:
+            raise ValueError(f"oracle rejected the mesh: {ERRORS.get(st.value, st.value)}")
+        out = (C.c_int64 * 12)()
+        lib().orc_info(self._h, out)
+        self.info = dict(zip(self.INFO, [int(v) for v in out]))
+        self.levels = levels
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_free(self._h)
+            self._h = None
+
+    def level_sizes(self, level):
+        o = np.zeros(4, np.int32)
+        lib().orc_export(self._h, 16, level, o.ctypes.data_as(C.c_void_p))
+        return dict(n=int(o[0]), t=int(o[1]), nb=int(o[2]), ne=int(o[3]))
+
+    def export(self, what: str, level: int | None = None):
+        lv = self.levels if level is None else level
+        s = self.level_sizes(lv)
+        inf = self.info
+        table = {
+            "xy": (0, (s["n"], 2), np.float64), "tri": (1, (s["t"], 3), np.int32),
+            "bedge": (2, (s["nb"], 2), np.int32), "bkind": (3, (s["nb"],), np.int32),
+            "parent": (4, (s["n"] - (self.level_sizes(lv - 1)["n"] if lv > 0 else 0), 2), np.int32),
+            "edges": (5, (s["ne"], 2), np.int32),
+            "rowptr_f": (6, (inf["n_f"] + 1,), np.int32), "col_f": (7, (inf["nnz_f"],), np.int32),
+            "slot_f": (8, (inf["t_f"], 9), np.int32), "colour_f": (9, (inf["t_f"],), np.int32),
+            "rowptr_c": (10, (inf["n_c"] + 1,), np.int32), "col_c": (11, (inf["nnz_c"],), np.int32),
+            "slot_c": (12, (inf["t_c"], 9), np.int32), "colour_c": (13, (inf["t_c"],), np.int32),
+            "vdir": (14, (inf["n_f"],), np.int32), "pdir": (15, (inf["n_c"],), np.int32),
+        }
+        code, shape, dt = table[what]
+        out = np.zeros(shape, dt)
+        st = lib().orc_export(self._h, code, lv, out.ctypes.data_as(C.c_void_p))
+        if st:
+            raise ValueError(f"export {what} failed")
+        return out
+
+    def assemble(self, rho, mu, dt, restrict_mode=0, mass_mode=0):
+        st = lib().orc_assemble(self._h, rho, mu, dt, restrict_mode, mass_mode)
+        if st:
+            raise ValueError("assemble failed")
+        self.params = dict(rho=rho, mu=mu, dt=dt, restrict_mode=restrict_mode, mass_mode=mass_mode)
+
+    def values(self, what: str):
+        names = ["M_f", "K_f", "Dx_f", "Dy_f", "ml_f", "K_c", "K_c_bc", "Dx_c", "Dy_c", "m_c"]
+        code = names.index(what)
+        n = {4: self.info["n_f"], 9: self.info["n_c"]}.get(code)
+        if n is None:
+            n = self.info["nnz_f"] if code < 4 else self.info["nnz_c"]
+        out = np.zeros(n)
+        if lib().orc_export_values(self._h, code, _d(out)):
+            raise ValueError("not assembled")
+        return out
+
+    def momentum(self, g, u, f=None, tol=1e-12, maxit=100000):
+        g = np.ascontiguousarray(g, np.float64)
+        u = np.ascontiguousarray(u, np.float64)
+        ut = np.zeros_like(u)
+        st = Stats()
+        fa = np.ascontiguousarray(f, np.float64) if f is not None else None
+        code = lib().orc_momentum(self._h, _d(g), _d(fa) if fa is not None else None, _d(u), _d(ut), tol, maxit,
+                                  C.byref(st))
+        return ut, code, st.asdict()
+
+    def restrict(self, ut, mode=0):
+        ut = np.ascontiguousarray(ut, np.float64)
+        b = np.zeros(self.info["n_c"])
+        if lib().orc_restrict(self._h, mode, _d(ut), _d(b)):
+            raise ValueError("bad restriction mode")
+        return b
+
+    def prolong(self, pc):
+        pc = np.ascontiguousarray(pc, np.float64)
+        pf = np.zeros(self.info["n_f"])
+        lib().orc_prolong(self._h, _d(pc), _d(pf))
+        return pf
+
+    def poisson_solve(self, b, x0=None, tol=1e-12, maxit=100000):
+        b = np.ascontiguousarray(b, np.float64)
+        x = np.zeros_like(b) if x0 is None else np.array(x0, np.float64)
+        it, rr = C.c_int(), C.c_double()
+        code = lib().orc_poisson_solve(self._h, _d(b), _d(x), tol, maxit, C.byref(it), C.byref(rr))
+        return x, code, it.value, rr.value
+
+    def step(self, g, u, pc=None, f=None, tol_mom=1e-12, tol_p=1e-12, tol_mass=1e-12, maxit=100000,
+             x0_prev=True):
+        g = np.ascontiguousarray(g, np.float64)
+        u = np.array(u, np.float64, order="C")
+        pf = np.zeros(self.info["n_f"])
+        pc = np.zeros(self.info["n_c"]) if pc is None else np.array(pc, np.float64)
+        fa = np.ascontiguousarray(f, np.float64) if f is not None else None
+        st = Stats()
+        code = lib().orc_step(self._h, _d(g), _d(fa) if fa is not None else None, _d(u), _d(pf), _d(pc), tol_mom,
+                              tol_p, tol_mass, maxit, int(x0_prev), C.byref(st))
+        return u, pf, pc, code, st.asdict()
+
+    def projection_step(self, g, u, f=None, tol_mom=1e-12, tol_p=1e-12, tol_mass=1e-12, maxit=100000):
+        g = np.ascontiguousarray(g, np.float64)
+        u = np.array(u, np.float64, order="C")
+        pf = np.zeros(self.info["n_f"])
+        fa = np.ascontiguousarray(f, np.float64) if f is not None else None
+        st = Stats()
+        code = lib().orc_projection_step(self._h, _d(g), _d(fa) if fa is not None else None, _d(u), _d(pf),
+                                         tol_mom, tol_p, tol_mass, maxit, C.byref(st))
+        return u, pf, code, st.asdict()
+
+
+def _declare_learn(L):
+    pass
