@@ -1,0 +1,203 @@
+/*
+ * cgp.h - C ABI of libcgp, an MI355X (gfx950) implementation of the
+ * finite-element coarse-grid projection (IFE-CGP) time step of Kashefi &
+ * Staples, "A Finite-Element Coarse-Grid Projection Method" (Section 2).
+ *
+ * The problem statement the arguments follow (Section 2.1): density rho,
+ * viscosity mu, time step dt, body force f, velocity data u_GammaD on the
+ * Dirichlet boundary Gamma_D, zero traction on Gamma_N (Eqs. 1-4, 9-15); P1
+ * elements for velocity and pressure (Eqs. 16-18); pressure solved on a mesh
+ * coarsened l times by inverting the 1:4 subdivision (Section 2.2), resolution
+ * M:N with N = 4^-l M (Section 3).
+ *
+ * Conventions
+ *  - Every function returns cgp_status (0 = CGP_OK).  On failure a message
+ *    is available from cgp_last_error() (thread-local, valid until the next
+ *    call on the same thread).
+ *  - Host arrays passed in are copied; the caller keeps ownership.
+ *  - Device arrays are raw HIP device pointers (e.g. torch tensor
+ *    data_ptr()); the caller owns them and keeps them alive until the call
+ *    returns.  Velocity-like vectors are interleaved [n][2] doubles.
+ *  - All device work is enqueued on the stream given to cgp_mesh_create.
+ *    Calls that run Krylov iterations synchronise that stream to test
+ *    convergence, so they return with their results complete.
+ *  - The library owns every internal device buffer and frees it in
+ *    cgp_mesh_destroy.  One mesh handle must be used by one host thread at a
+ *    time; calls on different handles are independent.
+ *  - Node numbering (Section 2.2, Remark 2.2): the nodes of level k keep their
+ *    numbers on level k+1 and the midpoint of the r-th edge of level k, edges
+ *    taken as sorted (min,max) pairs, is node N_k + r.  Coarse nodes are
+ *    therefore the first N_c fine nodes, which makes the injection of Eq. (30)
+ *    the identity on that prefix, and the two endpoints of an edge are the
+ *    parents of its midpoint in the linear interpolation of Eq. (29).
+ */
+#ifndef CGP_H
+#define CGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CGP_ABI_VERSION 1
+
+typedef enum {
+  CGP_OK = 0,
+  CGP_E_ARG = 1,       /* null pointer, bad size, bad enum, unsupported option */
+  CGP_E_MESH = 2,      /* clockwise/degenerate triangle, non-manifold edge, untagged boundary edge */
+  CGP_E_NOCONV = 3,    /* Krylov solve hit max_iter; last iterate kept, stats filled */
+  CGP_E_NONFINITE = 4, /* NaN/Inf in an input or a residual */
+  CGP_E_DEVICE = 5,    /* HIP runtime error */
+  CGP_E_OOM = 6,       /* device allocation failed */
+  CGP_E_STATE = 7      /* call out of order (e.g. step before assemble, device call on a host-only mesh) */
+} cgp_status;
+
+/* boundary edge kinds (Eqs. 3-4) */
+enum { CGP_EDGE_VEL_DIRICHLET = 1, /* Gamma_D: velocity given; pressure Neumann (Eq. 13) */
+       CGP_EDGE_OUTFLOW = 2 };     /* Gamma_N: zero traction; pressure p = 0 (Eq. 14)   */
+
+enum { CGP_MESH_HOST_ONLY = 1 };   /* cgp_mesh_desc.flags: build topology only, no device memory */
+
+enum { CGP_RESTRICT_INJECT = 0,    /* Eqs. (20), (30): values at shared nodes (the paper's choice) */
+       CGP_RESTRICT_GALERKIN = 1 };/* transpose of prolongation applied to the fine divergence (Section 2.2) */
+
+enum { CGP_MASS_CONSISTENT = 0,    /* Eq. (23) solved with the consistent mass matrix */
+       CGP_MASS_LUMPED = 1 };      /* Eq. (23) with the row-sum lumped mass matrix */
+
+enum { CGP_PREC_FP64 = 0,          /* all Krylov arithmetic in FP64 */
+       CGP_PREC_FP32_IR = 1 };     /* Poisson: FP32 Jacobi-PCG inside FP64 iterative refinement */
+
+enum { CGP_X0_ZERO = 0,            /* Krylov initial guess zero */
+       CGP_X0_PREV = 1,            /* initial guess = the output array's current contents */
+       CGP_X0_LEARNED = 2 };       /* Poisson only: guess from the attached POD/MLP model */
+
+enum { CGP_LAUNCH_AUTO = 0,        /* library choice */
+       CGP_LAUNCH_LOOP = 1,        /* one kernel launch per Krylov phase, host polls every chunk */
+       CGP_LAUNCH_PERSISTENT = 2 };/* Poisson: one cooperative kernel for the whole Krylov loop */
+
+typedef struct cgp_mesh cgp_mesh;
+
+typedef struct {
+  int32_t n_nodes;            /* coarse nodes */
+  const double *xy;           /* host [n_nodes][2] */
+  int32_t n_tris;
+  const int32_t *tri;         /* host [n_tris][3], counter-clockwise, 0-based */
+  int32_t n_bedges;
+  const int32_t *bedge;       /* host [n_bedges][2]: every edge used by exactly one triangle, once */
+  const int32_t *bedge_kind;  /* host [n_bedges]: CGP_EDGE_* */
+  int32_t levels;             /* l >= 0 subdivisions; l = 0 is the standard projection method */
+  int32_t flags;              /* CGP_MESH_* */
+} cgp_mesh_desc;
+
+typedef struct {
+  double rho, mu, dt;         /* density, dynamic viscosity, time step (Eqs. 5-15) */
+  int32_t restrict_mode;      /* CGP_RESTRICT_* */
+  int32_t mass_mode;          /* CGP_MASS_* */
+} cgp_params;
+
+typedef struct {
+  int32_t precision;          /* CGP_PREC_*; only the Poisson solve honours FP32_IR */
+  double tol;                 /* stop when ||b - A x||_2 <= tol ||b||_2 (unpreconditioned) */
+  int32_t max_iter;           /* Krylov iterations (inner iterations summed for FP32_IR) */
+  double inner_tol;           /* FP32_IR: relative reduction asked of each inner FP32 solve */
+  int32_t x0_mode;            /* CGP_X0_* */
+  int32_t launch;             /* CGP_LAUNCH_* */
+} cgp_solver_opts;
+
+typedef struct {
+  cgp_solver_opts momentum;   /* step 1, Eq. (19): Jacobi-BiCGStab, both components together */
+  cgp_solver_opts poisson;    /* step 3, Eq. (21): Jacobi-PCG on the coarse mesh */
+  cgp_solver_opts mass;       /* step 5, Eq. (23): Jacobi-PCG with the consistent mass matrix */
+  int32_t timing;             /* non-zero: per-phase HIP-event times in cgp_stats */
+} cgp_step_opts;
+
+typedef struct {
+  int32_t mom_iters, p_iters, p_outer, mass_iters;
+  double mom_relres, p_relres, mass_relres;   /* max over components */
+  float ms_assemble, ms_momentum, ms_restrict, ms_poisson, ms_prolong, ms_correct;
+} cgp_stats;
+
+typedef struct {
+  int64_t n_f, t_f, n_c, t_c, nnz_f, nnz_c, ncol_f, ncol_c, nb_f, nb_c, levels, n_pdir;
+} cgp_mesh_info;
+
+/* cgp_mesh_export selectors.  Topology (int32 unless noted, host copies): */
+enum {
+  CGP_X_XY = 0,          /* double [n][2] of the given level */
+  CGP_X_TRI = 1,         /* [t][3] of the given level, subdivision order (children of t are 4t..4t+3) */
+  CGP_X_BEDGE = 2,       /* [nb][2]; a tagged edge (a,b) becomes (a,m),(m,b) */
+  CGP_X_BKIND = 3,       /* [nb] */
+  CGP_X_PARENT = 4,      /* [n_k - n_{k-1}][2] interpolation parents of level k >= 1 (Eq. 29) */
+  CGP_X_EDGES = 5,       /* [ne][2] sorted unique edges of the level */
+  CGP_X_ROWPTR_F = 6, CGP_X_COL_F = 7, CGP_X_SLOT_F = 8, CGP_X_COLOUR_F = 9,
+  CGP_X_ROWPTR_C = 10, CGP_X_COL_C = 11, CGP_X_SLOT_C = 12, CGP_X_COLOUR_C = 13,
+  CGP_X_VDIR = 14,       /* [n_f] velocity-Dirichlet node mask (0/1) */
+  CGP_X_PDIR = 15,       /* [n_c] pressure-Dirichlet node mask (0/1) */
+  CGP_X_SIZES = 16,      /* int32[4]: n, t, nb, ne of the level */
+  /* assembled values, copied from the device after cgp_assemble (double): */
+  CGP_X_S_F = 20,        /* rho M + dt mu K on the fine pattern */
+  CGP_X_M_F = 21, CGP_X_DX_F = 22, CGP_X_DY_F = 23,
+  CGP_X_K_C = 24,        /* coarse stiffness, no boundary conditions */
+  CGP_X_KBC_C = 25,      /* coarse stiffness with p = 0 rows/columns eliminated */
+  CGP_X_DX_C = 26, CGP_X_DY_C = 27,
+  CGP_X_MC = 28,         /* coarse lumped mass [n_c] */
+  CGP_X_A_F = 29,        /* momentum matrix of the last step, after Dirichlet elimination */
+  CGP_X_ML_F = 30        /* fine lumped mass [n_f] */
+};
+
+/* operators for cgp_spmv */
+enum { CGP_OP_KBC_C = 0,   /* y[n_c]   = Kbar_bc x           (FP64) */
+       CGP_OP_M_F = 1,     /* y[n_f][2] = M_f x, both columns  (FP64) */
+       CGP_OP_A_F = 2,     /* y[n_f][2] = A x, momentum matrix of the last step */
+       CGP_OP_KBC_C32 = 3  /* float y[n_c] = Kbar_bc x in FP32 (after cgp_assemble) */ };
+
+int32_t cgp_abi_version(void);
+const char *cgp_last_error(void);
+
+/* Validate the coarse mesh (CCW, manifold, every boundary edge tagged),
+ * subdivide it `levels` times, build numbering, parents, CSR patterns (sorted
+ * columns, diagonal included), slot maps, element colourings and boundary
+ * masks, and upload them.  hip_stream: hipStream_t (NULL = default stream). */
+cgp_status cgp_mesh_create(const cgp_mesh_desc *desc, void *hip_stream, cgp_mesh **out);
+cgp_status cgp_mesh_query(const cgp_mesh *mesh, cgp_mesh_info *out);
+/* Copy a topology array or an assembled operator into host memory; bytes must equal its size. */
+cgp_status cgp_mesh_export(const cgp_mesh *mesh, int32_t what, int32_t level, void *host_dst, size_t bytes);
+void cgp_mesh_destroy(cgp_mesh *mesh);
+
+/* Assemble the step-independent operators (Eqs. 16-18, Section 2.2):
+ * fine rho M + dt mu K, M, (Dx, Dy); coarse Kbar and (Dbar_x, Dbar_y) from
+ * coarse shape functions, coarse lumped mass, pressure-Dirichlet elimination,
+ * Jacobi diagonals.  Element contributions are added colour by colour. */
+cgp_status cgp_assemble(cgp_mesh *mesh, const cgp_params *params);
+
+/* One IFE-CGP step n -> n+1 (Eqs. 19-23):
+ *   g_next   dev [n_f][2]  velocity data at t^{n+1}; read at velocity-Dirichlet nodes only
+ *   f_next   dev [n_f][2]  body force F^{n+1}, or NULL for F = 0
+ *   u        dev [n_f][2]  in: U^n, out: U^{n+1}
+ *   p_fine   dev [n_f]     out: P_f^{n+1} (prolonged pressure)
+ *   p_coarse dev [n_c]     in: initial guess when poisson.x0_mode = CGP_X0_PREV, out: P_c^{n+1}
+ *   stats    host or NULL
+ * Returns CGP_E_NOCONV if a solve hits its iteration limit (the step is still
+ * completed with the last iterates), CGP_E_NONFINITE on NaN/Inf residuals. */
+cgp_status cgp_step(cgp_mesh *mesh, const cgp_step_opts *opts, const double *g_next, const double *f_next,
+                    double *u, double *p_fine, double *p_coarse, cgp_stats *stats);
+
+/* The five steps one at a time (same arguments and layouts as cgp_step). */
+cgp_status cgp_momentum(cgp_mesh *mesh, const cgp_solver_opts *opts, const double *g_next, const double *f_next,
+                        const double *u, double *u_tilde, cgp_stats *stats);                 /* Eq. (19) */
+cgp_status cgp_restrict(cgp_mesh *mesh, const double *u_tilde, double *b_coarse);            /* Eqs. (20)-(21) rhs, no BCs */
+cgp_status cgp_poisson_solve(cgp_mesh *mesh, const double *b_coarse, double *x, const cgp_solver_opts *opts,
+                             cgp_stats *stats);                                             /* Eq. (21), BCs applied */
+cgp_status cgp_prolong(cgp_mesh *mesh, const double *p_coarse, double *p_fine);              /* Eq. (22) */
+cgp_status cgp_correct(cgp_mesh *mesh, const cgp_solver_opts *opts, const double *g_next, const double *u_tilde,
+                       const double *p_fine, double *u, cgp_stats *stats);                  /* Eq. (23) */
+
+/* y = op x on device vectors (layouts listed with CGP_OP_*). */
+cgp_status cgp_spmv(cgp_mesh *mesh, int32_t op, const void *x, void *y);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,131 @@
+// Internal declarations of libcgp (host topology, device buffers, kernel launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "cgp.h"
+
+namespace cgp {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string &msg);
+#define CGP_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      ::cgp::set_error(std::string(#call) + ": " + hipGetErrorString(e_));             \
+      return (e_ == hipErrorOutOfMemory) ? CGP_E_OOM : CGP_E_DEVICE;                   \
+    }                                                                                  \
+  } while (0)
+
+// ------------------------------------------------------------------ host topology
+struct HostLevel {
+  int n = 0, t = 0, nb = 0, ne = 0;
+  std::vector<double> xy;     // [n][2]
+  std::vector<int> tri;       // [t][3]
+  std::vector<int> bedge;     // [nb][2]
+  std::vector<int> bkind;     // [nb]
+  std::vector<int> edge;      // [ne][2] sorted (min,max)
+  std::vector<int> parent;    // [n - n_prev][2]
+};
+
+struct HostCSR {
+  int n = 0, nnz = 0;
+  std::vector<int> rp, col;
+};
+
+struct HostColouring {
+  int ncol = 0;
+  std::vector<int> colour;    // [t]
+  std::vector<int> perm;      // elements sorted by (colour, id)
+  std::vector<int> cptr;      // [ncol+1] ranges in perm
+};
+
+namespace topo {
+cgp_status validate(int n, const double *xy, int t, const int *tri, int nb, const int *bedge, const int *bkind);
+void edges(const HostLevel &L, std::vector<int> &edge);
+void refine(const HostLevel &c, HostLevel &f);
+void csr(int n, const std::vector<int> &tri, HostCSR &A);
+void slots(const std::vector<int> &tri, const HostCSR &A, std::vector<int> &slot);
+void colour(int n, const std::vector<int> &tri, HostColouring &C);
+uint64_t priority(uint64_t t);
+}  // namespace topo
+
+// ------------------------------------------------------------------ device state
+template <typename T>
+struct DBuf {
+  T *p = nullptr;
+  size_t n = 0;
+};
+
+// scalars of a Krylov solve kept in device memory (read by every kernel of the loop)
+struct KrylovState {
+  double bnorm[2], rnorm[2], tol;
+  double rho[2], alpha[2], omega[2], beta[2], rz[2];
+  int done[2];          // component converged (or zero rhs)
+  int iters;            // completed iterations
+  int status;           // 0 running/ok, CGP_E_NONFINITE ...
+  int ncomp;
+  int maxit;
+  int zero_b[2];
+};
+
+struct ReduceScratch {
+  double *partials = nullptr;   // [8][max_blocks]
+  unsigned *counter = nullptr;
+  int max_blocks = 0;
+};
+
+}  // namespace cgp
+
+struct cgp_mesh {
+  hipStream_t stream = nullptr;
+  bool host_only = false;
+  int levels = 0;
+  std::vector<cgp::HostLevel> lev;
+  cgp::HostCSR pf, pc;
+  std::vector<int> slot_f, slot_c;             // original element order
+  cgp::HostColouring col_f, col_c;
+  std::vector<int> vdir, pdir;                 // masks
+  int n_pdir = 0;
+  std::vector<std::vector<int>> rt_ptr, rt_idx; // per level k>=1: coarse node -> midpoints (Galerkin restriction)
+  bool assembled = false;
+  cgp_params params{};
+
+  // device topology
+  double *d_xy_f = nullptr, *d_xy_c = nullptr;
+  int *d_tri_f = nullptr, *d_slot_f = nullptr;      // permuted by colour
+  int *d_tri_c = nullptr, *d_slot_c = nullptr;
+  int *d_rp_f = nullptr, *d_col_f = nullptr, *d_rp_c = nullptr, *d_col_c = nullptr;
+  unsigned char *d_vdir = nullptr, *d_pdir = nullptr;
+  std::vector<int *> d_parent;                      // per level k>=1
+  std::vector<int *> d_rt_ptr, d_rt_idx;            // per level k>=1
+  // device operators
+  double *d_S = nullptr, *d_M = nullptr, *d_D = nullptr, *d_Mbc = nullptr, *d_dinvM = nullptr, *d_ml = nullptr;
+  double *d_A = nullptr, *d_dinvA = nullptr;
+  double *d_K = nullptr, *d_Kbc = nullptr, *d_Dc = nullptr, *d_mc = nullptr, *d_dinvK = nullptr;
+  float *d_Kbc32 = nullptr, *d_dinvK32 = nullptr;
+  double mc_sum = 0.0;
+  // work vectors: fine [n_f][2], coarse [n_c]
+  std::vector<double *> d_wf;     // 10 fine 2-vectors
+  std::vector<double *> d_wc;     // 8 coarse vectors
+  std::vector<float *> d_wc32;    // 6 coarse float vectors
+  std::vector<double *> d_wlev;   // per level scratch [n_k] (prolong/restrict chains)
+  double *d_ut = nullptr;         // u-tilde [n_f][2] for cgp_step
+  double *d_bc = nullptr;         // coarse rhs
+  cgp::KrylovState *d_state = nullptr;   // 4 solver states
+  cgp::KrylovState *h_state = nullptr;   // pinned mirror
+  cgp::ReduceScratch red;
+  int cu_count = 0;
+  int coop_blocks = 0;            // co-resident blocks for the persistent PCG
+  std::vector<void *> allocations;
+  double *d_scalar = nullptr;     // device scalar for sums (means)
+  double *h_scalar = nullptr;     // pinned [4]
+  int *d_flag = nullptr;
+  int lanes_f = 8, lanes_c = 8;   // lanes per CSR row in SpMV-type kernels
+  int mom_chunk = 4, p_chunk = 32, p32_chunk = 16, mass_chunk = 8;  // Krylov iterations queued before a poll
+};

@@ -1,0 +1,269 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: bit-exact for indices and for the prolongation gather; relative
+error <= 1e-13 for single assembly / SpMV / restriction passes; relative L2
+<= 1e-10 for Krylov-solved quantities and full steps (FP64 path, Krylov
+tolerance 1e-13 on both sides); <= 1e-6 for the FP32-in-FP64 refinement."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TIGHT = 1e-13
+
+
+def _say(*a):
+    print("[gpu-test]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import oracle
+    import paper_1610_06993_amd as cgp
+    cgp.lib()
+    oracle.lib()
+    return torch, cgp, oracle
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0)
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def make_pair(env, mesh, levels, rho, mu, dt, restrict_mode=0, mass_mode=0):
+    torch, cgp, oracle = env
+    g = cgp.Mesh(mesh, levels)
+    g.assemble(rho, mu, dt, restrict_mode, mass_mode)
+    o = oracle.Problem(mesh, levels)
+    o.assemble(rho, mu, dt, restrict_mode, mass_mode)
+    return g, o
+
+
+def tight_opts(cgp, tol=TIGHT, x0=None):
+    s = cgp.SolverOpts(tol=tol, max_iter=100000)
+    return cgp.StepOpts(momentum=s, poisson=s, mass=s)
+
+
+# ---------------------------------------------------------------- single passes
+def test_assembly_matches_oracle(env):
+    case = W.case_bfs(nx=60, ny=10)
+    _say("assembly bfs 60x10 l=1")
+    g, o = make_pair(env, case.mesh, 1, 1.3, 0.02, 0.01)
+    S_ref = 1.3 * o.values("M_f") + 0.01 * 0.02 * o.values("K_f")
+    assert rel(g.export("S_f"), S_ref) <= 1e-14
+    for a, b in (("M_f", "M_f"), ("Dx_f", "Dx_f"), ("Dy_f", "Dy_f"), ("K_c", "K_c"), ("K_c_bc", "K_c_bc"),
+                 ("Dx_c", "Dx_c"), ("Dy_c", "Dy_c"), ("m_c", "m_c"), ("ml_f", "ml_f")):
+        assert rel(g.export(a), o.values(b)) <= 1e-14, a
+
+
+def test_spmv_matches_oracle(env):
+    torch, cgp, oracle = env
+    case = W.case_cylinder(20000, seed=4)
+    _say("spmv cylinder 20k")
+    g, o = make_pair(env, case.mesh, 1, 1.0, 1e-3, 1e-3)
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=g.info["n_c"])
+    y = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
+    g.spmv(cgp._native.OP_KBC_C, dev(torch, x), y)
+    ref = oracle.spmv(o.export("rowptr_c"), o.export("col_c"), o.values("K_c_bc"), x)
+    assert rel(y.cpu().numpy(), ref) <= 1e-14
+    x2 = rng.normal(size=(g.info["n_f"], 2))
+    y2 = torch.zeros_like(dev(torch, x2))
+    g.spmv(cgp._native.OP_M_F, dev(torch, x2), y2)
+    rp, col, M = o.export("rowptr_f"), o.export("col_f"), o.values("M_f")
+    ref2 = np.stack([oracle.spmv(rp, col, M, x2[:, 0]), oracle.spmv(rp, col, M, x2[:, 1])], 1)
+    assert rel(y2.cpu().numpy(), ref2) <= 1e-14
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_restriction_and_prolongation(env, levels):
+    torch, cgp, oracle = env
+    case = W.case_cylinder(6000, seed=6)
+    _say("restrict/prolong cylinder 6k levels", levels)
+    for mode in (0, 1):
+        g, o = make_pair(env, case.mesh, levels, 1.0, 1e-3, 2e-3, restrict_mode=mode)
+        rng = np.random.default_rng(mode)
+        ut = rng.normal(size=(g.info["n_f"], 2))
+        b = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
+        g.restrict(dev(torch, ut), b)
+        assert rel(b.cpu().numpy(), o.restrict(ut, mode)) <= 1e-13, mode
+    pc = rng.normal(size=g.info["n_c"])
+    pf = torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda")
+    g.prolong(dev(torch, pc), pf)
+    assert np.array_equal(pf.cpu().numpy(), o.prolong(pc))  # same two-term average, bitwise
+
+
+# ---------------------------------------------------------------- solves
+def test_momentum_solve(env):
+    torch, cgp, oracle = env
+    case = W.case_bfs(nx=80, ny=10)
+    _say("momentum bfs 80x10")
+    g, o = make_pair(env, case.mesh, 1, case.rho, case.mu, case.dt)
+    xy = g.export("xy")
+    rng = np.random.default_rng(3)
+    u = case.initial(xy, g.export("vdir")) + 0.1 * rng.normal(size=(g.info["n_f"], 2))
+    gd = case.dirichlet(xy, case.dt)
+    ut = torch.zeros(g.info["n_f"], 2, dtype=torch.float64, device="cuda")
+    st = g.momentum(dev(torch, gd), dev(torch, u), ut, opts=cgp.SolverOpts(tol=TIGHT, max_iter=5000))
+    ref, code, ost = o.momentum(gd, u, tol=TIGHT)
+    assert code == 0
+    assert rel(ut.cpu().numpy(), ref) <= 1e-10, (st, ost)
+
+
+@pytest.mark.parametrize("which", ["neumann", "dirichlet"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_poisson_solve(env, which, precision):
+    torch, cgp, oracle = env
+    mesh = W.unit_square_tg(24, seed=3) if which == "neumann" else W.cylinder_channel(8000, seed=2)
+    _say("poisson", which, "precision", precision)
+    g, o = make_pair(env, mesh, 1, 1.0, 1e-3, 1e-3)
+    rng = np.random.default_rng(7)
+    b = rng.normal(size=g.info["n_c"])
+    x = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
+    tol = TIGHT if precision == 0 else 1e-10
+    st = g.poisson_solve(dev(torch, b), x, cgp.SolverOpts(tol=tol, precision=precision, x0_mode=0,
+                                                           max_iter=100000))
+    ref, code, it, rr = o.poisson_solve(b, tol=1e-14)
+    assert code == 0
+    err = rel(x.cpu().numpy(), ref)
+    assert err <= (1e-10 if precision == 0 else 1e-6), (err, st)
+    if precision == 1:
+        assert st["p_outer"] >= 2
+
+
+def _run_steps(env, case, levels, nsteps, opts_gpu, restrict_mode=0, mass_mode=0, check_every=True, bar=1e-10,
+               tol=TIGHT):
+    torch, cgp, oracle = env
+    g, o = make_pair(env, case.mesh, levels, case.rho, case.mu, case.dt, restrict_mode, mass_mode)
+    xy = g.export("xy")
+    u0 = case.initial(xy, g.export("vdir"))
+    u = dev(torch, u0.copy())
+    pf = torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda")
+    pc = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
+    ur, pcr = u0.copy(), None
+    worst = 0.0
+    for k in range(nsteps):
+        gd = case.dirichlet(xy, (k + 1) * case.dt)
+        if not check_every:
+            # per-step local error: restart the GPU from the oracle state
+            u.copy_(dev(torch, ur))
+            if pcr is not None:
+                pc.copy_(dev(torch, pcr))
+        g.step(dev(torch, gd), u, pf, pc, opts=opts_gpu)
+        ur, pfr, pcr, code, _ = o.step(gd, ur, pcr, tol_mom=tol, tol_p=tol, tol_mass=tol)
+        assert code == 0
+        eu, ep = rel(u.cpu().numpy(), ur), rel(pf.cpu().numpy(), pfr)
+        worst = max(worst, eu, ep)
+        assert eu <= bar and ep <= bar, (k, eu, ep)
+    return worst
+
+
+def test_taylor_green_100_steps(env):
+    torch, cgp, oracle = env
+    case = W.case_tg()
+    _say("taylor-green 32x32 l=1, 100 steps")
+    worst = _run_steps(env, case, 1, 100, tight_opts(cgp))
+    _say("worst rel err", worst)
+
+
+@pytest.mark.parametrize("restrict_mode,mass_mode,levels", [(1, 0, 1), (0, 1, 1), (0, 0, 2), (0, 0, 0)])
+def test_step_variants(env, restrict_mode, mass_mode, levels):
+    torch, cgp, oracle = env
+    case = W.case_bfs(nx=100, ny=12)
+    _say("bfs step variant", restrict_mode, mass_mode, levels)
+    _run_steps(env, case, levels, 5, tight_opts(cgp), restrict_mode, mass_mode)
+
+
+def test_cylinder_steps(env):
+    torch, cgp, oracle = env
+    case = W.case_cylinder(12000, seed=3)
+    _say("cylinder 12k l=1, 5 steps")
+    _run_steps(env, case, 1, 5, tight_opts(cgp))
+
+
+def test_fp32_ir_step_within_1e6(env):
+    torch, cgp, oracle = env
+    case = W.case_cylinder(12000, seed=3)
+    _say("cylinder 12k FP32-IR, per-step local error")
+    s64 = cgp.SolverOpts(tol=TIGHT, max_iter=100000)
+    sp = cgp.SolverOpts(tol=1e-10, max_iter=100000, precision=1, inner_tol=1e-4)
+    opts = cgp.StepOpts(momentum=s64, poisson=sp, mass=s64)
+    _run_steps(env, case, 1, 3, opts, check_every=False, bar=1e-6)
+
+
+def test_deterministic_bitwise(env):
+    torch, cgp, oracle = env
+    case = W.case_cylinder(8000, seed=1)
+    _say("determinism cylinder 8k")
+    outs = []
+    for _ in range(2):
+        g = cgp.Mesh(case.mesh, 1)
+        g.assemble(case.rho, case.mu, case.dt)
+        xy = g.export("xy")
+        u = dev(torch, case.initial(xy, g.export("vdir")))
+        pf = torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda")
+        pc = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
+        gd = dev(torch, case.dirichlet(xy, case.dt))
+        for _ in range(3):
+            g.step(gd, u, pf, pc)
+        outs.append((u.cpu().numpy(), pf.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_failure_paths(env):
+    torch, cgp, oracle = env
+    case = W.case_bfs(nx=40, ny=8)
+    _say("failure paths")
+    g = cgp.Mesh(case.mesh, 1)
+    g.assemble(case.rho, case.mu, case.dt)
+    xy = g.export("xy")
+    u = dev(torch, case.initial(xy, g.export("vdir")))
+    pf = torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda")
+    pc = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
+    gd = dev(torch, case.dirichlet(xy, case.dt))
+    one = cgp.StepOpts(poisson=cgp.SolverOpts(tol=1e-12, max_iter=1))
+    st = g.step(gd, u, pf, pc, opts=one, allow_noconv=True)
+    assert st["status"] == 3 and st["p_iters"] == 1 and st["p_relres"] > 1e-12
+    with pytest.raises(cgp.CGPError) as e:
+        g.step(gd, u, pf, pc, opts=one)
+    assert e.value.status == 3
+    bad = u.clone()
+    bad[5, 0] = float("nan")
+    with pytest.raises(cgp.CGPError) as e:
+        g.step(gd, bad, pf, pc)
+    assert e.value.status == 4
+    # the library keeps working after errors
+    g.step(gd, u, pf, pc)
+    assert torch.isfinite(u).all()
+
+
+def test_full_size_cylinder_step_against_oracle(env):
+    """One FP64 step at the 1M-fine-triangle size, in the benchmark's launch
+    configuration, compared with the oracle from the same state."""
+    torch, cgp, oracle = env
+    case = W.case_cylinder()
+    _say("full-size cylinder", case.mesh.n_tris, "coarse triangles")
+    g, o = make_pair(env, case.mesh, 1, case.rho, case.mu, case.dt)
+    assert g.info["t_f"] >= 950_000
+    xy = g.export("xy")
+    u0 = case.initial(xy, g.export("vdir"))
+    gd = case.dirichlet(xy, case.dt)
+    u = dev(torch, u0.copy())
+    pf = torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda")
+    pc = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
+    st = g.step(dev(torch, gd), u, pf, pc, opts=tight_opts(cgp))
+    ur, pfr, pcr, code, ost = o.step(gd, u0, None, tol_mom=TIGHT, tol_p=TIGHT, tol_mass=TIGHT)
+    assert code == 0
+    eu, ep = rel(u.cpu().numpy(), ur), rel(pf.cpu().numpy(), pfr)
+    _say("full-size rel err u", eu, "p", ep, "gpu stats", st, "oracle stats", ost)
+    assert eu <= 1e-10 and ep <= 1e-10
