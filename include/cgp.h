@@ -110,13 +110,18 @@ typedef struct {
   cgp_solver_opts momentum;   /* step 1, Eq. (19): Jacobi-BiCGStab, both components together */
   cgp_solver_opts poisson;    /* step 3, Eq. (21): Jacobi-PCG on the coarse mesh */
   cgp_solver_opts mass;       /* step 5, Eq. (23): Jacobi-PCG with the consistent mass matrix */
-  int32_t timing;             /* non-zero: per-phase HIP-event times in cgp_stats */
+  int32_t timing;             /* 1: per-phase HIP-event times in cgp_stats; 2: also bracket every launch of
+                                 the Poisson Krylov kernel with HIP events (slows the step; for measurement) */
 } cgp_step_opts;
 
 typedef struct {
   int32_t mom_iters, p_iters, p_outer, mass_iters;
   double mom_relres, p_relres, mass_relres;   /* max over components */
   float ms_assemble, ms_momentum, ms_restrict, ms_poisson, ms_prolong, ms_correct;
+  double ms_dominant;         /* timing == 2: summed duration of the Poisson Krylov kernel launches (the SpMV
+                                 kernel of the launch-per-phase loop, or the persistent kernel) */
+  int32_t n_dominant;         /* timing == 2: number of those launches */
+  int32_t dominant_iters;     /* timing == 2: Krylov iterations those launches performed */
 } cgp_stats;
 
 typedef struct {

@@ -57,7 +57,8 @@ class _Stats(C.Structure):
     _fields_ = [("mom_iters", C.c_int32), ("p_iters", C.c_int32), ("p_outer", C.c_int32), ("mass_iters", C.c_int32),
                 ("mom_relres", C.c_double), ("p_relres", C.c_double), ("mass_relres", C.c_double),
                 ("ms_assemble", C.c_float), ("ms_momentum", C.c_float), ("ms_restrict", C.c_float),
-                ("ms_poisson", C.c_float), ("ms_prolong", C.c_float), ("ms_correct", C.c_float)]
+                ("ms_poisson", C.c_float), ("ms_prolong", C.c_float), ("ms_correct", C.c_float),
+                ("ms_dominant", C.c_double), ("n_dominant", C.c_int32), ("dominant_iters", C.c_int32)]
 
     def asdict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -86,7 +87,7 @@ class StepOpts:
     momentum: SolverOpts = field(default_factory=lambda: SolverOpts(tol=1e-10, max_iter=2000))
     poisson: SolverOpts = field(default_factory=lambda: SolverOpts(tol=1e-10))
     mass: SolverOpts = field(default_factory=lambda: SolverOpts(tol=1e-12, max_iter=2000))
-    timing: bool = False
+    timing: int = 0
 
     def c(self):
         return _StepOpts(self.momentum.c(), self.poisson.c(), self.mass.c(), int(self.timing))

@@ -108,15 +108,12 @@ cgp_status build_device(cgp_mesh *m) {
   TRY(dalloc(m, &m->d_ut, 2 * Nf));
   TRY(dalloc(m, &m->d_bc, Nc));
   TRY(dalloc(m, &m->d_state, 4));
-  TRY(dalloc(m, &m->red.partials, size_t(kPartials)));
-  TRY(dalloc(m, &m->red.counter, 1));
+  m->red_grid = std::max(8, m->cu_count);
+  TRY(dalloc(m, &m->red.partials, size_t(4) * 8 * m->red_grid));
   TRY(dalloc(m, &m->d_scalar, 4));
-  TRY(dalloc(m, &m->d_flag, 4));
-  CGP_HIP(hipMemsetAsync(m->red.counter, 0, sizeof(unsigned), m->stream));
   CGP_HIP(hipMemsetAsync(m->d_state, 0, 4 * sizeof(KrylovState), m->stream));
   CGP_HIP(hipHostMalloc((void **)&m->h_state, 4 * sizeof(KrylovState), hipHostMallocDefault));
   CGP_HIP(hipHostMalloc((void **)&m->h_scalar, 4 * sizeof(double), hipHostMallocDefault));
-  m->red.max_blocks = kPartials / 8;
   CGP_HIP(hipStreamSynchronize(m->stream));
   return CGP_OK;
 }
@@ -126,6 +123,7 @@ bool valid_opts(const cgp_solver_opts *o, bool poisson) {
   if (!(o->tol > 0.0) || o->max_iter < 1) return false;
   if (o->precision != CGP_PREC_FP64 && !(poisson && o->precision == CGP_PREC_FP32_IR)) return false;
   if (o->x0_mode != CGP_X0_ZERO && o->x0_mode != CGP_X0_PREV) return false;
+  if (o->launch < CGP_LAUNCH_AUTO || o->launch > CGP_LAUNCH_PERSISTENT) return false;
   return true;
 }
 
@@ -327,6 +325,7 @@ void cgp_mesh_destroy(cgp_mesh *m) {
   if (!m->host_only) {
     (void)hipStreamSynchronize(m->stream);
     for (void *p : m->allocations) (void)hipFree(p);
+    for (hipEvent_t e : m->kt_ev) (void)hipEventDestroy(e);
     if (m->h_state) (void)hipHostFree(m->h_state);
     if (m->h_scalar) (void)hipHostFree(m->h_scalar);
   }
@@ -426,6 +425,11 @@ cgp_status cgp_step(cgp_mesh *m, const cgp_step_opts *o, const double *g, const 
   };
   cgp_status s = CGP_OK;
   std::string msg;
+  m->kt_on = (o->timing == 2);
+  m->kt_ms = 0.0;
+  m->kt_count = 0;
+  m->kt_iters = 0;
+  m->kt_used = 0;
   // step 1 (Eq. 19): momentum on the fine mesh
   s = drv_momentum(m, &o->momentum, g, f, u, m->d_ut, S);
   if (!note(s)) goto out;
@@ -458,9 +462,13 @@ cgp_status cgp_step(cgp_mesh *m, const cgp_step_opts *o, const double *g, const 
     (void)hipEventElapsedTime(&ms, ev[4], ev[5]); S->ms_prolong = ms;
     (void)hipEventElapsedTime(&ms, ev[5], ev[6]); S->ms_correct = ms;
   }
+  S->ms_dominant = m->kt_ms;
+  S->n_dominant = int32_t(m->kt_count);
+  S->dominant_iters = int32_t(m->kt_iters);
   s = worst;
   if (s) g_err = msg;
 out:
+  m->kt_on = false;
   if (timing)
     for (auto &e : ev)
       if (e) (void)hipEventDestroy(e);

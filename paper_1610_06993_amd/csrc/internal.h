@@ -62,22 +62,22 @@ struct DBuf {
   size_t n = 0;
 };
 
-// scalars of a Krylov solve kept in device memory (read by every kernel of the loop)
+// scalars of a Krylov solve kept in device memory.  Scalars that a later
+// kernel of the same loop reads are kept per iteration parity ([it & 1]).
 struct KrylovState {
-  double bnorm[2], rnorm[2], tol;
-  double rho[2], alpha[2], omega[2], beta[2], rz[2];
-  int done[2];          // component converged (or zero rhs)
-  int iters;            // completed iterations
-  int status;           // 0 running/ok, CGP_E_NONFINITE ...
-  int ncomp;
-  int maxit;
+  double tol;
+  int maxit, ncomp;
+  double bnorm[2], rnorm[2];
+  double rz[2][2];                  // PCG r.z
+  double rho[2][2], alpha[2][2], omega[2][2];  // BiCGStab
+  int done[2];                      // component converged (or zero right-hand side)
   int zero_b[2];
+  int iters;                        // completed iterations
+  int status;                       // 0, or CGP_E_NONFINITE / CGP_E_NOCONV / CGP_E_DEVICE
 };
 
 struct ReduceScratch {
-  double *partials = nullptr;   // [8][max_blocks]
-  unsigned *counter = nullptr;
-  int max_blocks = 0;
+  double *partials = nullptr;   // 4 regions of [8][red_grid] block partials
 };
 
 }  // namespace cgp
@@ -121,11 +121,23 @@ struct cgp_mesh {
   cgp::KrylovState *h_state = nullptr;   // pinned mirror
   cgp::ReduceScratch red;
   int cu_count = 0;
+  int red_grid = 0;               // blocks of every reducing kernel (one partial per block)
   int coop_blocks = 0;            // co-resident blocks for the persistent PCG
+  int *d_row_begin = nullptr;     // row range per persistent block
+  void *d_bar = nullptr;          // grid barrier
+  double *d_ppartials = nullptr;  // persistent-kernel partials
+  bool coop_ok = true;            // cooperative launch available (checked once)
   std::vector<void *> allocations;
   double *d_scalar = nullptr;     // device scalar for sums (means)
   double *h_scalar = nullptr;     // pinned [4]
-  int *d_flag = nullptr;
   int lanes_f = 8, lanes_c = 8;   // lanes per CSR row in SpMV-type kernels
   int mom_chunk = 4, p_chunk = 32, p32_chunk = 16, mass_chunk = 8;  // Krylov iterations queued before a poll
+  // HIP-event timing of every launch of the Poisson SpMV kernel (cgp_step_opts.timing == 2)
+  bool kt_on = false;
+  std::vector<hipEvent_t> kt_ev;   // event pairs
+  std::vector<int> kt_iter;        // Krylov iteration of each pair
+  int kt_used = 0;                 // pairs recorded since the last harvest
+  double kt_ms = 0.0;
+  long kt_count = 0;
+  long kt_iters = 0;               // Krylov iterations covered by the timed launches
 };

@@ -1,17 +1,30 @@
 // Device-side reduction scratch and the host drivers that enqueue libcgp's kernels.
 #pragma once
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace cgp {
 
-struct Reduce {
-  double *partials;   // [K][gridDim.x] block partials
-  unsigned *counter;  // blocks finished; reset to 0 by the last block
-};
+constexpr int kMaxGrid = 2048;        // cap on blocks of row kernels (grid-stride loops)
 
-constexpr int kMaxGrid = 2048;        // cap on blocks of reducing kernels (grid-stride loops)
-constexpr int kPartials = 8 * 4096;   // doubles in the partials buffer
+inline int grid_for(long long threads) {
+  long long b = (threads + 255) / 256;
+  b = b < 8 ? 8 : (b + 7) / 8 * 8;
+  return int(b < kMaxGrid ? b : kMaxGrid);
+}
+inline int blocks_1d(long long n) { return int(n < 1 ? 1 : (n + 255) / 256); }
+
+// run f with std::integral_constant<int, L> for the supported lanes-per-row values
+template <typename F>
+void dispatch_L(int L, F &&f) {
+  switch (L) {
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    default: f(std::integral_constant<int, 8>{}); break;
+  }
+}
 
 // drivers (implemented in kernels.hip); all enqueue on mesh->stream
 cgp_status drv_assemble(cgp_mesh *m);
@@ -23,6 +36,15 @@ cgp_status drv_prolong(cgp_mesh *m, const double *pc, double *pf);
 cgp_status drv_correct(cgp_mesh *m, const cgp_solver_opts *o, const double *g, const double *ut, const double *pf,
                        double *u, cgp_stats *st);
 cgp_status drv_spmv(cgp_mesh *m, int op, const void *x, void *y);
-cgp_status drv_check_finite(cgp_mesh *m, const double *x, size_t n, bool *finite);
+
+// launchers of kernels.hip used by the Krylov drivers (enqueue only)
+void launch_conv_assembly(cgp_mesh *m, const double *u);
+void launch_mom_rhs(cgp_mesh *m, const double *g, const double *u, const double *f, double *rhs);
+void launch_correct_rhs(cgp_mesh *m, const double *g, const double *ut, const double *pf, double *rhs);
+void launch_correct_lumped(cgp_mesh *m, const double *g, const double *ut, const double *pf, double *u);
+void launch_set_dirichlet(cgp_mesh *m, const double *g, double *u);
+void launch_pdir_zero(cgp_mesh *m, double *b, double *x);
+// x -= (sum_i w_i x_i) / den over the coarse vector (w = NULL: plain sum); P: partial scratch
+void launch_mean_shift(cgp_mesh *m, double *x, const double *w, double den, double *P);
 
 }  // namespace cgp

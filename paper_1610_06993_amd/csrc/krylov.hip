@@ -1,0 +1,1006 @@
+// Krylov solvers of libcgp: Jacobi-PCG (pressure Poisson, Eq. 21, and the
+// consistent-mass correction, Eq. 23), Jacobi-BiCGStab for the two velocity
+// components of the momentum system (Eq. 19), and FP32 Jacobi-PCG inside FP64
+// iterative refinement for the pressure.
+//
+// Structure of every loop: the host enqueues a chunk of iterations, each a
+// fixed sequence of kernels that all take the iteration index, then one
+// single-block "finish" kernel, then reads the small solver state back.  Grid
+// sums are fence-free (devutil.h): a kernel reduces the partials of the kernel
+// before it, every block derives the same scalars, block 0 publishes them in
+// the state (scalars read by a later kernel live in slots indexed by the
+// iteration parity, so no kernel writes a slot that one of its own blocks
+// reads).  Once a component converges it is frozen; once all have, every
+// remaining kernel of the chunk returns at its first instruction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <type_traits>
+
+#include "devutil.h"
+#include "kernels.h"
+#include "persistent.h"
+
+namespace cgp {
+namespace dev {
+
+template <typename T, int NC>
+struct Vec;
+template <typename T>
+struct Vec<T, 1> {
+  static __device__ __forceinline__ void get(const T *p, int i, double (&o)[1]) { o[0] = (double)p[i]; }
+  static __device__ __forceinline__ void put(T *p, int i, const double (&o)[1]) { p[i] = (T)o[0]; }
+};
+template <>
+struct Vec<double, 2> {
+  static __device__ __forceinline__ void get(const double *p, int i, double (&o)[2]) {
+    const double2 t = reinterpret_cast<const double2 *>(p)[i];
+    o[0] = t.x;
+    o[1] = t.y;
+  }
+  static __device__ __forceinline__ void put(double *p, int i, const double (&o)[2]) {
+    reinterpret_cast<double2 *>(p)[i] = make_double2(o[0], o[1]);
+  }
+};
+
+template <int NC>
+__device__ __forceinline__ bool all_done(const KrylovState *st) {
+  bool a = true;
+#pragma unroll
+  for (int c = 0; c < NC; c++) a = a && st->done[c];
+  return a;
+}
+
+// ------------------------------------------------------------------ PCG
+// r = b - A x, z = D^-1 r, p0 = p1 = 0; partials (r.z, r.r, b.b) per component.
+template <int NC, int L>
+__global__ void __launch_bounds__(kRedBlock) k_cg_init(int n, const int *__restrict__ rp, const int *__restrict__ col,
+                                                      const double *__restrict__ A, const double *__restrict__ b,
+                                                      const double *__restrict__ x, const double *__restrict__ dinv,
+                                                      double *__restrict__ r, double *__restrict__ z,
+                                                      double *__restrict__ p0, double *__restrict__ p1,
+                                                      double *__restrict__ Pout) {
+  const int lane = threadIdx.x & (L - 1);
+  const int rows_per_grid = gridDim.x * blockDim.x / L;
+  double acc[3 * NC];
+#pragma unroll
+  for (int c = 0; c < 3 * NC; c++) acc[c] = 0.0;
+  for (int row = (xcd_block() * blockDim.x + threadIdx.x) / L; row < n; row += rows_per_grid) {
+    double s[NC];
+#pragma unroll
+    for (int c = 0; c < NC; c++) s[c] = 0.0;
+    for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
+      double xc[NC];
+      Vec<double, NC>::get(x, col[k], xc);
+      const double a = A[k];
+#pragma unroll
+      for (int c = 0; c < NC; c++) s[c] += a * xc[c];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; c++) s[c] = group_sum<L>(s[c]);
+    if (lane == 0) {
+      double bb[NC], rr[NC], zz[NC], zero[NC];
+      Vec<double, NC>::get(b, row, bb);
+      const double d = dinv[row];
+#pragma unroll
+      for (int c = 0; c < NC; c++) {
+        rr[c] = bb[c] - s[c];
+        zz[c] = d * rr[c];
+        zero[c] = 0.0;
+        acc[c] += rr[c] * zz[c];
+        acc[NC + c] += rr[c] * rr[c];
+        acc[2 * NC + c] += bb[c] * bb[c];
+      }
+      Vec<double, NC>::put(r, row, rr);
+      Vec<double, NC>::put(z, row, zz);
+      Vec<double, NC>::put(p0, row, zero);
+      Vec<double, NC>::put(p1, row, zero);
+    }
+  }
+  put_partials<3 * NC>(acc, Pout);
+}
+
+// Iteration `it`, first half.  Reduces the partials of the kernel before it
+// (the init partials for it = 0, else the update partials (r.z, r.r)), tests
+// convergence, forms beta = (r.z)_it / (r.z)_{it-1}, then p_new = z + beta p_old
+// on its own rows and q = A p_new with p_new formed on the fly for the
+// gathered columns; partials p_new.q.  T is the vector/matrix type (double, or
+// float for the inner solve of iterative refinement); sums are in double.
+template <typename T, int NC, int L>
+__global__ void __launch_bounds__(kRedBlock) k_cg_spmv(int it, int n, const int *__restrict__ rp,
+                                                      const int *__restrict__ col, const T *__restrict__ A,
+                                                      const T *__restrict__ z, const T *__restrict__ p_old,
+                                                      T *__restrict__ p_new, T *__restrict__ q,
+                                                      const double *__restrict__ Pin, double *__restrict__ Pout,
+                                                      KrylovState *__restrict__ st) {
+  if (st->status || all_done<NC>(st)) return;
+  double rz[NC], rr[NC], bb[NC];
+  if (it == 0) {
+    double t3[3 * NC];
+    sum_partials<3 * NC>(Pin, gridDim.x, t3);
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      rz[c] = t3[c];
+      rr[c] = t3[NC + c];
+      bb[c] = t3[2 * NC + c];
+    }
+  } else {
+    double t2[2 * NC];
+    sum_partials<2 * NC>(Pin, gridDim.x, t2);
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      rz[c] = t2[c];
+      rr[c] = t2[NC + c];
+      bb[c] = st->bnorm[c] * st->bnorm[c];
+    }
+  }
+  const double tol = st->tol;
+  bool done[NC], all = true, bad = false;
+  double beta[NC];
+#pragma unroll
+  for (int c = 0; c < NC; c++) {
+    done[c] = st->done[c] || bb[c] == 0.0 || sqrt(rr[c]) <= tol * sqrt(bb[c]);
+    all = all && done[c];
+    bad = bad || !is_finite(rr[c]) || !is_finite(rz[c]);
+    beta[c] = (it == 0 || done[c]) ? 0.0 : rz[c] / st->rz[(it - 1) & 1][c];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      if (it == 0) {
+        st->bnorm[c] = sqrt(bb[c]);
+        st->zero_b[c] = (bb[c] == 0.0);
+      }
+      st->rz[it & 1][c] = rz[c];
+      st->done[c] = done[c];
+      st->rnorm[c] = sqrt(rr[c]);
+    }
+    st->iters = it;
+    if (bad) st->status = CGP_E_NONFINITE;
+  }
+  if (all || bad) return;
+  const int lane = threadIdx.x & (L - 1);
+  const int rows_per_grid = gridDim.x * blockDim.x / L;
+  double acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; c++) acc[c] = 0.0;
+  if (NC == 1) {
+    const T bt = (T)beta[0];
+    for (int row = (xcd_block() * blockDim.x + threadIdx.x) / L; row < n; row += rows_per_grid) {
+      T s = (T)0;
+      for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
+        const int j = col[k];
+        s += A[k] * (z[j] + bt * p_old[j]);
+      }
+      double sd;
+      if constexpr (sizeof(T) == 4)
+        sd = (double)group_sumf<L>(s);
+      else
+        sd = group_sum<L>(s);
+      if (lane == 0) {
+        const T pn = z[row] + bt * p_old[row];
+        p_new[row] = pn;
+        q[row] = (T)sd;
+        acc[0] += (double)pn * (double)(T)sd;
+      }
+    }
+  } else {
+    for (int row = (xcd_block() * blockDim.x + threadIdx.x) / L; row < n; row += rows_per_grid) {
+      double s[NC];
+#pragma unroll
+      for (int c = 0; c < NC; c++) s[c] = 0.0;
+      for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
+        const int j = col[k];
+        double zc[NC], pc[NC];
+        Vec<T, NC>::get(z, j, zc);
+        Vec<T, NC>::get(p_old, j, pc);
+        const double a = A[k];
+#pragma unroll
+        for (int c = 0; c < NC; c++) s[c] += a * (zc[c] + beta[c] * pc[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < NC; c++) s[c] = group_sum<L>(s[c]);
+      if (lane == 0) {
+        double zc[NC], pc[NC];
+        Vec<T, NC>::get(z, row, zc);
+        Vec<T, NC>::get(p_old, row, pc);
+#pragma unroll
+        for (int c = 0; c < NC; c++) {
+          pc[c] = zc[c] + beta[c] * pc[c];
+          acc[c] += pc[c] * s[c];
+        }
+        Vec<T, NC>::put(p_new, row, pc);
+        Vec<T, NC>::put(q, row, s);
+      }
+    }
+  }
+  put_partials<NC>(acc, Pout);
+}
+
+// Iteration `it`, second half: alpha = (r.z)_it / (p.q); x += alpha p,
+// r -= alpha q, z = D^-1 r on the components not yet converged; partials
+// (r.z, r.r).
+template <typename T, int NC>
+__global__ void __launch_bounds__(kRedBlock) k_cg_update(int it, int n, T *__restrict__ x, T *__restrict__ r,
+                                                        T *__restrict__ z, const T *__restrict__ dinv,
+                                                        const T *__restrict__ p, const T *__restrict__ q,
+                                                        const double *__restrict__ Pin, double *__restrict__ Pout,
+                                                        KrylovState *__restrict__ st) {
+  if (st->status || all_done<NC>(st)) return;
+  double pq[NC];
+  sum_partials<NC>(Pin, gridDim.x, pq);
+  bool act[NC], bad = false;
+  double alpha[NC];
+#pragma unroll
+  for (int c = 0; c < NC; c++) {
+    act[c] = !st->done[c];
+    alpha[c] = act[c] ? st->rz[it & 1][c] / pq[c] : 0.0;
+    bad = bad || !is_finite(alpha[c]);
+  }
+  if (bad) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->status = CGP_E_NONFINITE;
+    return;
+  }
+  double acc[2 * NC];
+#pragma unroll
+  for (int c = 0; c < 2 * NC; c++) acc[c] = 0.0;
+  const int stride = gridDim.x * blockDim.x;
+  for (int i = xcd_block() * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double xx[NC], rr[NC], zz[NC], pp[NC], qq[NC];
+    Vec<T, NC>::get(x, i, xx);
+    Vec<T, NC>::get(r, i, rr);
+    Vec<T, NC>::get(p, i, pp);
+    Vec<T, NC>::get(q, i, qq);
+    Vec<T, NC>::get(z, i, zz);
+    const T d = dinv[i];
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      if (act[c]) {
+        const T xn = (T)xx[c] + (T)alpha[c] * (T)pp[c];
+        const T rn = (T)rr[c] - (T)alpha[c] * (T)qq[c];
+        xx[c] = (double)xn;
+        rr[c] = (double)rn;
+        zz[c] = (double)(d * rn);
+      }
+      acc[c] += rr[c] * zz[c];
+      acc[NC + c] += rr[c] * rr[c];
+    }
+    Vec<T, NC>::put(x, i, xx);
+    Vec<T, NC>::put(r, i, rr);
+    Vec<T, NC>::put(z, i, zz);
+  }
+  put_partials<2 * NC>(acc, Pout);
+}
+
+// After a chunk: publish residual norms, convergence and the iteration count
+// from the last update's partials (one block).
+template <int NC>
+__global__ void __launch_bounds__(kRedBlock) k_cg_finish(int it_end, int G, const double *__restrict__ Pin,
+                                                        KrylovState *__restrict__ st) {
+  if (st->status || all_done<NC>(st)) return;
+  double t2[2 * NC];
+  sum_partials<2 * NC>(Pin, G, t2);
+  if (threadIdx.x != 0) return;
+  bool bad = false;
+  for (int c = 0; c < NC; c++) {
+    const double rn = sqrt(t2[NC + c]);
+    st->rnorm[c] = rn;
+    bad = bad || !is_finite(rn);
+    if (!st->done[c] && rn <= st->tol * st->bnorm[c]) st->done[c] = 1;
+  }
+  st->iters = it_end;
+  if (bad) st->status = CGP_E_NONFINITE;
+}
+
+// components with a zero right-hand side get x = 0
+template <int NC>
+__global__ void k_zero_b_fix(int n, double *__restrict__ x, const KrylovState *__restrict__ st) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int c = 0; c < NC; c++)
+    if (st->zero_b[c]) x[NC * i + c] = 0.0;
+}
+
+// ------------------------------------------------------------------ BiCGStab, 2 components
+// r = b - A x, r^ = r, p = v = 0; partials (r.r, b.b) per component.
+template <int L>
+__global__ void __launch_bounds__(kRedBlock) k_bi_init(int n, const int *__restrict__ rp, const int *__restrict__ col,
+                                                      const double *__restrict__ A, const double2 *__restrict__ b,
+                                                      const double2 *__restrict__ x, double2 *__restrict__ r,
+                                                      double2 *__restrict__ rh, double2 *__restrict__ p,
+                                                      double2 *__restrict__ v, double *__restrict__ Pout) {
+  const int lane = threadIdx.x & (L - 1);
+  const int rows_per_grid = gridDim.x * blockDim.x / L;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int row = (xcd_block() * blockDim.x + threadIdx.x) / L; row < n; row += rows_per_grid) {
+    double sx = 0.0, sy = 0.0;
+    for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
+      const double a = A[k];
+      const double2 xc = x[col[k]];
+      sx += a * xc.x;
+      sy += a * xc.y;
+    }
+    sx = group_sum<L>(sx);
+    sy = group_sum<L>(sy);
+    if (lane == 0) {
+      const double2 bb = b[row];
+      const double2 rr = make_double2(bb.x - sx, bb.y - sy);
+      r[row] = rr;
+      rh[row] = rr;
+      p[row] = make_double2(0.0, 0.0);
+      v[row] = make_double2(0.0, 0.0);
+      acc[0] += rr.x * rr.x;
+      acc[1] += rr.y * rr.y;
+      acc[2] += bb.x * bb.x;
+      acc[3] += bb.y * bb.y;
+    }
+  }
+  put_partials<4>(acc, Pout);
+}
+
+// Iteration `it` start: reduce (r.r, r^.r) of the previous iteration (or the
+// init partials), test convergence, rho_it = r^.r, beta = (rho_it /
+// rho_{it-1}) (alpha_{it-1} / omega_{it-1}); p = r + beta (p - omega v), p^ = D^-1 p.
+__global__ void __launch_bounds__(kRedBlock) k_bi_p(int it, int n, const double2 *__restrict__ r,
+                                                   double2 *__restrict__ p, const double2 *__restrict__ v,
+                                                   const double *__restrict__ dinv, double2 *__restrict__ ph,
+                                                   const double *__restrict__ Pin, KrylovState *__restrict__ st) {
+  if (st->status || all_done<2>(st)) return;
+  double t4[4];
+  sum_partials<4>(Pin, gridDim.x, t4);
+  double rr[2], rho[2], bb[2], beta[2], om[2];
+  bool done[2], all = true, bad = false, brk = false;
+  const double tol = st->tol;
+  for (int c = 0; c < 2; c++) {
+    rr[c] = t4[c];
+    if (it == 0) {
+      bb[c] = t4[2 + c];
+      rho[c] = rr[c];  // r^ = r0
+    } else {
+      bb[c] = st->bnorm[c] * st->bnorm[c];
+      rho[c] = t4[2 + c];
+    }
+    done[c] = st->done[c] || bb[c] == 0.0 || sqrt(rr[c]) <= tol * sqrt(bb[c]);
+    all = all && done[c];
+    bad = bad || !is_finite(rr[c]);
+    beta[c] = 0.0;
+    om[c] = 0.0;
+    if (it > 0 && !done[c]) {
+      const int pp = (it - 1) & 1;
+      om[c] = st->omega[pp][c];
+      if (om[c] == 0.0) brk = true;  // breakdown
+      beta[c] = (rho[c] / st->rho[pp][c]) * (st->alpha[pp][c] / om[c]);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int c = 0; c < 2; c++) {
+      if (it == 0) {
+        st->bnorm[c] = sqrt(bb[c]);
+        st->zero_b[c] = (bb[c] == 0.0);
+      }
+      st->rho[it & 1][c] = rho[c];
+      st->done[c] = done[c];
+      st->rnorm[c] = sqrt(rr[c]);
+    }
+    st->iters = it;
+    if (bad) st->status = CGP_E_NONFINITE;
+    else if (brk && !all) st->status = CGP_E_NOCONV;
+  }
+  if (all || bad || brk) return;
+  const bool a0 = !done[0], a1 = !done[1];
+  const int stride = gridDim.x * blockDim.x;
+  for (int i = xcd_block() * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double2 rr2 = r[i], vv = v[i];
+    double2 pp = p[i];
+    if (a0) pp.x = rr2.x + beta[0] * (pp.x - om[0] * vv.x);
+    if (a1) pp.y = rr2.y + beta[1] * (pp.y - om[1] * vv.y);
+    p[i] = pp;
+    const double d = dinv[i];
+    ph[i] = make_double2(d * pp.x, d * pp.y);
+  }
+}
+
+// v = A p^; partials r^.v
+template <int L>
+__global__ void __launch_bounds__(kRedBlock) k_bi_v(int n, const int *__restrict__ rp, const int *__restrict__ col,
+                                                   const double *__restrict__ A, const double2 *__restrict__ ph,
+                                                   double2 *__restrict__ v, const double2 *__restrict__ rh,
+                                                   double *__restrict__ Pout, const KrylovState *__restrict__ st) {
+  if (st->status || all_done<2>(st)) return;
+  const int lane = threadIdx.x & (L - 1);
+  const int rows_per_grid = gridDim.x * blockDim.x / L;
+  double acc[2] = {0.0, 0.0};
+  for (int row = (xcd_block() * blockDim.x + threadIdx.x) / L; row < n; row += rows_per_grid) {
+    double sx = 0.0, sy = 0.0;
+    for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
+      const double a = A[k];
+      const double2 xc = ph[col[k]];
+      sx += a * xc.x;
+      sy += a * xc.y;
+    }
+    sx = group_sum<L>(sx);
+    sy = group_sum<L>(sy);
+    if (lane == 0) {
+      v[row] = make_double2(sx, sy);
+      const double2 h = rh[row];
+      acc[0] += h.x * sx;
+      acc[1] += h.y * sy;
+    }
+  }
+  put_partials<2>(acc, Pout);
+}
+
+// alpha = rho / (r^.v); s = r - alpha v formed on the fly; t = A (D^-1 s); partials (t.s, t.t)
+template <int L>
+__global__ void __launch_bounds__(kRedBlock) k_bi_t(int it, int n, const int *__restrict__ rp,
+                                                   const int *__restrict__ col, const double *__restrict__ A,
+                                                   const double2 *__restrict__ r, const double2 *__restrict__ v,
+                                                   const double *__restrict__ dinv, double2 *__restrict__ t,
+                                                   const double *__restrict__ Pin, double *__restrict__ Pout,
+                                                   KrylovState *__restrict__ st) {
+  if (st->status || all_done<2>(st)) return;
+  double rv[2];
+  sum_partials<2>(Pin, gridDim.x, rv);
+  double al[2];
+  bool bad = false;
+  for (int c = 0; c < 2; c++) {
+    al[c] = st->done[c] ? 0.0 : st->rho[it & 1][c] / rv[c];
+    bad = bad || !is_finite(al[c]);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->alpha[it & 1][0] = al[0];
+    st->alpha[it & 1][1] = al[1];
+    if (bad) st->status = CGP_E_NONFINITE;
+  }
+  if (bad) return;
+  const int lane = threadIdx.x & (L - 1);
+  const int rows_per_grid = gridDim.x * blockDim.x / L;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int row = (xcd_block() * blockDim.x + threadIdx.x) / L; row < n; row += rows_per_grid) {
+    double sx = 0.0, sy = 0.0;
+    for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
+      const int j = col[k];
+      const double a = A[k] * dinv[j];
+      const double2 rr = r[j], vv = v[j];
+      sx += a * (rr.x - al[0] * vv.x);
+      sy += a * (rr.y - al[1] * vv.y);
+    }
+    sx = group_sum<L>(sx);
+    sy = group_sum<L>(sy);
+    if (lane == 0) {
+      t[row] = make_double2(sx, sy);
+      const double2 rr = r[row], vv = v[row];
+      const double s0 = rr.x - al[0] * vv.x, s1 = rr.y - al[1] * vv.y;
+      acc[0] += sx * s0;
+      acc[1] += sy * s1;
+      acc[2] += sx * sx;
+      acc[3] += sy * sy;
+    }
+  }
+  put_partials<4>(acc, Pout);
+}
+
+// omega = (t.s)/(t.t); x += alpha p^ + omega D^-1 s, r = s - omega t; partials (r.r, r^.r)
+__global__ void __launch_bounds__(kRedBlock) k_bi_x(int it, int n, double2 *__restrict__ x, double2 *__restrict__ r,
+                                                   const double2 *__restrict__ v, const double2 *__restrict__ t,
+                                                   const double *__restrict__ dinv, const double2 *__restrict__ ph,
+                                                   const double2 *__restrict__ rh, const double *__restrict__ Pin,
+                                                   double *__restrict__ Pout, KrylovState *__restrict__ st) {
+  if (st->status || all_done<2>(st)) return;
+  double t4[4];
+  sum_partials<4>(Pin, gridDim.x, t4);
+  double w[2], al[2];
+  bool act[2];
+  for (int c = 0; c < 2; c++) {
+    act[c] = !st->done[c];
+    w[c] = (act[c] && t4[2 + c] > 0.0) ? t4[c] / t4[2 + c] : 0.0;
+    al[c] = st->alpha[it & 1][c];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->omega[it & 1][0] = w[0];
+    st->omega[it & 1][1] = w[1];
+  }
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int stride = gridDim.x * blockDim.x;
+  for (int i = xcd_block() * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double2 xx = x[i], rr = r[i];
+    const double2 vv = v[i], tt = t[i], pp = ph[i], hh = rh[i];
+    const double d = dinv[i];
+    if (act[0]) {
+      const double s = rr.x - al[0] * vv.x;
+      xx.x += al[0] * pp.x + w[0] * (d * s);
+      rr.x = s - w[0] * tt.x;
+    }
+    if (act[1]) {
+      const double s = rr.y - al[1] * vv.y;
+      xx.y += al[1] * pp.y + w[1] * (d * s);
+      rr.y = s - w[1] * tt.y;
+    }
+    x[i] = xx;
+    r[i] = rr;
+    acc[0] += rr.x * rr.x;
+    acc[1] += rr.y * rr.y;
+    acc[2] += hh.x * rr.x;
+    acc[3] += hh.y * rr.y;
+  }
+  put_partials<4>(acc, Pout);
+}
+
+__global__ void __launch_bounds__(kRedBlock) k_bi_finish(int it_end, int G, const double *__restrict__ Pin,
+                                                        KrylovState *__restrict__ st) {
+  if (st->status || all_done<2>(st)) return;
+  double t4[4];
+  sum_partials<4>(Pin, G, t4);
+  if (threadIdx.x != 0) return;
+  bool bad = false;
+  for (int c = 0; c < 2; c++) {
+    const double rn = sqrt(t4[c]);
+    st->rnorm[c] = rn;
+    bad = bad || !is_finite(rn);
+    if (!st->done[c] && rn <= st->tol * st->bnorm[c]) st->done[c] = 1;
+  }
+  st->iters = it_end;
+  if (bad) st->status = CGP_E_NONFINITE;
+}
+
+// ------------------------------------------------------------------ iterative refinement (FP32 inner PCG)
+// r64 = b - K x in FP64; partials (r.r, b.b)
+template <int L>
+__global__ void __launch_bounds__(kRedBlock) k_ir_residual(int n, const int *__restrict__ rp,
+                                                          const int *__restrict__ col, const double *__restrict__ A,
+                                                          const double *__restrict__ b, const double *__restrict__ x,
+                                                          double *__restrict__ r, double *__restrict__ Pout) {
+  const int lane = threadIdx.x & (L - 1);
+  const int rows_per_grid = gridDim.x * blockDim.x / L;
+  double acc[2] = {0.0, 0.0};
+  for (int row = (xcd_block() * blockDim.x + threadIdx.x) / L; row < n; row += rows_per_grid) {
+    double s = 0.0;
+    for (int k = rp[row] + lane; k < rp[row + 1]; k += L) s += A[k] * x[col[k]];
+    s = group_sum<L>(s);
+    if (lane == 0) {
+      const double bb = b[row], rr = bb - s;
+      r[row] = rr;
+      acc[0] += rr * rr;
+      acc[1] += bb * bb;
+    }
+  }
+  put_partials<2>(acc, Pout);
+}
+
+// Outer convergence test and start of the inner solve K32 d = r64 / ||r64||:
+// r = r64/||r64|| (FP32), z = D^-1 r, d = 0, p0 = p1 = 0; partials (r.z, r.r, r.r).
+__global__ void __launch_bounds__(kRedBlock) k_ir_inner_init(int n, const double *__restrict__ r64,
+                                                            const float *__restrict__ dinv, float *__restrict__ r,
+                                                            float *__restrict__ z, float *__restrict__ d,
+                                                            float *__restrict__ p0, float *__restrict__ p1,
+                                                            const double *__restrict__ Pin, double *__restrict__ Pout,
+                                                            KrylovState *__restrict__ so, KrylovState *__restrict__ si) {
+  double t2[2];
+  sum_partials<2>(Pin, gridDim.x, t2);
+  const double rn = sqrt(t2[0]), bn = sqrt(t2[1]);
+  const bool bad = !is_finite(rn) || !is_finite(bn);
+  const bool done = bn == 0.0 || rn <= so->tol * bn;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    so->rnorm[0] = rn;
+    so->bnorm[0] = bn;
+    so->zero_b[0] = (bn == 0.0);
+    so->done[0] = done;
+    if (bad) so->status = CGP_E_NONFINITE;
+    si->done[0] = done || bad;
+    si->status = 0;
+    si->iters = 0;
+  }
+  if (done || bad) return;
+  const double inv = 1.0 / rn;
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int stride = gridDim.x * blockDim.x;
+  for (int i = xcd_block() * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float rr = (float)(r64[i] * inv);
+    const float zz = dinv[i] * rr;
+    r[i] = rr;
+    z[i] = zz;
+    d[i] = 0.0f;
+    p0[i] = 0.0f;
+    p1[i] = 0.0f;
+    acc[0] += (double)rr * (double)zz;
+    acc[1] += (double)rr * (double)rr;
+    acc[2] += (double)rr * (double)rr;
+  }
+  put_partials<3>(acc, Pout);
+}
+
+// x += ||r64|| d (FP64 update of the outer iterate)
+__global__ void k_ir_update(int n, double *__restrict__ x, const float *__restrict__ d,
+                            const KrylovState *__restrict__ so, const KrylovState *__restrict__ si) {
+  if (so->done[0] || so->status || si->status) return;
+  const double s = so->rnorm[0];
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  x[i] += s * (double)d[i];
+}
+
+__global__ void k_state_init(KrylovState *st, double tol, int maxit, int ncomp) {
+  KrylovState s{};
+  s.tol = tol;
+  s.maxit = maxit;
+  s.ncomp = ncomp;
+  *st = s;
+}
+
+}  // namespace dev
+
+// ====================================================================== host drivers
+using namespace dev;
+
+namespace {
+
+enum { SLOT_MOM = 0, SLOT_P = 1, SLOT_PIN = 2, SLOT_MASS = 3 };
+// partial-sum regions (each holds up to 8 arrays of red_grid doubles)
+enum { R_INIT = 0, R_A = 1, R_B = 2, R_C = 3 };
+
+inline double *region(cgp_mesh *m, int k) { return m->red.partials + size_t(k) * 8 * m->red_grid; }
+
+cgp_status poll(cgp_mesh *m, int slot, int count = 1) {
+  CGP_HIP(hipMemcpyAsync(&m->h_state[slot], m->d_state + slot, sizeof(KrylovState) * count, hipMemcpyDeviceToHost,
+                         m->stream));
+  CGP_HIP(hipStreamSynchronize(m->stream));
+  return CGP_OK;
+}
+
+bool host_all_done(const KrylovState &s) {
+  for (int c = 0; c < s.ncomp; c++)
+    if (!s.done[c]) return false;
+  return true;
+}
+
+cgp_status status_of(const KrylovState &s) {
+  if (s.status == CGP_E_NONFINITE) {
+    set_error("Krylov solve produced a non-finite residual");
+    return CGP_E_NONFINITE;
+  }
+  if (s.status == CGP_E_DEVICE) {
+    set_error("persistent Krylov kernel aborted at a grid barrier");
+    return CGP_E_DEVICE;
+  }
+  if (s.status == CGP_E_NOCONV || !host_all_done(s)) {
+    set_error("Krylov solve reached its iteration limit (or broke down)");
+    return CGP_E_NOCONV;
+  }
+  return CGP_OK;
+}
+
+// ---- optional HIP-event bracketing of the dominant Poisson kernel
+cgp_status kt_harvest(cgp_mesh *m, int done_iters) {
+  for (int i = 0; i < m->kt_used; i++) {
+    if (m->kt_iter[i] >= done_iters) continue;  // launched after convergence: returned at once
+    float ms = 0.0f;
+    CGP_HIP(hipEventElapsedTime(&ms, m->kt_ev[2 * i], m->kt_ev[2 * i + 1]));
+    m->kt_ms += ms;
+    m->kt_count++;
+    m->kt_iters++;
+  }
+  m->kt_used = 0;
+  return CGP_OK;
+}
+
+void kt_begin(cgp_mesh *m, int iter) {
+  if (!m->kt_on) return;
+  if (m->kt_used * 2 + 2 > (int)m->kt_ev.size()) {
+    const size_t old = m->kt_ev.size();
+    m->kt_ev.resize(std::max<size_t>(512, 2 * old));
+    m->kt_iter.resize(m->kt_ev.size() / 2);
+    for (size_t i = old; i < m->kt_ev.size(); i++) (void)hipEventCreate(&m->kt_ev[i]);
+  }
+  m->kt_iter[m->kt_used] = iter;
+  (void)hipEventRecord(m->kt_ev[2 * m->kt_used], m->stream);
+}
+
+void kt_end(cgp_mesh *m) {
+  if (!m->kt_on) return;
+  (void)hipEventRecord(m->kt_ev[2 * m->kt_used + 1], m->stream);
+  m->kt_used++;
+}
+
+// Jacobi-PCG loop (init done by the caller): T = double or float vectors.
+template <typename T, int NC>
+cgp_status pcg_loop(cgp_mesh *m, int slot, int n, const int *rp, const int *col, const T *A, const T *dinv, T *x,
+                    T *r, T *z, T *p0, T *p1, T *q, int L, int maxit, int *chunk_hint, bool timed, KrylovState *out) {
+  KrylovState *st = m->d_state + slot;
+  hipStream_t s = m->stream;
+  const int G = m->red_grid;
+  double *Pinit = region(m, R_INIT), *Ppq = region(m, R_A), *Pupd = region(m, R_B);
+  int it = 0, chunk = std::max(1, std::min(*chunk_hint, maxit));
+  for (;;) {
+    dispatch_L(L, [&](auto LC) {
+      constexpr int LL = decltype(LC)::value;
+      for (int c = 0; c < chunk && it < maxit; c++, it++) {
+        T *po = (it & 1) ? p1 : p0, *pn = (it & 1) ? p0 : p1;
+        if (timed) kt_begin(m, it);
+        hipLaunchKernelGGL((k_cg_spmv<T, NC, LL>), dim3(G), dim3(kRedBlock), 0, s, it, n, rp, col, A,
+                           (const T *)z, (const T *)po, pn, q, (const double *)(it == 0 ? Pinit : Pupd), Ppq, st);
+        if (timed) kt_end(m);
+        hipLaunchKernelGGL((k_cg_update<T, NC>), dim3(G), dim3(kRedBlock), 0, s, it, n, x, r, z, dinv, (const T *)pn,
+                           (const T *)q, (const double *)Ppq, Pupd, st);
+      }
+    });
+    hipLaunchKernelGGL((k_cg_finish<NC>), dim3(1), dim3(kRedBlock), 0, s, it, G, (const double *)Pupd, st);
+    CGP_HIP(hipGetLastError());
+    cgp_status ps = poll(m, slot);
+    if (ps) return ps;
+    const KrylovState &h = m->h_state[slot];
+    if (timed && m->kt_on && (ps = kt_harvest(m, h.iters))) return ps;
+    if (h.status || host_all_done(h) || it >= maxit) break;
+    chunk = 8;
+  }
+  *out = m->h_state[slot];
+  *chunk_hint = std::max(1, out->iters - 2);
+  return CGP_OK;
+}
+
+template <int NC>
+cgp_status run_pcg64(cgp_mesh *m, int slot, int n, const int *rp, const int *col, const double *A,
+                     const double *dinv, const double *b, double *x, double **w, int L, double tol, int maxit,
+                     int *chunk_hint, bool timed, KrylovState *out) {
+  KrylovState *st = m->d_state + slot;
+  hipStream_t s = m->stream;
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, st, tol, maxit, NC);
+  dispatch_L(L, [&](auto LC) {
+    constexpr int LL = decltype(LC)::value;
+    hipLaunchKernelGGL((k_cg_init<NC, LL>), dim3(m->red_grid), dim3(kRedBlock), 0, s, n, rp, col, A, b,
+                       (const double *)x, dinv, w[0], w[1], w[2], w[3], region(m, R_INIT));
+  });
+  cgp_status ls = pcg_loop<double, NC>(m, slot, n, rp, col, A, dinv, x, w[0], w[1], w[2], w[3], w[4], L, maxit,
+                                       chunk_hint, timed, out);
+  if (ls) return ls;
+  hipLaunchKernelGGL((k_zero_b_fix<NC>), dim3(blocks_1d(n)), dim3(256), 0, s, n, x, (const KrylovState *)st);
+  return status_of(*out);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ step 1
+cgp_status drv_momentum(cgp_mesh *m, const cgp_solver_opts *o, const double *g, const double *f, const double *u,
+                        double *ut, cgp_stats *stats) {
+  hipStream_t s = m->stream;
+  const int n = m->pf.n;
+  const size_t nnz = m->pf.nnz;
+  CGP_HIP(hipMemcpyAsync(m->d_A, m->d_S, nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_conv_assembly(m, u);
+  double2 *rhs = (double2 *)m->d_wf[0];
+  launch_mom_rhs(m, g, u, f, (double *)rhs);
+  if (o->x0_mode == CGP_X0_ZERO)
+    CGP_HIP(hipMemsetAsync(ut, 0, 2 * n * sizeof(double), s));
+  else
+    CGP_HIP(hipMemcpyAsync(ut, u, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  double2 *r = (double2 *)m->d_wf[1], *rh = (double2 *)m->d_wf[2], *p = (double2 *)m->d_wf[3];
+  double2 *v = (double2 *)m->d_wf[4], *t = (double2 *)m->d_wf[5], *ph = (double2 *)m->d_wf[6];
+  KrylovState *st = m->d_state + SLOT_MOM;
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, st, o->tol, o->max_iter, 2);
+  const int L = m->lanes_f, G = m->red_grid;
+  const int *rp = m->d_rp_f, *col = m->d_col_f;
+  const double *A = m->d_A, *dinv = m->d_dinvA;
+  double2 *x = (double2 *)ut;
+  double *Pinit = region(m, R_INIT), *Pv = region(m, R_A), *Pt = region(m, R_B), *Px = region(m, R_C);
+  dispatch_L(L, [&](auto LC) {
+    constexpr int LL = decltype(LC)::value;
+    hipLaunchKernelGGL((k_bi_init<LL>), dim3(G), dim3(kRedBlock), 0, s, n, rp, col, A, (const double2 *)rhs,
+                       (const double2 *)x, r, rh, p, v, Pinit);
+  });
+  int it = 0, chunk = std::max(1, std::min(m->mom_chunk, o->max_iter));
+  for (;;) {
+    dispatch_L(L, [&](auto LC) {
+      constexpr int LL = decltype(LC)::value;
+      for (int c = 0; c < chunk && it < o->max_iter; c++, it++) {
+        hipLaunchKernelGGL(k_bi_p, dim3(G), dim3(kRedBlock), 0, s, it, n, (const double2 *)r, p, (const double2 *)v,
+                           dinv, ph, (const double *)(it == 0 ? Pinit : Px), st);
+        hipLaunchKernelGGL((k_bi_v<LL>), dim3(G), dim3(kRedBlock), 0, s, n, rp, col, A, (const double2 *)ph, v,
+                           (const double2 *)rh, Pv, (const KrylovState *)st);
+        hipLaunchKernelGGL((k_bi_t<LL>), dim3(G), dim3(kRedBlock), 0, s, it, n, rp, col, A, (const double2 *)r,
+                           (const double2 *)v, dinv, t, (const double *)Pv, Pt, st);
+        hipLaunchKernelGGL(k_bi_x, dim3(G), dim3(kRedBlock), 0, s, it, n, x, r, (const double2 *)v,
+                           (const double2 *)t, dinv, (const double2 *)ph, (const double2 *)rh, (const double *)Pt, Px,
+                           st);
+      }
+    });
+    hipLaunchKernelGGL(k_bi_finish, dim3(1), dim3(kRedBlock), 0, s, it, G, (const double *)Px, st);
+    CGP_HIP(hipGetLastError());
+    cgp_status ps = poll(m, SLOT_MOM);
+    if (ps) return ps;
+    const KrylovState &h = m->h_state[SLOT_MOM];
+    if (h.status || host_all_done(h) || it >= o->max_iter) break;
+    chunk = 2;
+  }
+  hipLaunchKernelGGL((k_zero_b_fix<2>), dim3(blocks_1d(n)), dim3(256), 0, s, n, ut, (const KrylovState *)st);
+  const KrylovState h = m->h_state[SLOT_MOM];
+  m->mom_chunk = std::max(1, h.iters - 1);
+  if (stats) {
+    stats->mom_iters = h.iters;
+    stats->mom_relres = 0.0;
+    for (int c = 0; c < 2; c++)
+      stats->mom_relres = std::max(stats->mom_relres, h.bnorm[c] > 0 ? h.rnorm[c] / h.bnorm[c] : 0.0);
+  }
+  return status_of(h);
+}
+
+// ------------------------------------------------------------------ step 3
+namespace {
+
+// FP32 Jacobi-PCG inside FP64 iterative refinement, launch-per-phase loop or persistent inner kernel.
+cgp_status poisson_ir(cgp_mesh *m, const double *b, double *x, const cgp_solver_opts *o, bool persistent,
+                      KrylovState *fin, int *total_iters, int *outer_out) {
+  hipStream_t s = m->stream;
+  const int n = m->pc.n, L = m->lanes_c, G = m->red_grid;
+  KrylovState *so = m->d_state + SLOT_P, *si = m->d_state + SLOT_PIN;
+  double *r64 = m->d_wc[1];
+  float *r = m->d_wc32[0], *z = m->d_wc32[1], *d = m->d_wc32[2], *p0 = m->d_wc32[3], *p1 = m->d_wc32[4],
+        *q = m->d_wc32[5];
+  const double inner_tol = o->inner_tol > 0 ? o->inner_tol : 1e-4;
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, so, o->tol, o->max_iter, 1);
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, si, inner_tol, o->max_iter, 1);
+  int outer = 0;
+  *total_iters = 0;
+  for (outer = 0; outer < 200; outer++) {
+    dispatch_L(L, [&](auto LC) {
+      constexpr int LL = decltype(LC)::value;
+      hipLaunchKernelGGL((k_ir_residual<LL>), dim3(G), dim3(kRedBlock), 0, s, n, m->d_rp_c, m->d_col_c,
+                         (const double *)m->d_Kbc, b, (const double *)x, r64, region(m, R_C));
+    });
+    hipLaunchKernelGGL(k_ir_inner_init, dim3(G), dim3(kRedBlock), 0, s, n, (const double *)r64,
+                       (const float *)m->d_dinvK32, r, z, d, p0, p1, (const double *)region(m, R_C),
+                       region(m, R_INIT), so, si);
+    const int budget = std::max(1, o->max_iter - *total_iters);
+    KrylovState hi{};
+    if (persistent) {
+      void *w[5] = {r, z, p0, p1, q};
+      kt_begin(m, 0);
+      cgp_status ls = persistent_pcg(m, true, nullptr, d, w, inner_tol, budget, si, so, r64);
+      kt_end(m);
+      if (ls) return ls;
+      cgp_status ps = poll(m, SLOT_P, 2);
+      if (ps) return ps;
+      hi = m->h_state[SLOT_PIN];
+      if (m->kt_on) {
+        const int used = m->kt_used;
+        if ((ps = kt_harvest(m, m->h_state[SLOT_P].done[0] ? 0 : 1))) return ps;
+        if (!m->h_state[SLOT_P].done[0]) m->kt_iters += (long)hi.iters - used;
+      }
+    } else {
+      cgp_status ls = pcg_loop<float, 1>(m, SLOT_PIN, n, m->d_rp_c, m->d_col_c, (const float *)m->d_Kbc32,
+                                         (const float *)m->d_dinvK32, d, r, z, p0, p1, q, L, budget, &m->p32_chunk,
+                                         true, &hi);
+      if (ls) return ls;
+      cgp_status ps = poll(m, SLOT_P);
+      if (ps) return ps;
+    }
+    const KrylovState ho = m->h_state[SLOT_P];
+    if (ho.done[0] || ho.status) {
+      *fin = ho;
+      break;
+    }
+    if (hi.status) {
+      *fin = hi;
+      break;
+    }
+    *total_iters += hi.iters;
+    hipLaunchKernelGGL(k_ir_update, dim3(blocks_1d(n)), dim3(256), 0, s, n, x, (const float *)d,
+                       (const KrylovState *)so, (const KrylovState *)si);
+    if (*total_iters >= o->max_iter) {
+      // residual of the last iterate, for the report
+      dispatch_L(L, [&](auto LC) {
+        constexpr int LL = decltype(LC)::value;
+        hipLaunchKernelGGL((k_ir_residual<LL>), dim3(G), dim3(kRedBlock), 0, s, n, m->d_rp_c, m->d_col_c,
+                           (const double *)m->d_Kbc, b, (const double *)x, r64, region(m, R_C));
+      });
+      hipLaunchKernelGGL(k_ir_inner_init, dim3(G), dim3(kRedBlock), 0, s, n, (const double *)r64,
+                         (const float *)m->d_dinvK32, r, z, d, p0, p1, (const double *)region(m, R_C),
+                         region(m, R_INIT), so, si);
+      cgp_status ps = poll(m, SLOT_P);
+      if (ps) return ps;
+      *fin = m->h_state[SLOT_P];
+      outer++;
+      break;
+    }
+  }
+  hipLaunchKernelGGL((k_zero_b_fix<1>), dim3(blocks_1d(n)), dim3(256), 0, s, n, x, (const KrylovState *)so);
+  *outer_out = outer + 1;
+  return status_of(*fin);
+}
+
+}  // namespace
+
+cgp_status drv_poisson(cgp_mesh *m, const double *b_in, double *x, const cgp_solver_opts *o, cgp_stats *stats) {
+  hipStream_t s = m->stream;
+  const int n = m->pc.n;
+  double *b = m->d_wc[0];
+  CGP_HIP(hipMemcpyAsync(b, b_in, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (o->x0_mode == CGP_X0_ZERO) CGP_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s));
+  if (m->n_pdir > 0) {
+    launch_pdir_zero(m, b, x);
+  } else {
+    // pure Neumann (Eq. 13 on all of the boundary): project b onto the range of Kbar
+    launch_mean_shift(m, b, nullptr, double(n), region(m, R_A));
+  }
+  bool persistent = (o->launch == CGP_LAUNCH_PERSISTENT);
+  if (persistent) {
+    cgp_status ss = persistent_setup(m);
+    if (ss) return ss;
+  }
+  KrylovState fin{};
+  cgp_status rs = CGP_OK;
+  int total_iters = 0, outer = 1;
+  if (o->precision == CGP_PREC_FP64) {
+    if (persistent) {
+      void *w[5] = {m->d_wc[1], m->d_wc[2], m->d_wc[3], m->d_wc[4], m->d_wc[5]};
+      KrylovState *so = m->d_state + SLOT_P;
+      hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, so, o->tol, o->max_iter, 1);
+      kt_begin(m, 0);
+      cgp_status ls = persistent_pcg(m, false, b, x, w, o->tol, o->max_iter, so, nullptr, nullptr);
+      kt_end(m);
+      if (ls) return ls;
+      hipLaunchKernelGGL((k_zero_b_fix<1>), dim3(blocks_1d(n)), dim3(256), 0, s, n, x, (const KrylovState *)so);
+      cgp_status ps = poll(m, SLOT_P);
+      if (ps) return ps;
+      fin = m->h_state[SLOT_P];
+      if (m->kt_on) {
+        const int used = m->kt_used;
+        if ((ps = kt_harvest(m, 1))) return ps;
+        m->kt_iters += (long)fin.iters - used;
+      }
+      rs = status_of(fin);
+    } else {
+      double *w[5] = {m->d_wc[1], m->d_wc[2], m->d_wc[3], m->d_wc[4], m->d_wc[5]};
+      rs = run_pcg64<1>(m, SLOT_P, n, m->d_rp_c, m->d_col_c, m->d_Kbc, m->d_dinvK, b, x, w, m->lanes_c, o->tol,
+                        o->max_iter, &m->p_chunk, true, &fin);
+    }
+    total_iters = fin.iters;
+  } else {
+    rs = poisson_ir(m, b, x, o, persistent, &fin, &total_iters, &outer);
+  }
+  if (rs != CGP_OK && rs != CGP_E_NOCONV) return rs;
+  if (m->n_pdir == 0) launch_mean_shift(m, x, m->d_mc, m->mc_sum, region(m, R_A));  // zero weighted mean
+  CGP_HIP(hipGetLastError());
+  if (stats) {
+    stats->p_iters = total_iters;
+    stats->p_outer = outer;
+    stats->p_relres = fin.bnorm[0] > 0 ? fin.rnorm[0] / fin.bnorm[0] : 0.0;
+  }
+  return rs;
+}
+
+// ------------------------------------------------------------------ step 5
+cgp_status drv_correct(cgp_mesh *m, const cgp_solver_opts *o, const double *g, const double *ut, const double *pf,
+                       double *u, cgp_stats *stats) {
+  hipStream_t s = m->stream;
+  const int n = m->pf.n, L = m->lanes_f;
+  if (m->params.mass_mode == CGP_MASS_LUMPED) {
+    launch_correct_lumped(m, g, ut, pf, u);
+    CGP_HIP(hipGetLastError());
+    if (stats) {
+      stats->mass_iters = 0;
+      stats->mass_relres = 0.0;
+    }
+    return CGP_OK;
+  }
+  double *rhs = m->d_wf[0];
+  launch_correct_rhs(m, g, ut, pf, rhs);
+  if (o->x0_mode == CGP_X0_ZERO)
+    CGP_HIP(hipMemsetAsync(u, 0, 2 * n * sizeof(double), s));
+  else
+    CGP_HIP(hipMemcpyAsync(u, ut, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  double *w[5] = {m->d_wf[1], m->d_wf[2], m->d_wf[3], m->d_wf[4], m->d_wf[5]};
+  KrylovState fin{};
+  cgp_status rs = run_pcg64<2>(m, SLOT_MASS, n, m->d_rp_f, m->d_col_f, m->d_Mbc, m->d_dinvM, rhs, u, w, L, o->tol,
+                               o->max_iter, &m->mass_chunk, false, &fin);
+  launch_set_dirichlet(m, g, u);
+  CGP_HIP(hipGetLastError());
+  if (stats) {
+    stats->mass_iters = fin.iters;
+    stats->mass_relres = 0.0;
+    for (int c = 0; c < 2; c++)
+      stats->mass_relres = std::max(stats->mass_relres, fin.bnorm[c] > 0 ? fin.rnorm[c] / fin.bnorm[c] : 0.0);
+  }
+  return rs;
+}
+
+}  // namespace cgp

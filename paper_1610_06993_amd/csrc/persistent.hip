@@ -1,0 +1,326 @@
+// Persistent Jacobi-PCG for the coarse pressure Poisson solve (Eq. 21).
+//
+// One cooperative launch runs the whole Krylov loop.  Each block owns a fixed
+// contiguous range of rows (balanced by nonzeros) for the life of the kernel,
+// so a block's matrix rows and vector segments stay in the L2 of the XCD it
+// runs on.  Per iteration there are two grid-wide synchronisations, each of
+// which also completes a deterministic reduction: every block writes one
+// partial, passes the barrier, and then sums all partials in the same fixed
+// order, so every block derives bit-identical alpha, beta and convergence
+// decisions and leaves the loop together.
+//
+//   phase A: p_new = z + beta p_old (own rows); q = K p_new, with p_new formed
+//            on the fly for the gathered columns; partial p_new.q  -> sync
+//   phase B: x += alpha p_new; r -= alpha q; z = D^-1 r; partials r.z, r.r -> sync
+//
+// The same kernel serves the FP64 solve (T = double) and the inner FP32 solve
+// of iterative refinement (T = float, right-hand side r64/||r64||, zero guess);
+// dot products are accumulated in FP64 in both.  Every barrier wait is bounded:
+// a block that spins too long sets an abort flag, and all blocks leave.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "persistent.h"
+
+namespace cgp {
+namespace pdev {
+
+constexpr int kBlock = 1024;
+constexpr long long kSpinLimit = 1ll << 27;
+
+struct GridBar {
+  unsigned count;
+  unsigned gen;
+  int abort;
+  int pad;
+};
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// Grid barrier: release this block's writes, wait for every block, acquire theirs.
+__device__ __forceinline__ void grid_sync(GridBar *bar) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned gen = __hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned arrived = __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == gridDim.x - 1) {
+      __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&bar->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      long long spins = 0;
+      while (__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit) {
+          __hip_atomic_store(&bar->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  __threadfence();
+}
+
+// Block-reduce K values, publish one partial per block in buf[k][grid], barrier,
+// then sum all partials in a fixed order; tot[] is identical in every block.
+template <int K>
+__device__ __forceinline__ void grid_allreduce(double (&v)[K], double *buf, GridBar *bar, double (&tot)[K]) {
+  __shared__ double sh[K][kBlock / 64];
+  __shared__ double res[K];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const double x = wave_sum(v[k]);
+    if (lane == 0) sh[k][wid] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0.0;
+    for (int w = 0; w < nw; w++) s += sh[threadIdx.x][w];
+    __hip_atomic_store(&buf[threadIdx.x * gridDim.x + blockIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  grid_sync(bar);
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    double x = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
+      x += __hip_atomic_load(&buf[k * gridDim.x + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    x = wave_sum(x);
+    if (lane == 0) sh[k][wid] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0.0;
+    for (int w = 0; w < nw; w++) s += sh[threadIdx.x][w];
+    res[threadIdx.x] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; k++) tot[k] = res[k];
+}
+
+__device__ __forceinline__ bool finite(double x) { return x == x && x - x == 0.0; }
+
+template <typename T, int L, bool IR>
+__global__ void __launch_bounds__(kBlock) k_pcg_persistent(PersistArgs args) {
+  const PersistArgs &a = args;
+  const T *__restrict__ K = static_cast<const T *>(a.val);
+  const T *__restrict__ dinv = static_cast<const T *>(a.dinv);
+  T *__restrict__ x = static_cast<T *>(a.x);
+  T *__restrict__ r = static_cast<T *>(a.r);
+  T *__restrict__ z = static_cast<T *>(a.z);
+  T *__restrict__ pv[2] = {static_cast<T *>(a.p0), static_cast<T *>(a.p1)};
+  T *__restrict__ q = static_cast<T *>(a.q);
+  const int *__restrict__ rp = a.rp;
+  const int *__restrict__ col = a.col;
+  GridBar *bar = reinterpret_cast<GridBar *>(a.bar);
+  const int r0 = a.row_begin[blockIdx.x], r1 = a.row_begin[blockIdx.x + 1];
+  const int lane = threadIdx.x & (L - 1), grp = threadIdx.x / L, ngrp = blockDim.x / L;
+  int red = 0;  // alternates the two partial buffers
+  auto buf = [&]() { double *b = a.partials + (red & 1) * 4 * gridDim.x; red++; return b; };
+
+  // ---- init: r = b - K x, z = D^-1 r, p_old = 0
+  double scale = 1.0;
+  if (IR) {
+    const double rn = a.outer->rnorm[0];
+    scale = rn > 0.0 ? 1.0 / rn : 0.0;
+  }
+  for (int row = r0 + grp; row < r1; row += ngrp) {
+    double s = 0.0;
+    if (!IR)
+      for (int k = rp[row] + lane; k < rp[row + 1]; k += L) s += (double)K[k] * (double)x[col[k]];
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
+    if (lane == 0) {
+      double bb = IR ? a.b64[row] * scale : (double)static_cast<const T *>(a.b)[row];
+      const T rr = (T)(bb - s);
+      r[row] = rr;
+      z[row] = dinv[row] * rr;
+      pv[0][row] = (T)0;
+      if (IR) x[row] = (T)0;
+    }
+  }
+  __syncthreads();
+  double acc3[3] = {0.0, 0.0, 0.0};
+  for (int row = r0 + threadIdx.x; row < r1; row += blockDim.x) {
+    const double rr = r[row], zz = z[row];
+    const double bb = IR ? a.b64[row] * scale : (double)static_cast<const T *>(a.b)[row];
+    acc3[0] += rr * zz;
+    acc3[1] += rr * rr;
+    acc3[2] += bb * bb;
+  }
+  double tot3[3];
+  grid_allreduce<3>(acc3, buf(), bar, tot3);
+  double rz = tot3[0], rnorm = sqrt(tot3[1]);
+  const double bnorm = sqrt(tot3[2]);
+  const double tol = a.tol;
+  int status = (finite(rnorm) && finite(bnorm)) ? 0 : CGP_E_NONFINITE;
+  bool done = (bnorm == 0.0) || (rnorm <= tol * bnorm);
+  if (IR && (a.outer->done[0] || a.outer->status)) done = true;  // refinement already converged
+  double beta = 0.0;
+  int it = 0;
+  while (!done && status == 0 && it < a.maxit) {
+    if (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+      status = CGP_E_DEVICE;
+      break;
+    }
+    T *p_old = pv[it & 1], *p_new = pv[(it + 1) & 1];
+    const T bt = (T)beta;
+    // ---- phase A
+    double acc1[1] = {0.0};
+    for (int row = r0 + grp; row < r1; row += ngrp) {
+      T s = (T)0;
+      for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
+        const int j = col[k];
+        s += K[k] * (z[j] + bt * p_old[j]);
+      }
+#pragma unroll
+      for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
+      if (lane == 0) {
+        const T pn = z[row] + bt * p_old[row];
+        p_new[row] = pn;
+        q[row] = s;
+        acc1[0] += (double)pn * (double)s;
+      }
+    }
+    double tot1[1];
+    grid_allreduce<1>(acc1, buf(), bar, tot1);
+    const double alpha = rz / tot1[0];
+    if (!finite(alpha)) {
+      status = CGP_E_NONFINITE;
+      break;
+    }
+    const T al = (T)alpha;
+    // ---- phase B
+    double acc2[2] = {0.0, 0.0};
+    for (int row = r0 + threadIdx.x; row < r1; row += blockDim.x) {
+      const T xx = x[row] + al * p_new[row];
+      const T rr = r[row] - al * q[row];
+      const T zz = dinv[row] * rr;
+      x[row] = xx;
+      r[row] = rr;
+      z[row] = zz;
+      acc2[0] += (double)rr * (double)zz;
+      acc2[1] += (double)rr * (double)rr;
+    }
+    double tot2[2];
+    grid_allreduce<2>(acc2, buf(), bar, tot2);
+    beta = tot2[0] / rz;
+    rz = tot2[0];
+    rnorm = sqrt(tot2[1]);
+    it++;
+    if (!finite(rnorm)) status = CGP_E_NONFINITE;
+    done = rnorm <= tol * bnorm;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    KrylovState *st = a.state;
+    st->iters = it;
+    st->rnorm[0] = rnorm;
+    st->bnorm[0] = bnorm;
+    st->done[0] = done;
+    st->zero_b[0] = (bnorm == 0.0);
+    st->status = status ? status : ((!done && !IR) ? CGP_E_NOCONV : 0);
+  }
+}
+
+}  // namespace pdev
+
+// ---------------------------------------------------------------- host side
+namespace {
+template <typename T, bool IR>
+const void *kernel_ptr(int L) {
+  const void *fn = nullptr;
+  dispatch_L(L, [&](auto LC) {
+    constexpr int LL = decltype(LC)::value;
+    fn = reinterpret_cast<const void *>(&pdev::k_pcg_persistent<T, LL, IR>);
+  });
+  return fn;
+}
+}  // namespace
+
+int persistent_block() { return pdev::kBlock; }
+
+cgp_status persistent_setup(cgp_mesh *m) {
+  if (m->coop_blocks > 0) return CGP_OK;
+  int dev = 0;
+  CGP_HIP(hipGetDevice(&dev));
+  int coop = 0;
+  CGP_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+  if (!coop) {
+    set_error("device does not support cooperative launches");
+    return CGP_E_DEVICE;
+  }
+  // co-resident blocks for the heaviest instantiation
+  int per_cu = 0;
+  for (const void *fn : {kernel_ptr<double, false>(m->lanes_c), kernel_ptr<float, true>(m->lanes_c)}) {
+    int b = 0;
+    CGP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, pdev::kBlock, 0));
+    per_cu = per_cu == 0 ? b : std::min(per_cu, b);
+  }
+  if (per_cu < 1) {
+    set_error("persistent PCG kernel cannot be resident");
+    return CGP_E_DEVICE;
+  }
+  const int n = m->pc.n;
+  int grid = std::min(per_cu * m->cu_count, std::max(1, (n + pdev::kBlock - 1) / 256));
+  grid = std::max(1, grid);
+  // rows split by nonzeros: block b owns rows [rb[b], rb[b+1])
+  std::vector<int> rb(grid + 1, n);
+  rb[0] = 0;
+  const long long nnz = m->pc.nnz;
+  int row = 0;
+  for (int b = 1; b < grid; b++) {
+    const long long target = nnz * b / grid;
+    while (row < n && m->pc.rp[row] < target) row++;
+    rb[b] = row;
+  }
+  void *p = nullptr;
+  CGP_HIP(hipMalloc(&p, sizeof(int) * (grid + 1)));
+  m->allocations.push_back(p);
+  m->d_row_begin = static_cast<int *>(p);
+  CGP_HIP(hipMemcpy(m->d_row_begin, rb.data(), sizeof(int) * (grid + 1), hipMemcpyHostToDevice));
+  CGP_HIP(hipMalloc(&p, sizeof(pdev::GridBar)));
+  m->allocations.push_back(p);
+  m->d_bar = p;
+  CGP_HIP(hipMalloc(&p, sizeof(double) * 8 * grid));
+  m->allocations.push_back(p);
+  m->d_ppartials = static_cast<double *>(p);
+  m->coop_blocks = grid;
+  return CGP_OK;
+}
+
+cgp_status persistent_pcg(cgp_mesh *m, bool fp32_inner, const double *b, void *x, void *const *w, double tol,
+                          int maxit, KrylovState *state, const KrylovState *outer, const double *b64) {
+  CGP_HIP(hipMemsetAsync(m->d_bar, 0, sizeof(pdev::GridBar), m->stream));
+  PersistArgs a{};
+  a.rp = m->d_rp_c;
+  a.col = m->d_col_c;
+  a.val = fp32_inner ? (const void *)m->d_Kbc32 : (const void *)m->d_Kbc;
+  a.dinv = fp32_inner ? (const void *)m->d_dinvK32 : (const void *)m->d_dinvK;
+  a.b = b;
+  a.b64 = b64;
+  a.x = x;
+  a.r = w[0];
+  a.z = w[1];
+  a.p0 = w[2];
+  a.p1 = w[3];
+  a.q = w[4];
+  a.row_begin = m->d_row_begin;
+  a.partials = m->d_ppartials;
+  a.bar = m->d_bar;
+  a.state = state;
+  a.outer = outer;
+  a.tol = tol;
+  a.maxit = maxit;
+  void *args[] = {&a};
+  const void *fn = fp32_inner ? kernel_ptr<float, true>(m->lanes_c) : kernel_ptr<double, false>(m->lanes_c);
+  CGP_HIP(hipLaunchCooperativeKernel(fn, dim3(m->coop_blocks), dim3(pdev::kBlock), args, 0, m->stream));
+  return CGP_OK;
+}
+
+}  // namespace cgp

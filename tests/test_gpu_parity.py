@@ -126,17 +126,18 @@ def test_momentum_solve(env):
 
 @pytest.mark.parametrize("which", ["neumann", "dirichlet"])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_poisson_solve(env, which, precision):
+@pytest.mark.parametrize("launch", [1, 2])
+def test_poisson_solve(env, which, precision, launch):
     torch, cgp, oracle = env
     mesh = W.unit_square_tg(24, seed=3) if which == "neumann" else W.cylinder_channel(8000, seed=2)
-    _say("poisson", which, "precision", precision)
+    _say("poisson", which, "precision", precision, "launch", launch)
     g, o = make_pair(env, mesh, 1, 1.0, 1e-3, 1e-3)
     rng = np.random.default_rng(7)
     b = rng.normal(size=g.info["n_c"])
     x = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
     tol = TIGHT if precision == 0 else 1e-10
     st = g.poisson_solve(dev(torch, b), x, cgp.SolverOpts(tol=tol, precision=precision, x0_mode=0,
-                                                           max_iter=100000))
+                                                           max_iter=100000, launch=launch))
     ref, code, it, rr = o.poisson_solve(b, tol=1e-14)
     assert code == 0
     err = rel(x.cpu().numpy(), ref)
@@ -188,11 +189,14 @@ def test_step_variants(env, restrict_mode, mass_mode, levels):
     _run_steps(env, case, levels, 5, tight_opts(cgp), restrict_mode, mass_mode)
 
 
-def test_cylinder_steps(env):
+@pytest.mark.parametrize("launch", [1, 2])
+def test_cylinder_steps(env, launch):
     torch, cgp, oracle = env
     case = make(CYLINDER_CASE)
-    _say("cylinder", case.mesh.n_tris, "coarse triangles, l=1, 5 steps")
-    _run_steps(env, case, 1, 5, tight_opts(cgp))
+    _say("cylinder", case.mesh.n_tris, "coarse triangles, l=1, 5 steps, launch", launch)
+    opts = tight_opts(cgp)
+    opts.poisson.launch = launch
+    _run_steps(env, case, 1, 5, opts)
 
 
 def test_fp32_ir_step_within_1e6(env):
