@@ -158,6 +158,20 @@ enum { CGP_OP_KBC_C = 0,   /* y[n_c]   = Kbar_bc x           (FP64) */
        CGP_OP_A_F = 2,     /* y[n_f][2] = A x, momentum matrix of the last step */
        CGP_OP_KBC_C32 = 3  /* float y[n_c] = Kbar_bc x in FP32 (after cgp_assemble) */ };
 
+/* Launch shape of the Krylov kernels on one mesh level (set by hand or by the autotuner). */
+typedef struct {
+  int32_t lanes;   /* threads per CSR row in SpMV-type kernels: 4, 8 or 16 */
+  int32_t block;   /* threads per block of the Krylov kernels: 64, 128, 256, 512 or 1024 */
+  int32_t passes;  /* rows (SpMV-type kernels) or entries (vector kernels) per lane group: 1..64 */
+} cgp_tuning_knobs;
+
+typedef struct {
+  cgp_tuning_knobs fine;    /* momentum and mass solves */
+  cgp_tuning_knobs coarse;  /* pressure Poisson solve */
+  int32_t pcg_barrier;      /* persistent Poisson kernel: 0 = library grid barrier, 1 = HIP cooperative-groups sync */
+  int32_t pcg_grid;         /* persistent Poisson kernel: blocks of 1024 threads (0 = one per compute unit) */
+} cgp_tuning;
+
 int32_t cgp_abi_version(void);
 const char *cgp_last_error(void);
 
@@ -198,6 +212,11 @@ cgp_status cgp_poisson_solve(cgp_mesh *mesh, const double *b_coarse, double *x, 
 cgp_status cgp_prolong(cgp_mesh *mesh, const double *p_coarse, double *p_fine);              /* Eq. (22) */
 cgp_status cgp_correct(cgp_mesh *mesh, const cgp_solver_opts *opts, const double *g_next, const double *u_tilde,
                        const double *p_fine, double *u, cgp_stats *stats);                  /* Eq. (23) */
+
+/* Read or replace the Krylov launch shapes of a mesh (results do not depend on them beyond
+ * rounding order).  Invalid knobs return CGP_E_ARG and leave the mesh unchanged. */
+cgp_status cgp_mesh_get_tuning(const cgp_mesh *mesh, cgp_tuning *out);
+cgp_status cgp_mesh_set_tuning(cgp_mesh *mesh, const cgp_tuning *tuning);
 
 /* y = op x on device vectors (layouts listed with CGP_OP_*). */
 cgp_status cgp_spmv(cgp_mesh *mesh, int32_t op, const void *x, void *y);

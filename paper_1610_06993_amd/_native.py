@@ -64,6 +64,14 @@ class _Stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class _Knobs(C.Structure):
+    _fields_ = [("lanes", C.c_int32), ("block", C.c_int32), ("passes", C.c_int32)]
+
+
+class _Tuning(C.Structure):
+    _fields_ = [("fine", _Knobs), ("coarse", _Knobs), ("pcg_barrier", C.c_int32), ("pcg_grid", C.c_int32)]
+
+
 class _Info(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("n_f", "t_f", "n_c", "t_c", "nnz_f", "nnz_c", "ncol_f", "ncol_c", "nb_f",
                                           "nb_c", "levels", "n_pdir")]
@@ -121,7 +129,9 @@ def lib():
     L.cgp_prolong.argtypes = [vp, vp, vp]
     L.cgp_correct.argtypes = [vp, C.POINTER(_SolverOpts), vp, vp, vp, vp, C.POINTER(_Stats)]
     L.cgp_spmv.argtypes = [vp, C.c_int32, vp, vp]
-    for name in ("cgp_mesh_create", "cgp_mesh_query", "cgp_mesh_export", "cgp_assemble", "cgp_step", "cgp_momentum",
+    L.cgp_mesh_get_tuning.argtypes = [vp, C.POINTER(_Tuning)]
+    L.cgp_mesh_set_tuning.argtypes = [vp, C.POINTER(_Tuning)]
+    for name in ("cgp_mesh_get_tuning", "cgp_mesh_set_tuning","cgp_mesh_create", "cgp_mesh_query", "cgp_mesh_export", "cgp_assemble", "cgp_step", "cgp_momentum",
                  "cgp_restrict", "cgp_poisson_solve", "cgp_prolong", "cgp_correct", "cgp_spmv"):
         getattr(L, name).restype = C.c_int32
     _lib = L
@@ -260,6 +270,23 @@ class Mesh:
         st = _Stats()
         _check(lib().cgp_correct(self._h, C.byref(o), _ptr(g), _ptr(u_tilde), _ptr(p_fine), _ptr(u), C.byref(st)))
         return st.asdict()
+
+    def get_tuning(self):
+        t = _Tuning()
+        _check(lib().cgp_mesh_get_tuning(self._h, C.byref(t)))
+        d = {lvl: (getattr(t, lvl).lanes, getattr(t, lvl).block, getattr(t, lvl).passes) for lvl in ("fine", "coarse")}
+        d["pcg_barrier"] = t.pcg_barrier
+        d["pcg_grid"] = t.pcg_grid
+        return d
+
+    def set_tuning(self, fine=None, coarse=None, pcg_barrier=None, pcg_grid=None):
+        cur = self.get_tuning()
+        f = fine or cur["fine"]
+        c = coarse or cur["coarse"]
+        b = cur["pcg_barrier"] if pcg_barrier is None else pcg_barrier
+        g = cur["pcg_grid"] if pcg_grid is None else pcg_grid
+        t = _Tuning(_Knobs(*f), _Knobs(*c), b, g)
+        _check(lib().cgp_mesh_set_tuning(self._h, C.byref(t)))
 
     def spmv(self, op: int, x, y):
         _check(lib().cgp_spmv(self._h, op, _ptr(x), _ptr(y)))

@@ -109,7 +109,7 @@ cgp_status build_device(cgp_mesh *m) {
   TRY(dalloc(m, &m->d_bc, Nc));
   TRY(dalloc(m, &m->d_state, 4));
   m->red_grid = std::max(8, m->cu_count);
-  TRY(dalloc(m, &m->red.partials, size_t(4) * 8 * m->red_grid));
+  TRY(dalloc(m, &m->red.partials, size_t(4) * 8 * kMaxRedGrid));
   TRY(dalloc(m, &m->d_scalar, 4));
   CGP_HIP(hipMemsetAsync(m->d_state, 0, 4 * sizeof(KrylovState), m->stream));
   CGP_HIP(hipHostMalloc((void **)&m->h_state, 4 * sizeof(KrylovState), hipHostMallocDefault));
@@ -474,6 +474,36 @@ out:
       if (e) (void)hipEventDestroy(e);
   if (st) CGP_HIP(hipStreamSynchronize(m->stream));
   return s;
+}
+
+cgp_status cgp_mesh_get_tuning(const cgp_mesh *m, cgp_tuning *out) {
+  if (!m || !out) {
+    set_error("cgp_mesh_get_tuning: null argument");
+    return CGP_E_ARG;
+  }
+  *out = m->tune;
+  return CGP_OK;
+}
+
+cgp_status cgp_mesh_set_tuning(cgp_mesh *m, const cgp_tuning *t) {
+  if (!m || !t) {
+    set_error("cgp_mesh_set_tuning: null argument");
+    return CGP_E_ARG;
+  }
+  for (const cgp_tuning_knobs *k : {&t->fine, &t->coarse}) {
+    const bool lanes_ok = k->lanes == 4 || k->lanes == 8 || k->lanes == 16;
+    const bool block_ok = k->block == 64 || k->block == 128 || k->block == 256 || k->block == 512 || k->block == 1024;
+    if (!lanes_ok || !block_ok || k->passes < 1 || k->passes > 64) {
+      set_error("cgp_mesh_set_tuning: lanes must be 4/8/16, block 64..1024 (power of two), passes 1..64");
+      return CGP_E_ARG;
+    }
+  }
+  if ((t->pcg_barrier != 0 && t->pcg_barrier != 1) || t->pcg_grid < 0) {
+    set_error("cgp_mesh_set_tuning: pcg_barrier must be 0 or 1 and pcg_grid >= 0");
+    return CGP_E_ARG;
+  }
+  m->tune = *t;
+  return CGP_OK;
 }
 
 cgp_status cgp_spmv(cgp_mesh *m, int32_t op, const void *x, void *y) {

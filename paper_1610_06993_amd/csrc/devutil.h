@@ -18,7 +18,7 @@
 namespace cgp {
 namespace dev {
 
-constexpr int kRedBlock = 1024;  // threads of every reducing kernel
+constexpr int kMaxBlock = 1024;  // largest block of a reducing kernel (sizes the LDS scratch)
 
 // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
 // contiguous range of the logical block index so that the rows a block
@@ -54,7 +54,7 @@ __device__ __forceinline__ bool is_finite(double x) { return x == x && x - x == 
 // Sum K values over the block in a fixed order; every thread gets the totals.
 template <int K>
 __device__ __forceinline__ void block_sum(const double (&v)[K], double (&tot)[K]) {
-  __shared__ double sh[K][kRedBlock / 64];
+  __shared__ double sh[K][kMaxBlock / 64];
   __shared__ double res[K];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll

@@ -122,7 +122,8 @@ struct cgp_mesh {
   cgp::ReduceScratch red;
   int cu_count = 0;
   int red_grid = 0;               // blocks of every reducing kernel (one partial per block)
-  int coop_blocks = 0;            // co-resident blocks for the persistent PCG
+  int coop_blocks = 0;            // blocks of the persistent PCG (0: not set up)
+  int coop_max = 0;               // co-resident blocks reported by the runtime
   int *d_row_begin = nullptr;     // row range per persistent block
   void *d_bar = nullptr;          // grid barrier
   double *d_ppartials = nullptr;  // persistent-kernel partials
@@ -130,7 +131,7 @@ struct cgp_mesh {
   std::vector<void *> allocations;
   double *d_scalar = nullptr;     // device scalar for sums (means)
   double *h_scalar = nullptr;     // pinned [4]
-  int lanes_f = 8, lanes_c = 8;   // lanes per CSR row in SpMV-type kernels
+  cgp_tuning tune{{4, 512, 2}, {4, 512, 1}, 0, 0};  // Krylov launch shapes (fine, coarse), persistent kernel
   int mom_chunk = 4, p_chunk = 32, p32_chunk = 16, mass_chunk = 8;  // Krylov iterations queued before a poll
   // HIP-event timing of every launch of the Poisson SpMV kernel (cgp_step_opts.timing == 2)
   bool kt_on = false;

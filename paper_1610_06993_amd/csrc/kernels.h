@@ -7,7 +7,20 @@
 
 namespace cgp {
 
-constexpr int kMaxGrid = 2048;        // cap on blocks of row kernels (grid-stride loops)
+constexpr int kMaxGrid = 2048;        // cap on blocks of non-reducing row kernels (grid-stride loops)
+constexpr int kMaxRedGrid = 8192;     // cap on blocks of reducing kernels (one partial each)
+
+// Launch shape of a reducing kernel: `lanes` threads per CSR row (row kernels),
+// `block` threads per block, each lane group covering `passes` rows.
+struct Shape {
+  int grid, block;
+};
+inline Shape shape_rows(const cgp_tuning_knobs &t, long long n, int lanes) {
+  long long per_block = (long long)t.block * t.passes / lanes;
+  long long g = (n + per_block - 1) / per_block;
+  g = g < 8 ? 8 : (g + 7) / 8 * 8;
+  return Shape{int(g < kMaxRedGrid ? g : kMaxRedGrid), t.block};
+}
 
 inline int grid_for(long long threads) {
   long long b = (threads + 255) / 256;

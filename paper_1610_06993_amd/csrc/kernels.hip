@@ -291,7 +291,7 @@ __global__ void k_pdir_zero(int n, const unsigned char *__restrict__ pdir, doubl
 }
 
 // Partials of sum_i w[i] x[i] (w = NULL: plain sum), one per block.
-__global__ void __launch_bounds__(kRedBlock) k_wsum(int n, const double *__restrict__ w, const double *__restrict__ x,
+__global__ void __launch_bounds__(kMaxBlock) k_wsum(int n, const double *__restrict__ w, const double *__restrict__ x,
                                                     double *__restrict__ P) {
   double acc[1] = {0.0};
   const int stride = gridDim.x * blockDim.x;
@@ -300,7 +300,7 @@ __global__ void __launch_bounds__(kRedBlock) k_wsum(int n, const double *__restr
 }
 
 // x -= (sum of the G partials) / den
-__global__ void __launch_bounds__(kRedBlock) k_shift(int n, double *__restrict__ x, const double *__restrict__ P,
+__global__ void __launch_bounds__(kMaxBlock) k_shift(int n, double *__restrict__ x, const double *__restrict__ P,
                                                      int G, double den) {
   double tot[1];
   sum_partials<1>(P, G, tot);
@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(kRedBlock) k_shift(int n, double *__restrict__
 }
 
 // *out = sum of the G partials (one block)
-__global__ void __launch_bounds__(kRedBlock) k_reduce_scalar(const double *__restrict__ P, int G,
+__global__ void __launch_bounds__(kMaxBlock) k_reduce_scalar(const double *__restrict__ P, int G,
                                                              double *__restrict__ out) {
   double tot[1];
   sum_partials<1>(P, G, tot);
@@ -409,7 +409,7 @@ void launch_mom_rhs(cgp_mesh *m, const double *g, const double *u, const double 
 void launch_correct_rhs(cgp_mesh *m, const double *g, const double *ut, const double *pf, double *rhs) {
   const int n = m->pf.n;
   const double sc = m->params.dt / m->params.rho;
-  dispatch_L(m->lanes_f, [&](auto LC) {
+  dispatch_L(m->tune.fine.lanes, [&](auto LC) {
     constexpr int LL = decltype(LC)::value;
     hipLaunchKernelGGL((k_correct_rhs<LL>), dim3(grid_for((long long)n * LL)), dim3(256), 0, m->stream, n, m->d_rp_f,
                        m->d_col_f, m->d_vdir, m->d_M, (const double2 *)m->d_D, (const double2 *)ut, pf,
@@ -420,7 +420,7 @@ void launch_correct_rhs(cgp_mesh *m, const double *g, const double *ut, const do
 void launch_correct_lumped(cgp_mesh *m, const double *g, const double *ut, const double *pf, double *u) {
   const int n = m->pf.n;
   const double sc = m->params.dt / m->params.rho;
-  dispatch_L(m->lanes_f, [&](auto LC) {
+  dispatch_L(m->tune.fine.lanes, [&](auto LC) {
     constexpr int LL = decltype(LC)::value;
     hipLaunchKernelGGL((k_correct_lumped<LL>), dim3(grid_for((long long)n * LL)), dim3(256), 0, m->stream, n,
                        m->d_rp_f, m->d_col_f, m->d_vdir, (const double2 *)m->d_D, (const double2 *)ut, pf, m->d_ml,
@@ -440,9 +440,9 @@ void launch_pdir_zero(cgp_mesh *m, double *b, double *x) {
 }
 
 void launch_mean_shift(cgp_mesh *m, double *x, const double *w, double den, double *P) {
-  const int n = m->pc.n, G = m->red_grid;
-  hipLaunchKernelGGL(k_wsum, dim3(G), dim3(kRedBlock), 0, m->stream, n, w, (const double *)x, P);
-  hipLaunchKernelGGL(k_shift, dim3(G), dim3(kRedBlock), 0, m->stream, n, x, (const double *)P, G, den);
+  const int n = m->pc.n, G = 256;
+  hipLaunchKernelGGL(k_wsum, dim3(G), dim3(256), 0, m->stream, n, w, (const double *)x, P);
+  hipLaunchKernelGGL(k_shift, dim3(G), dim3(256), 0, m->stream, n, x, (const double *)P, G, den);
 }
 
 
@@ -472,10 +472,9 @@ cgp_status drv_assemble(cgp_mesh *m) {
                      m->d_Kbc, m->d_dinvK, m->d_Kbc32, m->d_dinvK32);
   hipLaunchKernelGGL(k_mass_bc, dim3(blocks_1d(Nf)), dim3(256), 0, s, Nf, m->d_rp_f, m->d_col_f, m->d_vdir, m->d_M,
                      m->d_Mbc, m->d_dinvM, m->d_ml);
-  hipLaunchKernelGGL(k_wsum, dim3(m->red_grid), dim3(kRedBlock), 0, s, Nc, (const double *)nullptr,
-                     (const double *)m->d_mc, m->red.partials);
-  hipLaunchKernelGGL(k_reduce_scalar, dim3(1), dim3(kRedBlock), 0, s, (const double *)m->red.partials, m->red_grid,
-                     m->d_scalar);
+  hipLaunchKernelGGL(k_wsum, dim3(256), dim3(256), 0, s, Nc, (const double *)nullptr, (const double *)m->d_mc,
+                     m->red.partials);
+  hipLaunchKernelGGL(k_reduce_scalar, dim3(1), dim3(256), 0, s, (const double *)m->red.partials, 256, m->d_scalar);
   CGP_HIP(hipGetLastError());
   CGP_HIP(hipMemcpyAsync(&m->h_scalar[0], m->d_scalar, sizeof(double), hipMemcpyDeviceToHost, s));
   CGP_HIP(hipStreamSynchronize(s));
@@ -488,14 +487,14 @@ cgp_status drv_restrict(cgp_mesh *m, const double *ut, double *bc) {
   hipStream_t s = m->stream;
   const double sc = -m->params.rho / m->params.dt;
   if (m->params.restrict_mode == CGP_RESTRICT_INJECT || m->levels == 0) {
-    const int n = m->pc.n, L = m->lanes_c;
+    const int n = m->pc.n, L = m->tune.coarse.lanes;
     dispatch_L(L, [&](auto LC) {
       constexpr int LL = decltype(LC)::value;
       hipLaunchKernelGGL((k_div<LL>), dim3(grid_for((long long)n * LL)), dim3(256), 0, s, n, m->d_rp_c, m->d_col_c,
                          (const double2 *)m->d_Dc, (const double2 *)ut, sc, bc);
     });
   } else {
-    const int n = m->pf.n, L = m->lanes_f;
+    const int n = m->pf.n, L = m->tune.fine.lanes;
     double *bf = m->d_wlev[m->levels];
     dispatch_L(L, [&](auto LC) {
       constexpr int LL = decltype(LC)::value;
@@ -537,14 +536,14 @@ cgp_status drv_spmv(cgp_mesh *m, int op, const void *x, void *y) {
   hipStream_t s = m->stream;
   switch (op) {
     case CGP_OP_KBC_C:
-      dispatch_L(m->lanes_c, [&](auto LC) {
+      dispatch_L(m->tune.coarse.lanes, [&](auto LC) {
         constexpr int LL = decltype(LC)::value;
         hipLaunchKernelGGL((k_spmv1<LL>), dim3(grid_for((long long)m->pc.n * LL)), dim3(256), 0, s, m->pc.n,
                            m->d_rp_c, m->d_col_c, (const double *)m->d_Kbc, (const double *)x, (double *)y);
       });
       break;
     case CGP_OP_KBC_C32:
-      dispatch_L(m->lanes_c, [&](auto LC) {
+      dispatch_L(m->tune.coarse.lanes, [&](auto LC) {
         constexpr int LL = decltype(LC)::value;
         hipLaunchKernelGGL((k_spmv1_f32<LL>), dim3(grid_for((long long)m->pc.n * LL)), dim3(256), 0, s, m->pc.n,
                            m->d_rp_c, m->d_col_c, (const float *)m->d_Kbc32, (const float *)x, (float *)y);
@@ -552,7 +551,7 @@ cgp_status drv_spmv(cgp_mesh *m, int op, const void *x, void *y) {
       break;
     case CGP_OP_M_F:
     case CGP_OP_A_F:
-      dispatch_L(m->lanes_f, [&](auto LC) {
+      dispatch_L(m->tune.fine.lanes, [&](auto LC) {
         constexpr int LL = decltype(LC)::value;
         hipLaunchKernelGGL((k_spmv2<LL>), dim3(grid_for((long long)m->pf.n * LL)), dim3(256), 0, s, m->pf.n,
                            m->d_rp_f, m->d_col_f, (const double *)(op == CGP_OP_M_F ? m->d_M : m->d_A),

@@ -54,7 +54,7 @@ __device__ __forceinline__ bool all_done(const KrylovState *st) {
 // ------------------------------------------------------------------ PCG
 // r = b - A x, z = D^-1 r, p0 = p1 = 0; partials (r.z, r.r, b.b) per component.
 template <int NC, int L>
-__global__ void __launch_bounds__(kRedBlock) k_cg_init(int n, const int *__restrict__ rp, const int *__restrict__ col,
+__global__ void __launch_bounds__(kMaxBlock) k_cg_init(int n, const int *__restrict__ rp, const int *__restrict__ col,
                                                       const double *__restrict__ A, const double *__restrict__ b,
                                                       const double *__restrict__ x, const double *__restrict__ dinv,
                                                       double *__restrict__ r, double *__restrict__ z,
@@ -107,7 +107,7 @@ __global__ void __launch_bounds__(kRedBlock) k_cg_init(int n, const int *__restr
 // gathered columns; partials p_new.q.  T is the vector/matrix type (double, or
 // float for the inner solve of iterative refinement); sums are in double.
 template <typename T, int NC, int L>
-__global__ void __launch_bounds__(kRedBlock) k_cg_spmv(int it, int n, const int *__restrict__ rp,
+__global__ void __launch_bounds__(kMaxBlock) k_cg_spmv(int Gin, int it, int n, const int *__restrict__ rp,
                                                       const int *__restrict__ col, const T *__restrict__ A,
                                                       const T *__restrict__ z, const T *__restrict__ p_old,
                                                       T *__restrict__ p_new, T *__restrict__ q,
@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(kRedBlock) k_cg_spmv(int it, int n, const int 
   double rz[NC], rr[NC], bb[NC];
   if (it == 0) {
     double t3[3 * NC];
-    sum_partials<3 * NC>(Pin, gridDim.x, t3);
+    sum_partials<3 * NC>(Pin, Gin, t3);
 #pragma unroll
     for (int c = 0; c < NC; c++) {
       rz[c] = t3[c];
@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(kRedBlock) k_cg_spmv(int it, int n, const int 
     }
   } else {
     double t2[2 * NC];
-    sum_partials<2 * NC>(Pin, gridDim.x, t2);
+    sum_partials<2 * NC>(Pin, Gin, t2);
 #pragma unroll
     for (int c = 0; c < NC; c++) {
       rz[c] = t2[c];
@@ -221,14 +221,14 @@ __global__ void __launch_bounds__(kRedBlock) k_cg_spmv(int it, int n, const int 
 // r -= alpha q, z = D^-1 r on the components not yet converged; partials
 // (r.z, r.r).
 template <typename T, int NC>
-__global__ void __launch_bounds__(kRedBlock) k_cg_update(int it, int n, T *__restrict__ x, T *__restrict__ r,
+__global__ void __launch_bounds__(kMaxBlock) k_cg_update(int Gin, int it, int n, T *__restrict__ x, T *__restrict__ r,
                                                         T *__restrict__ z, const T *__restrict__ dinv,
                                                         const T *__restrict__ p, const T *__restrict__ q,
                                                         const double *__restrict__ Pin, double *__restrict__ Pout,
                                                         KrylovState *__restrict__ st) {
   if (st->status || all_done<NC>(st)) return;
   double pq[NC];
-  sum_partials<NC>(Pin, gridDim.x, pq);
+  sum_partials<NC>(Pin, Gin, pq);
   bool act[NC], bad = false;
   double alpha[NC];
 #pragma unroll
@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(kRedBlock) k_cg_update(int it, int n, T *__res
 // After a chunk: publish residual norms, convergence and the iteration count
 // from the last update's partials (one block).
 template <int NC>
-__global__ void __launch_bounds__(kRedBlock) k_cg_finish(int it_end, int G, const double *__restrict__ Pin,
+__global__ void __launch_bounds__(kMaxBlock) k_cg_finish(int it_end, int G, const double *__restrict__ Pin,
                                                         KrylovState *__restrict__ st) {
   if (st->status || all_done<NC>(st)) return;
   double t2[2 * NC];
@@ -305,7 +305,7 @@ __global__ void k_zero_b_fix(int n, double *__restrict__ x, const KrylovState *_
 // ------------------------------------------------------------------ BiCGStab, 2 components
 // r = b - A x, r^ = r, p = v = 0; partials (r.r, b.b) per component.
 template <int L>
-__global__ void __launch_bounds__(kRedBlock) k_bi_init(int n, const int *__restrict__ rp, const int *__restrict__ col,
+__global__ void __launch_bounds__(kMaxBlock) k_bi_init(int n, const int *__restrict__ rp, const int *__restrict__ col,
                                                       const double *__restrict__ A, const double2 *__restrict__ b,
                                                       const double2 *__restrict__ x, double2 *__restrict__ r,
                                                       double2 *__restrict__ rh, double2 *__restrict__ p,
@@ -342,13 +342,13 @@ __global__ void __launch_bounds__(kRedBlock) k_bi_init(int n, const int *__restr
 // Iteration `it` start: reduce (r.r, r^.r) of the previous iteration (or the
 // init partials), test convergence, rho_it = r^.r, beta = (rho_it /
 // rho_{it-1}) (alpha_{it-1} / omega_{it-1}); p = r + beta (p - omega v), p^ = D^-1 p.
-__global__ void __launch_bounds__(kRedBlock) k_bi_p(int it, int n, const double2 *__restrict__ r,
+__global__ void __launch_bounds__(kMaxBlock) k_bi_p(int Gin, int it, int n, const double2 *__restrict__ r,
                                                    double2 *__restrict__ p, const double2 *__restrict__ v,
                                                    const double *__restrict__ dinv, double2 *__restrict__ ph,
                                                    const double *__restrict__ Pin, KrylovState *__restrict__ st) {
   if (st->status || all_done<2>(st)) return;
   double t4[4];
-  sum_partials<4>(Pin, gridDim.x, t4);
+  sum_partials<4>(Pin, Gin, t4);
   double rr[2], rho[2], bb[2], beta[2], om[2];
   bool done[2], all = true, bad = false, brk = false;
   const double tol = st->tol;
@@ -403,7 +403,7 @@ __global__ void __launch_bounds__(kRedBlock) k_bi_p(int it, int n, const double2
 
 // v = A p^; partials r^.v
 template <int L>
-__global__ void __launch_bounds__(kRedBlock) k_bi_v(int n, const int *__restrict__ rp, const int *__restrict__ col,
+__global__ void __launch_bounds__(kMaxBlock) k_bi_v(int n, const int *__restrict__ rp, const int *__restrict__ col,
                                                    const double *__restrict__ A, const double2 *__restrict__ ph,
                                                    double2 *__restrict__ v, const double2 *__restrict__ rh,
                                                    double *__restrict__ Pout, const KrylovState *__restrict__ st) {
@@ -433,7 +433,7 @@ __global__ void __launch_bounds__(kRedBlock) k_bi_v(int n, const int *__restrict
 
 // alpha = rho / (r^.v); s = r - alpha v formed on the fly; t = A (D^-1 s); partials (t.s, t.t)
 template <int L>
-__global__ void __launch_bounds__(kRedBlock) k_bi_t(int it, int n, const int *__restrict__ rp,
+__global__ void __launch_bounds__(kMaxBlock) k_bi_t(int Gin, int it, int n, const int *__restrict__ rp,
                                                    const int *__restrict__ col, const double *__restrict__ A,
                                                    const double2 *__restrict__ r, const double2 *__restrict__ v,
                                                    const double *__restrict__ dinv, double2 *__restrict__ t,
@@ -441,7 +441,7 @@ __global__ void __launch_bounds__(kRedBlock) k_bi_t(int it, int n, const int *__
                                                    KrylovState *__restrict__ st) {
   if (st->status || all_done<2>(st)) return;
   double rv[2];
-  sum_partials<2>(Pin, gridDim.x, rv);
+  sum_partials<2>(Pin, Gin, rv);
   double al[2];
   bool bad = false;
   for (int c = 0; c < 2; c++) {
@@ -482,14 +482,14 @@ __global__ void __launch_bounds__(kRedBlock) k_bi_t(int it, int n, const int *__
 }
 
 // omega = (t.s)/(t.t); x += alpha p^ + omega D^-1 s, r = s - omega t; partials (r.r, r^.r)
-__global__ void __launch_bounds__(kRedBlock) k_bi_x(int it, int n, double2 *__restrict__ x, double2 *__restrict__ r,
+__global__ void __launch_bounds__(kMaxBlock) k_bi_x(int Gin, int it, int n, double2 *__restrict__ x, double2 *__restrict__ r,
                                                    const double2 *__restrict__ v, const double2 *__restrict__ t,
                                                    const double *__restrict__ dinv, const double2 *__restrict__ ph,
                                                    const double2 *__restrict__ rh, const double *__restrict__ Pin,
                                                    double *__restrict__ Pout, KrylovState *__restrict__ st) {
   if (st->status || all_done<2>(st)) return;
   double t4[4];
-  sum_partials<4>(Pin, gridDim.x, t4);
+  sum_partials<4>(Pin, Gin, t4);
   double w[2], al[2];
   bool act[2];
   for (int c = 0; c < 2; c++) {
@@ -527,7 +527,7 @@ __global__ void __launch_bounds__(kRedBlock) k_bi_x(int it, int n, double2 *__re
   put_partials<4>(acc, Pout);
 }
 
-__global__ void __launch_bounds__(kRedBlock) k_bi_finish(int it_end, int G, const double *__restrict__ Pin,
+__global__ void __launch_bounds__(kMaxBlock) k_bi_finish(int it_end, int G, const double *__restrict__ Pin,
                                                         KrylovState *__restrict__ st) {
   if (st->status || all_done<2>(st)) return;
   double t4[4];
@@ -547,7 +547,7 @@ __global__ void __launch_bounds__(kRedBlock) k_bi_finish(int it_end, int G, cons
 // ------------------------------------------------------------------ iterative refinement (FP32 inner PCG)
 // r64 = b - K x in FP64; partials (r.r, b.b)
 template <int L>
-__global__ void __launch_bounds__(kRedBlock) k_ir_residual(int n, const int *__restrict__ rp,
+__global__ void __launch_bounds__(kMaxBlock) k_ir_residual(int n, const int *__restrict__ rp,
                                                           const int *__restrict__ col, const double *__restrict__ A,
                                                           const double *__restrict__ b, const double *__restrict__ x,
                                                           double *__restrict__ r, double *__restrict__ Pout) {
@@ -570,14 +570,14 @@ __global__ void __launch_bounds__(kRedBlock) k_ir_residual(int n, const int *__r
 
 // Outer convergence test and start of the inner solve K32 d = r64 / ||r64||:
 // r = r64/||r64|| (FP32), z = D^-1 r, d = 0, p0 = p1 = 0; partials (r.z, r.r, r.r).
-__global__ void __launch_bounds__(kRedBlock) k_ir_inner_init(int n, const double *__restrict__ r64,
+__global__ void __launch_bounds__(kMaxBlock) k_ir_inner_init(int Gin, int n, const double *__restrict__ r64,
                                                             const float *__restrict__ dinv, float *__restrict__ r,
                                                             float *__restrict__ z, float *__restrict__ d,
                                                             float *__restrict__ p0, float *__restrict__ p1,
                                                             const double *__restrict__ Pin, double *__restrict__ Pout,
                                                             KrylovState *__restrict__ so, KrylovState *__restrict__ si) {
   double t2[2];
-  sum_partials<2>(Pin, gridDim.x, t2);
+  sum_partials<2>(Pin, Gin, t2);
   const double rn = sqrt(t2[0]), bn = sqrt(t2[1]);
   const bool bad = !is_finite(rn) || !is_finite(bn);
   const bool done = bn == 0.0 || rn <= so->tol * bn;
@@ -636,10 +636,10 @@ using namespace dev;
 namespace {
 
 enum { SLOT_MOM = 0, SLOT_P = 1, SLOT_PIN = 2, SLOT_MASS = 3 };
-// partial-sum regions (each holds up to 8 arrays of red_grid doubles)
+// partial-sum regions (each holds up to 8 arrays of kMaxRedGrid doubles)
 enum { R_INIT = 0, R_A = 1, R_B = 2, R_C = 3 };
 
-inline double *region(cgp_mesh *m, int k) { return m->red.partials + size_t(k) * 8 * m->red_grid; }
+inline double *region(cgp_mesh *m, int k) { return m->red.partials + size_t(k) * 8 * kMaxRedGrid; }
 
 cgp_status poll(cgp_mesh *m, int slot, int count = 1) {
   CGP_HIP(hipMemcpyAsync(&m->h_state[slot], m->d_state + slot, sizeof(KrylovState) * count, hipMemcpyDeviceToHost,
@@ -702,29 +702,42 @@ void kt_end(cgp_mesh *m) {
   m->kt_used++;
 }
 
-// Jacobi-PCG loop (init done by the caller): T = double or float vectors.
+// Launch shapes of one PCG/BiCGStab iteration on a mesh level.
+struct LoopShapes {
+  Shape rows;   // SpMV-type kernels (lanes per row)
+  Shape elem;   // vector kernels (one lane per entry)
+};
+LoopShapes loop_shapes(const cgp_tuning_knobs &t, int n) {
+  return LoopShapes{shape_rows(t, n, t.lanes), shape_rows(t, n, 1)};
+}
+
+// Jacobi-PCG loop (init done by the caller, with its partials in R_INIT from a
+// grid of G0 blocks): T = double or float vectors.
 template <typename T, int NC>
 cgp_status pcg_loop(cgp_mesh *m, int slot, int n, const int *rp, const int *col, const T *A, const T *dinv, T *x,
-                    T *r, T *z, T *p0, T *p1, T *q, int L, int maxit, int *chunk_hint, bool timed, KrylovState *out) {
+                    T *r, T *z, T *p0, T *p1, T *q, const cgp_tuning_knobs &tk, int G0, int maxit, int *chunk_hint,
+                    bool timed, KrylovState *out) {
   KrylovState *st = m->d_state + slot;
   hipStream_t s = m->stream;
-  const int G = m->red_grid;
+  const LoopShapes sh = loop_shapes(tk, n);
   double *Pinit = region(m, R_INIT), *Ppq = region(m, R_A), *Pupd = region(m, R_B);
   int it = 0, chunk = std::max(1, std::min(*chunk_hint, maxit));
   for (;;) {
-    dispatch_L(L, [&](auto LC) {
+    dispatch_L(tk.lanes, [&](auto LC) {
       constexpr int LL = decltype(LC)::value;
       for (int c = 0; c < chunk && it < maxit; c++, it++) {
         T *po = (it & 1) ? p1 : p0, *pn = (it & 1) ? p0 : p1;
         if (timed) kt_begin(m, it);
-        hipLaunchKernelGGL((k_cg_spmv<T, NC, LL>), dim3(G), dim3(kRedBlock), 0, s, it, n, rp, col, A,
-                           (const T *)z, (const T *)po, pn, q, (const double *)(it == 0 ? Pinit : Pupd), Ppq, st);
+        hipLaunchKernelGGL((k_cg_spmv<T, NC, LL>), dim3(sh.rows.grid), dim3(sh.rows.block), 0, s,
+                           it == 0 ? G0 : sh.elem.grid, it, n, rp, col, A, (const T *)z, (const T *)po, pn, q,
+                           (const double *)(it == 0 ? Pinit : Pupd), Ppq, st);
         if (timed) kt_end(m);
-        hipLaunchKernelGGL((k_cg_update<T, NC>), dim3(G), dim3(kRedBlock), 0, s, it, n, x, r, z, dinv, (const T *)pn,
-                           (const T *)q, (const double *)Ppq, Pupd, st);
+        hipLaunchKernelGGL((k_cg_update<T, NC>), dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, sh.rows.grid, it, n,
+                           x, r, z, dinv, (const T *)pn, (const T *)q, (const double *)Ppq, Pupd, st);
       }
     });
-    hipLaunchKernelGGL((k_cg_finish<NC>), dim3(1), dim3(kRedBlock), 0, s, it, G, (const double *)Pupd, st);
+    hipLaunchKernelGGL((k_cg_finish<NC>), dim3(1), dim3(256), 0, s, it, it == 0 ? G0 : sh.elem.grid,
+                       (const double *)(it == 0 ? Pinit : Pupd), st);
     CGP_HIP(hipGetLastError());
     cgp_status ps = poll(m, slot);
     if (ps) return ps;
@@ -740,18 +753,19 @@ cgp_status pcg_loop(cgp_mesh *m, int slot, int n, const int *rp, const int *col,
 
 template <int NC>
 cgp_status run_pcg64(cgp_mesh *m, int slot, int n, const int *rp, const int *col, const double *A,
-                     const double *dinv, const double *b, double *x, double **w, int L, double tol, int maxit,
-                     int *chunk_hint, bool timed, KrylovState *out) {
+                     const double *dinv, const double *b, double *x, double **w, const cgp_tuning_knobs &tk,
+                     double tol, int maxit, int *chunk_hint, bool timed, KrylovState *out) {
   KrylovState *st = m->d_state + slot;
   hipStream_t s = m->stream;
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, st, tol, maxit, NC);
-  dispatch_L(L, [&](auto LC) {
+  const Shape init = shape_rows(tk, n, tk.lanes);
+  dispatch_L(tk.lanes, [&](auto LC) {
     constexpr int LL = decltype(LC)::value;
-    hipLaunchKernelGGL((k_cg_init<NC, LL>), dim3(m->red_grid), dim3(kRedBlock), 0, s, n, rp, col, A, b,
+    hipLaunchKernelGGL((k_cg_init<NC, LL>), dim3(init.grid), dim3(init.block), 0, s, n, rp, col, A, b,
                        (const double *)x, dinv, w[0], w[1], w[2], w[3], region(m, R_INIT));
   });
-  cgp_status ls = pcg_loop<double, NC>(m, slot, n, rp, col, A, dinv, x, w[0], w[1], w[2], w[3], w[4], L, maxit,
-                                       chunk_hint, timed, out);
+  cgp_status ls = pcg_loop<double, NC>(m, slot, n, rp, col, A, dinv, x, w[0], w[1], w[2], w[3], w[4], tk, init.grid,
+                                       maxit, chunk_hint, timed, out);
   if (ls) return ls;
   hipLaunchKernelGGL((k_zero_b_fix<NC>), dim3(blocks_1d(n)), dim3(256), 0, s, n, x, (const KrylovState *)st);
   return status_of(*out);
@@ -777,33 +791,36 @@ cgp_status drv_momentum(cgp_mesh *m, const cgp_solver_opts *o, const double *g, 
   double2 *v = (double2 *)m->d_wf[4], *t = (double2 *)m->d_wf[5], *ph = (double2 *)m->d_wf[6];
   KrylovState *st = m->d_state + SLOT_MOM;
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, st, o->tol, o->max_iter, 2);
-  const int L = m->lanes_f, G = m->red_grid;
+  const cgp_tuning_knobs &tk = m->tune.fine;
+  const LoopShapes sh = loop_shapes(tk, n);
   const int *rp = m->d_rp_f, *col = m->d_col_f;
   const double *A = m->d_A, *dinv = m->d_dinvA;
   double2 *x = (double2 *)ut;
   double *Pinit = region(m, R_INIT), *Pv = region(m, R_A), *Pt = region(m, R_B), *Px = region(m, R_C);
-  dispatch_L(L, [&](auto LC) {
+  dispatch_L(tk.lanes, [&](auto LC) {
     constexpr int LL = decltype(LC)::value;
-    hipLaunchKernelGGL((k_bi_init<LL>), dim3(G), dim3(kRedBlock), 0, s, n, rp, col, A, (const double2 *)rhs,
-                       (const double2 *)x, r, rh, p, v, Pinit);
+    hipLaunchKernelGGL((k_bi_init<LL>), dim3(sh.rows.grid), dim3(sh.rows.block), 0, s, n, rp, col, A,
+                       (const double2 *)rhs, (const double2 *)x, r, rh, p, v, Pinit);
   });
   int it = 0, chunk = std::max(1, std::min(m->mom_chunk, o->max_iter));
   for (;;) {
-    dispatch_L(L, [&](auto LC) {
+    dispatch_L(tk.lanes, [&](auto LC) {
       constexpr int LL = decltype(LC)::value;
       for (int c = 0; c < chunk && it < o->max_iter; c++, it++) {
-        hipLaunchKernelGGL(k_bi_p, dim3(G), dim3(kRedBlock), 0, s, it, n, (const double2 *)r, p, (const double2 *)v,
-                           dinv, ph, (const double *)(it == 0 ? Pinit : Px), st);
-        hipLaunchKernelGGL((k_bi_v<LL>), dim3(G), dim3(kRedBlock), 0, s, n, rp, col, A, (const double2 *)ph, v,
-                           (const double2 *)rh, Pv, (const KrylovState *)st);
-        hipLaunchKernelGGL((k_bi_t<LL>), dim3(G), dim3(kRedBlock), 0, s, it, n, rp, col, A, (const double2 *)r,
-                           (const double2 *)v, dinv, t, (const double *)Pv, Pt, st);
-        hipLaunchKernelGGL(k_bi_x, dim3(G), dim3(kRedBlock), 0, s, it, n, x, r, (const double2 *)v,
-                           (const double2 *)t, dinv, (const double2 *)ph, (const double2 *)rh, (const double *)Pt, Px,
-                           st);
+        hipLaunchKernelGGL(k_bi_p, dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, it == 0 ? sh.rows.grid : sh.elem.grid,
+                           it, n, (const double2 *)r, p, (const double2 *)v, dinv, ph,
+                           (const double *)(it == 0 ? Pinit : Px), st);
+        hipLaunchKernelGGL((k_bi_v<LL>), dim3(sh.rows.grid), dim3(sh.rows.block), 0, s, n, rp, col, A,
+                           (const double2 *)ph, v, (const double2 *)rh, Pv, (const KrylovState *)st);
+        hipLaunchKernelGGL((k_bi_t<LL>), dim3(sh.rows.grid), dim3(sh.rows.block), 0, s, sh.rows.grid, it, n, rp, col,
+                           A, (const double2 *)r, (const double2 *)v, dinv, t, (const double *)Pv, Pt, st);
+        hipLaunchKernelGGL(k_bi_x, dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, sh.rows.grid, it, n, x, r,
+                           (const double2 *)v, (const double2 *)t, dinv, (const double2 *)ph, (const double2 *)rh,
+                           (const double *)Pt, Px, st);
       }
     });
-    hipLaunchKernelGGL(k_bi_finish, dim3(1), dim3(kRedBlock), 0, s, it, G, (const double *)Px, st);
+    hipLaunchKernelGGL(k_bi_finish, dim3(1), dim3(256), 0, s, it, it == 0 ? sh.rows.grid : sh.elem.grid,
+                       (const double *)(it == 0 ? Pinit : Px), st);
     CGP_HIP(hipGetLastError());
     cgp_status ps = poll(m, SLOT_MOM);
     if (ps) return ps;
@@ -830,7 +847,9 @@ namespace {
 cgp_status poisson_ir(cgp_mesh *m, const double *b, double *x, const cgp_solver_opts *o, bool persistent,
                       KrylovState *fin, int *total_iters, int *outer_out) {
   hipStream_t s = m->stream;
-  const int n = m->pc.n, L = m->lanes_c, G = m->red_grid;
+  const int n = m->pc.n;
+  const cgp_tuning_knobs &tk = m->tune.coarse;
+  const LoopShapes sh = loop_shapes(tk, n);
   KrylovState *so = m->d_state + SLOT_P, *si = m->d_state + SLOT_PIN;
   double *r64 = m->d_wc[1];
   float *r = m->d_wc32[0], *z = m->d_wc32[1], *d = m->d_wc32[2], *p0 = m->d_wc32[3], *p1 = m->d_wc32[4],
@@ -838,17 +857,20 @@ cgp_status poisson_ir(cgp_mesh *m, const double *b, double *x, const cgp_solver_
   const double inner_tol = o->inner_tol > 0 ? o->inner_tol : 1e-4;
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, so, o->tol, o->max_iter, 1);
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, si, inner_tol, o->max_iter, 1);
+  auto residual = [&]() {
+    dispatch_L(tk.lanes, [&](auto LC) {
+      constexpr int LL = decltype(LC)::value;
+      hipLaunchKernelGGL((k_ir_residual<LL>), dim3(sh.rows.grid), dim3(sh.rows.block), 0, s, n, m->d_rp_c,
+                         m->d_col_c, (const double *)m->d_Kbc, b, (const double *)x, r64, region(m, R_C));
+    });
+    hipLaunchKernelGGL(k_ir_inner_init, dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, sh.rows.grid, n,
+                       (const double *)r64, (const float *)m->d_dinvK32, r, z, d, p0, p1,
+                       (const double *)region(m, R_C), region(m, R_INIT), so, si);
+  };
   int outer = 0;
   *total_iters = 0;
   for (outer = 0; outer < 200; outer++) {
-    dispatch_L(L, [&](auto LC) {
-      constexpr int LL = decltype(LC)::value;
-      hipLaunchKernelGGL((k_ir_residual<LL>), dim3(G), dim3(kRedBlock), 0, s, n, m->d_rp_c, m->d_col_c,
-                         (const double *)m->d_Kbc, b, (const double *)x, r64, region(m, R_C));
-    });
-    hipLaunchKernelGGL(k_ir_inner_init, dim3(G), dim3(kRedBlock), 0, s, n, (const double *)r64,
-                       (const float *)m->d_dinvK32, r, z, d, p0, p1, (const double *)region(m, R_C),
-                       region(m, R_INIT), so, si);
+    residual();
     const int budget = std::max(1, o->max_iter - *total_iters);
     KrylovState hi{};
     if (persistent) {
@@ -867,8 +889,8 @@ cgp_status poisson_ir(cgp_mesh *m, const double *b, double *x, const cgp_solver_
       }
     } else {
       cgp_status ls = pcg_loop<float, 1>(m, SLOT_PIN, n, m->d_rp_c, m->d_col_c, (const float *)m->d_Kbc32,
-                                         (const float *)m->d_dinvK32, d, r, z, p0, p1, q, L, budget, &m->p32_chunk,
-                                         true, &hi);
+                                         (const float *)m->d_dinvK32, d, r, z, p0, p1, q, tk, sh.elem.grid, budget,
+                                         &m->p32_chunk, true, &hi);
       if (ls) return ls;
       cgp_status ps = poll(m, SLOT_P);
       if (ps) return ps;
@@ -886,15 +908,7 @@ cgp_status poisson_ir(cgp_mesh *m, const double *b, double *x, const cgp_solver_
     hipLaunchKernelGGL(k_ir_update, dim3(blocks_1d(n)), dim3(256), 0, s, n, x, (const float *)d,
                        (const KrylovState *)so, (const KrylovState *)si);
     if (*total_iters >= o->max_iter) {
-      // residual of the last iterate, for the report
-      dispatch_L(L, [&](auto LC) {
-        constexpr int LL = decltype(LC)::value;
-        hipLaunchKernelGGL((k_ir_residual<LL>), dim3(G), dim3(kRedBlock), 0, s, n, m->d_rp_c, m->d_col_c,
-                           (const double *)m->d_Kbc, b, (const double *)x, r64, region(m, R_C));
-      });
-      hipLaunchKernelGGL(k_ir_inner_init, dim3(G), dim3(kRedBlock), 0, s, n, (const double *)r64,
-                         (const float *)m->d_dinvK32, r, z, d, p0, p1, (const double *)region(m, R_C),
-                         region(m, R_INIT), so, si);
+      residual();  // residual of the last iterate, for the report
       cgp_status ps = poll(m, SLOT_P);
       if (ps) return ps;
       *fin = m->h_state[SLOT_P];
@@ -950,7 +964,7 @@ cgp_status drv_poisson(cgp_mesh *m, const double *b_in, double *x, const cgp_sol
       rs = status_of(fin);
     } else {
       double *w[5] = {m->d_wc[1], m->d_wc[2], m->d_wc[3], m->d_wc[4], m->d_wc[5]};
-      rs = run_pcg64<1>(m, SLOT_P, n, m->d_rp_c, m->d_col_c, m->d_Kbc, m->d_dinvK, b, x, w, m->lanes_c, o->tol,
+      rs = run_pcg64<1>(m, SLOT_P, n, m->d_rp_c, m->d_col_c, m->d_Kbc, m->d_dinvK, b, x, w, m->tune.coarse, o->tol,
                         o->max_iter, &m->p_chunk, true, &fin);
     }
     total_iters = fin.iters;
@@ -972,7 +986,7 @@ cgp_status drv_poisson(cgp_mesh *m, const double *b_in, double *x, const cgp_sol
 cgp_status drv_correct(cgp_mesh *m, const cgp_solver_opts *o, const double *g, const double *ut, const double *pf,
                        double *u, cgp_stats *stats) {
   hipStream_t s = m->stream;
-  const int n = m->pf.n, L = m->lanes_f;
+  const int n = m->pf.n;
   if (m->params.mass_mode == CGP_MASS_LUMPED) {
     launch_correct_lumped(m, g, ut, pf, u);
     CGP_HIP(hipGetLastError());
@@ -990,8 +1004,8 @@ cgp_status drv_correct(cgp_mesh *m, const cgp_solver_opts *o, const double *g, c
     CGP_HIP(hipMemcpyAsync(u, ut, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
   double *w[5] = {m->d_wf[1], m->d_wf[2], m->d_wf[3], m->d_wf[4], m->d_wf[5]};
   KrylovState fin{};
-  cgp_status rs = run_pcg64<2>(m, SLOT_MASS, n, m->d_rp_f, m->d_col_f, m->d_Mbc, m->d_dinvM, rhs, u, w, L, o->tol,
-                               o->max_iter, &m->mass_chunk, false, &fin);
+  cgp_status rs = run_pcg64<2>(m, SLOT_MASS, n, m->d_rp_f, m->d_col_f, m->d_Mbc, m->d_dinvM, rhs, u, w, m->tune.fine,
+                               o->tol, o->max_iter, &m->mass_chunk, false, &fin);
   launch_set_dirichlet(m, g, u);
   CGP_HIP(hipGetLastError());
   if (stats) {

@@ -17,6 +17,7 @@
 // of iterative refinement (T = float, right-hand side r64/||r64||, zero guess);
 // dot products are accumulated in FP64 in both.  Every barrier wait is bounded:
 // a block that spins too long sets an abort flag, and all blocks leave.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -26,7 +27,7 @@ namespace cgp {
 namespace pdev {
 
 constexpr int kBlock = 1024;
-constexpr long long kSpinLimit = 1ll << 27;
+constexpr long long kSpinLimit = 1ll << 24;
 
 struct GridBar {
   unsigned count;
@@ -41,35 +42,42 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
-// Grid barrier: release this block's writes, wait for every block, acquire theirs.
-__device__ __forceinline__ void grid_sync(GridBar *bar) {
-  __threadfence();
+// Grid barrier.  BAR = 0: one arrival counter that only ever grows (zeroed
+// before the launch); barrier number k of the kernel completes when it
+// reaches gridDim.x * (k + 1), so there is no reset to race with.  Only
+// thread 0 of a block orders memory (agent-scope release on arrival, acquire
+// after the wait); the workgroup barriers around it cover the block's other
+// waves, so a block pays one L2 writeback and one invalidate per barrier.
+// BAR = 1: the HIP cooperative-groups grid barrier.
+template <int BAR>
+__device__ __forceinline__ void grid_sync(GridBar *bar, unsigned &epoch) {
+  if (BAR == 1) {
+    cooperative_groups::this_grid().sync();
+    return;
+  }
+  epoch += 1;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned gen = __hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned arrived = __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == gridDim.x - 1) {
-      __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&bar->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      long long spins = 0;
-      while (__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > kSpinLimit) {
-          __hip_atomic_store(&bar->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
+    const unsigned target = gridDim.x * epoch;
+    __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    long long spins = 0;
+    while (__hip_atomic_load(&bar->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kSpinLimit) {
+        __hip_atomic_store(&bar->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see every block's writes made before the barrier
   }
   __syncthreads();
-  __threadfence();
 }
 
 // Block-reduce K values, publish one partial per block in buf[k][grid], barrier,
 // then sum all partials in a fixed order; tot[] is identical in every block.
-template <int K>
-__device__ __forceinline__ void grid_allreduce(double (&v)[K], double *buf, GridBar *bar, double (&tot)[K]) {
+template <int K, int BAR>
+__device__ __forceinline__ void grid_allreduce(double (&v)[K], double *buf, GridBar *bar, unsigned &epoch,
+                                               double (&tot)[K]) {
   __shared__ double sh[K][kBlock / 64];
   __shared__ double res[K];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -82,14 +90,14 @@ __device__ __forceinline__ void grid_allreduce(double (&v)[K], double *buf, Grid
   if (threadIdx.x < K) {
     double s = 0.0;
     for (int w = 0; w < nw; w++) s += sh[threadIdx.x][w];
-    __hip_atomic_store(&buf[threadIdx.x * gridDim.x + blockIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    buf[threadIdx.x * gridDim.x + blockIdx.x] = s;
   }
-  grid_sync(bar);
+  grid_sync<BAR>(bar, epoch);
 #pragma unroll
   for (int k = 0; k < K; k++) {
     double x = 0.0;
     for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
-      x += __hip_atomic_load(&buf[k * gridDim.x + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      x += buf[k * gridDim.x + b];
     x = wave_sum(x);
     if (lane == 0) sh[k][wid] = x;
   }
@@ -106,7 +114,7 @@ __device__ __forceinline__ void grid_allreduce(double (&v)[K], double *buf, Grid
 
 __device__ __forceinline__ bool finite(double x) { return x == x && x - x == 0.0; }
 
-template <typename T, int L, bool IR>
+template <typename T, int L, bool IR, int BAR>
 __global__ void __launch_bounds__(kBlock) k_pcg_persistent(PersistArgs args) {
   const PersistArgs &a = args;
   const T *__restrict__ K = static_cast<const T *>(a.val);
@@ -121,7 +129,8 @@ __global__ void __launch_bounds__(kBlock) k_pcg_persistent(PersistArgs args) {
   GridBar *bar = reinterpret_cast<GridBar *>(a.bar);
   const int r0 = a.row_begin[blockIdx.x], r1 = a.row_begin[blockIdx.x + 1];
   const int lane = threadIdx.x & (L - 1), grp = threadIdx.x / L, ngrp = blockDim.x / L;
-  int red = 0;  // alternates the two partial buffers
+  int red = 0;          // alternates the two partial buffers
+  unsigned epoch = 0;   // grid barriers passed
   auto buf = [&]() { double *b = a.partials + (red & 1) * 4 * gridDim.x; red++; return b; };
 
   // ---- init: r = b - K x, z = D^-1 r, p_old = 0
@@ -155,7 +164,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_persistent(PersistArgs args) {
     acc3[2] += bb * bb;
   }
   double tot3[3];
-  grid_allreduce<3>(acc3, buf(), bar, tot3);
+  grid_allreduce<3, BAR>(acc3, buf(), bar, epoch, tot3);
   double rz = tot3[0], rnorm = sqrt(tot3[1]);
   const double bnorm = sqrt(tot3[2]);
   const double tol = a.tol;
@@ -189,7 +198,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_persistent(PersistArgs args) {
       }
     }
     double tot1[1];
-    grid_allreduce<1>(acc1, buf(), bar, tot1);
+    grid_allreduce<1, BAR>(acc1, buf(), bar, epoch, tot1);
     const double alpha = rz / tot1[0];
     if (!finite(alpha)) {
       status = CGP_E_NONFINITE;
@@ -209,7 +218,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_persistent(PersistArgs args) {
       acc2[1] += (double)rr * (double)rr;
     }
     double tot2[2];
-    grid_allreduce<2>(acc2, buf(), bar, tot2);
+    grid_allreduce<2, BAR>(acc2, buf(), bar, epoch, tot2);
     beta = tot2[0] / rz;
     rz = tot2[0];
     rnorm = sqrt(tot2[1]);
@@ -233,11 +242,12 @@ __global__ void __launch_bounds__(kBlock) k_pcg_persistent(PersistArgs args) {
 // ---------------------------------------------------------------- host side
 namespace {
 template <typename T, bool IR>
-const void *kernel_ptr(int L) {
+const void *kernel_ptr(int L, int bar) {
   const void *fn = nullptr;
   dispatch_L(L, [&](auto LC) {
     constexpr int LL = decltype(LC)::value;
-    fn = reinterpret_cast<const void *>(&pdev::k_pcg_persistent<T, LL, IR>);
+    fn = bar == 1 ? reinterpret_cast<const void *>(&pdev::k_pcg_persistent<T, LL, IR, 1>)
+                  : reinterpret_cast<const void *>(&pdev::k_pcg_persistent<T, LL, IR, 0>);
   });
   return fn;
 }
@@ -246,29 +256,34 @@ const void *kernel_ptr(int L) {
 int persistent_block() { return pdev::kBlock; }
 
 cgp_status persistent_setup(cgp_mesh *m) {
-  if (m->coop_blocks > 0) return CGP_OK;
   int dev = 0;
   CGP_HIP(hipGetDevice(&dev));
-  int coop = 0;
-  CGP_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
-  if (!coop) {
-    set_error("device does not support cooperative launches");
-    return CGP_E_DEVICE;
-  }
-  // co-resident blocks for the heaviest instantiation
-  int per_cu = 0;
-  for (const void *fn : {kernel_ptr<double, false>(m->lanes_c), kernel_ptr<float, true>(m->lanes_c)}) {
-    int b = 0;
-    CGP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, pdev::kBlock, 0));
-    per_cu = per_cu == 0 ? b : std::min(per_cu, b);
-  }
-  if (per_cu < 1) {
-    set_error("persistent PCG kernel cannot be resident");
-    return CGP_E_DEVICE;
+  if (m->coop_max == 0) {
+    int coop = 0;
+    CGP_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    if (!coop) {
+      set_error("device does not support cooperative launches");
+      return CGP_E_DEVICE;
+    }
+    int per_cu = 0;
+    for (int bar = 0; bar < 2; bar++)
+      for (const void *fn : {kernel_ptr<double, false>(m->tune.coarse.lanes, bar),
+                             kernel_ptr<float, true>(m->tune.coarse.lanes, bar)}) {
+        int b = 0;
+        CGP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, pdev::kBlock, 0));
+        per_cu = per_cu == 0 ? b : std::min(per_cu, b);
+      }
+    if (per_cu < 1) {
+      set_error("persistent PCG kernel cannot be resident");
+      return CGP_E_DEVICE;
+    }
+    m->coop_max = per_cu * m->cu_count;
   }
   const int n = m->pc.n;
-  int grid = std::min(per_cu * m->cu_count, std::max(1, (n + pdev::kBlock - 1) / 256));
-  grid = std::max(1, grid);
+  int grid = m->tune.pcg_grid > 0 ? m->tune.pcg_grid : m->cu_count;
+  grid = std::min(grid, m->coop_max);
+  grid = std::max(1, std::min(grid, (n + 255) / 256));
+  if (grid == m->coop_blocks) return CGP_OK;
   // rows split by nonzeros: block b owns rows [rb[b], rb[b+1])
   std::vector<int> rb(grid + 1, n);
   rb[0] = 0;
@@ -280,13 +295,15 @@ cgp_status persistent_setup(cgp_mesh *m) {
     rb[b] = row;
   }
   void *p = nullptr;
+  if (!m->d_bar) {
+    CGP_HIP(hipMalloc(&p, sizeof(pdev::GridBar)));
+    m->allocations.push_back(p);
+    m->d_bar = p;
+  }
   CGP_HIP(hipMalloc(&p, sizeof(int) * (grid + 1)));
   m->allocations.push_back(p);
   m->d_row_begin = static_cast<int *>(p);
   CGP_HIP(hipMemcpy(m->d_row_begin, rb.data(), sizeof(int) * (grid + 1), hipMemcpyHostToDevice));
-  CGP_HIP(hipMalloc(&p, sizeof(pdev::GridBar)));
-  m->allocations.push_back(p);
-  m->d_bar = p;
   CGP_HIP(hipMalloc(&p, sizeof(double) * 8 * grid));
   m->allocations.push_back(p);
   m->d_ppartials = static_cast<double *>(p);
@@ -318,7 +335,9 @@ cgp_status persistent_pcg(cgp_mesh *m, bool fp32_inner, const double *b, void *x
   a.tol = tol;
   a.maxit = maxit;
   void *args[] = {&a};
-  const void *fn = fp32_inner ? kernel_ptr<float, true>(m->lanes_c) : kernel_ptr<double, false>(m->lanes_c);
+  const int bar = m->tune.pcg_barrier;
+  const void *fn = fp32_inner ? kernel_ptr<float, true>(m->tune.coarse.lanes, bar)
+                              : kernel_ptr<double, false>(m->tune.coarse.lanes, bar);
   CGP_HIP(hipLaunchCooperativeKernel(fn, dim3(m->coop_blocks), dim3(pdev::kBlock), args, 0, m->stream));
   return CGP_OK;
 }
