@@ -57,7 +57,7 @@ def main():
     ap.add_argument("--target-tris", type=int, default=250_000, help="coarse triangles (fine = 4x)")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps timed for the CPU baseline (0: skip)")
     ap.add_argument("--no-instrumented", action="store_true", help="skip the event-bracketed kernel pass")
-    ap.add_argument("--launch", choices=["loop", "persistent"], default="persistent",
+    ap.add_argument("--launch", choices=["loop", "persistent", "fused"], default="fused",
                     help="Poisson Krylov launch strategy")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -92,7 +92,7 @@ def main():
     pc = torch.zeros(info["n_c"], dtype=torch.float64, device=dev)
 
     tol = 1e-8
-    launch = {"loop": 1, "persistent": 2}[args.launch]
+    launch = {"loop": 1, "persistent": 2, "fused": 3}[args.launch]
     fp64 = StepOpts(momentum=SolverOpts(tol=tol, max_iter=5000),
                     poisson=SolverOpts(tol=tol, max_iter=100000, launch=launch),
                     mass=SolverOpts(tol=1e-10, max_iter=2000))
@@ -158,10 +158,15 @@ def main():
             its += s["dominant_iters"]
         nnz_c, n_c = info["nnz_c"], info["n_c"]
         if args.launch == "loop":
-            kname = "k_cg32_spmv"
+            kname = "k_cg_spmv<float>"
             # values 4 B + column 4 B per nonzero; row pointer 4 B, z and p_old 4+4 B read, p_new and q
             # 4+4 B written per row (each vector touched once)
             bytes_per_iter = 8 * nnz_c + 20 * n_c
+        elif args.launch == "fused":
+            kname = "k_cg1_iter<float>"
+            # one whole FP32 iteration: values + columns 8 B per nonzero; row pointer 4 B, D^-1, r, w, s, p, x
+            # read (24 B) and x, p, s, r, w written (20 B) per row, each vector touched once
+            bytes_per_iter = 8 * nnz_c + 48 * n_c
         else:
             kname = "k_pcg_persistent<float>"
             # one FP32 PCG iteration: the SpMV phase above (8 nnz + 20 n) plus the update phase reading

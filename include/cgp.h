@@ -73,9 +73,10 @@ enum { CGP_X0_ZERO = 0,            /* Krylov initial guess zero */
        CGP_X0_PREV = 1,            /* initial guess = the output array's current contents */
        CGP_X0_LEARNED = 2 };       /* Poisson only: guess from the attached POD/MLP model */
 
-enum { CGP_LAUNCH_AUTO = 0,        /* library choice */
-       CGP_LAUNCH_LOOP = 1,        /* one kernel launch per Krylov phase, host polls every chunk */
-       CGP_LAUNCH_PERSISTENT = 2 };/* Poisson: one cooperative kernel for the whole Krylov loop */
+enum { CGP_LAUNCH_AUTO = 0,        /* library choice (FUSED for the Poisson solve) */
+       CGP_LAUNCH_LOOP = 1,        /* two kernels per PCG iteration (textbook recurrences), host polls every chunk */
+       CGP_LAUNCH_PERSISTENT = 2,  /* Poisson: one cooperative kernel for the whole Krylov loop */
+       CGP_LAUNCH_FUSED = 3 };     /* Poisson: one kernel per PCG iteration (Chronopoulos-Gear recurrences) */
 
 typedef struct cgp_mesh cgp_mesh;
 

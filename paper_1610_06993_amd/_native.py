@@ -18,7 +18,7 @@ RESTRICT_INJECT, RESTRICT_GALERKIN = 0, 1
 MASS_CONSISTENT, MASS_LUMPED = 0, 1
 PREC_FP64, PREC_FP32_IR = 0, 1
 X0_ZERO, X0_PREV, X0_LEARNED = 0, 1, 2
-LAUNCH_AUTO, LAUNCH_LOOP, LAUNCH_PERSISTENT = 0, 1, 2
+LAUNCH_AUTO, LAUNCH_LOOP, LAUNCH_PERSISTENT, LAUNCH_FUSED = 0, 1, 2, 3
 OP_KBC_C, OP_M_F, OP_A_F, OP_KBC_C32 = 0, 1, 2, 3
 
 EXPORT = {"xy": 0, "tri": 1, "bedge": 2, "bkind": 3, "parent": 4, "edges": 5, "rowptr_f": 6, "col_f": 7,

@@ -101,7 +101,7 @@ cgp_status build_device(cgp_mesh *m) {
   for (auto &p : m->d_wf) TRY(dalloc(m, &p, 2 * Nf));
   m->d_wc.assign(8, nullptr);
   for (auto &p : m->d_wc) TRY(dalloc(m, &p, Nc));
-  m->d_wc32.assign(6, nullptr);
+  m->d_wc32.assign(8, nullptr);
   for (auto &p : m->d_wc32) TRY(dalloc(m, &p, Nc));
   m->d_wlev.assign(m->levels + 1, nullptr);
   for (int k = 0; k <= m->levels; k++) TRY(dalloc(m, &m->d_wlev[k], size_t(m->lev[k].n)));
@@ -123,7 +123,7 @@ bool valid_opts(const cgp_solver_opts *o, bool poisson) {
   if (!(o->tol > 0.0) || o->max_iter < 1) return false;
   if (o->precision != CGP_PREC_FP64 && !(poisson && o->precision == CGP_PREC_FP32_IR)) return false;
   if (o->x0_mode != CGP_X0_ZERO && o->x0_mode != CGP_X0_PREV) return false;
-  if (o->launch < CGP_LAUNCH_AUTO || o->launch > CGP_LAUNCH_PERSISTENT) return false;
+  if (o->launch < CGP_LAUNCH_AUTO || o->launch > CGP_LAUNCH_FUSED) return false;
   return true;
 }
 

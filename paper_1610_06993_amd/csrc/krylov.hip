@@ -302,6 +302,201 @@ __global__ void k_zero_b_fix(int n, double *__restrict__ x, const KrylovState *_
     if (st->zero_b[c]) x[NC * i + c] = 0.0;
 }
 
+// ------------------------------------------------------------------ single-kernel PCG (Chronopoulos-Gear)
+// The same Jacobi-PCG in the recurrences of Chronopoulos & Gear (1989), which
+// need one global synchronisation per iteration instead of two:
+//   p_i = u_i + beta_i p_{i-1},  s_i = w_i + beta_i s_{i-1}   (s_i = K p_i)
+//   x_{i+1} = x_i + alpha_i p_i,  r_{i+1} = r_i - alpha_i s_i,  u_{i+1} = D^-1 r_{i+1}
+//   w_{i+1} = K u_{i+1},  gamma_{i+1} = r_{i+1}.u_{i+1},  delta_{i+1} = w_{i+1}.u_{i+1}
+//   beta_{i+1} = gamma_{i+1}/gamma_i,  alpha_{i+1} = gamma_{i+1}/(delta_{i+1} - beta_{i+1} gamma_{i+1}/alpha_i)
+// One kernel does a whole iteration: the SpMV forms u_{i+1} on the fly for its
+// gathered columns from the previous iteration's r, w and s, which are kept
+// double-buffered (slot it & 1 is read, the other written).  p and x are only
+// touched on their own rows and are updated in place.
+
+template <typename T>
+__device__ __forceinline__ T cg1_u_next(T dinv, T r, T w, T s, T alpha, T beta) {
+  return dinv * (r - alpha * (w + beta * s));
+}
+
+// init, second kernel: w0 = K u0 with u0 = D^-1 r0 gathered; partials (gamma0, delta0, r0.r0).
+// Reduces the first kernel's partials (b.b) and publishes ||b||.
+template <typename T, int L>
+__global__ void __launch_bounds__(kMaxBlock) k_cg1_init_w(int Gin, int n, const int *__restrict__ rp,
+                                                         const int *__restrict__ col, const T *__restrict__ A,
+                                                         const T *__restrict__ dinv, const T *__restrict__ r0,
+                                                         T *__restrict__ w0, const double *__restrict__ Pin,
+                                                         double *__restrict__ Pout, KrylovState *__restrict__ st) {
+  if (st->status || st->done[0]) return;
+  double tb[1];
+  sum_partials<1>(Pin, Gin, tb);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->bnorm[0] = sqrt(tb[0]);
+    st->zero_b[0] = (tb[0] == 0.0);
+    if (!is_finite(tb[0])) st->status = CGP_E_NONFINITE;
+  }
+  const int lane = threadIdx.x & (L - 1);
+  const int rows_per_grid = gridDim.x * blockDim.x / L;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int row = (xcd_block() * blockDim.x + threadIdx.x) / L; row < n; row += rows_per_grid) {
+    double sum = 0.0;
+    for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
+      const int j = col[k];
+      sum += (double)(A[k] * (dinv[j] * r0[j]));
+    }
+    sum = group_sum<L>(sum);
+    if (lane == 0) {
+      const T w = (T)sum;
+      const double r = (double)r0[row], u = (double)(dinv[row] * r0[row]);
+      w0[row] = w;
+      acc[0] += r * u;
+      acc[1] += (double)w * u;
+      acc[2] += r * r;
+    }
+  }
+  put_partials<3>(acc, Pout);
+}
+
+template <typename T, int L>
+__global__ void __launch_bounds__(kMaxBlock) k_cg1_iter(int Gin, int it, int n, const int *__restrict__ rp,
+                                                       const int *__restrict__ col, const T *__restrict__ A,
+                                                       const T *__restrict__ dinv, T *__restrict__ x,
+                                                       T *__restrict__ p, const T *__restrict__ r_cur,
+                                                       const T *__restrict__ w_cur, const T *__restrict__ s_cur,
+                                                       T *__restrict__ r_nxt, T *__restrict__ w_nxt,
+                                                       T *__restrict__ s_nxt, const double *__restrict__ Pin,
+                                                       double *__restrict__ Pout, KrylovState *__restrict__ st) {
+  if (st->status || st->done[0]) return;
+  double t3[3];
+  sum_partials<3>(Pin, Gin, t3);
+  const double gam = t3[0], del = t3[1], rr = t3[2];
+  const double bb = st->bnorm[0] * st->bnorm[0];
+  const bool done = bb == 0.0 || sqrt(rr) <= st->tol * sqrt(bb);
+  double beta = 0.0, alpha = 0.0;
+  if (it == 0) {
+    alpha = gam / del;
+  } else {
+    beta = gam / st->rz[(it - 1) & 1][0];
+    alpha = gam / (del - beta * gam / st->alpha[(it - 1) & 1][0]);
+  }
+  const bool bad = !is_finite(rr) || (!done && (!is_finite(alpha) || !is_finite(beta)));
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->rz[it & 1][0] = gam;
+    st->alpha[it & 1][0] = alpha;
+    st->rnorm[0] = sqrt(rr);
+    st->iters = it;
+    if (done) st->done[0] = 1;
+    if (bad) st->status = CGP_E_NONFINITE;
+  }
+  if (done || bad) return;
+  const T al = (T)alpha, bt = (T)beta;
+  const int lane = threadIdx.x & (L - 1);
+  const int rows_per_grid = gridDim.x * blockDim.x / L;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int row = (xcd_block() * blockDim.x + threadIdx.x) / L; row < n; row += rows_per_grid) {
+    double sum = 0.0;
+    for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
+      const int j = col[k];
+      sum += (double)(A[k] * cg1_u_next<T>(dinv[j], r_cur[j], w_cur[j], s_cur[j], al, bt));
+    }
+    sum = group_sum<L>(sum);
+    if (lane == 0) {
+      const T d = dinv[row], rc = r_cur[row], wc = w_cur[row], sc = s_cur[row];
+      const T si = wc + bt * sc;
+      const T pi = d * rc + bt * p[row];
+      const T rn = rc - al * si;
+      const T un = cg1_u_next<T>(d, rc, wc, sc, al, bt);
+      const T wn = (T)sum;
+      x[row] = x[row] + al * pi;
+      p[row] = pi;
+      s_nxt[row] = si;
+      r_nxt[row] = rn;
+      w_nxt[row] = wn;
+      acc[0] += (double)rn * (double)un;
+      acc[1] += (double)wn * (double)un;
+      acc[2] += (double)rn * (double)rn;
+    }
+  }
+  put_partials<3>(acc, Pout);
+}
+
+// after a chunk: convergence and iteration count from the last iteration's partials
+__global__ void __launch_bounds__(kMaxBlock) k_cg1_finish(int it_end, int G, const double *__restrict__ Pin,
+                                                         KrylovState *__restrict__ st) {
+  if (st->status || st->done[0]) return;
+  double t3[3];
+  sum_partials<3>(Pin, G, t3);
+  if (threadIdx.x != 0) return;
+  const double rn = sqrt(t3[2]);
+  st->rnorm[0] = rn;
+  st->iters = it_end;
+  if (!is_finite(rn)) st->status = CGP_E_NONFINITE;
+  else if (rn <= st->tol * st->bnorm[0]) st->done[0] = 1;
+}
+
+// FP64 init, first kernel: r0 = b - K x0, p = s_{-1} = 0; partials b.b
+template <int L>
+__global__ void __launch_bounds__(kMaxBlock) k_cg1_init_r(int n, const int *__restrict__ rp,
+                                                         const int *__restrict__ col, const double *__restrict__ A,
+                                                         const double *__restrict__ b, const double *__restrict__ x,
+                                                         double *__restrict__ r0, double *__restrict__ p,
+                                                         double *__restrict__ s0, double *__restrict__ Pout) {
+  const int lane = threadIdx.x & (L - 1);
+  const int rows_per_grid = gridDim.x * blockDim.x / L;
+  double acc[1] = {0.0};
+  for (int row = (xcd_block() * blockDim.x + threadIdx.x) / L; row < n; row += rows_per_grid) {
+    double sum = 0.0;
+    for (int k = rp[row] + lane; k < rp[row + 1]; k += L) sum += A[k] * x[col[k]];
+    sum = group_sum<L>(sum);
+    if (lane == 0) {
+      const double bb = b[row];
+      r0[row] = bb - sum;
+      p[row] = 0.0;
+      s0[row] = 0.0;
+      acc[0] += bb * bb;
+    }
+  }
+  put_partials<1>(acc, Pout);
+}
+
+// FP32 inner solve of iterative refinement, first kernel: outer convergence test on
+// the FP64 residual partials (r.r, b.b); r0 = r64/||r64|| in FP32, d = p = s_{-1} = 0;
+// partials r0.r0 (the inner right-hand side norm).
+__global__ void __launch_bounds__(kMaxBlock) k_cg1_ir_init(int Gin, int n, const double *__restrict__ r64,
+                                                          float *__restrict__ r0, float *__restrict__ d,
+                                                          float *__restrict__ p, float *__restrict__ s0,
+                                                          const double *__restrict__ Pin, double *__restrict__ Pout,
+                                                          KrylovState *__restrict__ so, KrylovState *__restrict__ si) {
+  double t2[2];
+  sum_partials<2>(Pin, Gin, t2);
+  const double rn = sqrt(t2[0]), bn = sqrt(t2[1]);
+  const bool bad = !is_finite(rn) || !is_finite(bn);
+  const bool done = bn == 0.0 || rn <= so->tol * bn;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    so->rnorm[0] = rn;
+    so->bnorm[0] = bn;
+    so->zero_b[0] = (bn == 0.0);
+    so->done[0] = done;
+    if (bad) so->status = CGP_E_NONFINITE;
+    si->done[0] = done || bad;
+    si->status = 0;
+    si->iters = 0;
+  }
+  if (done || bad) return;
+  const double inv = 1.0 / rn;
+  double acc[1] = {0.0};
+  const int stride = gridDim.x * blockDim.x;
+  for (int i = xcd_block() * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float rr = (float)(r64[i] * inv);
+    r0[i] = rr;
+    d[i] = 0.0f;
+    p[i] = 0.0f;
+    s0[i] = 0.0f;
+    acc[0] += (double)rr * (double)rr;
+  }
+  put_partials<1>(acc, Pout);
+}
+
 // ------------------------------------------------------------------ BiCGStab, 2 components
 // r = b - A x, r^ = r, p = v = 0; partials (r.r, b.b) per component.
 template <int L>
@@ -771,6 +966,51 @@ cgp_status run_pcg64(cgp_mesh *m, int slot, int n, const int *rp, const int *col
   return status_of(*out);
 }
 
+// Single-kernel PCG loop.  Precondition: r0 = b - K x0 (or the normalised
+// refinement residual), p = s0 = 0, and the b.b partials in R_INIT from a grid
+// of g_first blocks.
+template <typename T>
+cgp_status cg1_loop(cgp_mesh *m, int slot, int n, const int *rp, const int *col, const T *A, const T *dinv, T *x,
+                    T *p, T *const r[2], T *const w[2], T *const sv[2], const cgp_tuning_knobs &tk, int g_first,
+                    int maxit, int *chunk_hint, bool timed, KrylovState *out) {
+  KrylovState *st = m->d_state + slot;
+  hipStream_t s = m->stream;
+  const Shape sh = shape_rows(tk, n, tk.lanes);
+  double *Pw = region(m, R_A);
+  auto pin = [&](int it) { return it == 0 ? Pw : region(m, ((it - 1) & 1) ? R_C : R_B); };
+  auto pout = [&](int it) { return region(m, (it & 1) ? R_C : R_B); };
+  dispatch_L(tk.lanes, [&](auto LC) {
+    constexpr int LL = decltype(LC)::value;
+    hipLaunchKernelGGL((k_cg1_init_w<T, LL>), dim3(sh.grid), dim3(sh.block), 0, s, g_first, n, rp, col, A, dinv,
+                       (const T *)r[0], w[0], (const double *)region(m, R_INIT), Pw, st);
+  });
+  int it = 0, chunk = std::max(1, std::min(*chunk_hint, maxit));
+  for (;;) {
+    dispatch_L(tk.lanes, [&](auto LC) {
+      constexpr int LL = decltype(LC)::value;
+      for (int c = 0; c < chunk && it < maxit; c++, it++) {
+        const int cur = it & 1, nxt = cur ^ 1;
+        if (timed) kt_begin(m, it);
+        hipLaunchKernelGGL((k_cg1_iter<T, LL>), dim3(sh.grid), dim3(sh.block), 0, s, sh.grid, it, n, rp, col, A,
+                           dinv, x, p, (const T *)r[cur], (const T *)w[cur], (const T *)sv[cur], r[nxt], w[nxt],
+                           sv[nxt], (const double *)pin(it), pout(it), st);
+        if (timed) kt_end(m);
+      }
+    });
+    hipLaunchKernelGGL(k_cg1_finish, dim3(1), dim3(256), 0, s, it, sh.grid, (const double *)pin(it), st);
+    CGP_HIP(hipGetLastError());
+    cgp_status ps = poll(m, slot);
+    if (ps) return ps;
+    const KrylovState &h = m->h_state[slot];
+    if (timed && m->kt_on && (ps = kt_harvest(m, h.iters))) return ps;
+    if (h.status || h.done[0] || it >= maxit) break;
+    chunk = 8;
+  }
+  *out = m->h_state[slot];
+  *chunk_hint = std::max(1, out->iters - 2);
+  return CGP_OK;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ step 1
@@ -844,7 +1084,7 @@ cgp_status drv_momentum(cgp_mesh *m, const cgp_solver_opts *o, const double *g, 
 namespace {
 
 // FP32 Jacobi-PCG inside FP64 iterative refinement, launch-per-phase loop or persistent inner kernel.
-cgp_status poisson_ir(cgp_mesh *m, const double *b, double *x, const cgp_solver_opts *o, bool persistent,
+cgp_status poisson_ir(cgp_mesh *m, const double *b, double *x, const cgp_solver_opts *o, bool persistent, bool fused,
                       KrylovState *fin, int *total_iters, int *outer_out) {
   hipStream_t s = m->stream;
   const int n = m->pc.n;
@@ -854,6 +1094,8 @@ cgp_status poisson_ir(cgp_mesh *m, const double *b, double *x, const cgp_solver_
   double *r64 = m->d_wc[1];
   float *r = m->d_wc32[0], *z = m->d_wc32[1], *d = m->d_wc32[2], *p0 = m->d_wc32[3], *p1 = m->d_wc32[4],
         *q = m->d_wc32[5];
+  float *f1r[2] = {m->d_wc32[0], m->d_wc32[1]}, *f1w[2] = {m->d_wc32[3], m->d_wc32[4]},
+        *f1s[2] = {m->d_wc32[5], m->d_wc32[6]}, *f1p = m->d_wc32[7];
   const double inner_tol = o->inner_tol > 0 ? o->inner_tol : 1e-4;
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, so, o->tol, o->max_iter, 1);
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, si, inner_tol, o->max_iter, 1);
@@ -863,9 +1105,14 @@ cgp_status poisson_ir(cgp_mesh *m, const double *b, double *x, const cgp_solver_
       hipLaunchKernelGGL((k_ir_residual<LL>), dim3(sh.rows.grid), dim3(sh.rows.block), 0, s, n, m->d_rp_c,
                          m->d_col_c, (const double *)m->d_Kbc, b, (const double *)x, r64, region(m, R_C));
     });
-    hipLaunchKernelGGL(k_ir_inner_init, dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, sh.rows.grid, n,
-                       (const double *)r64, (const float *)m->d_dinvK32, r, z, d, p0, p1,
-                       (const double *)region(m, R_C), region(m, R_INIT), so, si);
+    if (fused)
+      hipLaunchKernelGGL(k_cg1_ir_init, dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, sh.rows.grid, n,
+                         (const double *)r64, f1r[0], d, f1p, f1s[0], (const double *)region(m, R_C),
+                         region(m, R_INIT), so, si);
+    else
+      hipLaunchKernelGGL(k_ir_inner_init, dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, sh.rows.grid, n,
+                         (const double *)r64, (const float *)m->d_dinvK32, r, z, d, p0, p1,
+                         (const double *)region(m, R_C), region(m, R_INIT), so, si);
   };
   int outer = 0;
   *total_iters = 0;
@@ -887,6 +1134,13 @@ cgp_status poisson_ir(cgp_mesh *m, const double *b, double *x, const cgp_solver_
         if ((ps = kt_harvest(m, m->h_state[SLOT_P].done[0] ? 0 : 1))) return ps;
         if (!m->h_state[SLOT_P].done[0]) m->kt_iters += (long)hi.iters - used;
       }
+    } else if (fused) {
+      cgp_status ls = cg1_loop<float>(m, SLOT_PIN, n, m->d_rp_c, m->d_col_c, (const float *)m->d_Kbc32,
+                                      (const float *)m->d_dinvK32, d, f1p, f1r, f1w, f1s, tk, sh.elem.grid, budget,
+                                      &m->p32_chunk, true, &hi);
+      if (ls) return ls;
+      cgp_status ps = poll(m, SLOT_P);
+      if (ps) return ps;
     } else {
       cgp_status ls = pcg_loop<float, 1>(m, SLOT_PIN, n, m->d_rp_c, m->d_col_c, (const float *)m->d_Kbc32,
                                          (const float *)m->d_dinvK32, d, r, z, p0, p1, q, tk, sh.elem.grid, budget,
@@ -935,7 +1189,8 @@ cgp_status drv_poisson(cgp_mesh *m, const double *b_in, double *x, const cgp_sol
     // pure Neumann (Eq. 13 on all of the boundary): project b onto the range of Kbar
     launch_mean_shift(m, b, nullptr, double(n), region(m, R_A));
   }
-  bool persistent = (o->launch == CGP_LAUNCH_PERSISTENT);
+  const bool persistent = (o->launch == CGP_LAUNCH_PERSISTENT);
+  const bool fused = (o->launch == CGP_LAUNCH_FUSED || o->launch == CGP_LAUNCH_AUTO);
   if (persistent) {
     cgp_status ss = persistent_setup(m);
     if (ss) return ss;
@@ -962,6 +1217,25 @@ cgp_status drv_poisson(cgp_mesh *m, const double *b_in, double *x, const cgp_sol
         m->kt_iters += (long)fin.iters - used;
       }
       rs = status_of(fin);
+    } else if (fused) {
+      KrylovState *so = m->d_state + SLOT_P;
+      const cgp_tuning_knobs &tk = m->tune.coarse;
+      const Shape sh = shape_rows(tk, n, tk.lanes);
+      double *r[2] = {m->d_wc[1], m->d_wc[2]}, *w[2] = {m->d_wc[3], m->d_wc[4]}, *sv[2] = {m->d_wc[5], m->d_wc[6]};
+      double *p = m->d_wc[7];
+      hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, so, o->tol, o->max_iter, 1);
+      dispatch_L(tk.lanes, [&](auto LC) {
+        constexpr int LL = decltype(LC)::value;
+        hipLaunchKernelGGL((k_cg1_init_r<LL>), dim3(sh.grid), dim3(sh.block), 0, s, n, m->d_rp_c, m->d_col_c,
+                           (const double *)m->d_Kbc, (const double *)b, (const double *)x, r[0], p, sv[0],
+                           region(m, R_INIT));
+      });
+      cgp_status ls = cg1_loop<double>(m, SLOT_P, n, m->d_rp_c, m->d_col_c, (const double *)m->d_Kbc,
+                                       (const double *)m->d_dinvK, x, p, r, w, sv, tk, sh.grid, o->max_iter,
+                                       &m->p_chunk, true, &fin);
+      if (ls) return ls;
+      hipLaunchKernelGGL((k_zero_b_fix<1>), dim3(blocks_1d(n)), dim3(256), 0, s, n, x, (const KrylovState *)so);
+      rs = status_of(fin);
     } else {
       double *w[5] = {m->d_wc[1], m->d_wc[2], m->d_wc[3], m->d_wc[4], m->d_wc[5]};
       rs = run_pcg64<1>(m, SLOT_P, n, m->d_rp_c, m->d_col_c, m->d_Kbc, m->d_dinvK, b, x, w, m->tune.coarse, o->tol,
@@ -969,7 +1243,7 @@ cgp_status drv_poisson(cgp_mesh *m, const double *b_in, double *x, const cgp_sol
     }
     total_iters = fin.iters;
   } else {
-    rs = poisson_ir(m, b, x, o, persistent, &fin, &total_iters, &outer);
+    rs = poisson_ir(m, b, x, o, persistent, fused && !persistent, &fin, &total_iters, &outer);
   }
   if (rs != CGP_OK && rs != CGP_E_NOCONV) return rs;
   if (m->n_pdir == 0) launch_mean_shift(m, x, m->d_mc, m->mc_sum, region(m, R_A));  // zero weighted mean

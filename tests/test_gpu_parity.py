@@ -126,7 +126,7 @@ def test_momentum_solve(env):
 
 @pytest.mark.parametrize("which", ["neumann", "dirichlet"])
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("launch", [1, 2])
+@pytest.mark.parametrize("launch", [1, 2, 3])
 def test_poisson_solve(env, which, precision, launch):
     torch, cgp, oracle = env
     mesh = W.unit_square_tg(24, seed=3) if which == "neumann" else W.cylinder_channel(8000, seed=2)
@@ -189,7 +189,7 @@ def test_step_variants(env, restrict_mode, mass_mode, levels):
     _run_steps(env, case, levels, 5, tight_opts(cgp), restrict_mode, mass_mode)
 
 
-@pytest.mark.parametrize("launch", [1, 2])
+@pytest.mark.parametrize("launch", [1, 2, 3])
 def test_cylinder_steps(env, launch):
     torch, cgp, oracle = env
     case = make(CYLINDER_CASE)
