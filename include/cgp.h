@@ -71,7 +71,9 @@ enum { CGP_PREC_FP64 = 0,          /* all Krylov arithmetic in FP64 */
 
 enum { CGP_X0_ZERO = 0,            /* Krylov initial guess zero */
        CGP_X0_PREV = 1,            /* initial guess = the output array's current contents */
-       CGP_X0_LEARNED = 2 };       /* Poisson only: guess from the attached POD/MLP model */
+       CGP_X0_LEARNED = 2,         /* Poisson only: x0 = Phi c, c from the attached POD/MLP model */
+       CGP_X0_LEARNED_CORR = 3,    /* Poisson only: previous pressure with its POD component replaced by Phi c */
+       CGP_X0_POD_GALERKIN = 4 };  /* Poisson only: previous pressure plus the Galerkin correction in span(Phi) */
 
 enum { CGP_LAUNCH_AUTO = 0,        /* library choice (FUSED for the Poisson solve) */
        CGP_LAUNCH_LOOP = 1,        /* two kernels per PCG iteration (textbook recurrences), host polls every chunk */
@@ -213,6 +215,41 @@ cgp_status cgp_poisson_solve(cgp_mesh *mesh, const double *b_coarse, double *x, 
 cgp_status cgp_prolong(cgp_mesh *mesh, const double *p_coarse, double *p_fine);              /* Eq. (22) */
 cgp_status cgp_correct(cgp_mesh *mesh, const cgp_solver_opts *opts, const double *g_next, const double *u_tilde,
                        const double *p_fine, double *u, cgp_stats *stats);                  /* Eq. (23) */
+
+/* ---- learned initial guess (Poisson x0): a POD basis of pressure snapshots, M_c-orthonormal, and
+ * an MLP n_modes -> hidden -> hidden -> n_modes (GELU) from the normalised modal projection of the
+ * Poisson right-hand side to the normalised modal coefficients of the pressure.  GEMMs run in BF16
+ * with FP32 accumulation on the matrix cores; basis projections are FP64.  PCG still converges to
+ * the requested tolerance whatever the guess. */
+typedef struct cgp_guess cgp_guess;
+typedef struct { int32_t n_modes; int32_t hidden; uint64_t seed; } cgp_guess_desc;   /* n_modes <= 64 */
+typedef struct { int32_t epochs; int32_t batch; double lr, beta1, beta2, eps; uint64_t seed; } cgp_train_opts;
+typedef struct { double loss_first, loss_last; int32_t steps; float ms; } cgp_train_stats;
+
+cgp_status cgp_guess_create(cgp_mesh *mesh, const cgp_guess_desc *desc, cgp_guess **out);
+void cgp_guess_destroy(cgp_guess *g);
+/* Basis from snapshots (device [S][n_c], rows = snapshots): eigenvectors of S M_c S^T for the n_modes
+ * largest eigenvalues (randomised subspace iteration on the host), Phi = S^T V Lambda^-1/2.
+ * energy: host [n_modes] eigenvalues or NULL. */
+cgp_status cgp_guess_build_pod(cgp_guess *g, const double *snaps, int32_t S, double *energy);
+/* Train on pairs (device [S][n_c] right-hand sides after boundary conditions, [S][n_c] pressures). */
+cgp_status cgp_guess_train(cgp_guess *g, const double *rhs, const double *p, int32_t S, const cgp_train_opts *opts,
+                           cgp_train_stats *stats);
+/* Enable CGP_X0_LEARNED / _CORR / POD_GALERKIN on the mesh's Poisson solve (NULL detaches). */
+cgp_status cgp_guess_attach(cgp_mesh *mesh, cgp_guess *g);
+/* x0 (device [n_c]) for right-hand side b (device [n_c]); x holds the previous pressure for _CORR/_GALERKIN. */
+cgp_status cgp_guess_predict(cgp_guess *g, int32_t mode, const double *b, double *x);
+/* Parameters (host FP32, layout [W1 h*m | b1 h | W2 h*h | b2 h | W3 m*h | b3 m], W row-major [out][in]). */
+cgp_status cgp_guess_get_params(const cgp_guess *g, float *host, size_t count);
+cgp_status cgp_guess_set_params(cgp_guess *g, const float *host, size_t count);
+/* One forward/backward pass on a given batch (host, already normalised): x [B][m], t [B][m];
+ * returns the MSE loss, outputs y [B][m] and parameter gradients (host, layout as above). */
+cgp_status cgp_guess_mlp_grad(cgp_guess *g, const float *x, const float *t, int32_t B, double *loss, float *y,
+                              float *grad);
+/* Basis export (host [n_c][n_modes]) */
+cgp_status cgp_guess_export_basis(const cgp_guess *g, double *host, size_t count);
+/* Copy the right-hand side of the last Poisson solve, after boundary conditions (device [n_c]). */
+cgp_status cgp_last_poisson_rhs(const cgp_mesh *mesh, double *dst);
 
 /* Read or replace the Krylov launch shapes of a mesh (results do not depend on them beyond
  * rounding order).  Invalid knobs return CGP_E_ARG and leave the mesh unchanged. */

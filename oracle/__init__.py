@@ -99,7 +99,7 @@ def _declare(L):
         f.restype = C.c_int
         f.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double, C.c_int, _ip, _dp]
     L.orc_spmv.argtypes = [C.c_void_p, _dp, _dp, _dp]
-    if hasattr(L, "orc_mlp_forward"):
+    if hasattr(L, "orc_mlp_forward_backward"):
         _declare_learn(L)
 
 
@@ -280,4 +280,47 @@ class Problem:
 
 
 def _declare_learn(L):
-    pass
+    L.orc_bf16.restype = C.c_double
+    L.orc_bf16.argtypes = [C.c_double]
+    L.orc_gelu.restype = C.c_double
+    L.orc_gelu.argtypes = [C.c_double]
+    L.orc_gelu_grad.restype = C.c_double
+    L.orc_gelu_grad.argtypes = [C.c_double]
+    fp = C.POINTER(C.c_float)
+    L.orc_mlp_forward_backward.argtypes = [C.c_int, C.c_int, C.c_int, fp, fp, fp, C.c_int, _dp, _dp, _dp]
+    L.orc_adam.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double]
+
+
+def bf16(x: float) -> float:
+    return lib().orc_bf16(float(x))
+
+
+def gelu(z: float) -> float:
+    return lib().orc_gelu(float(z))
+
+
+def gelu_grad(z: float) -> float:
+    return lib().orc_gelu_grad(float(z))
+
+
+def mlp_nparams(m: int, h: int) -> int:
+    return h * m + h + h * h + h + m * h + m
+
+
+def mlp(m, h, params, X, T, emulate=True):
+    """Loss, outputs [B][m] and parameter gradients of the guess network (FP64, BF16 emulated)."""
+    fp = C.POINTER(C.c_float)
+    params = np.ascontiguousarray(params, np.float32)
+    X = np.ascontiguousarray(X, np.float32)
+    T = np.ascontiguousarray(T, np.float32)
+    B = X.shape[0]
+    loss = C.c_double()
+    Y = np.zeros((B, m))
+    g = np.zeros(mlp_nparams(m, h))
+    lib().orc_mlp_forward_backward(m, h, B, params.ctypes.data_as(fp), X.ctypes.data_as(fp), T.ctypes.data_as(fp),
+                                   int(emulate), C.byref(loss), _d(Y), _d(g))
+    return loss.value, Y, g
+
+
+def adam(w, g, m1, m2, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    lib().orc_adam(len(w), _d(w), _d(np.ascontiguousarray(g, np.float64)), _d(m1), _d(m2), t, lr, b1, b2, eps)

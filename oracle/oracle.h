@@ -109,4 +109,13 @@ int orc_projection_step(orc_problem *p, const double *g_next, const double *f_ne
 int orc_momentum(orc_problem *p, const double *g_next, const double *f_next, const double *u, double *ut,
                  double tol, int maxit, orc_stats *st);
 
+/* ---- learned guess network (oracle/learn.c) */
+double orc_bf16(double x);
+double orc_gelu(double z);
+double orc_gelu_grad(double z);
+void orc_mlp_forward_backward(int m, int h, int B, const float *params, const float *X, const float *T, int emulate,
+                              double *loss, double *Y, double *grad);
+void orc_adam(int n, double *w, const double *g, double *m1, double *m2, int t, double lr, double b1, double b2,
+              double eps);
+
 #endif

@@ -17,7 +17,7 @@ VEL_DIRICHLET, OUTFLOW = 1, 2
 RESTRICT_INJECT, RESTRICT_GALERKIN = 0, 1
 MASS_CONSISTENT, MASS_LUMPED = 0, 1
 PREC_FP64, PREC_FP32_IR = 0, 1
-X0_ZERO, X0_PREV, X0_LEARNED = 0, 1, 2
+X0_ZERO, X0_PREV, X0_LEARNED, X0_LEARNED_CORR, X0_POD_GALERKIN = 0, 1, 2, 3, 4
 LAUNCH_AUTO, LAUNCH_LOOP, LAUNCH_PERSISTENT, LAUNCH_FUSED = 0, 1, 2, 3
 OP_KBC_C, OP_M_F, OP_A_F, OP_KBC_C32 = 0, 1, 2, 3
 
@@ -70,6 +70,19 @@ class _Knobs(C.Structure):
 
 class _Tuning(C.Structure):
     _fields_ = [("fine", _Knobs), ("coarse", _Knobs), ("pcg_barrier", C.c_int32), ("pcg_grid", C.c_int32)]
+
+
+class _GuessDesc(C.Structure):
+    _fields_ = [("n_modes", C.c_int32), ("hidden", C.c_int32), ("seed", C.c_uint64)]
+
+
+class _TrainOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double), ("seed", C.c_uint64)]
+
+
+class _TrainStats(C.Structure):
+    _fields_ = [("loss_first", C.c_double), ("loss_last", C.c_double), ("steps", C.c_int32), ("ms", C.c_float)]
 
 
 class _Info(C.Structure):
@@ -131,7 +144,22 @@ def lib():
     L.cgp_spmv.argtypes = [vp, C.c_int32, vp, vp]
     L.cgp_mesh_get_tuning.argtypes = [vp, C.POINTER(_Tuning)]
     L.cgp_mesh_set_tuning.argtypes = [vp, C.POINTER(_Tuning)]
-    for name in ("cgp_mesh_get_tuning", "cgp_mesh_set_tuning","cgp_mesh_create", "cgp_mesh_query", "cgp_mesh_export", "cgp_assemble", "cgp_step", "cgp_momentum",
+    L.cgp_guess_create.argtypes = [vp, C.POINTER(_GuessDesc), C.POINTER(vp)]
+    L.cgp_guess_destroy.argtypes = [vp]
+    L.cgp_guess_destroy.restype = None
+    L.cgp_guess_build_pod.argtypes = [vp, vp, C.c_int32, vp]
+    L.cgp_guess_train.argtypes = [vp, vp, vp, C.c_int32, C.POINTER(_TrainOpts), C.POINTER(_TrainStats)]
+    L.cgp_guess_attach.argtypes = [vp, vp]
+    L.cgp_guess_predict.argtypes = [vp, C.c_int32, vp, vp]
+    L.cgp_guess_get_params.argtypes = [vp, vp, C.c_size_t]
+    L.cgp_guess_set_params.argtypes = [vp, vp, C.c_size_t]
+    L.cgp_guess_mlp_grad.argtypes = [vp, vp, vp, C.c_int32, C.POINTER(C.c_double), vp, vp]
+    L.cgp_guess_export_basis.argtypes = [vp, vp, C.c_size_t]
+    L.cgp_last_poisson_rhs.argtypes = [vp, vp]
+    for name in ("cgp_guess_create", "cgp_guess_build_pod", "cgp_guess_train", "cgp_guess_attach", "cgp_guess_predict",
+                 "cgp_guess_get_params", "cgp_guess_set_params", "cgp_guess_mlp_grad", "cgp_guess_export_basis",
+                 "cgp_last_poisson_rhs",
+                 "cgp_mesh_get_tuning", "cgp_mesh_set_tuning","cgp_mesh_create", "cgp_mesh_query", "cgp_mesh_export", "cgp_assemble", "cgp_step", "cgp_momentum",
                  "cgp_restrict", "cgp_poisson_solve", "cgp_prolong", "cgp_correct", "cgp_spmv"):
         getattr(L, name).restype = C.c_int32
     _lib = L
@@ -288,5 +316,77 @@ class Mesh:
         t = _Tuning(_Knobs(*f), _Knobs(*c), b, g)
         _check(lib().cgp_mesh_set_tuning(self._h, C.byref(t)))
 
+    def last_poisson_rhs(self, dst):
+        _check(lib().cgp_last_poisson_rhs(self._h, _ptr(dst)))
+
     def spmv(self, op: int, x, y):
         _check(lib().cgp_spmv(self._h, op, _ptr(x), _ptr(y)))
+
+
+class Guess:
+    """Learned initial guess for the Poisson solve: POD basis + BF16 MFMA MLP (include/cgp.h)."""
+
+    def __init__(self, mesh: Mesh, n_modes: int = 64, hidden: int = 256, seed: int = 4):
+        self.mesh = mesh
+        self.n_modes, self.hidden = n_modes, hidden
+        h = C.c_void_p()
+        _check(lib().cgp_guess_create(mesh._h, C.byref(_GuessDesc(n_modes, hidden, seed)), C.byref(h)))
+        self._h = h
+        m, hd = n_modes, hidden
+        self.nparams = hd * m + hd + hd * hd + hd + m * hd + m
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cgp_guess_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build_pod(self, snaps):
+        energy = np.zeros(self.n_modes)
+        _check(lib().cgp_guess_build_pod(self._h, _ptr(snaps), snaps.shape[0], energy.ctypes.data))
+        return energy
+
+    def train(self, rhs, p, epochs=200, batch=256, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=4):
+        st = _TrainStats()
+        o = _TrainOpts(epochs, batch, lr, beta1, beta2, eps, seed)
+        _check(lib().cgp_guess_train(self._h, _ptr(rhs), _ptr(p), rhs.shape[0], C.byref(o), C.byref(st)))
+        return {k: getattr(st, k) for k, _ in _TrainStats._fields_}
+
+    def attach(self):
+        _check(lib().cgp_guess_attach(self.mesh._h, self._h))
+
+    def detach(self):
+        _check(lib().cgp_guess_attach(self.mesh._h, None))
+
+    def predict(self, mode: int, b, x):
+        _check(lib().cgp_guess_predict(self._h, mode, _ptr(b), _ptr(x)))
+
+    def get_params(self):
+        out = np.zeros(self.nparams, np.float32)
+        _check(lib().cgp_guess_get_params(self._h, out.ctypes.data, out.size))
+        return out
+
+    def set_params(self, w):
+        w = np.ascontiguousarray(w, np.float32)
+        _check(lib().cgp_guess_set_params(self._h, w.ctypes.data, w.size))
+
+    def mlp_grad(self, x, t):
+        x = np.ascontiguousarray(x, np.float32)
+        t = np.ascontiguousarray(t, np.float32)
+        B = x.shape[0]
+        loss = C.c_double()
+        y = np.zeros((B, self.n_modes), np.float32)
+        g = np.zeros(self.nparams, np.float32)
+        _check(lib().cgp_guess_mlp_grad(self._h, x.ctypes.data, t.ctypes.data, B, C.byref(loss), y.ctypes.data,
+                                        g.ctypes.data))
+        return loss.value, y, g
+
+    def basis(self):
+        out = np.zeros((self.mesh.info["n_c"], self.n_modes))
+        _check(lib().cgp_guess_export_basis(self._h, out.ctypes.data, out.size))
+        return out

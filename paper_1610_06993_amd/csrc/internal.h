@@ -82,6 +82,8 @@ struct ReduceScratch {
 
 }  // namespace cgp
 
+struct cgp_guess;
+
 struct cgp_mesh {
   hipStream_t stream = nullptr;
   bool host_only = false;
@@ -95,6 +97,7 @@ struct cgp_mesh {
   std::vector<std::vector<int>> rt_ptr, rt_idx; // per level k>=1: coarse node -> midpoints (Galerkin restriction)
   bool assembled = false;
   cgp_params params{};
+  cgp_guess *guess = nullptr;                  // learned initial guess attached to the Poisson solve
 
   // device topology
   double *d_xy_f = nullptr, *d_xy_c = nullptr;

@@ -19,6 +19,7 @@
 
 #include "devutil.h"
 #include "kernels.h"
+#include "learn.h"
 #include "persistent.h"
 
 namespace cgp {
@@ -1188,6 +1189,11 @@ cgp_status drv_poisson(cgp_mesh *m, const double *b_in, double *x, const cgp_sol
   } else {
     // pure Neumann (Eq. 13 on all of the boundary): project b onto the range of Kbar
     launch_mean_shift(m, b, nullptr, double(n), region(m, R_A));
+  }
+  if (o->x0_mode >= CGP_X0_LEARNED) {
+    cgp_status gs = guess_initial(m, o->x0_mode, b, x);
+    if (gs) return gs;
+    if (m->n_pdir > 0) launch_pdir_zero(m, b, x);  // the guess knows nothing of p = 0 on the outflow
   }
   const bool persistent = (o->launch == CGP_LAUNCH_PERSISTENT);
   const bool fused = (o->launch == CGP_LAUNCH_FUSED || o->launch == CGP_LAUNCH_AUTO);

@@ -1,0 +1,247 @@
+"""Learned initial guess for the coarse Poisson solve on the GPU, checked
+against the oracle and against numpy (FP64):
+
+* the BF16 matrix-core network (forward, loss, every parameter gradient)
+  against the oracle's FP64 network that rounds to BF16 at the same places;
+* the POD basis (M_c-orthonormality, eigenvalues, spanned subspace) against a
+  numpy eigen-decomposition of the same snapshot Gram matrix;
+* the POD-Galerkin guess against its closed form;
+* the learned guess, trained on pressures of a real run, against the zero and
+  previous-step guesses on held-out steps (fewer iterations, same solution).
+
+Tolerances: the GPU accumulates each product of at most 256 terms in FP32, a
+relative error of order 256 * 2^-24 ~ 1e-5 in the worst case; an activation
+whose FP32 value falls across a BF16 rounding boundary moves by 2^-8, which a
+few hundred of 65536 activations may do.  Relative L2 error <= 2e-3 on
+outputs and gradients covers both with margin; the FP64-without-rounding
+network differs from the rounded one by ~1e-2, so the bar still shows that
+the rounding happens where the oracle says it does."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+BAR_NET = 2e-3
+
+
+def _say(*a):
+    print("[gpu-test]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import oracle
+    import paper_1610_06993_amd as cgp
+    cgp.lib()
+    oracle.lib()
+    return torch, cgp, oracle
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a, np.float64) - np.asarray(b, np.float64)) / (nb if nb > 0 else 1.0)
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+@pytest.fixture(scope="module")
+def small_mesh(env):
+    torch, cgp, oracle = env
+    case = W.case_cylinder(3000, seed=5)
+    g = cgp.Mesh(case.mesh, 1)
+    g.assemble(case.rho, case.mu, case.dt)
+    o = oracle.Problem(case.mesh, 1)
+    o.assemble(case.rho, case.mu, case.dt, 0, 0)
+    return case, g, o
+
+
+@pytest.mark.parametrize("m,h,B", [(64, 256, 256), (20, 40, 37), (16, 48, 1), (64, 256, 100)])
+def test_network_matches_oracle(env, small_mesh, m, h, B):
+    torch, cgp, oracle = env
+    case, g, o = small_mesh
+    _say(f"network m={m} h={h} B={B}")
+    net = cgp.Guess(g, n_modes=m, hidden=h, seed=7)
+    rng = np.random.default_rng(m * 1000 + h + B)
+    params = (net.get_params() * 2.0).astype(np.float32)
+    params[-m:] = rng.normal(size=m).astype(np.float32) * 0.1
+    net.set_params(params)
+    assert np.array_equal(net.get_params(), params)
+    X = rng.normal(size=(B, m)).astype(np.float32)
+    T = rng.normal(size=(B, m)).astype(np.float32)
+    loss, y, grad = net.mlp_grad(X, T)
+    l_ref, y_ref, g_ref = oracle.mlp(m, h, params, X, T, emulate=True)
+    l_raw, y_raw, g_raw = oracle.mlp(m, h, params, X, T, emulate=False)
+    e_y, e_g = rel(y, y_ref), rel(grad, g_ref)
+    _say(f"  rel err y {e_y:.2e} (vs unrounded {rel(y, y_raw):.2e}), grad {e_g:.2e} (vs unrounded {rel(grad, g_raw):.2e})")
+    assert abs(loss - l_ref) <= BAR_NET * l_ref
+    assert e_y <= BAR_NET and e_g <= BAR_NET
+    assert e_y < 0.5 * rel(y, y_raw) or rel(y_ref, y_raw) < BAR_NET
+    # every block of the gradient, not just its norm
+    o = 0
+    for name, k in (("W1", h * m), ("b1", h), ("W2", h * h), ("b2", h), ("W3", m * h), ("b3", m)):
+        assert rel(grad[o:o + k], g_ref[o:o + k]) <= 2 * BAR_NET, name
+        o += k
+    net.close()
+
+
+def _snapshots(rng, n, S, r, mc):
+    """S snapshots of rank r with geometrically decaying amplitudes (rows = snapshots)."""
+    A = rng.normal(size=(S, r)) * (0.7 ** np.arange(r))
+    B = rng.normal(size=(r, n))
+    return A @ B
+
+
+def test_pod_basis_against_numpy(env, small_mesh):
+    torch, cgp, oracle = env
+    case, g, o = small_mesh
+    n = g.info["n_c"]
+    nm, S, r = 16, 120, 24   # rank 24 fits in the 16 + 16 subspace iteration
+    _say(f"POD n={n} S={S} rank={r} modes={nm}")
+    mc = o.values("m_c")
+    snaps = _snapshots(np.random.default_rng(2), n, S, r, mc)
+    net = cgp.Guess(g, n_modes=nm, hidden=32, seed=3)
+    energy = net.build_pod(dev(torch, snaps))
+    Phi = net.basis()
+    Gram = snaps @ (mc[:, None] * snaps.T)
+    lam, V = np.linalg.eigh(Gram)
+    lam, V = lam[::-1][:nm], V[:, ::-1][:, :nm]
+    assert rel(energy, lam) <= 1e-10
+    # M_c-orthonormal
+    assert np.max(np.abs(Phi.T @ (mc[:, None] * Phi) - np.eye(nm))) <= 1e-10
+    # same subspace as numpy's Phi = S^T V Lambda^-1/2 (compare M-orthogonal projectors)
+    Phi_np = snaps.T @ V / np.sqrt(lam)
+    P1 = Phi @ (Phi.T * mc)
+    P2 = Phi_np @ (Phi_np.T * mc)
+    assert np.linalg.norm(P1 - P2) <= 1e-8 * np.linalg.norm(P2)
+    net.close()
+
+
+def _csr_matvec(o, x):
+    import oracle
+    return oracle.spmv(o.export("rowptr_c"), o.export("col_c"), o.values("K_c_bc"), x)
+
+
+def test_pod_galerkin_guess_closed_form(env, small_mesh):
+    torch, cgp, oracle = env
+    case, g, o = small_mesh
+    n = g.info["n_c"]
+    nm = 12
+    _say(f"POD-Galerkin guess n={n} modes={nm}")
+    rng = np.random.default_rng(4)
+    mc = o.values("m_c")
+    snaps = _snapshots(rng, n, 60, 20, mc)
+    net = cgp.Guess(g, n_modes=nm, hidden=32, seed=3)
+    net.build_pod(dev(torch, snaps))
+    Phi = net.basis()
+    b = rng.normal(size=n)
+    xp = rng.normal(size=n)
+    x = dev(torch, xp.copy())
+    net.predict(cgp._native.X0_POD_GALERKIN, dev(torch, b), x)
+    KPhi = np.stack([_csr_matvec(o, Phi[:, k]) for k in range(nm)], 1)
+    c = np.linalg.solve(Phi.T @ KPhi, Phi.T @ (b - _csr_matvec(o, xp)))
+    ref = xp + Phi @ c
+    assert rel(x.cpu().numpy(), ref) <= 1e-10
+    net.close()
+
+
+@pytest.fixture(scope="module")
+def trajectory(env):
+    """Pressure right-hand sides and solutions of 240 steps of the cylinder flow."""
+    torch, cgp, oracle = env
+    case = W.case_cylinder(6000, seed=5)
+    g = cgp.Mesh(case.mesh, 1)
+    g.assemble(case.rho, case.mu, case.dt)
+    xy = g.export("xy")
+    nc = g.info["n_c"]
+    steps = 240
+    _say(f"trajectory: cylinder {case.mesh.n_tris} coarse triangles, {steps} steps")
+    u = dev(torch, case.initial(xy, g.export("vdir")))
+    pf = torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda")
+    pc = torch.zeros(nc, dtype=torch.float64, device="cuda")
+    rhs = torch.zeros((steps, nc), dtype=torch.float64, device="cuda")
+    ps = torch.zeros((steps, nc), dtype=torch.float64, device="cuda")
+    opts = cgp.StepOpts(poisson=cgp.SolverOpts(tol=1e-10))
+    for k in range(steps):
+        gd = dev(torch, case.dirichlet(xy, (k + 1) * case.dt))
+        g.step(gd, u, pf, pc, opts=opts)
+        g.last_poisson_rhs(rhs[k])
+        ps[k].copy_(pc)
+    torch.cuda.synchronize()
+    return case, g, rhs, ps
+
+
+def test_learned_guess_reduces_iterations(env, trajectory):
+    torch, cgp, oracle = env
+    case, g, rhs, ps = trajectory
+    n_train = 200
+    net = cgp.Guess(g, n_modes=32, hidden=128, seed=11)
+    energy = net.build_pod(ps[:n_train].contiguous())
+    assert np.all(np.diff(energy) <= 0) and energy[-1] > 0
+    st = net.train(rhs[:n_train].contiguous(), ps[:n_train].contiguous(), epochs=300, batch=64, lr=2e-3)
+    _say(f"  training: loss {st['loss_first']:.3e} -> {st['loss_last']:.3e} in {st['steps']} steps, {st['ms']:.0f} ms")
+    assert st["loss_last"] < 0.05 * st["loss_first"]
+    net.attach()
+    X0 = cgp._native
+    modes = {"zero": X0.X0_ZERO, "prev": X0.X0_PREV, "learned": X0.X0_LEARNED, "learned_corr": X0.X0_LEARNED_CORR,
+             "pod_galerkin": X0.X0_POD_GALERKIN}
+    iters = {k: [] for k in modes}
+    for k in range(n_train, rhs.shape[0]):
+        b = rhs[k]
+        ref = ps[k].cpu().numpy()
+        for name, mode in modes.items():
+            x = ps[k - 1].clone() if mode != X0.X0_ZERO else torch.zeros_like(b)
+            s = g.poisson_solve(b, x, cgp.SolverOpts(tol=1e-10, x0_mode=mode))
+            iters[name].append(s["p_iters"])
+            assert rel(x.cpu().numpy(), ref) <= 1e-6, (name, k)
+    mean = {k: float(np.mean(v)) for k, v in iters.items()}
+    _say("  mean Poisson iterations on held-out steps:", {k: round(v, 1) for k, v in mean.items()})
+    assert mean["learned"] < 0.8 * mean["zero"]
+    assert mean["pod_galerkin"] <= mean["prev"] + 1
+    net.detach()
+    net.close()
+
+
+def test_learned_corr_identity(env, trajectory):
+    """x0(LEARNED_CORR, x) - x0(LEARNED) = x - Phi Phi^T M x for any previous pressure x."""
+    torch, cgp, oracle = env
+    case, g, rhs, ps = trajectory
+    net = cgp.Guess(g, n_modes=16, hidden=64, seed=2)
+    net.build_pod(ps[:100].contiguous())
+    net.train(rhs[:100].contiguous(), ps[:100].contiguous(), epochs=5, batch=32)
+    X0 = cgp._native
+    b = rhs[150]
+    xp = ps[149].clone()
+    x1 = torch.zeros_like(b)
+    net.predict(X0.X0_LEARNED, b, x1)
+    x2 = xp.clone()
+    net.predict(X0.X0_LEARNED_CORR, b, x2)
+    Phi = net.basis()
+    mc = g.export("m_c")
+    xpn = xp.cpu().numpy()
+    ref = xpn - Phi @ (Phi.T @ (mc * xpn))
+    assert rel((x2 - x1).cpu().numpy(), ref) <= 1e-10
+    net.close()
+
+
+def test_guess_errors(env, small_mesh):
+    torch, cgp, oracle = env
+    case, g, o = small_mesh
+    with pytest.raises(cgp.CGPError):
+        cgp.Guess(g, n_modes=65, hidden=64)
+    net = cgp.Guess(g, n_modes=8, hidden=32)
+    b = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    # no basis, no training: the learned guess refuses instead of guessing
+    net.attach()
+    with pytest.raises(cgp.CGPError):
+        g.poisson_solve(b, x, cgp.SolverOpts(x0_mode=cgp._native.X0_LEARNED))
+    net.detach()
+    with pytest.raises(cgp.CGPError):
+        net.mlp_grad(np.zeros((257, 8), np.float32), np.zeros((257, 8), np.float32))
+    net.close()
