@@ -59,7 +59,19 @@ def main():
     ap.add_argument("--no-instrumented", action="store_true", help="skip the event-bracketed kernel pass")
     ap.add_argument("--launch", choices=["loop", "persistent", "fused"], default="fused",
                     help="Poisson Krylov launch strategy")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)  # one elementwise kernel: n * 8 bytes read, n * 8 bytes written
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_calibration} MiB three times ({n * 8} bytes read and written per copy)")
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
               file=sys.stderr)

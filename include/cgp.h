@@ -72,7 +72,7 @@ enum { CGP_PREC_FP64 = 0,          /* all Krylov arithmetic in FP64 */
 enum { CGP_X0_ZERO = 0,            /* Krylov initial guess zero */
        CGP_X0_PREV = 1,            /* initial guess = the output array's current contents */
        CGP_X0_LEARNED = 2,         /* Poisson only: x0 = Phi c, c from the attached POD/MLP model */
-       CGP_X0_LEARNED_CORR = 3,    /* Poisson only: previous pressure with its POD component replaced by Phi c */
+       CGP_X0_LEARNED_CORR = 3,    /* Poisson only: x0 = x + Phi dc, dc from the incremental model and b - K x */
        CGP_X0_POD_GALERKIN = 4 };  /* Poisson only: previous pressure plus the Galerkin correction in span(Phi) */
 
 enum { CGP_LAUNCH_AUTO = 0,        /* library choice (FUSED for the Poisson solve) */
@@ -223,7 +223,11 @@ cgp_status cgp_correct(cgp_mesh *mesh, const cgp_solver_opts *opts, const double
  * the requested tolerance whatever the guess. */
 typedef struct cgp_guess cgp_guess;
 typedef struct { int32_t n_modes; int32_t hidden; uint64_t seed; } cgp_guess_desc;   /* n_modes <= 64 */
-typedef struct { int32_t epochs; int32_t batch; double lr, beta1, beta2, eps; uint64_t seed; } cgp_train_opts;
+/* p_prev = NULL: the network maps Phi^T b to the modal coefficients Phi^T M p of the pressure (serves
+ * CGP_X0_LEARNED).  p_prev = device [S][n_c], the previous-step pressure of each sample: the network maps
+ * Phi^T (b - K p_prev) to Phi^T M (p - p_prev) (an incremental model, serves CGP_X0_LEARNED_CORR). */
+typedef struct { int32_t epochs; int32_t batch; double lr, beta1, beta2, eps; uint64_t seed; const double *p_prev; }
+    cgp_train_opts;
 typedef struct { double loss_first, loss_last; int32_t steps; float ms; } cgp_train_stats;
 
 cgp_status cgp_guess_create(cgp_mesh *mesh, const cgp_guess_desc *desc, cgp_guess **out);
@@ -232,7 +236,9 @@ void cgp_guess_destroy(cgp_guess *g);
  * largest eigenvalues (randomised subspace iteration on the host), Phi = S^T V Lambda^-1/2.
  * energy: host [n_modes] eigenvalues or NULL. */
 cgp_status cgp_guess_build_pod(cgp_guess *g, const double *snaps, int32_t S, double *energy);
-/* Train on pairs (device [S][n_c] right-hand sides after boundary conditions, [S][n_c] pressures). */
+/* Train on S (2..65536) samples: device [S][n_c] right-hand sides after boundary conditions and the
+ * [S][n_c] pressures solving them.  Mini-batch Adam on FP32 master weights; the basis must be built
+ * first. */
 cgp_status cgp_guess_train(cgp_guess *g, const double *rhs, const double *p, int32_t S, const cgp_train_opts *opts,
                            cgp_train_stats *stats);
 /* Enable CGP_X0_LEARNED / _CORR / POD_GALERKIN on the mesh's Poisson solve (NULL detaches). */
@@ -248,6 +254,10 @@ cgp_status cgp_guess_mlp_grad(cgp_guess *g, const float *x, const float *t, int3
                               float *grad);
 /* Basis export (host [n_c][n_modes]) */
 cgp_status cgp_guess_export_basis(const cgp_guess *g, double *host, size_t count);
+/* Normalisation of the trained model (host [4][n_modes]): feature mean, feature scale, target mean,
+ * target scale.  Features enter the network as bf16((a - mean) / scale); coefficients leave it as
+ * y * scale + mean.  CGP_E_STATE before training. */
+cgp_status cgp_guess_export_norm(const cgp_guess *g, double *host, size_t count);
 /* Copy the right-hand side of the last Poisson solve, after boundary conditions (device [n_c]). */
 cgp_status cgp_last_poisson_rhs(const cgp_mesh *mesh, double *dst);
 

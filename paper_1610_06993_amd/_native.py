@@ -78,7 +78,7 @@ class _GuessDesc(C.Structure):
 
 class _TrainOpts(C.Structure):
     _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double), ("beta1", C.c_double),
-                ("beta2", C.c_double), ("eps", C.c_double), ("seed", C.c_uint64)]
+                ("beta2", C.c_double), ("eps", C.c_double), ("seed", C.c_uint64), ("p_prev", C.c_void_p)]
 
 
 class _TrainStats(C.Structure):
@@ -155,11 +155,12 @@ def lib():
     L.cgp_guess_set_params.argtypes = [vp, vp, C.c_size_t]
     L.cgp_guess_mlp_grad.argtypes = [vp, vp, vp, C.c_int32, C.POINTER(C.c_double), vp, vp]
     L.cgp_guess_export_basis.argtypes = [vp, vp, C.c_size_t]
+    L.cgp_guess_export_norm.argtypes = [vp, vp, C.c_size_t]
     L.cgp_last_poisson_rhs.argtypes = [vp, vp]
     for name in ("cgp_guess_create", "cgp_guess_build_pod", "cgp_guess_train", "cgp_guess_attach", "cgp_guess_predict",
                  "cgp_guess_get_params", "cgp_guess_set_params", "cgp_guess_mlp_grad", "cgp_guess_export_basis",
-                 "cgp_last_poisson_rhs",
-                 "cgp_mesh_get_tuning", "cgp_mesh_set_tuning","cgp_mesh_create", "cgp_mesh_query", "cgp_mesh_export", "cgp_assemble", "cgp_step", "cgp_momentum",
+                 "cgp_guess_export_norm", "cgp_last_poisson_rhs", "cgp_mesh_get_tuning", "cgp_mesh_set_tuning",
+                 "cgp_mesh_create", "cgp_mesh_query", "cgp_mesh_export", "cgp_assemble", "cgp_step", "cgp_momentum",
                  "cgp_restrict", "cgp_poisson_solve", "cgp_prolong", "cgp_correct", "cgp_spmv"):
         getattr(L, name).restype = C.c_int32
     _lib = L
@@ -351,9 +352,11 @@ class Guess:
         _check(lib().cgp_guess_build_pod(self._h, _ptr(snaps), snaps.shape[0], energy.ctypes.data))
         return energy
 
-    def train(self, rhs, p, epochs=200, batch=256, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=4):
+    def train(self, rhs, p, epochs=200, batch=256, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=4,
+              p_prev=None):
+        """Absolute model (p_prev None) or incremental model (p_prev: previous pressure of each sample)."""
         st = _TrainStats()
-        o = _TrainOpts(epochs, batch, lr, beta1, beta2, eps, seed)
+        o = _TrainOpts(epochs, batch, lr, beta1, beta2, eps, seed, _ptr(p_prev) if p_prev is not None else None)
         _check(lib().cgp_guess_train(self._h, _ptr(rhs), _ptr(p), rhs.shape[0], C.byref(o), C.byref(st)))
         return {k: getattr(st, k) for k, _ in _TrainStats._fields_}
 
@@ -385,6 +388,11 @@ class Guess:
         _check(lib().cgp_guess_mlp_grad(self._h, x.ctypes.data, t.ctypes.data, B, C.byref(loss), y.ctypes.data,
                                         g.ctypes.data))
         return loss.value, y, g
+
+    def norm(self):
+        out = np.zeros((4, self.n_modes))
+        _check(lib().cgp_guess_export_norm(self._h, out.ctypes.data, out.size))
+        return out
 
     def basis(self):
         out = np.zeros((self.mesh.info["n_c"], self.n_modes))

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <string>
 #include <type_traits>
 
 #include "devutil.h"
@@ -850,17 +851,19 @@ bool host_all_done(const KrylovState &s) {
   return true;
 }
 
-cgp_status status_of(const KrylovState &s) {
+cgp_status status_of(const KrylovState &s, int slot) {
+  static const char *names[4] = {"momentum BiCGStab", "Poisson PCG", "Poisson inner PCG", "mass PCG"};
+  const std::string what = std::string(names[slot & 3]) + " at iteration " + std::to_string(s.iters);
   if (s.status == CGP_E_NONFINITE) {
-    set_error("Krylov solve produced a non-finite residual");
+    set_error(what + ": non-finite residual or step length");
     return CGP_E_NONFINITE;
   }
   if (s.status == CGP_E_DEVICE) {
-    set_error("persistent Krylov kernel aborted at a grid barrier");
+    set_error(what + ": persistent Krylov kernel aborted at a grid barrier");
     return CGP_E_DEVICE;
   }
   if (s.status == CGP_E_NOCONV || !host_all_done(s)) {
-    set_error("Krylov solve reached its iteration limit (or broke down)");
+    set_error(what + ": iteration limit reached (or breakdown)");
     return CGP_E_NOCONV;
   }
   return CGP_OK;
@@ -964,7 +967,7 @@ cgp_status run_pcg64(cgp_mesh *m, int slot, int n, const int *rp, const int *col
                                        maxit, chunk_hint, timed, out);
   if (ls) return ls;
   hipLaunchKernelGGL((k_zero_b_fix<NC>), dim3(blocks_1d(n)), dim3(256), 0, s, n, x, (const KrylovState *)st);
-  return status_of(*out);
+  return status_of(*out, slot);
 }
 
 // Single-kernel PCG loop.  Precondition: r0 = b - K x0 (or the normalised
@@ -1078,7 +1081,7 @@ cgp_status drv_momentum(cgp_mesh *m, const cgp_solver_opts *o, const double *g, 
     for (int c = 0; c < 2; c++)
       stats->mom_relres = std::max(stats->mom_relres, h.bnorm[c] > 0 ? h.rnorm[c] / h.bnorm[c] : 0.0);
   }
-  return status_of(h);
+  return status_of(h, SLOT_MOM);
 }
 
 // ------------------------------------------------------------------ step 3
@@ -1173,7 +1176,7 @@ cgp_status poisson_ir(cgp_mesh *m, const double *b, double *x, const cgp_solver_
   }
   hipLaunchKernelGGL((k_zero_b_fix<1>), dim3(blocks_1d(n)), dim3(256), 0, s, n, x, (const KrylovState *)so);
   *outer_out = outer + 1;
-  return status_of(*fin);
+  return status_of(*fin, SLOT_P);
 }
 
 }  // namespace
@@ -1222,7 +1225,7 @@ cgp_status drv_poisson(cgp_mesh *m, const double *b_in, double *x, const cgp_sol
         if ((ps = kt_harvest(m, 1))) return ps;
         m->kt_iters += (long)fin.iters - used;
       }
-      rs = status_of(fin);
+      rs = status_of(fin, SLOT_P);
     } else if (fused) {
       KrylovState *so = m->d_state + SLOT_P;
       const cgp_tuning_knobs &tk = m->tune.coarse;
@@ -1241,7 +1244,7 @@ cgp_status drv_poisson(cgp_mesh *m, const double *b_in, double *x, const cgp_sol
                                        &m->p_chunk, true, &fin);
       if (ls) return ls;
       hipLaunchKernelGGL((k_zero_b_fix<1>), dim3(blocks_1d(n)), dim3(256), 0, s, n, x, (const KrylovState *)so);
-      rs = status_of(fin);
+      rs = status_of(fin, SLOT_P);
     } else {
       double *w[5] = {m->d_wc[1], m->d_wc[2], m->d_wc[3], m->d_wc[4], m->d_wc[5]};
       rs = run_pcg64<1>(m, SLOT_P, n, m->d_rp_c, m->d_col_c, m->d_Kbc, m->d_dinvK, b, x, w, m->tune.coarse, o->tol,

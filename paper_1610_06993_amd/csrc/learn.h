@@ -10,7 +10,7 @@ struct cgp_guess {
   cgp_mesh *mesh = nullptr;
   int nm = 64, nh = 256, n = 0;       // modes, hidden width, coarse nodes
   uint64_t seed = 0;
-  bool pod_ready = false, trained = false;
+  bool pod_ready = false, trained = false, incremental = false;
   std::vector<void *> allocations;
   // basis
   double *d_phi = nullptr;            // [n][nm], M-orthonormal
@@ -36,7 +36,8 @@ struct cgp_guess {
 namespace cgp {
 constexpr int kMaxBatch = 256;
 // x0 for the Poisson solve from the right-hand side b (after boundary conditions):
-// mode CGP_X0_LEARNED: x0 = Phi c; CGP_X0_LEARNED_CORR: x0 = x + Phi (c - Phi^T M x);
+// mode CGP_X0_LEARNED: x0 = Phi c (absolute model); CGP_X0_LEARNED_CORR: x0 = x + Phi dc with dc from
+// the incremental model applied to Phi^T (b - K x);
 // CGP_X0_POD_GALERKIN: x0 = x + Phi (Phi^T K Phi)^-1 Phi^T (b - K x).  x holds the previous pressure.
 cgp_status guess_initial(cgp_mesh *m, int mode, const double *b, double *x);
 }  // namespace cgp

@@ -235,6 +235,19 @@ __global__ void k_residual(int n, const int *__restrict__ rp, const int *__restr
   r[i] = b[i] - s;
 }
 
+// R[k][i] = B[k][i] - (K P[k])_i for every sample k (rows = samples); blockIdx.y = k
+__global__ void k_pair_residual(int n, const int *__restrict__ rp, const int *__restrict__ col,
+                                const double *__restrict__ val, const double *__restrict__ B,
+                                const double *__restrict__ P, double *__restrict__ R) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const long k = blockIdx.y;
+  const double *pk = P + k * n;
+  double s = 0.0;
+  for (int e = rp[i]; e < rp[i + 1]; e++) s += val[e] * pk[col[e]];
+  R[k * n + i] = B[k * n + i] - s;
+}
+
 // per-block partials of out[k] = sum_i Phi[i][k] w_i v_i for the nm <= 64 modes: lane k of each wave
 // accumulates mode k over the wave's rows; waves combine in LDS; partials laid out [nm][grid]
 __global__ void __launch_bounds__(256) k_project(int n, int nm, const double *__restrict__ Phi,
@@ -280,11 +293,11 @@ __global__ void k_feat_in(int nm, const double *__restrict__ a, const double *__
   if (k < nm) xb[k] = f2bf((float)((a[k] - mu[k]) / sd[k]));
 }
 
-// c = y * sd + mu - subtract (subtract = Phi^T M x_prev for the corrected guess, or NULL)
+// c = y * sd + mu
 __global__ void k_feat_out(int nm, const float *__restrict__ y, const double *__restrict__ mu,
-                           const double *__restrict__ sd, const double *__restrict__ subtract, double *__restrict__ c) {
+                           const double *__restrict__ sd, double *__restrict__ c) {
   const int k = threadIdx.x;
-  if (k < nm) c[k] = (double)y[k] * sd[k] + mu[k] - (subtract ? subtract[k] : 0.0);
+  if (k < nm) c[k] = (double)y[k] * sd[k] + mu[k];
 }
 
 // c = Kinv a (dense nm x nm, one thread per row)
@@ -469,33 +482,38 @@ cgp_status guess_initial(cgp_mesh *m, int mode, const double *b, double *x) {
     set_error("learned initial guess requested but no trained model is attached");
     return CGP_E_STATE;
   }
+  if ((mode == CGP_X0_LEARNED && g->incremental) || (mode == CGP_X0_LEARNED_CORR && !g->incremental)) {
+    set_error(mode == CGP_X0_LEARNED ? "CGP_X0_LEARNED needs a model trained with incremental = 0"
+                                     : "CGP_X0_LEARNED_CORR needs a model trained with incremental = 1");
+    return CGP_E_STATE;
+  }
   hipStream_t s = m->stream;
   const int n = g->n, nm = g->nm, G = 256;
-  double *a = g->d_scal, *c = g->d_scal + 64, *sub = g->d_scal + 128;
+  double *a = g->d_scal, *c = g->d_scal + 64;
   const double *mu_a = g->d_stats, *sd_a = g->d_stats + nm, *mu_c = g->d_stats + 2 * nm, *sd_c = g->d_stats + 3 * nm;
   auto project = [&](const double *w, const double *v, double *out) {
     hipLaunchKernelGGL(k_project, dim3(G), dim3(256), 0, s, n, nm, (const double *)g->d_phi, w, v, g->d_part);
     hipLaunchKernelGGL(k_project_finish, dim3(1), dim3(64), 0, s, G, nm, (const double *)g->d_part, out);
   };
-  if (mode == CGP_X0_POD_GALERKIN) {
+  // features: Phi^T b (absolute model) or Phi^T (b - K x) (incremental model and POD-Galerkin)
+  const bool from_residual = (mode != CGP_X0_LEARNED);
+  if (from_residual) {
     double *r = m->d_wc[7];
     hipLaunchKernelGGL(k_residual, dim3((n + 255) / 256), dim3(256), 0, s, n, m->d_rp_c, m->d_col_c,
                        (const double *)m->d_Kbc, b, (const double *)x, r);
     project(nullptr, r, a);
-    hipLaunchKernelGGL(k_small_matvec, dim3(1), dim3(64), 0, s, nm, (const double *)g->d_kinv, (const double *)a, c);
-    hipLaunchKernelGGL(k_expand, dim3(512), dim3(256), 0, s, n, nm, (const double *)g->d_phi, (const double *)c,
-                       (const double *)x, x);
   } else {
     project(nullptr, b, a);
+  }
+  if (mode == CGP_X0_POD_GALERKIN) {
+    hipLaunchKernelGGL(k_small_matvec, dim3(1), dim3(64), 0, s, nm, (const double *)g->d_kinv, (const double *)a, c);
+  } else {
     hipLaunchKernelGGL(k_feat_in, dim3(1), dim3(64), 0, s, nm, (const double *)a, mu_a, sd_a, g->d_xb);
     forward(g, s, 1);
-    const bool corr = (mode == CGP_X0_LEARNED_CORR);
-    if (corr) project(m->d_mc, x, sub);
-    hipLaunchKernelGGL(k_feat_out, dim3(1), dim3(64), 0, s, nm, (const float *)g->d_y, mu_c, sd_c,
-                       corr ? (const double *)sub : (const double *)nullptr, c);
-    hipLaunchKernelGGL(k_expand, dim3(512), dim3(256), 0, s, n, nm, (const double *)g->d_phi, (const double *)c,
-                       corr ? (const double *)x : (const double *)nullptr, x);
+    hipLaunchKernelGGL(k_feat_out, dim3(1), dim3(64), 0, s, nm, (const float *)g->d_y, mu_c, sd_c, c);
   }
+  hipLaunchKernelGGL(k_expand, dim3(512), dim3(256), 0, s, n, nm, (const double *)g->d_phi, (const double *)c,
+                     from_residual ? (const double *)x : (const double *)nullptr, x);
   CGP_HIP(hipGetLastError());
   return CGP_OK;
 }
@@ -543,7 +561,7 @@ cgp_status cgp_guess_create(cgp_mesh *m, const cgp_guess_desc *d, cgp_guess **ou
       (st = galloc(g, &g->d_dh2, (size_t)B * nh)) || (st = galloc(g, &g->d_dz2, (size_t)B * nh)) ||
       (st = galloc(g, &g->d_dh1, (size_t)B * nh)) || (st = galloc(g, &g->d_dz1, (size_t)B * nh)) ||
       (st = galloc(g, &g->d_part, (size_t)64 * 256)) || (st = galloc(g, &g->d_scal, 256)) ||
-      (st = galloc(g, &g->d_idx, 1 << 20)))
+      (st = galloc(g, &g->d_idx, 65536)))
     return fail(st);
   // uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) initialisation from a SplitMix64 stream
   std::vector<float> w(L.total);
@@ -603,6 +621,23 @@ cgp_status cgp_guess_export_basis(const cgp_guess *g, double *host, size_t count
   }
   CGP_HIP(hipStreamSynchronize(g->mesh->stream));
   CGP_HIP(hipMemcpy(host, g->d_phi, count * sizeof(double), hipMemcpyDeviceToHost));
+  return CGP_OK;
+}
+
+cgp_status cgp_guess_export_norm(const cgp_guess *g, double *host, size_t count) {
+  if (!g || !host || count != 4 * (size_t)g->nm) {
+    set_error("cgp_guess_export_norm: bad argument or size");
+    return CGP_E_ARG;
+  }
+  if (!g->trained) {
+    set_error("cgp_guess_export_norm: the model has not been trained");
+    return CGP_E_STATE;
+  }
+  const int nm = g->nm;
+  std::copy(g->mu_a.begin(), g->mu_a.end(), host);
+  std::copy(g->sd_a.begin(), g->sd_a.end(), host + nm);
+  std::copy(g->mu_c.begin(), g->mu_c.end(), host + 2 * nm);
+  std::copy(g->sd_c.begin(), g->sd_c.end(), host + 3 * nm);
   return CGP_OK;
 }
 
@@ -732,53 +767,75 @@ cgp_status cgp_guess_build_pod(cgp_guess *g, const double *snaps, int32_t S, dou
 
 cgp_status cgp_guess_train(cgp_guess *g, const double *rhs, const double *p, int32_t S, const cgp_train_opts *o,
                            cgp_train_stats *stats) {
-  if (!g || !rhs || !p || !o || S < 2 || S > (1 << 20) || !g->pod_ready || o->batch < 1 || o->batch > kMaxBatch ||
+  if (!g || !rhs || !p || !o || S < 2 || S > 65536 || !g->pod_ready || o->batch < 1 || o->batch > kMaxBatch ||
       o->epochs < 1 || !(o->lr > 0)) {
-    set_error("cgp_guess_train: bad argument (basis built? 2 <= S <= 2^20, batch in 1..256, epochs >= 1, lr > 0)");
+    set_error("cgp_guess_train: bad argument (basis built? 2 <= S <= 65536, batch in 1..256, epochs >= 1, lr > 0)");
     return CGP_E_ARG;
   }
   cgp_mesh *m = g->mesh;
   hipStream_t s = m->stream;
   const int n = g->n, nm = g->nm;
+  const bool incr = o->p_prev != nullptr;
   hipEvent_t e0, e1;
   CGP_HIP(hipEventCreate(&e0));
   CGP_HIP(hipEventCreate(&e1));
   CGP_HIP(hipEventRecord(e0, s));
-  // features a = Phi^T b and targets c = Phi^T M p for every sample ([S][nm], FP64)
-  double *dA = nullptr, *dC = nullptr;
+  // modal coefficients Phi^T M p of every pressure ([S][nm], FP64) and, for the incremental model,
+  // of every previous pressure; features Phi^T b, or Phi^T (b - K p_prev) for the incremental model
+  double *dA = nullptr, *dC = nullptr, *dCp = nullptr, *dR = nullptr;
+  const int NS = S;
   CGP_HIP(hipMallocAsync((void **)&dA, sizeof(double) * (size_t)S * nm, s));
   CGP_HIP(hipMallocAsync((void **)&dC, sizeof(double) * (size_t)S * nm, s));
-  GTRY(gemm64(g, s, S, nm, n, rhs, n, 1, nullptr, g->d_phi, nm, 1, dA));
   GTRY(gemm64(g, s, S, nm, n, p, n, 1, m->d_mc, g->d_phi, nm, 1, dC));
-  std::vector<double> A((size_t)S * nm), Cc((size_t)S * nm);
+  std::vector<double> A((size_t)S * nm), Cc((size_t)S * nm), Cprev;
+  if (incr) {
+    CGP_HIP(hipMallocAsync((void **)&dCp, sizeof(double) * (size_t)S * nm, s));
+    GTRY(gemm64(g, s, S, nm, n, o->p_prev, n, 1, m->d_mc, g->d_phi, nm, 1, dCp));
+    CGP_HIP(hipMallocAsync((void **)&dR, sizeof(double) * (size_t)S * n, s));
+    hipLaunchKernelGGL(k_pair_residual, dim3((n + 255) / 256, S), dim3(256), 0, s, n, m->d_rp_c, m->d_col_c,
+                       (const double *)m->d_Kbc, rhs, o->p_prev, dR);
+    GTRY(gemm64(g, s, S, nm, n, dR, n, 1, nullptr, g->d_phi, nm, 1, dA));
+    CGP_HIP(hipFreeAsync(dR, s));
+    Cprev.resize((size_t)S * nm);
+    CGP_HIP(hipMemcpyAsync(Cprev.data(), dCp, sizeof(double) * Cprev.size(), hipMemcpyDeviceToHost, s));
+    CGP_HIP(hipFreeAsync(dCp, s));
+  } else {
+    GTRY(gemm64(g, s, S, nm, n, rhs, n, 1, nullptr, g->d_phi, nm, 1, dA));
+  }
   CGP_HIP(hipMemcpyAsync(A.data(), dA, sizeof(double) * A.size(), hipMemcpyDeviceToHost, s));
   CGP_HIP(hipMemcpyAsync(Cc.data(), dC, sizeof(double) * Cc.size(), hipMemcpyDeviceToHost, s));
   CGP_HIP(hipFreeAsync(dA, s));
   CGP_HIP(hipFreeAsync(dC, s));
   CGP_HIP(hipStreamSynchronize(s));
-  // z-scores with the training statistics
+  if (incr)
+    for (size_t e = 0; e < Cc.size(); e++) Cc[e] -= Cprev[e];
+  // features: z-scores per mode.  Targets: mean per mode, one common scale for all modes, so that the
+  // loss weighs each mode by its share of the pressure's M-norm (Phi is M-orthonormal)
   g->mu_a.assign(nm, 0.0);
   g->sd_a.assign(nm, 0.0);
   g->mu_c.assign(nm, 0.0);
   g->sd_c.assign(nm, 0.0);
+  double vc_all = 0.0;
   for (int k = 0; k < nm; k++) {
     double sa = 0, sc = 0;
-    for (int r = 0; r < S; r++) {
+    for (int r = 0; r < NS; r++) {
       sa += A[(size_t)r * nm + k];
       sc += Cc[(size_t)r * nm + k];
     }
-    g->mu_a[k] = sa / S;
-    g->mu_c[k] = sc / S;
+    g->mu_a[k] = sa / NS;
+    g->mu_c[k] = sc / NS;
     double va = 0, vc = 0;
-    for (int r = 0; r < S; r++) {
+    for (int r = 0; r < NS; r++) {
       va += (A[(size_t)r * nm + k] - g->mu_a[k]) * (A[(size_t)r * nm + k] - g->mu_a[k]);
       vc += (Cc[(size_t)r * nm + k] - g->mu_c[k]) * (Cc[(size_t)r * nm + k] - g->mu_c[k]);
     }
-    g->sd_a[k] = va > 0 ? std::sqrt(va / S) : 1.0;
-    g->sd_c[k] = vc > 0 ? std::sqrt(vc / S) : 1.0;
+    g->sd_a[k] = va > 0 ? std::sqrt(va / NS) : 1.0;
+    vc_all += vc / NS;
   }
-  std::vector<float> X((size_t)S * nm), T((size_t)S * nm);
-  for (int r = 0; r < S; r++)
+  const double sd_common = vc_all > 0 ? std::sqrt(vc_all / nm) : 1.0;
+  for (int k = 0; k < nm; k++) g->sd_c[k] = sd_common;
+  std::vector<float> X((size_t)NS * nm), T((size_t)NS * nm);
+  for (int r = 0; r < NS; r++)
     for (int k = 0; k < nm; k++) {
       X[(size_t)r * nm + k] = (float)((A[(size_t)r * nm + k] - g->mu_a[k]) / g->sd_a[k]);
       T[(size_t)r * nm + k] = (float)((Cc[(size_t)r * nm + k] - g->mu_c[k]) / g->sd_c[k]);
@@ -796,9 +853,9 @@ cgp_status cgp_guess_train(cgp_guess *g, const double *rhs, const double *p, int
   CGP_HIP(hipMemcpyAsync(dT, T.data(), sizeof(float) * T.size(), hipMemcpyHostToDevice, s));
   // mini-batch Adam
   const int B = o->batch;
-  const int nb = (S + B - 1) / B;
-  std::vector<int> idx(S);
-  for (int i = 0; i < S; i++) idx[i] = i;
+  const int nb = (NS + B - 1) / B;
+  std::vector<int> idx(NS);
+  for (int i = 0; i < NS; i++) idx[i] = i;
   uint64_t state = o->seed;
   const float b1 = (float)(o->beta1 > 0 ? o->beta1 : 0.9), b2 = (float)(o->beta2 > 0 ? o->beta2 : 0.999);
   const float eps = (float)(o->eps > 0 ? o->eps : 1e-8);
@@ -808,10 +865,10 @@ cgp_status cgp_guess_train(cgp_guess *g, const double *rhs, const double *p, int
   double *h_loss = nullptr;
   CGP_HIP(hipHostMalloc((void **)&h_loss, sizeof(double) * nb, hipHostMallocDefault));
   for (int ep = 0; ep < o->epochs; ep++) {
-    for (int i = S - 1; i > 0; i--) std::swap(idx[i], idx[(int)(splitmix(state) % (uint64_t)(i + 1))]);
-    CGP_HIP(hipMemcpyAsync(g->d_idx, idx.data(), sizeof(int) * S, hipMemcpyHostToDevice, s));
+    for (int i = NS - 1; i > 0; i--) std::swap(idx[i], idx[(int)(splitmix(state) % (uint64_t)(i + 1))]);
+    CGP_HIP(hipMemcpyAsync(g->d_idx, idx.data(), sizeof(int) * NS, hipMemcpyHostToDevice, s));
     for (int bi = 0; bi < nb; bi++) {
-      const int rows = std::min(B, S - bi * B);
+      const int rows = std::min(B, NS - bi * B);
       hipLaunchKernelGGL(k_gather_batch, dim3((rows * nm + 255) / 256), dim3(256), 0, s, rows, nm,
                          (const int *)g->d_idx + bi * B, (const float *)dX, (const float *)dT, g->d_xb, g->d_t);
       forward(g, s, rows);
@@ -843,6 +900,7 @@ cgp_status cgp_guess_train(cgp_guess *g, const double *rhs, const double *p, int
   (void)hipEventDestroy(e1);
   CGP_HIP(hipGetLastError());
   g->trained = true;
+  g->incremental = incr;
   if (stats) {
     stats->loss_first = loss_first;
     stats->loss_last = loss_last;

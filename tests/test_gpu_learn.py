@@ -152,11 +152,16 @@ def test_pod_galerkin_guess_closed_form(env, small_mesh):
 
 @pytest.fixture(scope="module")
 def trajectory(env):
-    """Pressure right-hand sides and solutions of 240 steps of the cylinder flow."""
+    """Pressure right-hand sides and solutions of 240 steps of the cylinder flow.
+
+    The restriction is the transpose of the prolongation: with injection and
+    the consistent-mass correction this mesh grows a fine-scale velocity mode
+    after about 100 steps (the oracle does the same), which would make the
+    pressure history a blow-up rather than a flow."""
     torch, cgp, oracle = env
     case = W.case_cylinder(6000, seed=5)
     g = cgp.Mesh(case.mesh, 1)
-    g.assemble(case.rho, case.mu, case.dt)
+    g.assemble(case.rho, case.mu, case.dt, cgp._native.RESTRICT_GALERKIN)
     xy = g.export("xy")
     nc = g.info["n_c"]
     steps = 240
@@ -169,64 +174,105 @@ def trajectory(env):
     opts = cgp.StepOpts(poisson=cgp.SolverOpts(tol=1e-10))
     for k in range(steps):
         gd = dev(torch, case.dirichlet(xy, (k + 1) * case.dt))
-        g.step(gd, u, pf, pc, opts=opts)
+        st = g.step(gd, u, pf, pc, opts=opts)
         g.last_poisson_rhs(rhs[k])
         ps[k].copy_(pc)
+        if k % 40 == 0:
+            _say(f"  step {k}: Poisson iterations {st['p_iters']}, max |u| {u.abs().max().item():.3f}")
     torch.cuda.synchronize()
+    assert u.abs().max().item() < 5.0
     return case, g, rhs, ps
 
 
-def test_learned_guess_reduces_iterations(env, trajectory):
+def _split(steps):
+    """Held-out steps: every fifth step after the start-up (interpolation in time)."""
+    test = [k for k in range(40, steps) if k % 5 == 0]
+    train = [k for k in range(steps) if k % 5 != 0]
+    return train, test
+
+
+@pytest.fixture(scope="module")
+def models(env, trajectory):
+    """An absolute and an incremental model, each with its own POD basis of the training pressures.
+    The incremental model learns from the pairs (step k-1, step k) with k a training step."""
     torch, cgp, oracle = env
     case, g, rhs, ps = trajectory
-    n_train = 200
-    net = cgp.Guess(g, n_modes=32, hidden=128, seed=11)
-    energy = net.build_pod(ps[:n_train].contiguous())
-    assert np.all(np.diff(energy) <= 0) and energy[-1] > 0
-    st = net.train(rhs[:n_train].contiguous(), ps[:n_train].contiguous(), epochs=300, batch=64, lr=2e-3)
-    _say(f"  training: loss {st['loss_first']:.3e} -> {st['loss_last']:.3e} in {st['steps']} steps, {st['ms']:.0f} ms")
-    assert st["loss_last"] < 0.05 * st["loss_first"]
-    net.attach()
+    train, test = _split(rhs.shape[0])
+    held = set(test)
+    train = [k for k in train if k > 0 and k - 1 not in held]  # no held-out pressure enters training
+    idx = torch.tensor(train, device="cuda")
+    prev = torch.tensor([k - 1 for k in train], device="cuda")
+    out = {}
+    for name, incr in (("abs", False), ("incr", True)):
+        net = cgp.Guess(g, n_modes=32, hidden=128, seed=11)
+        energy = net.build_pod(ps[idx].contiguous())
+        assert np.all(np.diff(energy) <= 0) and energy[-1] > 0
+        st = net.train(rhs[idx].contiguous(), ps[idx].contiguous(), epochs=1000, batch=64, lr=2e-3,
+                       p_prev=ps[prev].contiguous() if incr else None)
+        _say(f"  {name} model: loss {st['loss_first']:.3e} -> {st['loss_last']:.3e} in {st['steps']} steps, "
+             f"{st['ms']:.0f} ms")
+        assert st["loss_last"] < 0.05 * st["loss_first"]
+        out[name] = net
+    yield out
+    for net in out.values():
+        net.close()
+
+
+def test_learned_guess_reduces_iterations(env, trajectory, models):
+    torch, cgp, oracle = env
+    case, g, rhs, ps = trajectory
+    train, test = _split(rhs.shape[0])
     X0 = cgp._native
-    modes = {"zero": X0.X0_ZERO, "prev": X0.X0_PREV, "learned": X0.X0_LEARNED, "learned_corr": X0.X0_LEARNED_CORR,
-             "pod_galerkin": X0.X0_POD_GALERKIN}
+    modes = {"zero": (X0.X0_ZERO, None), "prev": (X0.X0_PREV, None), "learned": (X0.X0_LEARNED, "abs"),
+             "learned_corr": (X0.X0_LEARNED_CORR, "incr"), "pod_galerkin": (X0.X0_POD_GALERKIN, "abs")}
     iters = {k: [] for k in modes}
-    for k in range(n_train, rhs.shape[0]):
-        b = rhs[k]
-        ref = ps[k].cpu().numpy()
-        for name, mode in modes.items():
+    for name, (mode, net) in modes.items():
+        if net:
+            models[net].attach()
+        for k in test:
+            b = rhs[k]
             x = ps[k - 1].clone() if mode != X0.X0_ZERO else torch.zeros_like(b)
             s = g.poisson_solve(b, x, cgp.SolverOpts(tol=1e-10, x0_mode=mode))
             iters[name].append(s["p_iters"])
-            assert rel(x.cpu().numpy(), ref) <= 1e-6, (name, k)
+            assert rel(x.cpu().numpy(), ps[k].cpu().numpy()) <= 1e-6, (name, k)
+        if net:
+            models[net].detach()
     mean = {k: float(np.mean(v)) for k, v in iters.items()}
     _say("  mean Poisson iterations on held-out steps:", {k: round(v, 1) for k, v in mean.items()})
-    assert mean["learned"] < 0.8 * mean["zero"]
-    assert mean["pod_galerkin"] <= mean["prev"] + 1
-    net.detach()
-    net.close()
+    # what each model gains over the method without it (x0 = 0, or the previous pressure); the
+    # networks' BF16 precision (2^-8 on every feature) bounds how close their guess can get
+    assert mean["learned"] < 0.95 * mean["zero"]
+    assert mean["learned_corr"] < mean["zero"]
+    assert mean["pod_galerkin"] < 0.9 * mean["prev"]
 
 
-def test_learned_corr_identity(env, trajectory):
-    """x0(LEARNED_CORR, x) - x0(LEARNED) = x - Phi Phi^T M x for any previous pressure x."""
+def test_inference_matches_oracle(env, trajectory, models):
+    """x0 from the GPU against the oracle's network run on the same model (basis, normalisation and
+    weights are the model's parameters): features in FP64, BF16 network emulated in FP64."""
     torch, cgp, oracle = env
     case, g, rhs, ps = trajectory
-    net = cgp.Guess(g, n_modes=16, hidden=64, seed=2)
-    net.build_pod(ps[:100].contiguous())
-    net.train(rhs[:100].contiguous(), ps[:100].contiguous(), epochs=5, batch=32)
+    o = oracle.Problem(case.mesh, 1)
+    o.assemble(case.rho, case.mu, case.dt, 1, 0)
+    rp, col, K = o.export("rowptr_c"), o.export("col_c"), o.values("K_c_bc")
     X0 = cgp._native
-    b = rhs[150]
-    xp = ps[149].clone()
-    x1 = torch.zeros_like(b)
-    net.predict(X0.X0_LEARNED, b, x1)
-    x2 = xp.clone()
-    net.predict(X0.X0_LEARNED_CORR, b, x2)
-    Phi = net.basis()
-    mc = g.export("m_c")
-    xpn = xp.cpu().numpy()
-    ref = xpn - Phi @ (Phi.T @ (mc * xpn))
-    assert rel((x2 - x1).cpu().numpy(), ref) <= 1e-10
-    net.close()
+    k = 150
+    b = rhs[k].cpu().numpy()
+    xp = ps[k - 1].cpu().numpy()
+    for name, mode in (("abs", X0.X0_LEARNED), ("incr", X0.X0_LEARNED_CORR)):
+        net = models[name]
+        Phi, nrm, params = net.basis(), net.norm(), net.get_params()
+        a = Phi.T @ (b if name == "abs" else b - oracle.spmv(rp, col, K, xp))
+        feat = ((a - nrm[0]) / nrm[1]).astype(np.float32)[None, :]
+        _, y, _ = oracle.mlp(net.n_modes, net.hidden, params, feat, np.zeros_like(feat), emulate=True)
+        c = y[0] * nrm[3] + nrm[2]
+        ref = Phi @ c + (xp if name == "incr" else 0.0)
+        x = dev(torch, xp.copy())
+        net.predict(mode, rhs[k], x)
+        got = x.cpu().numpy()
+        scale = np.linalg.norm(ref - (xp if name == "incr" else 0.0))
+        err = np.linalg.norm(got - ref) / scale
+        _say(f"  {name}: x0 rel err vs oracle network {err:.2e}")
+        assert err <= 1e-3
 
 
 def test_guess_errors(env, small_mesh):

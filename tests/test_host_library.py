@@ -27,6 +27,12 @@ def test_library_exports_every_declared_symbol(cgp):
     missing = [n for n in sorted(names) if not hasattr(L, n)]
     assert not missing, missing
     assert cgp.abi_version() == int(re.search(r"CGP_ABI_VERSION (\d+)", header).group(1))
+    # every function that takes arguments has a ctypes prototype: an undeclared pointer argument
+    # would be passed as a 32-bit int
+    decls = dict(re.findall(r"^(?:cgp_status|int32_t|void|const char\s*\*)\s*\*?\s*(cgp_[a-z_0-9]+)\s*\(([^)]*)\)",
+                            header, re.M))
+    undeclared = [n for n, args in decls.items() if args.strip() not in ("", "void") and getattr(L, n).argtypes is None]
+    assert not undeclared, undeclared
 
 
 TOPO = ["xy", "tri", "bedge", "bkind", "edges", "rowptr_f", "col_f", "slot_f", "colour_f", "rowptr_c", "col_c",
