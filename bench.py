@@ -9,19 +9,28 @@ mesh, restriction and coarse divergence, coarse pressure Poisson solve,
 prolongation, velocity correction.
 
 Warm-up steps develop the flow from an impulsive start with the plain FP64
-path; the two paths are then timed from the same state:
-  * plain FP64 CGP (Jacobi-PCG to 1e-8, x0 = previous pressure);
-  * mixed precision: FP32 Jacobi-PCG inside FP64 iterative refinement to
-    the same 1e-8; its per-step output is compared with the FP64 GPU path
-    and with the FP64 CPU oracle from the same state.
-``value`` is the mixed-precision path's steps/s.  One JSON line goes to stdout.
+path; the next steps, also plain FP64, are recorded as training data (Poisson
+right-hand sides and pressures) for the POD basis and the two networks of the
+learned initial guess, which are then built and trained on the GPU.  Every
+path is then timed from the same state, all with PCG to a relative residual of
+1e-8:
+  * fp64:                plain FP64 CGP, x0 = previous pressure;
+  * fp64+pod_galerkin:   x0 = previous pressure + Galerkin correction in the POD space;
+  * fp64+learned:        x0 from the absolute network;
+  * fp64+learned_corr:   x0 = previous pressure + the incremental network's correction;
+  * fp64+online_pod:     Galerkin guess in a POD basis rebuilt after every solve from the last
+                         32 solutions (a recycled Krylov subspace);
+  * mixed, mixed+online_pod: FP32 PCG inside FP64 iterative refinement.
+Each path's one-step output is compared with the plain FP64 path's (and the
+FP64 CPU oracle's) from the same state.  ``value`` is the steps/s of the
+fastest path within 1e-6 relative error of plain FP64; every path is listed.
+One JSON line goes to stdout.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
-import os
 import sys
 import time
 from pathlib import Path
@@ -30,6 +39,7 @@ ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
 HBM_PEAK_GBS = 8000.0
+ERR_BAR = 1e-6
 
 
 def log(*a):
@@ -49,19 +59,45 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def dominant_kernel(precision: str, launch: str, nnz: int, n: int):
+    """Name and algorithmic bytes per launch (= per iteration) of the Poisson kernel of a path.
+
+    Each array is counted once per iteration, as if every gathered vector entry came from HBM once."""
+    w = 4 if precision == "f32" else 8
+    t = "float" if w == 4 else "double"
+    if launch == "fused":
+        # values + columns per nonzero; per row: row pointer, D^-1, r, w, s, p, x read, x, p, s, r, w written
+        return f"k_cg1_iter<{t}>", (w + 4) * nnz + (4 + 6 * w + 5 * w) * n
+    if launch == "loop":
+        # SpMV + p update: values + columns per nonzero; row pointer, z, p_old read, p_new, q written per row
+        return f"k_cg_spmv<{t}>", (w + 4) * nnz + (4 + 4 * w) * n
+    # one persistent PCG iteration: the SpMV phase plus x, p, r, q, D^-1 read and x, r, z written
+    return f"k_pcg_persistent<{t}>", (w + 4) * nnz + (4 + 12 * w) * n
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--target-tris", type=int, default=250_000, help="coarse triangles (fine = 4x)")
+    ap.add_argument("--snapshots", type=int, default=64, help="plain-FP64 steps recorded as training data")
+    ap.add_argument("--modes", type=int, default=32, help="POD modes of the learned guess")
+    ap.add_argument("--hidden", type=int, default=128, help="hidden width of the guess networks")
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--window", type=int, default=32, help="solutions kept for the online POD basis")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps timed for the CPU baseline (0: skip)")
-    ap.add_argument("--no-instrumented", action="store_true", help="skip the event-bracketed kernel pass")
+    ap.add_argument("--no-instrumented", action="store_true", help="skip the event-timed kernel pass")
     ap.add_argument("--launch", choices=["loop", "persistent", "fused"], default="fused",
                     help="Poisson Krylov launch strategy")
+    ap.add_argument("--paths", default="all", help="comma-separated subset of the timed paths")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
     if args.copy_calibration:
         import torch
         n = args.copy_calibration * (1 << 20) // 8
@@ -72,10 +108,6 @@ def main():
         torch.cuda.synchronize()
         log(f"copied {args.copy_calibration} MiB three times ({n * 8} bytes read and written per copy)")
         return
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
-              file=sys.stderr)
-        sys.exit(2)
 
     import numpy as np
     import torch
@@ -83,6 +115,7 @@ def main():
     import paper_1610_06993_amd as cgp
     import workloads as W
     from paper_1610_06993_amd import SolverOpts, StepOpts
+    X0 = cgp._native
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -93,112 +126,149 @@ def main():
     mesh = cgp.Mesh(case.mesh, 1)
     mesh.assemble(case.rho, case.mu, case.dt)
     info = mesh.info
-    log(f"mesh: coarse {info['t_c']} tris / {info['n_c']} nodes, fine {info['t_f']} tris / {info['n_f']} nodes, "
-        f"nnz_f {info['nnz_f']}, nnz_c {info['nnz_c']}, colours {info['ncol_f']}; setup {time.perf_counter() - t0:.1f}s")
+    nnz_c, n_c = info["nnz_c"], info["n_c"]
+    log(f"mesh: coarse {info['t_c']} tris / {n_c} nodes, fine {info['t_f']} tris / {info['n_f']} nodes, "
+        f"nnz_f {info['nnz_f']}, nnz_c {nnz_c}, colours {info['ncol_f']}; setup {time.perf_counter() - t0:.1f}s")
 
     xy = mesh.export("xy")
     vdir = mesh.export("vdir")
     g = torch.from_numpy(case.dirichlet(xy, 0.0)).to(dev)  # steady inflow data
     u = torch.from_numpy(case.initial(xy, vdir)).to(dev)
     pf = torch.zeros(info["n_f"], dtype=torch.float64, device=dev)
-    pc = torch.zeros(info["n_c"], dtype=torch.float64, device=dev)
+    pc = torch.zeros(n_c, dtype=torch.float64, device=dev)
 
     tol = 1e-8
     launch = {"loop": 1, "persistent": 2, "fused": 3}[args.launch]
-    fp64 = StepOpts(momentum=SolverOpts(tol=tol, max_iter=5000),
-                    poisson=SolverOpts(tol=tol, max_iter=100000, launch=launch),
-                    mass=SolverOpts(tol=1e-10, max_iter=2000))
-    mixed = StepOpts(momentum=SolverOpts(tol=tol, max_iter=5000),
-                     poisson=SolverOpts(tol=tol, max_iter=100000, precision=cgp._native.PREC_FP32_IR,
-                                        inner_tol=1e-4, launch=launch),
-                     mass=SolverOpts(tol=1e-10, max_iter=2000))
+
+    def opts(precision=0, x0=X0.X0_PREV, timing=0):
+        return StepOpts(momentum=SolverOpts(tol=tol, max_iter=5000),
+                        poisson=SolverOpts(tol=tol, max_iter=100000, precision=precision, inner_tol=1e-4,
+                                           x0_mode=x0, launch=launch),
+                        mass=SolverOpts(tol=1e-10, max_iter=2000), timing=timing)
 
     for k in range(args.warmup):
-        st = mesh.step(g, u, pf, pc, opts=fp64)
+        st = mesh.step(g, u, pf, pc, opts=opts())
     torch.cuda.synchronize()
-    log(f"warm-up {args.warmup} steps done; last: {st}")
+    log(f"warm-up {args.warmup} steps done; last Poisson iterations {st['p_iters']}")
+
+    # training data from the plain path, then the POD bases and networks, all on the GPU
+    S = args.snapshots
+    rhs = torch.zeros((S, n_c), dtype=torch.float64, device=dev)
+    ps = torch.zeros_like(rhs)
+    pprev = torch.zeros_like(rhs)
+    for k in range(S):
+        pprev[k].copy_(pc)
+        mesh.step(g, u, pf, pc, opts=opts())
+        mesh.last_poisson_rhs(rhs[k])
+        ps[k].copy_(pc)
+    torch.cuda.synchronize()
+    train = {}
+    models = {}
+    for name, prev in (("abs", None), ("incr", pprev)):
+        net = cgp.Guess(mesh, n_modes=args.modes, hidden=args.hidden, seed=11)
+        t1 = time.perf_counter()
+        net.build_pod(ps)
+        tr = net.train(rhs, ps, epochs=args.epochs, batch=64, lr=2e-3, p_prev=prev)
+        torch.cuda.synchronize()
+        train[name] = dict(loss_first=tr["loss_first"], loss_last=tr["loss_last"], adam_steps=tr["steps"],
+                           train_ms=round(tr["ms"], 1), pod_and_train_s=round(time.perf_counter() - t1, 3))
+        models[name] = net
+        log(f"{name} model: POD {args.modes} modes of {S} snapshots, training loss {tr['loss_first']:.3e} -> "
+            f"{tr['loss_last']:.3e} in {tr['steps']} Adam steps ({tr['ms']:.0f} ms on the GPU)")
+    # online basis: rebuilt after every solve from the last `window` solutions (a recycled subspace);
+    # restarting a path refills its window from the recorded pressures
+    online = cgp.Guess(mesh, n_modes=args.window, hidden=16, seed=5)
+    models["online"] = online
     snap_u, snap_pc = u.clone(), pc.clone()
 
-    def restore():
+    def restore(model=None):
+        """Back to the recorded state with `model` attached (None: no guess model)."""
         u.copy_(snap_u)
         pc.copy_(snap_pc)
         pf.zero_()
+        if model == "online":
+            online.set_online(args.window, 1)
+            online.attach()
+            for k in range(S - args.window, S):  # the newest recorded solves fill the window
+                mesh.poisson_solve(rhs[k], ps[k].clone(), SolverOpts(tol=tol, x0_mode=X0.X0_PREV))
+        elif model:
+            models[model].attach()
+        else:
+            online.detach()
         torch.cuda.synchronize()
 
+    F64, F32 = cgp._native.PREC_FP64, cgp._native.PREC_FP32_IR
+    paths = {
+        "fp64": (F64, X0.X0_PREV, None),
+        "fp64+pod_galerkin": (F64, X0.X0_POD_GALERKIN, "abs"),
+        "fp64+learned": (F64, X0.X0_LEARNED, "abs"),
+        "fp64+learned_corr": (F64, X0.X0_LEARNED_CORR, "incr"),
+        "fp64+online_pod": (F64, X0.X0_POD_GALERKIN, "online"),
+        "mixed": (F32, X0.X0_PREV, None),
+        "mixed+online_pod": (F32, X0.X0_POD_GALERKIN, "online"),
+    }
+    if args.paths != "all":
+        keep = set(args.paths.split(",")) | {"fp64"}
+        paths = {k: v for k, v in paths.items() if k in keep}
+
+    # one step of every path from the same state: accuracy against plain FP64 and the phase breakdown
+    restore()
+    mesh.step(g, u, pf, pc, opts=opts(timing=1))
+    u_ref, pf_ref = u.cpu().numpy(), pf.cpu().numpy()
     results = {}
-    for name, opts in (("fp64", fp64), ("mixed", mixed)):
-        restore()
-        mesh.step(g, u, pf, pc, opts=opts)  # one untimed step per path (solver chunk sizes adapt)
-        restore()
+    for name, (prec, x0, model) in paths.items():
+        restore(model)
+        st1 = mesh.step(g, u, pf, pc, opts=opts(prec, x0, timing=1))
+        err = max(rel(u.cpu().numpy(), u_ref), rel(pf.cpu().numpy(), pf_ref))
+        restore(model)
+        mesh.step(g, u, pf, pc, opts=opts(prec, x0))  # untimed: solver chunk sizes adapt
+        restore(model)
         iters = []
-        torch.cuda.synchronize()
         t1 = time.perf_counter()
         for k in range(args.steps):
-            st = mesh.step(g, u, pf, pc, opts=opts)
+            st = mesh.step(g, u, pf, pc, opts=opts(prec, x0))
             iters.append(st["p_iters"])
         torch.cuda.synchronize()
         el = time.perf_counter() - t1
-        results[name] = dict(steps_per_s=args.steps / el, ms_per_step=1e3 * el / args.steps,
-                             p_iters_mean=float(np.mean(iters)), last=st)
-        log(f"{name}: {args.steps / el:.2f} steps/s ({1e3 * el / args.steps:.2f} ms/step), mean Poisson iters "
-            f"{np.mean(iters):.0f}")
-
-    # per-phase breakdown and accuracy from the same state
+        results[name] = dict(steps_per_s=round(args.steps / el, 3), ms_per_step=round(1e3 * el / args.steps, 3),
+                             poisson_iters_mean=float(np.mean(iters)), rel_err_vs_fp64=err,
+                             phase_ms={k: round(st1[k], 4) for k in ("ms_momentum", "ms_restrict", "ms_poisson",
+                                                                     "ms_prolong", "ms_correct")})
+        log(f"{name}: {args.steps / el:.2f} steps/s ({1e3 * el / args.steps:.2f} ms/step), Poisson iterations "
+            f"{np.mean(iters):.0f}, one-step rel err vs fp64 {err:.1e}; phases (ms) mom {st1['ms_momentum']:.2f} "
+            f"poisson {st1['ms_poisson']:.2f} correct {st1['ms_correct']:.2f}")
     restore()
-    st64 = mesh.step(g, u, pf, pc, opts=StepOpts(fp64.momentum, fp64.poisson, fp64.mass, timing=1))
-    u64, pf64 = u.cpu().numpy(), pf.cpu().numpy()
-    restore()
-    stmx = mesh.step(g, u, pf, pc, opts=StepOpts(mixed.momentum, mixed.poisson, mixed.mass, timing=1))
-    umx, pfmx = u.cpu().numpy(), pf.cpu().numpy()
-    err_vs_fp64 = max(rel(umx, u64), rel(pfmx, pf64))
-    log(f"phases fp64 (ms): mom {st64['ms_momentum']:.2f} restr {st64['ms_restrict']:.3f} poisson "
-        f"{st64['ms_poisson']:.2f} prolong {st64['ms_prolong']:.3f} correct {st64['ms_correct']:.2f}")
-    log(f"phases mixed (ms): mom {stmx['ms_momentum']:.2f} poisson {stmx['ms_poisson']:.2f} "
-        f"(outer {stmx['p_outer']}, inner iters {stmx['p_iters']}); rel err vs fp64 {err_vs_fp64:.2e}")
 
-    # dominant kernel of the timed (mixed) path, every launch bracketed by HIP events on the mesh stream:
-    # the persistent FP32 PCG kernel (one launch per inner solve) or, in the launch-per-phase loop, the
-    # fused FP32 p-update + SpMV kernel (one launch per iteration)
+    eligible = {k: v for k, v in results.items() if v["rel_err_vs_fp64"] <= ERR_BAR}
+    best = max(eligible, key=lambda k: eligible[k]["steps_per_s"])
+    bprec, bx0, bmodel = paths[best]
+    res = results[best]
+
+    # dominant kernel of the best path: every launch bracketed by events that its own dispatch records
     dom = None
     if not args.no_instrumented:
-        restore()
+        restore(bmodel)
         tot_ms, cnt, its = 0.0, 0, 0
         for k in range(args.steps):
-            s = mesh.step(g, u, pf, pc, opts=StepOpts(mixed.momentum, mixed.poisson, mixed.mass, timing=2))
+            s = mesh.step(g, u, pf, pc, opts=opts(bprec, bx0, timing=2))
             tot_ms += s["ms_dominant"]
             cnt += s["n_dominant"]
             its += s["dominant_iters"]
-        nnz_c, n_c = info["nnz_c"], info["n_c"]
-        if args.launch == "loop":
-            kname = "k_cg_spmv<float>"
-            # values 4 B + column 4 B per nonzero; row pointer 4 B, z and p_old 4+4 B read, p_new and q
-            # 4+4 B written per row (each vector touched once)
-            bytes_per_iter = 8 * nnz_c + 20 * n_c
-        elif args.launch == "fused":
-            kname = "k_cg1_iter<float>"
-            # one whole FP32 iteration: values + columns 8 B per nonzero; row pointer 4 B, D^-1, r, w, s, p, x
-            # read (24 B) and x, p, s, r, w written (20 B) per row, each vector touched once
-            bytes_per_iter = 8 * nnz_c + 48 * n_c
-        else:
-            kname = "k_pcg_persistent<float>"
-            # one FP32 PCG iteration: the SpMV phase above (8 nnz + 20 n) plus the update phase reading
-            # x, p, r, q, D^-1 and writing x, r, z (32 n)
-            bytes_per_iter = 8 * nnz_c + 52 * n_c
-        total_bytes = bytes_per_iter * its
-        achieved = total_bytes / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
+        restore()
+        kname, bytes_per_iter = dominant_kernel("f32" if bprec == F32 else "f64", args.launch, nnz_c, n_c)
+        achieved = bytes_per_iter * its / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
         traffic = None
         tf = ROOT / "profiles" / "traffic_dominant.json"
         if tf.exists():
-            tj = json.loads(tf.read_text())
-            if tj.get("source_hash") == kernel_source_hash() and tj.get("kernel") == kname:
-                traffic = tj.get("bytes_per_iteration")
+            tj = json.loads(tf.read_text()).get(kname, {})
+            if tj.get("source_hash") == kernel_source_hash() and tj.get("n_c") == n_c:
+                traffic = tj.get("bytes_per_launch")
         dom = dict(kernel=kname, launches=cnt, iterations=its, avg_us=1e3 * tot_ms / max(cnt, 1),
-                   bytes_per_launch=total_bytes / max(cnt, 1), bytes_per_iteration=bytes_per_iter,
-                   achieved=achieved, traffic=traffic, us_per_iteration=1e3 * tot_ms / max(its, 1))
-        log(f"dominant kernel {kname}: {cnt} launches, {its} iterations, avg {dom['avg_us']:.1f} us/launch, "
-            f"{dom['us_per_iteration']:.2f} us/iteration, {achieved:.0f} GB/s algorithmic")
+                   bytes_per_launch=bytes_per_iter, achieved=achieved, traffic=traffic)
+        log(f"dominant kernel {kname}: {cnt} launches, avg {dom['avg_us']:.2f} us, {bytes_per_iter} algorithmic "
+            f"bytes per launch, {achieved:.0f} GB/s")
 
-    # CPU baseline: the FP64 oracle from the same state, and the accuracy of the timed path against it
+    # CPU baseline: the FP64 oracle from the same state, and the best path's accuracy against it
     cpu = None
     err_vs_oracle = None
     if args.cpu_steps > 0:
@@ -207,50 +277,50 @@ def main():
         ref.assemble(case.rho, case.mu, case.dt)
         ur, pcr = snap_u.cpu().numpy(), snap_pc.cpu().numpy()
         gh = g.cpu().numpy()
+        restore(bmodel)
+        mesh.step(g, u, pf, pc, opts=opts(bprec, bx0))
+        ub, pfb = u.cpu().numpy(), pf.cpu().numpy()
+        restore()
         t2 = time.perf_counter()
         outs = []
         for k in range(args.cpu_steps):
             ur, pfr, pcr, code, ost = ref.step(gh, ur, pcr, tol_mom=tol, tol_p=tol, tol_mass=1e-10)
             outs.append((ur.copy(), pfr.copy()))
         el = time.perf_counter() - t2
-        err_vs_oracle = max(rel(umx, outs[0][0]), rel(pfmx, outs[0][1]))
-        cpu = dict(value=args.cpu_steps / el, unit="CGP steps/s", cores=1, kind="oracle",
+        err_vs_oracle = max(rel(ub, outs[0][0]), rel(pfb, outs[0][1]))
+        cpu = dict(value=round(args.cpu_steps / el, 5), unit="CGP steps/s", cores=1, kind="oracle",
                    sample=f"{args.cpu_steps} FP64 oracle steps (single thread) of the same cylinder workload "
-                          f"from the post-warm-up state; {el:.1f} s")
-        log(f"oracle: {el / args.cpu_steps:.2f} s/step; mixed GPU step vs oracle rel err {err_vs_oracle:.2e}")
+                          f"from the post-training state; {el:.1f} s")
+        log(f"oracle: {el / args.cpu_steps:.2f} s/step; {best} step vs oracle rel err {err_vs_oracle:.2e}")
 
-    res = results["mixed"]
     line = {
         "metric": "CGP steps/s (1M-tri fine mesh) vs plain FP64 at <=1e-6 rel err; SpMV HBM GB/s",
-        "value": round(res["steps_per_s"], 3),
+        "value": res["steps_per_s"],
         "unit": "CGP steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(res["ms_per_step"], 3),
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64+f32-ir", "data": "synthetic",
+        "dtype": "f64+f32-ir" if bprec == F32 else "f64", "data": "synthetic",
         "config": {"workload": f"cylinder channel Re=100, coarse {info['t_c']} / fine {info['t_f']} P1 triangles, "
-                               f"l=1, dt=1e-3, PCG tol 1e-8 (FP32 inner in FP64 refinement)",
-                   "fine_nodes": info["n_f"], "coarse_nodes": info["n_c"], "nnz_f": info["nnz_f"],
-                   "nnz_c": info["nnz_c"], "parallelism": "single GPU"},
-        "fp64_steps_per_s": round(results["fp64"]["steps_per_s"], 3),
+                               f"l=1, dt=1e-3, PCG tol 1e-8, path {best}",
+                   "path": best, "fine_nodes": info["n_f"], "coarse_nodes": n_c, "nnz_f": info["nnz_f"],
+                   "nnz_c": nnz_c, "pod_modes": args.modes, "snapshots": S, "parallelism": "single GPU"},
+        "fp64_steps_per_s": results["fp64"]["steps_per_s"],
         "speedup_vs_fp64": round(res["steps_per_s"] / results["fp64"]["steps_per_s"], 3),
-        "rel_err_vs_fp64_gpu": err_vs_fp64,
+        "rel_err_vs_fp64_gpu": res["rel_err_vs_fp64"],
         "rel_err_vs_fp64_oracle": err_vs_oracle,
-        "poisson_iters_mean": {"fp64": results["fp64"]["p_iters_mean"], "mixed_inner": res["p_iters_mean"]},
-        "phase_ms_fp64": {k: round(st64[k], 4) for k in ("ms_momentum", "ms_restrict", "ms_poisson", "ms_prolong",
-                                                         "ms_correct")},
-        "phase_ms_mixed": {k: round(stmx[k], 4) for k in ("ms_momentum", "ms_restrict", "ms_poisson", "ms_prolong",
-                                                          "ms_correct")},
+        "paths": results,
+        "training": train,
     }
     if dom:
         line["roofline"] = {"bound": "hbm", "achieved": round(dom["achieved"], 1), "peak": HBM_PEAK_GBS,
                             "unit": "GB/s", "frac": round(dom["achieved"] / HBM_PEAK_GBS, 4),
                             "traffic": dom["traffic"], "kernel": dom["kernel"], "avg_us": round(dom["avg_us"], 3),
-                            "launches": dom["launches"], "iterations": dom["iterations"],
-                            "bytes_per_iteration": dom["bytes_per_iteration"],
-                            "us_per_iteration": round(dom["us_per_iteration"], 3)}
+                            "launches": dom["launches"], "bytes_per_launch": dom["bytes_per_launch"]}
     if cpu:
         line["cpu_baseline"] = cpu
+    for net in models.values():
+        net.close()
     print(json.dumps(line), flush=True)
 
 

@@ -233,7 +233,8 @@ typedef struct { double loss_first, loss_last; int32_t steps; float ms; } cgp_tr
 cgp_status cgp_guess_create(cgp_mesh *mesh, const cgp_guess_desc *desc, cgp_guess **out);
 void cgp_guess_destroy(cgp_guess *g);
 /* Basis from snapshots (device [S][n_c], rows = snapshots): eigenvectors of S M_c S^T for the n_modes
- * largest eigenvalues (randomised subspace iteration on the host), Phi = S^T V Lambda^-1/2.
+ * largest eigenvalues (randomised subspace iteration on the host), Phi = S^T V Lambda^-1/2.  Modes with
+ * an eigenvalue below 1e-20 of the largest are left out (zero columns, energy 0).
  * energy: host [n_modes] eigenvalues or NULL. */
 cgp_status cgp_guess_build_pod(cgp_guess *g, const double *snaps, int32_t S, double *energy);
 /* Train on S (2..65536) samples: device [S][n_c] right-hand sides after boundary conditions and the
@@ -241,6 +242,14 @@ cgp_status cgp_guess_build_pod(cgp_guess *g, const double *snaps, int32_t S, dou
  * first. */
 cgp_status cgp_guess_train(cgp_guess *g, const double *rhs, const double *p, int32_t S, const cgp_train_opts *opts,
                            cgp_train_stats *stats);
+/* Online basis: while the guess is attached, every converged Poisson solve of the mesh keeps its solution
+ * in a window of the last `window` solutions (device memory owned by the guess), and every `refresh`
+ * solves the basis is rebuilt from the window (as cgp_guess_build_pod).  The basis then spans recent
+ * pressures, including the components the solver converges on slowest, so that CGP_X0_POD_GALERKIN acts
+ * as a recycled Krylov subspace; until the window holds n_modes solutions that mode keeps the previous
+ * pressure.  A rebuilt basis invalidates a trained network.  window = 0 turns it off; otherwise
+ * n_modes <= window <= 1024 and refresh >= 1.  Synchronises the mesh stream at each rebuild. */
+cgp_status cgp_guess_set_online(cgp_guess *g, int32_t window, int32_t refresh);
 /* Enable CGP_X0_LEARNED / _CORR / POD_GALERKIN on the mesh's Poisson solve (NULL detaches). */
 cgp_status cgp_guess_attach(cgp_mesh *mesh, cgp_guess *g);
 /* x0 (device [n_c]) for right-hand side b (device [n_c]); x holds the previous pressure for _CORR/_GALERKIN. */

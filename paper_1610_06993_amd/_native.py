@@ -156,10 +156,11 @@ def lib():
     L.cgp_guess_mlp_grad.argtypes = [vp, vp, vp, C.c_int32, C.POINTER(C.c_double), vp, vp]
     L.cgp_guess_export_basis.argtypes = [vp, vp, C.c_size_t]
     L.cgp_guess_export_norm.argtypes = [vp, vp, C.c_size_t]
+    L.cgp_guess_set_online.argtypes = [vp, C.c_int32, C.c_int32]
     L.cgp_last_poisson_rhs.argtypes = [vp, vp]
     for name in ("cgp_guess_create", "cgp_guess_build_pod", "cgp_guess_train", "cgp_guess_attach", "cgp_guess_predict",
                  "cgp_guess_get_params", "cgp_guess_set_params", "cgp_guess_mlp_grad", "cgp_guess_export_basis",
-                 "cgp_guess_export_norm", "cgp_last_poisson_rhs", "cgp_mesh_get_tuning", "cgp_mesh_set_tuning",
+                 "cgp_guess_export_norm", "cgp_guess_set_online", "cgp_last_poisson_rhs", "cgp_mesh_get_tuning", "cgp_mesh_set_tuning",
                  "cgp_mesh_create", "cgp_mesh_query", "cgp_mesh_export", "cgp_assemble", "cgp_step", "cgp_momentum",
                  "cgp_restrict", "cgp_poisson_solve", "cgp_prolong", "cgp_correct", "cgp_spmv"):
         getattr(L, name).restype = C.c_int32
@@ -359,6 +360,10 @@ class Guess:
         o = _TrainOpts(epochs, batch, lr, beta1, beta2, eps, seed, _ptr(p_prev) if p_prev is not None else None)
         _check(lib().cgp_guess_train(self._h, _ptr(rhs), _ptr(p), rhs.shape[0], C.byref(o), C.byref(st)))
         return {k: getattr(st, k) for k, _ in _TrainStats._fields_}
+
+    def set_online(self, window: int, refresh: int = 1):
+        """Rebuild the basis every `refresh` Poisson solves from the last `window` solutions (0: off)."""
+        _check(lib().cgp_guess_set_online(self._h, window, refresh))
 
     def attach(self):
         _check(lib().cgp_guess_attach(self.mesh._h, self._h))

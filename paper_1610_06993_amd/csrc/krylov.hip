@@ -12,6 +12,7 @@
 // iteration parity, so no kernel writes a slot that one of its own blocks
 // reads).  Once a component converges it is frozen; once all have, every
 // remaining kernel of the chunk returns at its first instruction.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -901,6 +902,23 @@ void kt_end(cgp_mesh *m) {
   m->kt_used++;
 }
 
+// Event pair for one launch of the dominant kernel, recorded by the dispatch itself
+// (hipExtLaunchKernelGGL), so that it brackets the kernel's own execution; false when not timing.
+bool kt_slot(cgp_mesh *m, int iter, hipEvent_t *e0, hipEvent_t *e1) {
+  if (!m->kt_on) return false;
+  if (m->kt_used * 2 + 2 > (int)m->kt_ev.size()) {
+    const size_t old = m->kt_ev.size();
+    m->kt_ev.resize(std::max<size_t>(512, 2 * old));
+    m->kt_iter.resize(m->kt_ev.size() / 2);
+    for (size_t i = old; i < m->kt_ev.size(); i++) (void)hipEventCreate(&m->kt_ev[i]);
+  }
+  m->kt_iter[m->kt_used] = iter;
+  *e0 = m->kt_ev[2 * m->kt_used];
+  *e1 = m->kt_ev[2 * m->kt_used + 1];
+  m->kt_used++;
+  return true;
+}
+
 // Launch shapes of one PCG/BiCGStab iteration on a mesh level.
 struct LoopShapes {
   Shape rows;   // SpMV-type kernels (lanes per row)
@@ -926,11 +944,15 @@ cgp_status pcg_loop(cgp_mesh *m, int slot, int n, const int *rp, const int *col,
       constexpr int LL = decltype(LC)::value;
       for (int c = 0; c < chunk && it < maxit; c++, it++) {
         T *po = (it & 1) ? p1 : p0, *pn = (it & 1) ? p0 : p1;
-        if (timed) kt_begin(m, it);
-        hipLaunchKernelGGL((k_cg_spmv<T, NC, LL>), dim3(sh.rows.grid), dim3(sh.rows.block), 0, s,
-                           it == 0 ? G0 : sh.elem.grid, it, n, rp, col, A, (const T *)z, (const T *)po, pn, q,
-                           (const double *)(it == 0 ? Pinit : Pupd), Ppq, st);
-        if (timed) kt_end(m);
+        hipEvent_t e0, e1;
+        if (timed && kt_slot(m, it, &e0, &e1))
+          hipExtLaunchKernelGGL((k_cg_spmv<T, NC, LL>), dim3(sh.rows.grid), dim3(sh.rows.block), 0, s, e0, e1, 0,
+                                it == 0 ? G0 : sh.elem.grid, it, n, rp, col, A, (const T *)z, (const T *)po, pn, q,
+                                (const double *)(it == 0 ? Pinit : Pupd), Ppq, st);
+        else
+          hipLaunchKernelGGL((k_cg_spmv<T, NC, LL>), dim3(sh.rows.grid), dim3(sh.rows.block), 0, s,
+                             it == 0 ? G0 : sh.elem.grid, it, n, rp, col, A, (const T *)z, (const T *)po, pn, q,
+                             (const double *)(it == 0 ? Pinit : Pupd), Ppq, st);
         hipLaunchKernelGGL((k_cg_update<T, NC>), dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, sh.rows.grid, it, n,
                            x, r, z, dinv, (const T *)pn, (const T *)q, (const double *)Ppq, Pupd, st);
       }
@@ -994,11 +1016,15 @@ cgp_status cg1_loop(cgp_mesh *m, int slot, int n, const int *rp, const int *col,
       constexpr int LL = decltype(LC)::value;
       for (int c = 0; c < chunk && it < maxit; c++, it++) {
         const int cur = it & 1, nxt = cur ^ 1;
-        if (timed) kt_begin(m, it);
-        hipLaunchKernelGGL((k_cg1_iter<T, LL>), dim3(sh.grid), dim3(sh.block), 0, s, sh.grid, it, n, rp, col, A,
-                           dinv, x, p, (const T *)r[cur], (const T *)w[cur], (const T *)sv[cur], r[nxt], w[nxt],
-                           sv[nxt], (const double *)pin(it), pout(it), st);
-        if (timed) kt_end(m);
+        hipEvent_t e0, e1;
+        if (timed && kt_slot(m, it, &e0, &e1))
+          hipExtLaunchKernelGGL((k_cg1_iter<T, LL>), dim3(sh.grid), dim3(sh.block), 0, s, e0, e1, 0, sh.grid, it, n,
+                                rp, col, A, dinv, x, p, (const T *)r[cur], (const T *)w[cur], (const T *)sv[cur],
+                                r[nxt], w[nxt], sv[nxt], (const double *)pin(it), pout(it), st);
+        else
+          hipLaunchKernelGGL((k_cg1_iter<T, LL>), dim3(sh.grid), dim3(sh.block), 0, s, sh.grid, it, n, rp, col, A,
+                             dinv, x, p, (const T *)r[cur], (const T *)w[cur], (const T *)sv[cur], r[nxt], w[nxt],
+                             sv[nxt], (const double *)pin(it), pout(it), st);
       }
     });
     hipLaunchKernelGGL(k_cg1_finish, dim3(1), dim3(256), 0, s, it, sh.grid, (const double *)pin(it), st);
@@ -1257,6 +1283,10 @@ cgp_status drv_poisson(cgp_mesh *m, const double *b_in, double *x, const cgp_sol
   if (rs != CGP_OK && rs != CGP_E_NOCONV) return rs;
   if (m->n_pdir == 0) launch_mean_shift(m, x, m->d_mc, m->mc_sum, region(m, R_A));  // zero weighted mean
   CGP_HIP(hipGetLastError());
+  if (rs == CGP_OK) {
+    cgp_status gs = guess_record(m, x);
+    if (gs) return gs;
+  }
   if (stats) {
     stats->p_iters = total_iters;
     stats->p_outer = outer;

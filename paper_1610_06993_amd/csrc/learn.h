@@ -15,7 +15,12 @@ struct cgp_guess {
   // basis
   double *d_phi = nullptr;            // [n][nm], M-orthonormal
   double *d_kinv = nullptr;           // [nm][nm] inverse of Phi^T K Phi (POD-Galerkin guess)
-  std::vector<double> energy;         // POD eigenvalues (largest first)
+  std::vector<double> energy;         // POD eigenvalues (largest first; 0 for unused modes)
+  int rank = 0;                       // modes in use (the rest of Phi is zero)
+  // online basis: the pressures of the last `win` solves, the basis rebuilt every `refresh` solves
+  double *d_ring = nullptr;           // [ring_cap][n]
+  int ring_cap = 0, win = 0, refresh = 1, head = 0, filled = 0;
+  long recorded = 0;
   // network: parameters [W1 nh*nm | b1 nh | W2 nh*nh | b2 nh | W3 nm*nh | b3 nm]
   long nparams = 0;
   float *d_w = nullptr, *d_g = nullptr, *d_m = nullptr, *d_v = nullptr;
@@ -40,4 +45,6 @@ constexpr int kMaxBatch = 256;
 // the incremental model applied to Phi^T (b - K x);
 // CGP_X0_POD_GALERKIN: x0 = x + Phi (Phi^T K Phi)^-1 Phi^T (b - K x).  x holds the previous pressure.
 cgp_status guess_initial(cgp_mesh *m, int mode, const double *b, double *x);
+// After a converged Poisson solve: keep x in the attached guess's window and refresh its basis when due.
+cgp_status guess_record(cgp_mesh *m, const double *x);
 }  // namespace cgp

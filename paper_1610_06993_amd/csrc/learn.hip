@@ -373,8 +373,12 @@ void gemm(hipStream_t s, int M, int N, int K, const unsigned short *A, long sam,
 // FP64 C[M][N] = sum_i P(a,i) w_i Y(i,b) through split-K partials
 cgp_status gemm64(cgp_guess *g, hipStream_t s, int M, int N, int K, const double *P, long spa, long spi,
                   const double *w, const double *Y, long syi, long syb, double *C) {
-  const int kchunk = 8192;
-  const int chunks = (K + kchunk - 1) / kchunk;
+  // split K so that about 512 blocks run, within 64 MB of partial sums
+  const long tiles = (long)((N + 63) / 64) * ((M + 63) / 64);
+  long chunks = std::max(1L, std::min((long)(K + 255) / 256, 512 / tiles));
+  chunks = std::max(1L, std::min(chunks, (8L << 20) / ((long)M * N)));
+  const int kchunk = (int)(((K + chunks - 1) / chunks + 31) / 32 * 32);
+  chunks = (K + kchunk - 1) / kchunk;
   double *part = nullptr;
   CGP_HIP(hipMallocAsync((void **)&part, sizeof(double) * (size_t)chunks * M * N, s));
   dim3 grid((N + 63) / 64, (M + 63) / 64, chunks);
@@ -478,6 +482,7 @@ void orthonormalise(int S, int q, std::vector<double> &Y) {
 
 cgp_status guess_initial(cgp_mesh *m, int mode, const double *b, double *x) {
   cgp_guess *g = m->guess;
+  if (g && g->win > 0 && mode == CGP_X0_POD_GALERKIN && !g->pod_ready) return CGP_OK;  // window still filling
   if (!g || !g->pod_ready || (mode != CGP_X0_POD_GALERKIN && !g->trained)) {
     set_error("learned initial guess requested but no trained model is attached");
     return CGP_E_STATE;
@@ -518,11 +523,47 @@ cgp_status guess_initial(cgp_mesh *m, int mode, const double *b, double *x) {
   return CGP_OK;
 }
 
+cgp_status guess_record(cgp_mesh *m, const double *x) {
+  cgp_guess *g = m->guess;
+  if (!g || g->win <= 0) return CGP_OK;
+  CGP_HIP(hipMemcpyAsync(g->d_ring + (size_t)g->head * g->n, x, sizeof(double) * g->n, hipMemcpyDeviceToDevice,
+                         m->stream));
+  g->head = (g->head + 1) % g->win;
+  g->filled = std::min(g->filled + 1, g->win);
+  g->recorded++;
+  if (g->filled >= g->nm && g->recorded % g->refresh == 0) {
+    // the basis of the newest window (slot order does not matter to the POD)
+    cgp_status st = cgp_guess_build_pod(g, g->d_ring, g->filled, nullptr);
+    if (st) return st;
+  }
+  return CGP_OK;
+}
+
 }  // namespace cgp
 
 using namespace cgp;
 
 extern "C" {
+
+cgp_status cgp_guess_set_online(cgp_guess *g, int32_t window, int32_t refresh) {
+  if (!g || window < 0 || (window > 0 && (window < g->nm || window > 1024 || refresh < 1))) {
+    set_error("cgp_guess_set_online: window must be 0 (off) or in n_modes..1024, refresh >= 1");
+    return CGP_E_ARG;
+  }
+  if (window > g->ring_cap) {
+    double *r = nullptr;
+    cgp_status st = galloc(g, &r, (size_t)window * g->n);
+    if (st) return st;
+    g->d_ring = r;
+    g->ring_cap = window;
+  }
+  g->win = window;
+  g->refresh = std::max(1, refresh);
+  g->head = g->filled = 0;
+  g->recorded = 0;
+  if (window > 0) g->pod_ready = false;  // the basis comes from the window from now on
+  return CGP_OK;
+}
 
 cgp_status cgp_guess_create(cgp_mesh *m, const cgp_guess_desc *d, cgp_guess **out) {
   if (!m || !d || !out || m->host_only) {
@@ -692,15 +733,23 @@ cgp_status cgp_guess_build_pod(cgp_guess *g, const double *snaps, int32_t S, dou
   std::vector<int> order(q);
   for (int i = 0; i < q; i++) order[i] = i;
   std::sort(order.begin(), order.end(), [&](int a, int b) { return Bm[(size_t)a * q + a] > Bm[(size_t)b * q + b]; });
-  std::vector<double> Vs((size_t)S * nm);
+  // modes with an eigenvalue at the rounding level of the largest (below 1e-20 of it, or not positive)
+  // are left out: their basis columns are zero and the guesses ignore them.  Small but resolved
+  // eigenvalues stay: their modes carry the slowly converging components the Krylov solver left in
+  // the snapshots, which is what a Galerkin initial guess removes best.
+  std::vector<double> Vs((size_t)S * nm, 0.0);
   g->energy.assign(nm, 0.0);
+  const double lam0 = Bm[(size_t)order[0] * q + order[0]];
+  if (!(lam0 > 0.0) || !std::isfinite(lam0)) {
+    set_error("cgp_guess_build_pod: the snapshots are zero or not finite");
+    return CGP_E_ARG;
+  }
+  int rank = 0;
   for (int k = 0; k < nm; k++) {
     const int c = order[k];
     const double lam = Bm[(size_t)c * q + c];
-    if (!(lam > 0.0)) {
-      set_error("cgp_guess_build_pod: snapshot set has rank below n_modes");
-      return CGP_E_ARG;
-    }
+    if (!(lam > 1e-20 * lam0)) break;
+    rank = k + 1;
     g->energy[k] = lam;
     const double inv = 1.0 / std::sqrt(lam);
     for (int a = 0; a < S; a++) {
@@ -728,31 +777,32 @@ cgp_status cgp_guess_build_pod(cgp_guess *g, const double *snaps, int32_t S, dou
   CGP_HIP(hipFreeAsync(dKP, s));
   CGP_HIP(hipFreeAsync(dPKP, s));
   CGP_HIP(hipStreamSynchronize(s));
-  // inverse by Gauss-Jordan with partial pivoting (the matrix is SPD and tiny)
+  // inverse of the leading rank x rank block by Gauss-Jordan with partial pivoting (SPD and tiny);
+  // rows and columns of the unused modes stay zero
   std::vector<double> inv((size_t)nm * nm, 0.0);
-  for (int i = 0; i < nm; i++) inv[(size_t)i * nm + i] = 1.0;
-  for (int col = 0; col < nm; col++) {
+  for (int i = 0; i < rank; i++) inv[(size_t)i * nm + i] = 1.0;
+  for (int col = 0; col < rank; col++) {
     int piv = col;
-    for (int r = col + 1; r < nm; r++)
+    for (int r = col + 1; r < rank; r++)
       if (std::fabs(Kc[(size_t)r * nm + col]) > std::fabs(Kc[(size_t)piv * nm + col])) piv = r;
     if (Kc[(size_t)piv * nm + col] == 0.0) {
       set_error("cgp_guess_build_pod: Phi^T K Phi is singular");
       return CGP_E_ARG;
     }
-    for (int k = 0; k < nm; k++) {
+    for (int k = 0; k < rank; k++) {
       std::swap(Kc[(size_t)col * nm + k], Kc[(size_t)piv * nm + k]);
       std::swap(inv[(size_t)col * nm + k], inv[(size_t)piv * nm + k]);
     }
     const double d = Kc[(size_t)col * nm + col];
-    for (int k = 0; k < nm; k++) {
+    for (int k = 0; k < rank; k++) {
       Kc[(size_t)col * nm + k] /= d;
       inv[(size_t)col * nm + k] /= d;
     }
-    for (int r = 0; r < nm; r++) {
+    for (int r = 0; r < rank; r++) {
       if (r == col) continue;
       const double f = Kc[(size_t)r * nm + col];
       if (f == 0.0) continue;
-      for (int k = 0; k < nm; k++) {
+      for (int k = 0; k < rank; k++) {
         Kc[(size_t)r * nm + k] -= f * Kc[(size_t)col * nm + k];
         inv[(size_t)r * nm + k] -= f * inv[(size_t)col * nm + k];
       }
@@ -762,6 +812,7 @@ cgp_status cgp_guess_build_pod(cgp_guess *g, const double *snaps, int32_t S, dou
   CGP_HIP(hipStreamSynchronize(s));
   g->pod_ready = true;
   g->trained = false;
+  g->rank = rank;
   return CGP_OK;
 }
 

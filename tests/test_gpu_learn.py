@@ -275,6 +275,42 @@ def test_inference_matches_oracle(env, trajectory, models):
         assert err <= 1e-3
 
 
+def test_online_window_basis(env):
+    """The basis rebuilt from the last solves (a recycled subspace): same flow as the plain path within the
+    Krylov tolerance, far fewer Poisson iterations once the window is full."""
+    torch, cgp, oracle = env
+    case = W.case_cylinder(6000, seed=5)
+    g = cgp.Mesh(case.mesh, 1)
+    g.assemble(case.rho, case.mu, case.dt, cgp._native.RESTRICT_GALERKIN)
+    xy = g.export("xy")
+    u0 = case.initial(xy, g.export("vdir"))
+    steps, window = 60, 16
+    X0 = cgp._native
+    out = {}
+    net = cgp.Guess(g, n_modes=16, hidden=16, seed=1)
+    for name in ("plain", "online"):
+        u = dev(torch, u0.copy())
+        pf = torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda")
+        pc = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
+        if name == "online":
+            net.set_online(window, 1)
+            net.attach()
+        x0 = X0.X0_POD_GALERKIN if name == "online" else X0.X0_PREV
+        opts = cgp.StepOpts(poisson=cgp.SolverOpts(tol=1e-10, x0_mode=x0))
+        its = []
+        for k in range(steps):
+            st = g.step(dev(torch, case.dirichlet(xy, (k + 1) * case.dt)), u, pf, pc, opts=opts)
+            its.append(st["p_iters"])
+        out[name] = (u.cpu().numpy(), pf.cpu().numpy(), float(np.mean(its[window + 4:])))
+    net.detach()
+    net.close()
+    eu, ep = rel(out["online"][0], out["plain"][0]), rel(out["online"][1], out["plain"][1])
+    _say(f"  online window {window}: mean iterations {out['online'][2]:.0f} vs {out['plain'][2]:.0f}; "
+         f"rel diff u {eu:.1e} p {ep:.1e} after {steps} steps")
+    assert eu <= 1e-6 and ep <= 1e-6
+    assert out["online"][2] < 0.7 * out["plain"][2]
+
+
 def test_guess_errors(env, small_mesh):
     torch, cgp, oracle = env
     case, g, o = small_mesh
