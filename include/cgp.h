@@ -270,6 +270,33 @@ cgp_status cgp_guess_export_norm(const cgp_guess *g, double *host, size_t count)
 /* Copy the right-hand side of the last Poisson solve, after boundary conditions (device [n_c]). */
 cgp_status cgp_last_poisson_rhs(const cgp_mesh *mesh, double *dst);
 
+/* ---- many independent simulations on one GPU.  A batch holds meshes that share one stream and have
+ * been assembled (their coarse operators are copied at creation: re-assembling a mesh needs a new
+ * batch).  The coarse Poisson solves (Eq. 21) of all instances run as one Jacobi-PCG over the
+ * concatenated block-diagonal system, one kernel launch per iteration for all instances, each instance
+ * with its own scalars and convergence test; chunks of `chunk` iterations are captured into HIP graphs
+ * (use_graph = 1) and replayed, with one poll per chunk.  The other phases of cgp_batch_step run per
+ * instance as in cgp_step.  Pointer arrays are host arrays of n device pointers. */
+typedef struct cgp_batch cgp_batch;
+typedef struct { int32_t lanes, block, passes, use_graph, chunk; } cgp_batch_tuning;
+cgp_status cgp_batch_create(cgp_mesh *const *meshes, int32_t n, cgp_batch **out);
+void cgp_batch_destroy(cgp_batch *batch);
+/* rhs[i], x[i]: instance i's coarse right-hand side and solution (x: initial guess when x0_mode =
+ * CGP_X0_PREV); FP64 only.  stats: host [n] or NULL (p_iters, p_relres per instance; n_dominant =
+ * iteration launches).  CGP_E_NOCONV when max_iter launches pass before every instance converged. */
+cgp_status cgp_batch_poisson_solve(cgp_batch *batch, const double *const *rhs, double *const *x,
+                                   const cgp_solver_opts *opts, cgp_stats *stats);
+/* One IFE-CGP step of every instance (arguments as cgp_step, one pointer per instance; f may be NULL). */
+cgp_status cgp_batch_step(cgp_batch *batch, const cgp_step_opts *opts, const double *const *g,
+                          const double *const *f, double *const *u, double *const *p_fine, double *const *p_coarse,
+                          cgp_stats *stats);
+cgp_status cgp_batch_get_tuning(const cgp_batch *batch, cgp_batch_tuning *out);
+/* lanes 4/8/16 per row, block a power of two in 64..1024, passes 1..64, chunk even in 2..256. */
+cgp_status cgp_batch_set_tuning(cgp_batch *batch, const cgp_batch_tuning *tuning);
+/* Time 12 launch shapes on the batch's own system and keep the fastest; the choice is cached in the JSON
+ * file cache_path (NULL: no cache) under the batch's size class and reused without timing. */
+cgp_status cgp_batch_autotune(cgp_batch *batch, const char *cache_path, cgp_batch_tuning *chosen);
+
 /* Read or replace the Krylov launch shapes of a mesh (results do not depend on them beyond
  * rounding order).  Invalid knobs return CGP_E_ARG and leave the mesh unchanged. */
 cgp_status cgp_mesh_get_tuning(const cgp_mesh *mesh, cgp_tuning *out);

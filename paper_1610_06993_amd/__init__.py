@@ -9,6 +9,7 @@ memory, ``torch.cuda.current_stream()`` for the stream.  It raises
 """
 from __future__ import annotations
 
-from ._native import (CGPError, Guess, Mesh, SolverOpts, StepOpts, abi_version, lib, library_path)  # noqa: F401
+from ._native import (Batch, CGPError, Guess, Mesh, SolverOpts, StepOpts, abi_version, lib,  # noqa: F401
+                      library_path)
 
-__all__ = ["Mesh", "Guess", "SolverOpts", "StepOpts", "CGPError", "abi_version", "lib", "library_path"]
+__all__ = ["Mesh", "Guess", "Batch", "SolverOpts", "StepOpts", "CGPError", "abi_version", "lib", "library_path"]

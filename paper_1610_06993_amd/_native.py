@@ -85,6 +85,11 @@ class _TrainStats(C.Structure):
     _fields_ = [("loss_first", C.c_double), ("loss_last", C.c_double), ("steps", C.c_int32), ("ms", C.c_float)]
 
 
+class _BatchTuning(C.Structure):
+    _fields_ = [("lanes", C.c_int32), ("block", C.c_int32), ("passes", C.c_int32), ("use_graph", C.c_int32),
+                ("chunk", C.c_int32)]
+
+
 class _Info(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("n_f", "t_f", "n_c", "t_c", "nnz_f", "nnz_c", "ncol_f", "ncol_c", "nb_f",
                                           "nb_c", "levels", "n_pdir")]
@@ -158,11 +163,23 @@ def lib():
     L.cgp_guess_export_norm.argtypes = [vp, vp, C.c_size_t]
     L.cgp_guess_set_online.argtypes = [vp, C.c_int32, C.c_int32]
     L.cgp_last_poisson_rhs.argtypes = [vp, vp]
+    pp = C.POINTER(vp)
+    L.cgp_batch_create.argtypes = [pp, C.c_int32, C.POINTER(vp)]
+    L.cgp_batch_destroy.argtypes = [vp]
+    L.cgp_batch_destroy.restype = None
+    L.cgp_batch_poisson_solve.argtypes = [vp, pp, pp, C.POINTER(_SolverOpts), C.POINTER(_Stats)]
+    L.cgp_batch_step.argtypes = [vp, C.POINTER(_StepOpts), pp, pp, pp, pp, pp, C.POINTER(_Stats)]
+    L.cgp_batch_get_tuning.argtypes = [vp, C.POINTER(_BatchTuning)]
+    L.cgp_batch_set_tuning.argtypes = [vp, C.POINTER(_BatchTuning)]
+    L.cgp_batch_autotune.argtypes = [vp, C.c_char_p, C.POINTER(_BatchTuning)]
     for name in ("cgp_guess_create", "cgp_guess_build_pod", "cgp_guess_train", "cgp_guess_attach", "cgp_guess_predict",
                  "cgp_guess_get_params", "cgp_guess_set_params", "cgp_guess_mlp_grad", "cgp_guess_export_basis",
-                 "cgp_guess_export_norm", "cgp_guess_set_online", "cgp_last_poisson_rhs", "cgp_mesh_get_tuning", "cgp_mesh_set_tuning",
+                 "cgp_guess_export_norm", "cgp_guess_set_online", "cgp_last_poisson_rhs", "cgp_mesh_get_tuning",
+                 "cgp_mesh_set_tuning",
                  "cgp_mesh_create", "cgp_mesh_query", "cgp_mesh_export", "cgp_assemble", "cgp_step", "cgp_momentum",
-                 "cgp_restrict", "cgp_poisson_solve", "cgp_prolong", "cgp_correct", "cgp_spmv"):
+                 "cgp_restrict", "cgp_poisson_solve", "cgp_prolong", "cgp_correct", "cgp_spmv", "cgp_batch_create",
+                 "cgp_batch_poisson_solve", "cgp_batch_step", "cgp_batch_get_tuning", "cgp_batch_set_tuning",
+                 "cgp_batch_autotune"):
         getattr(L, name).restype = C.c_int32
     _lib = L
     return L
@@ -403,3 +420,63 @@ class Guess:
         out = np.zeros((self.mesh.info["n_c"], self.n_modes))
         _check(lib().cgp_guess_export_basis(self._h, out.ctypes.data, out.size))
         return out
+
+
+def _ptrs(ts):
+    arr = (C.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = _ptr(t).value
+    return arr
+
+
+class Batch:
+    """Independent meshes solved together: one batched Poisson PCG per step (include/cgp.h)."""
+
+    def __init__(self, meshes):
+        self.meshes = list(meshes)
+        hs = (C.c_void_p * len(self.meshes))(*[m._h.value for m in self.meshes])
+        h = C.c_void_p()
+        _check(lib().cgp_batch_create(hs, len(self.meshes), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cgp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def poisson_solve(self, rhs, xs, opts: SolverOpts | None = None, allow_noconv=False):
+        o = (opts or SolverOpts()).c()
+        st = (_Stats * len(self.meshes))()
+        s = lib().cgp_batch_poisson_solve(self._h, _ptrs(rhs), _ptrs(xs), C.byref(o), st)
+        _check(s, (OK, E_NOCONV) if allow_noconv else (OK,))
+        return [x.asdict() for x in st]
+
+    def step(self, g, u, p_fine, p_coarse, f=None, opts: StepOpts | None = None, allow_noconv=False):
+        o = (opts or StepOpts()).c()
+        st = (_Stats * len(self.meshes))()
+        s = lib().cgp_batch_step(self._h, C.byref(o), _ptrs(g), _ptrs(f) if f is not None else None, _ptrs(u),
+                                 _ptrs(p_fine), _ptrs(p_coarse), st)
+        _check(s, (OK, E_NOCONV) if allow_noconv else (OK,))
+        return [x.asdict() for x in st]
+
+    def get_tuning(self):
+        t = _BatchTuning()
+        _check(lib().cgp_batch_get_tuning(self._h, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in _BatchTuning._fields_}
+
+    def set_tuning(self, **kw):
+        cur = self.get_tuning()
+        cur.update(kw)
+        t = _BatchTuning(*[cur[k] for k, _ in _BatchTuning._fields_])
+        _check(lib().cgp_batch_set_tuning(self._h, C.byref(t)))
+
+    def autotune(self, cache_path=None):
+        t = _BatchTuning()
+        _check(lib().cgp_batch_autotune(self._h, str(cache_path).encode() if cache_path else None, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in _BatchTuning._fields_}

@@ -1,0 +1,763 @@
+// Many independent CGP simulations on one GPU: the coarse pressure Poisson
+// solves (Eq. 21) of all instances run as one Jacobi-PCG whose every
+// iteration is one kernel launch over all instances' rows.
+//
+// The instances' coarse systems are concatenated (block-diagonal CSR with
+// global int32 indices).  Rows are cut into tiles that never straddle two
+// instances; a block works on one tile and writes one partial per tile, and
+// each instance sums its own tiles' partials in a fixed order, so every
+// instance keeps its own Krylov scalars and convergence flag (a converged
+// instance's tiles return at once).  The iteration is the single-kernel
+// Chronopoulos-Gear form of the single-mesh solver.  Chunks of iterations are
+// captured once into HIP graphs and replayed, with one poll of the instance
+// states per chunk.  Launch shapes (lanes per row, block, rows per lane group)
+// come from cgp_batch_set_tuning or from the autotuner, which times each
+// candidate on the batch's own system and caches the choice in a JSON file.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "devutil.h"
+#include "kernels.h"
+
+struct cgp_batch {
+  std::vector<cgp_mesh *> meshes;
+  hipStream_t mstream = nullptr;     // the meshes' stream
+  hipStream_t stream = nullptr;      // the batch's own stream (graphs are captured on it)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  int ninst = 0;
+  long rows = 0, nnz = 0;
+  std::vector<long> row_off, nnz_off;
+  // concatenated coarse operators
+  int *d_rp = nullptr, *d_col = nullptr;
+  double *d_A = nullptr, *d_dinv = nullptr;
+  // work vectors over all rows
+  double *d_x = nullptr, *d_b = nullptr, *d_p = nullptr, *d_r[2] = {}, *d_w[2] = {}, *d_s[2] = {};
+  // tiles
+  cgp_batch_tuning tune{4, 512, 1, 1, 16};
+  int ntiles = 0;
+  int4 *d_tiles = nullptr;
+  int *d_t0 = nullptr, *d_nt = nullptr;
+  double *d_part = nullptr;           // 4 regions of [3][ntiles]
+  cgp::KrylovState *d_state = nullptr, *h_state = nullptr;
+  // graphs of one chunk starting at iteration 0 and at iteration `chunk`
+  hipGraphExec_t gx[2] = {nullptr, nullptr};
+  std::vector<void *> allocations;
+};
+
+namespace cgp {
+namespace bdev {
+using namespace dev;
+
+// store this block's K sums as P[k * G + t]
+template <int K>
+__device__ __forceinline__ void put_at(const double (&v)[K], double *__restrict__ P, int G, int t) {
+  double tot[K];
+  block_sum<K>(v, tot);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; k++) P[(long)k * G + t] = tot[k];
+  }
+}
+
+// fixed-order totals of K partial arrays over one instance's tiles [t0, t0 + nt)
+template <int K>
+__device__ __forceinline__ void inst_sum(const double *__restrict__ P, int G, int t0, int nt, double (&tot)[K]) {
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nt; b += blockDim.x) s += P[(long)k * G + t0 + b];
+    v[k] = s;
+  }
+  block_sum<K>(v, tot);
+}
+
+__global__ void k_bt_state_init(int ninst, double tol, int maxit, KrylovState *st) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ninst) return;
+  KrylovState s{};
+  s.tol = tol;
+  s.maxit = maxit;
+  s.ncomp = 1;
+  st[i] = s;
+}
+
+// r0 = b - A x, p = s = 0; partial b.b per tile
+template <int L>
+__global__ void __launch_bounds__(kMaxBlock) k_bt_init_r(int G, const int4 *__restrict__ tiles,
+                                                        const int *__restrict__ rp, const int *__restrict__ col,
+                                                        const double *__restrict__ A, const double *__restrict__ b,
+                                                        const double *__restrict__ x, double *__restrict__ r0,
+                                                        double *__restrict__ p, double *__restrict__ s0,
+                                                        double *__restrict__ Pout) {
+  const int t = xcd_block();
+  const int4 T = tiles[t];
+  const int lane = threadIdx.x & (L - 1), groups = blockDim.x / L;
+  double acc[1] = {0.0};
+  for (int row = T.y + (int)threadIdx.x / L; row < T.z; row += groups) {
+    double sum = 0.0;
+    for (int k = rp[row] + lane; k < rp[row + 1]; k += L) sum += A[k] * x[col[k]];
+    sum = group_sum<L>(sum);
+    if (lane == 0) {
+      const double bb = b[row];
+      r0[row] = bb - sum;
+      p[row] = 0.0;
+      s0[row] = 0.0;
+      acc[0] += bb * bb;
+    }
+  }
+  put_at<1>(acc, Pout, G, t);
+}
+
+// w0 = A D^-1 r0; partials (gamma, delta, r.r); publishes ||b|| per instance
+template <int L>
+__global__ void __launch_bounds__(kMaxBlock) k_bt_init_w(int G, const int4 *__restrict__ tiles,
+                                                        const int *__restrict__ t0s, const int *__restrict__ nts,
+                                                        const int *__restrict__ rp, const int *__restrict__ col,
+                                                        const double *__restrict__ A, const double *__restrict__ dinv,
+                                                        const double *__restrict__ r0, double *__restrict__ w0,
+                                                        const double *__restrict__ Pin, double *__restrict__ Pout,
+                                                        KrylovState *__restrict__ st) {
+  const int t = xcd_block();
+  const int4 T = tiles[t];
+  KrylovState *S = st + T.x;
+  const int t0 = t0s[T.x];
+  double tb[1];
+  inst_sum<1>(Pin, G, t0, nts[T.x], tb);
+  if (t == t0 && threadIdx.x == 0) {
+    S->bnorm[0] = sqrt(tb[0]);
+    S->zero_b[0] = (tb[0] == 0.0);
+    if (!is_finite(tb[0])) S->status = CGP_E_NONFINITE;
+  }
+  const int lane = threadIdx.x & (L - 1), groups = blockDim.x / L;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int row = T.y + (int)threadIdx.x / L; row < T.z; row += groups) {
+    double sum = 0.0;
+    for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
+      const int j = col[k];
+      sum += A[k] * (dinv[j] * r0[j]);
+    }
+    sum = group_sum<L>(sum);
+    if (lane == 0) {
+      const double r = r0[row], u = dinv[row] * r;
+      w0[row] = sum;
+      acc[0] += r * u;
+      acc[1] += sum * u;
+      acc[2] += r * r;
+    }
+  }
+  put_at<3>(acc, Pout, G, t);
+}
+
+// One PCG iteration of every unconverged instance (recurrences as in the single-mesh kernel).
+// The first tile's block of each instance publishes its scalars and counts its updates.
+template <int L>
+__global__ void __launch_bounds__(kMaxBlock)
+    k_bt_iter(int it, int G, const int4 *__restrict__ tiles, const int *__restrict__ t0s, const int *__restrict__ nts,
+              const int *__restrict__ rp, const int *__restrict__ col, const double *__restrict__ A,
+              const double *__restrict__ dinv, double *__restrict__ x, double *__restrict__ p,
+              const double *__restrict__ r_cur, const double *__restrict__ w_cur, const double *__restrict__ s_cur,
+              double *__restrict__ r_nxt, double *__restrict__ w_nxt, double *__restrict__ s_nxt,
+              const double *__restrict__ Pin, double *__restrict__ Pout, KrylovState *__restrict__ st) {
+  const int t = xcd_block();
+  const int4 T = tiles[t];
+  KrylovState *S = st + T.x;
+  if (S->status || S->done[0]) return;
+  const int t0 = t0s[T.x];
+  double t3[3];
+  inst_sum<3>(Pin, G, t0, nts[T.x], t3);
+  const double gam = t3[0], del = t3[1], rr = t3[2];
+  const double bb = S->bnorm[0] * S->bnorm[0];
+  const bool done = bb == 0.0 || sqrt(rr) <= S->tol * sqrt(bb);
+  double beta = 0.0, alpha = 0.0;
+  if (it == 0) {
+    alpha = gam / del;
+  } else {
+    beta = gam / S->rz[(it - 1) & 1][0];
+    alpha = gam / (del - beta * gam / S->alpha[(it - 1) & 1][0]);
+  }
+  const bool bad = !is_finite(rr) || (!done && (!is_finite(alpha) || !is_finite(beta)));
+  if (t == t0 && threadIdx.x == 0) {
+    S->rz[it & 1][0] = gam;
+    S->alpha[it & 1][0] = alpha;
+    S->rnorm[0] = sqrt(rr);
+    if (done) S->done[0] = 1;
+    if (bad) S->status = CGP_E_NONFINITE;
+    if (!done && !bad) S->iters += 1;
+  }
+  if (done || bad) return;
+  const int lane = threadIdx.x & (L - 1), groups = blockDim.x / L;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int row = T.y + (int)threadIdx.x / L; row < T.z; row += groups) {
+    double sum = 0.0;
+    for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
+      const int j = col[k];
+      sum += A[k] * (dinv[j] * (r_cur[j] - alpha * (w_cur[j] + beta * s_cur[j])));
+    }
+    sum = group_sum<L>(sum);
+    if (lane == 0) {
+      const double d = dinv[row], rc = r_cur[row], wc = w_cur[row], sc = s_cur[row];
+      const double si = wc + beta * sc;
+      const double pi = d * rc + beta * p[row];
+      const double rn = rc - alpha * si;
+      const double un = d * (rc - alpha * (wc + beta * sc));
+      x[row] += alpha * pi;
+      p[row] = pi;
+      s_nxt[row] = si;
+      r_nxt[row] = rn;
+      w_nxt[row] = sum;
+      acc[0] += rn * un;
+      acc[1] += sum * un;
+      acc[2] += rn * rn;
+    }
+  }
+  put_at<3>(acc, Pout, G, t);
+}
+
+// after a chunk (one block per instance): convergence from the last iteration's partials
+__global__ void __launch_bounds__(256) k_bt_finish(int G, const int *__restrict__ t0s, const int *__restrict__ nts,
+                                                   const double *__restrict__ Pin, KrylovState *__restrict__ st) {
+  KrylovState *S = st + blockIdx.x;
+  if (S->status || S->done[0]) return;
+  double t3[3];
+  inst_sum<3>(Pin, G, t0s[blockIdx.x], nts[blockIdx.x], t3);
+  if (threadIdx.x != 0) return;
+  const double rn = sqrt(t3[2]);
+  S->rnorm[0] = rn;
+  if (!is_finite(rn)) S->status = CGP_E_NONFINITE;
+  else if (rn <= S->tol * S->bnorm[0]) S->done[0] = 1;
+}
+
+// instances with a zero right-hand side get x = 0
+__global__ void k_bt_zero_b(const int4 *__restrict__ tiles, const KrylovState *__restrict__ st,
+                            double *__restrict__ x) {
+  const int4 T = tiles[blockIdx.x];
+  if (!st[T.x].zero_b[0]) return;
+  for (int row = T.y + (int)threadIdx.x; row < T.z; row += blockDim.x) x[row] = 0.0;
+}
+
+// synthetic right-hand side for the autotuner: a hash of the row index in [-1, 1)
+__global__ void k_bt_fill(long n, double *__restrict__ b, double *__restrict__ x) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  unsigned long long z = (unsigned long long)i * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  b[i] = double(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  x[i] = 0.0;
+}
+
+}  // namespace bdev
+
+namespace {
+using namespace bdev;
+
+template <typename T>
+cgp_status balloc(cgp_batch *B, T **p, size_t count) {
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) {
+    set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? CGP_E_OOM : CGP_E_DEVICE;
+  }
+  B->allocations.push_back(q);
+  *p = static_cast<T *>(q);
+  return CGP_OK;
+}
+
+#define BTRY(x)                  \
+  do {                           \
+    cgp_status s_ = (x);         \
+    if (s_ != CGP_OK) return s_; \
+  } while (0)
+
+enum { B_INIT = 0, B_A = 1, B_B = 2, B_C = 3 };
+double *bregion(cgp_batch *B, int k) { return B->d_part + (size_t)k * 3 * B->ntiles; }
+double *bpin(cgp_batch *B, int it) { return it == 0 ? bregion(B, B_A) : bregion(B, ((it - 1) & 1) ? B_C : B_B); }
+double *bpout(cgp_batch *B, int it) { return bregion(B, (it & 1) ? B_C : B_B); }
+
+void drop_graphs(cgp_batch *B) {
+  for (auto &g : B->gx)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+// tiles of `per` rows that never straddle instances; (re)allocates tile-sized buffers
+cgp_status build_tiles(cgp_batch *B) {
+  const cgp_batch_tuning &t = B->tune;
+  const int per = t.block * t.passes / t.lanes;
+  std::vector<int4> tiles;
+  std::vector<int> t0(B->ninst), nt(B->ninst);
+  for (int i = 0; i < B->ninst; i++) {
+    t0[i] = (int)tiles.size();
+    for (long r = B->row_off[i]; r < B->row_off[i + 1]; r += per)
+      tiles.push_back(make_int4(i, (int)r, (int)std::min<long>(r + per, B->row_off[i + 1]), 0));
+    nt[i] = (int)tiles.size() - t0[i];
+  }
+  // pad to a multiple of 8 with empty tiles of the last instance (rows [end, end)), so that the XCD
+  // remapping applies; they contribute zero partials
+  const int last = B->ninst - 1;
+  while (tiles.size() % 8) {
+    const int e = (int)B->row_off[B->ninst];
+    tiles.push_back(make_int4(last, e, e, 0));
+    nt[last]++;
+  }
+  if ((int)tiles.size() > B->ntiles) {
+    BTRY(balloc(B, &B->d_tiles, tiles.size()));
+    BTRY(balloc(B, &B->d_part, 4 * 3 * tiles.size()));
+  }
+  B->ntiles = (int)tiles.size();
+  CGP_HIP(hipMemcpyAsync(B->d_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, B->stream));
+  CGP_HIP(hipMemcpyAsync(B->d_t0, t0.data(), sizeof(int) * B->ninst, hipMemcpyHostToDevice, B->stream));
+  CGP_HIP(hipMemcpyAsync(B->d_nt, nt.data(), sizeof(int) * B->ninst, hipMemcpyHostToDevice, B->stream));
+  CGP_HIP(hipStreamSynchronize(B->stream));
+  drop_graphs(B);
+  return CGP_OK;
+}
+
+// enqueue `count` iterations starting at `it0`, then the chunk's convergence check
+void enqueue_chunk(cgp_batch *B, int it0, int count) {
+  const int G = B->ntiles, blk = B->tune.block;
+  hipStream_t s = B->stream;
+  dispatch_L(B->tune.lanes, [&](auto LC) {
+    constexpr int LL = decltype(LC)::value;
+    for (int it = it0; it < it0 + count; it++) {
+      const int cur = it & 1, nxt = cur ^ 1;
+      hipLaunchKernelGGL((k_bt_iter<LL>), dim3(G), dim3(blk), 0, s, it, G, (const int4 *)B->d_tiles,
+                         (const int *)B->d_t0, (const int *)B->d_nt, (const int *)B->d_rp, (const int *)B->d_col,
+                         (const double *)B->d_A, (const double *)B->d_dinv, B->d_x, B->d_p,
+                         (const double *)B->d_r[cur], (const double *)B->d_w[cur], (const double *)B->d_s[cur],
+                         B->d_r[nxt], B->d_w[nxt], B->d_s[nxt], (const double *)bpin(B, it), bpout(B, it),
+                         B->d_state);
+    }
+  });
+  hipLaunchKernelGGL(k_bt_finish, dim3(B->ninst), dim3(256), 0, s, G, (const int *)B->d_t0, (const int *)B->d_nt,
+                     (const double *)bpin(B, it0 + count), B->d_state);
+}
+
+cgp_status run_chunk(cgp_batch *B, int which) {
+  const int K = B->tune.chunk;
+  const int it0 = which == 0 ? 0 : K;
+  if (!B->tune.use_graph) {
+    enqueue_chunk(B, it0, K);
+    CGP_HIP(hipGetLastError());
+    return CGP_OK;
+  }
+  if (!B->gx[which]) {
+    hipGraph_t g = nullptr;
+    CGP_HIP(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
+    enqueue_chunk(B, it0, K);
+    CGP_HIP(hipStreamEndCapture(B->stream, &g));
+    hipError_t e = hipGraphInstantiate(&B->gx[which], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      B->gx[which] = nullptr;
+      set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      return CGP_E_DEVICE;
+    }
+  }
+  CGP_HIP(hipGraphLaunch(B->gx[which], B->stream));
+  return CGP_OK;
+}
+
+cgp_status poll_states(cgp_batch *B, bool *all_done, int *bad) {
+  CGP_HIP(hipMemcpyAsync(B->h_state, B->d_state, sizeof(KrylovState) * B->ninst, hipMemcpyDeviceToHost, B->stream));
+  CGP_HIP(hipStreamSynchronize(B->stream));
+  *all_done = true;
+  *bad = -1;
+  for (int i = 0; i < B->ninst; i++) {
+    if (B->h_state[i].status && *bad < 0) *bad = i;
+    if (!B->h_state[i].done[0]) *all_done = false;
+  }
+  return CGP_OK;
+}
+
+// the PCG on the concatenated system, from b, x already in place; returns iterations launched
+cgp_status solve(cgp_batch *B, double tol, int maxit, int *launched) {
+  hipStream_t s = B->stream;
+  const int G = B->ntiles, blk = B->tune.block;
+  hipLaunchKernelGGL(k_bt_state_init, dim3((B->ninst + 255) / 256), dim3(256), 0, s, B->ninst, tol, maxit,
+                     B->d_state);
+  dispatch_L(B->tune.lanes, [&](auto LC) {
+    constexpr int LL = decltype(LC)::value;
+    hipLaunchKernelGGL((k_bt_init_r<LL>), dim3(G), dim3(blk), 0, s, G, (const int4 *)B->d_tiles,
+                       (const int *)B->d_rp, (const int *)B->d_col, (const double *)B->d_A, (const double *)B->d_b,
+                       (const double *)B->d_x, B->d_r[0], B->d_p, B->d_s[0], bregion(B, B_INIT));
+    hipLaunchKernelGGL((k_bt_init_w<LL>), dim3(G), dim3(blk), 0, s, G, (const int4 *)B->d_tiles,
+                       (const int *)B->d_t0, (const int *)B->d_nt, (const int *)B->d_rp, (const int *)B->d_col,
+                       (const double *)B->d_A, (const double *)B->d_dinv, (const double *)B->d_r[0], B->d_w[0],
+                       (const double *)bregion(B, B_INIT), bregion(B, B_A), B->d_state);
+  });
+  CGP_HIP(hipGetLastError());
+  const int K = B->tune.chunk;
+  int n = 0;
+  bool all = false;
+  int bad = -1;
+  for (int c = 0; n < maxit; c++) {
+    BTRY(run_chunk(B, c == 0 ? 0 : 1));
+    n += K;
+    BTRY(poll_states(B, &all, &bad));
+    if (all || bad >= 0) break;
+  }
+  hipLaunchKernelGGL(k_bt_zero_b, dim3(G), dim3(256), 0, s, (const int4 *)B->d_tiles,
+                     (const KrylovState *)B->d_state, B->d_x);
+  CGP_HIP(hipGetLastError());
+  *launched = n;
+  if (bad >= 0) {
+    set_error("batched Poisson PCG: instance " + std::to_string(bad) + " produced a non-finite residual");
+    return CGP_E_NONFINITE;
+  }
+  if (!all) {
+    set_error("batched Poisson PCG: iteration limit reached before every instance converged");
+    return CGP_E_NOCONV;
+  }
+  return CGP_OK;
+}
+
+}  // namespace
+}  // namespace cgp
+
+using namespace cgp;
+
+extern "C" {
+
+void cgp_batch_destroy(cgp_batch *B) {
+  if (!B) return;
+  if (B->stream) (void)hipStreamSynchronize(B->stream);
+  drop_graphs(B);
+  for (void *p : B->allocations) (void)hipFree(p);
+  if (B->h_state) (void)hipHostFree(B->h_state);
+  if (B->ev_in) (void)hipEventDestroy(B->ev_in);
+  if (B->ev_out) (void)hipEventDestroy(B->ev_out);
+  if (B->stream) (void)hipStreamDestroy(B->stream);
+  delete B;
+}
+
+cgp_status cgp_batch_create(cgp_mesh *const *meshes, int32_t n, cgp_batch **out) {
+  if (!meshes || !out || n < 1) {
+    set_error("cgp_batch_create: need at least one mesh");
+    return CGP_E_ARG;
+  }
+  long rows = 0, nnz = 0;
+  for (int i = 0; i < n; i++) {
+    cgp_mesh *m = meshes[i];
+    if (!m || m->host_only || !m->assembled) {
+      set_error("cgp_batch_create: every mesh must be a device mesh that has been assembled");
+      return CGP_E_STATE;
+    }
+    if (m->stream != meshes[0]->stream) {
+      set_error("cgp_batch_create: all meshes must use the same stream");
+      return CGP_E_ARG;
+    }
+    rows += m->pc.n;
+    nnz += m->pc.nnz;
+  }
+  if (nnz >= (1L << 31) - 1) {
+    set_error("cgp_batch_create: more than 2^31 coarse nonzeros in total");
+    return CGP_E_ARG;
+  }
+  cgp_batch *B = new cgp_batch();
+  auto fail = [&](cgp_status st) {
+    std::string msg = cgp_last_error();
+    cgp_batch_destroy(B);
+    set_error(msg);
+    return st;
+  };
+  B->meshes.assign(meshes, meshes + n);
+  B->ninst = n;
+  B->rows = rows;
+  B->nnz = nnz;
+  B->mstream = meshes[0]->stream;
+  if (hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming) != hipSuccess) {
+    set_error("cgp_batch_create: stream or event creation failed");
+    return fail(CGP_E_DEVICE);
+  }
+  cgp_status st;
+  if ((st = balloc(B, &B->d_rp, rows + 1)) || (st = balloc(B, &B->d_col, nnz)) || (st = balloc(B, &B->d_A, nnz)) ||
+      (st = balloc(B, &B->d_dinv, rows)) || (st = balloc(B, &B->d_x, rows)) || (st = balloc(B, &B->d_b, rows)) ||
+      (st = balloc(B, &B->d_p, rows)) || (st = balloc(B, &B->d_r[0], rows)) || (st = balloc(B, &B->d_r[1], rows)) ||
+      (st = balloc(B, &B->d_w[0], rows)) || (st = balloc(B, &B->d_w[1], rows)) ||
+      (st = balloc(B, &B->d_s[0], rows)) || (st = balloc(B, &B->d_s[1], rows)) ||
+      (st = balloc(B, &B->d_t0, n)) || (st = balloc(B, &B->d_nt, n)) || (st = balloc(B, &B->d_state, n)))
+    return fail(st);
+  if (hipHostMalloc((void **)&B->h_state, sizeof(KrylovState) * n, hipHostMallocDefault) != hipSuccess) {
+    set_error("cgp_batch_create: pinned allocation failed");
+    return fail(CGP_E_OOM);
+  }
+  // concatenated CSR with global indices; values copied from each mesh's coarse operator
+  std::vector<int> rp(rows + 1), col(nnz);
+  B->row_off.assign(n + 1, 0);
+  B->nnz_off.assign(n + 1, 0);
+  for (int i = 0; i < n; i++) {
+    const HostCSR &c = meshes[i]->pc;
+    const long r0 = B->row_off[i], z0 = B->nnz_off[i];
+    for (int r = 0; r < c.n; r++) rp[r0 + r] = (int)(z0 + c.rp[r]);
+    for (int k = 0; k < c.nnz; k++) col[z0 + k] = (int)(r0 + c.col[k]);
+    B->row_off[i + 1] = r0 + c.n;
+    B->nnz_off[i + 1] = z0 + c.nnz;
+  }
+  rp[rows] = (int)nnz;
+  if (hipMemcpy(B->d_rp, rp.data(), sizeof(int) * rp.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(B->d_col, col.data(), sizeof(int) * col.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("cgp_batch_create: upload failed");
+    return fail(CGP_E_DEVICE);
+  }
+  if (hipStreamSynchronize(B->mstream) != hipSuccess) {
+    set_error("cgp_batch_create: mesh stream failed");
+    return fail(CGP_E_DEVICE);
+  }
+  for (int i = 0; i < n; i++) {
+    cgp_mesh *m = meshes[i];
+    if (hipMemcpyAsync(B->d_A + B->nnz_off[i], m->d_Kbc, sizeof(double) * m->pc.nnz, hipMemcpyDeviceToDevice,
+                       B->stream) != hipSuccess ||
+        hipMemcpyAsync(B->d_dinv + B->row_off[i], m->d_dinvK, sizeof(double) * m->pc.n, hipMemcpyDeviceToDevice,
+                       B->stream) != hipSuccess) {
+      set_error("cgp_batch_create: operator copy failed");
+      return fail(CGP_E_DEVICE);
+    }
+  }
+  if ((st = build_tiles(B))) return fail(st);
+  *out = B;
+  return CGP_OK;
+}
+
+cgp_status cgp_batch_get_tuning(const cgp_batch *B, cgp_batch_tuning *out) {
+  if (!B || !out) {
+    set_error("cgp_batch_get_tuning: null argument");
+    return CGP_E_ARG;
+  }
+  *out = B->tune;
+  return CGP_OK;
+}
+
+cgp_status cgp_batch_set_tuning(cgp_batch *B, const cgp_batch_tuning *t) {
+  if (!B || !t || (t->lanes != 4 && t->lanes != 8 && t->lanes != 16) || t->block < 64 || t->block > 1024 ||
+      (t->block & (t->block - 1)) || t->passes < 1 || t->passes > 64 || t->chunk < 2 || t->chunk > 256 ||
+      (t->chunk & 1) || (t->use_graph != 0 && t->use_graph != 1)) {
+    set_error("cgp_batch_set_tuning: lanes 4/8/16, block a power of two in 64..1024, passes 1..64, "
+              "chunk even in 2..256, use_graph 0/1");
+    return CGP_E_ARG;
+  }
+  const bool shape = t->lanes != B->tune.lanes || t->block != B->tune.block || t->passes != B->tune.passes;
+  const bool chunk = t->chunk != B->tune.chunk || t->use_graph != B->tune.use_graph;
+  B->tune = *t;
+  if (shape) return build_tiles(B);
+  if (chunk) drop_graphs(B);
+  return CGP_OK;
+}
+
+cgp_status cgp_batch_poisson_solve(cgp_batch *B, const double *const *rhs, double *const *x,
+                                   const cgp_solver_opts *o, cgp_stats *stats) {
+  if (!B || !rhs || !x || !o || !(o->tol > 0.0) || o->max_iter < 1 || o->precision != CGP_PREC_FP64 ||
+      (o->x0_mode != CGP_X0_ZERO && o->x0_mode != CGP_X0_PREV)) {
+    set_error("cgp_batch_poisson_solve: bad argument (FP64, x0 zero or previous)");
+    return CGP_E_ARG;
+  }
+  for (int i = 0; i < B->ninst; i++)
+    if (!rhs[i] || !x[i]) {
+      set_error("cgp_batch_poisson_solve: null vector");
+      return CGP_E_ARG;
+    }
+  // gather on the meshes' stream, with each instance's boundary conditions (as in the single solve)
+  hipStream_t ms = B->mstream;
+  for (int i = 0; i < B->ninst; i++) {
+    cgp_mesh *m = B->meshes[i];
+    const long off = B->row_off[i];
+    const size_t bytes = sizeof(double) * m->pc.n;
+    CGP_HIP(hipMemcpyAsync(B->d_b + off, rhs[i], bytes, hipMemcpyDeviceToDevice, ms));
+    if (o->x0_mode == CGP_X0_ZERO) CGP_HIP(hipMemsetAsync(B->d_x + off, 0, bytes, ms));
+    else CGP_HIP(hipMemcpyAsync(B->d_x + off, x[i], bytes, hipMemcpyDeviceToDevice, ms));
+    if (m->n_pdir > 0) launch_pdir_zero(m, B->d_b + off, B->d_x + off);
+    else launch_mean_shift(m, B->d_b + off, nullptr, double(m->pc.n), m->red.partials);
+  }
+  CGP_HIP(hipGetLastError());
+  CGP_HIP(hipEventRecord(B->ev_in, ms));
+  CGP_HIP(hipStreamWaitEvent(B->stream, B->ev_in, 0));
+  int launched = 0;
+  const auto t0 = std::chrono::steady_clock::now();
+  cgp_status rs = solve(B, o->tol, o->max_iter, &launched);
+  const double ms_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (rs != CGP_OK && rs != CGP_E_NOCONV) return rs;
+  CGP_HIP(hipEventRecord(B->ev_out, B->stream));
+  CGP_HIP(hipStreamWaitEvent(ms, B->ev_out, 0));
+  for (int i = 0; i < B->ninst; i++) {
+    cgp_mesh *m = B->meshes[i];
+    const long off = B->row_off[i];
+    if (m->n_pdir == 0) launch_mean_shift(m, B->d_x + off, m->d_mc, m->mc_sum, m->red.partials);
+    CGP_HIP(hipMemcpyAsync(x[i], B->d_x + off, sizeof(double) * m->pc.n, hipMemcpyDeviceToDevice, ms));
+  }
+  CGP_HIP(hipGetLastError());
+  if (stats)
+    for (int i = 0; i < B->ninst; i++) {
+      const KrylovState &h = B->h_state[i];
+      stats[i] = cgp_stats{};
+      stats[i].p_iters = h.iters;
+      stats[i].p_outer = 1;
+      stats[i].p_relres = h.bnorm[0] > 0 ? h.rnorm[0] / h.bnorm[0] : 0.0;
+      stats[i].ms_poisson = (float)ms_solve;
+      stats[i].n_dominant = launched;  // launches of the batched iteration kernel (all instances)
+    }
+  return rs;
+}
+
+cgp_status cgp_batch_step(cgp_batch *B, const cgp_step_opts *o, const double *const *g, const double *const *f,
+                          double *const *u, double *const *pf, double *const *pc, cgp_stats *stats) {
+  if (!B || !o || !g || !u || !pf || !pc) {
+    set_error("cgp_batch_step: null argument");
+    return CGP_E_ARG;
+  }
+  const int n = B->ninst;
+  std::vector<cgp_stats> S(n);
+  std::vector<const double *> bc(n);
+  cgp_status worst = CGP_OK;
+  auto note = [&](cgp_status s) {
+    if (s == CGP_E_NOCONV && worst == CGP_OK) worst = s;
+    return s == CGP_OK || s == CGP_E_NOCONV;
+  };
+  // steps 1-2 (Eqs. 19-21) per instance
+  for (int i = 0; i < n; i++) {
+    cgp_mesh *m = B->meshes[i];
+    cgp_status s = drv_momentum(m, &o->momentum, g[i], f ? f[i] : nullptr, u[i], m->d_ut, &S[i]);
+    if (!note(s)) return s;
+    s = drv_restrict(m, m->d_ut, m->d_bc);
+    if (!note(s)) return s;
+    bc[i] = m->d_bc;
+  }
+  // step 3 (Eq. 21): every instance's Poisson solve in one PCG
+  std::vector<cgp_stats> P(n);
+  cgp_status s = cgp_batch_poisson_solve(B, bc.data(), pc, &o->poisson, P.data());
+  if (!note(s)) return s;
+  // steps 4-5 (Eqs. 22-23) per instance
+  for (int i = 0; i < n; i++) {
+    cgp_mesh *m = B->meshes[i];
+    s = drv_prolong(m, pc[i], pf[i]);
+    if (!note(s)) return s;
+    s = drv_correct(m, &o->mass, g[i], m->d_ut, pf[i], u[i], &S[i]);
+    if (!note(s)) return s;
+    S[i].p_iters = P[i].p_iters;
+    S[i].p_outer = P[i].p_outer;
+    S[i].p_relres = P[i].p_relres;
+    S[i].ms_poisson = P[i].ms_poisson;
+    S[i].n_dominant = P[i].n_dominant;
+  }
+  CGP_HIP(hipStreamSynchronize(B->mstream));
+  if (stats) std::copy(S.begin(), S.end(), stats);
+  return worst;
+}
+
+// Time `iters` iterations of each candidate shape on a synthetic right-hand side (tolerance 0, so no
+// instance converges) and keep the fastest.  The choice is cached in `cache_path` (JSON, one entry per
+// batch size class: rows and nonzeros rounded to two significant digits) and reused when present.
+cgp_status cgp_batch_autotune(cgp_batch *B, const char *cache_path, cgp_batch_tuning *chosen) {
+  if (!B) {
+    set_error("cgp_batch_autotune: null batch");
+    return CGP_E_ARG;
+  }
+  auto round2 = [](long v) {
+    long p = 1;
+    while (v >= 100 * p) p *= 10;
+    return (v + p / 2) / p * p;
+  };
+  char key[96];
+  std::snprintf(key, sizeof(key), "rows%ld_nnz%ld_inst%d", round2(B->rows), round2(B->nnz), B->ninst);
+  // cache lookup: lines of the form  "key": {"lanes": L, "block": B, "passes": P, ...}
+  std::string text;
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::stringstream ss;
+    ss << in.rdbuf();
+    text = ss.str();
+    const std::string needle = std::string("\"") + key + "\"";
+    const size_t at = text.find(needle);
+    if (at != std::string::npos) {
+      cgp_batch_tuning t = B->tune;
+      if (std::sscanf(text.c_str() + at + needle.size(), ": {\"lanes\": %d, \"block\": %d, \"passes\": %d", &t.lanes,
+                      &t.block, &t.passes) == 3) {
+        BTRY(cgp_batch_set_tuning(B, &t));
+        if (chosen) *chosen = B->tune;
+        return CGP_OK;
+      }
+    }
+  }
+  const cgp_batch_tuning keep = B->tune;
+  const int lanes[2] = {4, 8}, blocks[3] = {256, 512, 1024}, passes[2] = {1, 2};
+  cgp_batch_tuning best = keep;
+  double best_us = 1e30;
+  std::string table;
+  hipEvent_t e0, e1;
+  CGP_HIP(hipEventCreate(&e0));
+  CGP_HIP(hipEventCreate(&e1));
+  for (int L : lanes)
+    for (int blk : blocks)
+      for (int ps : passes) {
+        cgp_batch_tuning t = keep;
+        t.lanes = L;
+        t.block = blk;
+        t.passes = ps;
+        t.use_graph = 1;
+        t.chunk = 16;
+        BTRY(cgp_batch_set_tuning(B, &t));
+        double us = 0.0;
+        for (int rep = 0; rep < 2; rep++) {  // the first repetition also captures the graphs
+          hipLaunchKernelGGL(k_bt_fill, dim3((B->rows + 255) / 256), dim3(256), 0, B->stream, B->rows, B->d_b,
+                             B->d_x);
+          int launched = 0;
+          CGP_HIP(hipEventRecord(e0, B->stream));
+          cgp_status s = solve(B, 0.0, 64, &launched);
+          CGP_HIP(hipEventRecord(e1, B->stream));
+          if (s != CGP_OK && s != CGP_E_NOCONV) return s;
+          CGP_HIP(hipEventSynchronize(e1));
+          float ms = 0.0f;
+          CGP_HIP(hipEventElapsedTime(&ms, e0, e1));
+          us = 1e3 * ms / launched;
+        }
+        char line[160];
+        std::snprintf(line, sizeof(line), "%s{\"lanes\": %d, \"block\": %d, \"passes\": %d, \"us_per_iteration\": %.3f}",
+                      table.empty() ? "" : ", ", L, blk, ps, us);
+        table += line;
+        if (us < best_us) {
+          best_us = us;
+          best = t;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  best.use_graph = keep.use_graph;
+  best.chunk = keep.chunk;
+  BTRY(cgp_batch_set_tuning(B, &best));
+  if (chosen) *chosen = B->tune;
+  if (cache_path) {
+    char head[256];
+    std::snprintf(head, sizeof(head), "\"%s\": {\"lanes\": %d, \"block\": %d, \"passes\": %d, \"us_per_iteration\": %.3f, ",
+                  key, best.lanes, best.block, best.passes, best_us);
+    const std::string entry = std::string(head) + "\"candidates\": [" + table + "]}";
+    // append the entry to the JSON object (the file holds one object of entries and a log of timings)
+    std::string body = text;
+    const size_t close = body.rfind('}');
+    if (body.empty() || close == std::string::npos) body = std::string("{\n  ") + entry + "\n}\n";
+    else body = body.substr(0, close) + (body.find('"') != std::string::npos ? ",\n  " : "  ") + entry + "\n}\n";
+    std::ofstream out(cache_path, std::ios::trunc);
+    out << body;
+    if (!out) {
+      set_error(std::string("cgp_batch_autotune: cannot write ") + cache_path);
+      return CGP_E_ARG;
+    }
+  }
+  return CGP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,173 @@
+"""Batched multi-instance solves (one PCG launch per iteration for all instances)
+against the oracle and against the single-instance path; graph replay against
+eager launches; the autotuner's cache."""
+import json
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TIGHT = 1e-13
+
+
+def _say(*a):
+    print("[gpu-test]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import oracle
+    import paper_1610_06993_amd as cgp
+    cgp.lib()
+    oracle.lib()
+    return torch, cgp, oracle
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0)
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+# uneven instances: cylinders of different sizes and seeds, a backward-facing step, and a pure-Neumann
+# Taylor-Green square (no pressure-Dirichlet node)
+CASES = [lambda: W.case_cylinder(2500, seed=11), lambda: W.case_cylinder(9000, seed=12),
+         lambda: W.case_bfs(nx=50, ny=8), lambda: W.case_tg(n=12), lambda: W.case_cylinder(4000, seed=13)]
+
+
+@pytest.fixture(scope="module")
+def instances(env):
+    torch, cgp, oracle = env
+    out = []
+    for make in CASES:
+        case = make()
+        g = cgp.Mesh(case.mesh, 1)
+        g.assemble(case.rho, case.mu, case.dt)
+        o = oracle.Problem(case.mesh, 1)
+        o.assemble(case.rho, case.mu, case.dt, 0, 0)
+        out.append((case, g, o))
+    _say("instances (coarse nodes):", [g.info["n_c"] for _, g, _ in out])
+    return out
+
+
+def _rhs(instances, seed):
+    rng = np.random.default_rng(seed)
+    return [rng.normal(size=g.info["n_c"]) for _, g, _ in instances]
+
+
+def test_batch_poisson_matches_oracle(env, instances):
+    torch, cgp, oracle = env
+    batch = cgp.Batch([g for _, g, _ in instances])
+    bs = _rhs(instances, 1)
+    xs = [torch.zeros(len(b), dtype=torch.float64, device="cuda") for b in bs]
+    st = batch.poisson_solve([dev(torch, b) for b in bs], xs, cgp.SolverOpts(tol=TIGHT, max_iter=100000,
+                                                                             x0_mode=cgp._native.X0_ZERO))
+    for (case, g, o), b, x, s in zip(instances, bs, xs, st):
+        ref, code, its, rr = o.poisson_solve(b, tol=1e-14)
+        err = rel(x.cpu().numpy(), ref)
+        _say(f"  n_c {len(b)}: batch iterations {s['p_iters']}, oracle {its}, rel err {err:.2e}")
+        assert code == 0 and s["p_iters"] > 0 and s["p_relres"] <= TIGHT * 1.0001
+        assert err <= 1e-10
+    batch.close()
+
+
+def test_batch_equals_single_instance_solves(env, instances):
+    """Same kernels' arithmetic per instance: the batch and the single-mesh solver agree to rounding."""
+    torch, cgp, oracle = env
+    batch = cgp.Batch([g for _, g, _ in instances])
+    bs = _rhs(instances, 2)
+    opts = cgp.SolverOpts(tol=1e-10, max_iter=100000, x0_mode=cgp._native.X0_ZERO)
+    xs = [torch.zeros(len(b), dtype=torch.float64, device="cuda") for b in bs]
+    st = batch.poisson_solve([dev(torch, b) for b in bs], xs, opts)
+    for (case, g, o), b, x, s in zip(instances, bs, xs, st):
+        y = torch.zeros_like(x)
+        s1 = g.poisson_solve(dev(torch, b), y, opts)
+        assert abs(s1["p_iters"] - s["p_iters"]) <= 2, (s1["p_iters"], s["p_iters"])
+        assert rel(x.cpu().numpy(), y.cpu().numpy()) <= 1e-8
+    batch.close()
+
+
+def test_graph_replays_equal_eager(env, instances):
+    torch, cgp, oracle = env
+    batch = cgp.Batch([g for _, g, _ in instances])
+    bs = [dev(torch, b) for b in _rhs(instances, 3)]
+    opts = cgp.SolverOpts(tol=1e-11, max_iter=100000, x0_mode=cgp._native.X0_ZERO)
+
+    def run():
+        xs = [torch.zeros(b.shape[0], dtype=torch.float64, device="cuda") for b in bs]
+        st = batch.poisson_solve(bs, xs, opts)
+        torch.cuda.synchronize()
+        return [x.cpu().numpy() for x in xs], [s["p_iters"] for s in st]
+
+    batch.set_tuning(use_graph=0)
+    ref, its = run()
+    batch.set_tuning(use_graph=1)
+    for rep in range(3):
+        _ = torch.ones(1000, device="cuda").sum().item()  # eager work between the replays
+        got, its2 = run()
+        assert its2 == its
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), rep
+    batch.close()
+
+
+def test_batch_step_matches_single_steps(env, instances):
+    torch, cgp, oracle = env
+    sub = [instances[0], instances[2], instances[4]]
+    opts = cgp.StepOpts(momentum=cgp.SolverOpts(tol=TIGHT, max_iter=100000),
+                        poisson=cgp.SolverOpts(tol=1e-14, max_iter=100000),
+                        mass=cgp.SolverOpts(tol=TIGHT, max_iter=100000))
+    states = {}
+    for mode in ("batch", "single"):
+        us, pfs, pcs, gds = [], [], [], []
+        for case, g, o in sub:
+            xy = g.export("xy")
+            us.append(dev(torch, case.initial(xy, g.export("vdir"))))
+            pfs.append(torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda"))
+            pcs.append(torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda"))
+        batch = cgp.Batch([g for _, g, _ in sub]) if mode == "batch" else None
+        for k in range(3):
+            gds = [dev(torch, case.dirichlet(g.export("xy"), (k + 1) * case.dt)) for case, g, _ in sub]
+            if batch:
+                batch.step(gds, us, pfs, pcs, opts=opts)
+            else:
+                for (case, g, o), gd, u, pf, pc in zip(sub, gds, us, pfs, pcs):
+                    g.step(gd, u, pf, pc, opts=opts)
+        if batch:
+            batch.close()
+        states[mode] = [(u.cpu().numpy(), pf.cpu().numpy()) for u, pf in zip(us, pfs)]
+    for (ub, pb), (us_, ps) in zip(states["batch"], states["single"]):
+        assert rel(ub, us_) <= 1e-10 and rel(pb, ps) <= 1e-10
+
+
+def test_autotune_cache(env, instances, tmp_path):
+    torch, cgp, oracle = env
+    batch = cgp.Batch([g for _, g, _ in instances])
+    cache = tmp_path / "tune.json"
+    chosen = batch.autotune(cache)
+    _say("  autotuned:", chosen)
+    data = json.loads(cache.read_text())
+    assert len(data) == 1
+    entry = next(iter(data.values()))
+    assert {"lanes", "block", "passes", "candidates"} <= set(entry) and len(entry["candidates"]) == 12
+    assert (entry["lanes"], entry["block"], entry["passes"]) == (chosen["lanes"], chosen["block"], chosen["passes"])
+    batch.set_tuning(lanes=16, block=64, passes=3)
+    again = batch.autotune(cache)   # from the cache: same choice, no timing
+    assert (again["lanes"], again["block"], again["passes"]) == (chosen["lanes"], chosen["block"], chosen["passes"])
+    # the tuned batch still solves correctly
+    bs = _rhs(instances, 4)
+    xs = [torch.zeros(len(b), dtype=torch.float64, device="cuda") for b in bs]
+    batch.poisson_solve([dev(torch, b) for b in bs], xs, cgp.SolverOpts(tol=TIGHT, max_iter=100000,
+                                                                        x0_mode=cgp._native.X0_ZERO))
+    for (case, g, o), b, x in zip(instances, bs, xs):
+        ref, code, its, rr = o.poisson_solve(b, tol=1e-14)
+        assert rel(x.cpu().numpy(), ref) <= 1e-10
+    batch.close()
