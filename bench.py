@@ -75,6 +75,112 @@ def dominant_kernel(precision: str, launch: str, nnz: int, n: int):
     return f"k_pcg_persistent<{t}>", (w + 4) * nnz + (4 + 12 * w) * n
 
 
+def run_batch(args, log):
+    """Config-4-style sweep: independent cylinder instances of uneven size stepped together."""
+    import numpy as np
+    import torch
+
+    import paper_1610_06993_amd as cgp
+    import workloads as W
+    from paper_1610_06993_amd import SolverOpts, StepOpts
+    t0 = time.perf_counter()
+    cases = W.batch_sweep(args.batch)
+    meshes, g, u, pf, pc = [], [], [], [], []
+    for c in cases:
+        m = cgp.Mesh(c.mesh, 1)
+        m.assemble(c.rho, c.mu, c.dt)
+        xy = m.export("xy")
+        meshes.append(m)
+        g.append(torch.from_numpy(c.dirichlet(xy, 0.0)).cuda())
+        u.append(torch.from_numpy(c.initial(xy, m.export("vdir"))).cuda())
+        pf.append(torch.zeros(m.info["n_f"], dtype=torch.float64, device="cuda"))
+        pc.append(torch.zeros(m.info["n_c"], dtype=torch.float64, device="cuda"))
+    rows = sum(m.info["n_c"] for m in meshes)
+    nnz = sum(m.info["nnz_c"] for m in meshes)
+    t_fine = sum(m.info["t_f"] for m in meshes)
+    batch = cgp.Batch(meshes)
+    cache = ROOT / "gpurun_out" / "batch_tuning.json"
+    cache.parent.mkdir(exist_ok=True)
+    tuned = batch.autotune(cache)
+    log(f"batch: {len(meshes)} instances, {t_fine} fine triangles, {rows} coarse rows, {nnz} coarse nonzeros; "
+        f"setup {time.perf_counter() - t0:.1f}s; autotuned {tuned}")
+    tol = 1e-8
+    opts = StepOpts(momentum=SolverOpts(tol=tol, max_iter=5000), poisson=SolverOpts(tol=tol, max_iter=100000),
+                    mass=SolverOpts(tol=1e-10, max_iter=2000))
+    for k in range(2):
+        batch.step(g, u, pf, pc, opts=opts)
+    torch.cuda.synchronize()
+    su, spc = [x.clone() for x in u], [x.clone() for x in pc]
+
+    def restore():
+        for a, b in zip(u, su):
+            a.copy_(b)
+        for a, b in zip(pc, spc):
+            a.copy_(b)
+        torch.cuda.synchronize()
+
+    # the sequential reference: one single-instance step of every instance
+    restore()
+    t1 = time.perf_counter()
+    for i, m in enumerate(meshes):
+        m.step(g[i], u[i], pf[i], pc[i], opts=opts)
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - t1
+    ref = [(a.cpu().numpy(), b.cpu().numpy()) for a, b in zip(u, pf)]
+    # batched steps
+    restore()
+    st = batch.step(g, u, pf, pc, opts=opts)
+    err = max(max(rel(a.cpu().numpy(), r[0]), rel(b.cpu().numpy(), r[1])) for a, b, r in zip(u, pf, ref))
+    restore()
+    t1 = time.perf_counter()
+    for k in range(args.batch_steps):
+        st = batch.step(g, u, pf, pc, opts=opts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    iters = [s["p_iters"] for s in st]
+    launches = st[0]["n_dominant"]
+    # the batched PCG kernel with every instance active: 64 iterations from a random right-hand side
+    rng = np.random.default_rng(0)
+    bs = [torch.from_numpy(rng.normal(size=m.info["n_c"])).cuda() for m in meshes]
+    xs = [torch.zeros_like(b) for b in bs]
+    batch.poisson_solve(bs, xs, SolverOpts(tol=1e-300, max_iter=64, x0_mode=0), allow_noconv=True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    batch.poisson_solve(bs, xs, SolverOpts(tol=1e-300, max_iter=64, x0_mode=0), allow_noconv=True)
+    torch.cuda.synchronize()
+    us_it = 1e6 * (time.perf_counter() - t2) / 64
+    kbytes = 12 * nnz + 92 * rows
+    # per-instance error against the FP64 oracle for the two smallest instances (one step from the same state)
+    import oracle
+    small = sorted(range(len(meshes)), key=lambda i: meshes[i].info["n_c"])[:2]
+    restore()
+    batch.step(g, u, pf, pc, opts=opts)
+    err_oracle = 0.0
+    for i in small:
+        o = oracle.Problem(cases[i].mesh, 1)
+        o.assemble(cases[i].rho, cases[i].mu, cases[i].dt)
+        ur, pfr, pcr, code, _ = o.step(g[i].cpu().numpy(), su[i].cpu().numpy(), spc[i].cpu().numpy(), tol_mom=tol,
+                                       tol_p=tol, tol_mass=1e-10)
+        err_oracle = max(err_oracle, rel(u[i].cpu().numpy(), ur), rel(pf[i].cpu().numpy(), pfr))
+    batch.close()
+    out = dict(instances=len(meshes), fine_triangles=t_fine, coarse_rows=rows, coarse_nnz=nnz,
+               instance_steps_per_s=round(len(meshes) * args.batch_steps / el, 3),
+               ms_per_batch_step=round(1e3 * el / args.batch_steps, 2),
+               sequential_instance_steps_per_s=round(len(meshes) / seq_s, 3),
+               speedup_vs_sequential=round(len(meshes) * args.batch_steps / el / (len(meshes) / seq_s), 3),
+               poisson_iters_min_max=[min(iters), max(iters)], batched_launches_per_step=launches,
+               rel_err_vs_single_instance_gpu=err, rel_err_vs_fp64_oracle_2_smallest=err_oracle,
+               tuning=tuned, batched_kernel_us_per_iteration_all_active=round(us_it, 2),
+               batched_kernel_bytes_per_iteration=kbytes,
+               batched_kernel_gbs=round(kbytes / (us_it * 1e-6) / 1e9, 1),
+               batched_kernel_frac_of_hbm_peak=round(kbytes / (us_it * 1e-6) / 1e9 / HBM_PEAK_GBS, 4))
+    log(f"batch: {out['instance_steps_per_s']} instance-steps/s ({out['ms_per_batch_step']} ms per batch step) vs "
+        f"{out['sequential_instance_steps_per_s']} sequential; Poisson iterations {min(iters)}..{max(iters)}; "
+        f"batched PCG kernel {us_it:.1f} us/iteration for {kbytes / 1e6:.0f} MB -> {out['batched_kernel_gbs']} GB/s; "
+        f"rel err vs single-instance {err:.1e}, vs oracle {err_oracle:.1e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +197,9 @@ def main():
     ap.add_argument("--launch", choices=["loop", "persistent", "fused"], default="fused",
                     help="Poisson Krylov launch strategy")
     ap.add_argument("--paths", default="all", help="comma-separated subset of the timed paths")
+    ap.add_argument("--batch", type=int, default=64, help="instances of the batched sweep (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--only-batch", action="store_true", help="run only the batched sweep")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -116,6 +225,9 @@ def main():
     import workloads as W
     from paper_1610_06993_amd import SolverOpts, StepOpts
     X0 = cgp._native
+    if args.only_batch:
+        print(json.dumps({"batch": run_batch(args, log)}), flush=True)
+        return
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -321,6 +433,12 @@ def main():
         line["cpu_baseline"] = cpu
     for net in models.values():
         net.close()
+    if args.batch > 0:
+        try:
+            line["batch"] = run_batch(args, log)
+        except Exception as e:  # the sweep is reported beside the headline metric, never instead of it
+            line["batch"] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"batch sweep failed: {e}")
     print(json.dumps(line), flush=True)
 
 

@@ -335,3 +335,16 @@ def case_bfs(nx=612, ny=42, seed=2, levels=1) -> Case:
 def case_cylinder(target_tris=250_000, seed=3, levels=1, mu=1e-3) -> Case:
     # D = 0.1, mean inlet speed 1, Re = 100 -> mu = 1e-3
     return Case("cylinder", cylinder_channel(target_tris, seed), levels, 1.0, mu, 1e-3, 2000, 1e-8, 1e-8, 1e-10, "cyl")
+
+
+def batch_sweep(n: int = 64, lo: int = 16_000, hi: int = 250_000, seed: int = 4, levels: int = 1) -> list:
+    """Independent cylinder-flow instances for a batched run: coarse sizes log-uniform in [lo, hi]
+    triangles, Re uniform in [60, 160] (mu = 0.1 / Re with rho = 1, mean inlet speed 1, D = 0.1), mesh
+    seeds 1000 + i."""
+    u = uniform01(seed, 0, 2 * n).reshape(n, 2)
+    out = []
+    for i in range(n):
+        tris = int(round(math.exp(math.log(lo) + u[i, 0] * (math.log(hi) - math.log(lo)))))
+        re = 60.0 + 100.0 * u[i, 1]
+        out.append(case_cylinder(tris, seed=1000 + i, levels=levels, mu=0.1 / re))
+    return out
