@@ -75,6 +75,59 @@ def dominant_kernel(precision: str, launch: str, nnz: int, n: int):
     return f"k_pcg_persistent<{t}>", (w + 4) * nnz + (4 + 12 * w) * n
 
 
+def run_spmv_sweep(args, log):
+    """Fine-mesh SpMV with two right-hand sides (the momentum operator's kernel) on jittered unit squares
+    of growing size, past the 256 MB Infinity Cache; plus a plain copy as the attainable ceiling."""
+    import numpy as np
+    import torch
+
+    import paper_1610_06993_amd as cgp
+    import workloads as W
+    sizes = [(128, 1), (256, 1), (256, 2), (256, 3)] + ([(512, 3)] if args.spmv_large else [])
+    out = []
+    for n, lev in sizes:
+        t0 = time.perf_counter()
+        m = cgp.Mesh(W.unit_square_tg(n, seed=1), lev)
+        m.assemble(1.0, 0.01, 1e-3)
+        nf, nnz = m.info["n_f"], m.info["nnz_f"]
+        x = torch.from_numpy(np.random.default_rng(0).normal(size=(nf, 2))).cuda()
+        y = torch.zeros_like(x)
+        for _ in range(3):
+            m.spmv(cgp._native.OP_M_F, x, y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record()
+        for _ in range(reps):
+            m.spmv(cgp._native.OP_M_F, x, y)
+        e1.record()
+        e1.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / reps
+        nbytes = 12 * nnz + 36 * nf  # values + columns per nonzero; row pointer, x read, y written per row
+        gbs = nbytes / (us * 1e-6) / 1e9
+        out.append(dict(fine_nodes=nf, nnz=nnz, mbytes=round(nbytes / 1e6, 1), us=round(us, 2), gbs=round(gbs, 1),
+                        frac=round(gbs / HBM_PEAK_GBS, 4)))
+        log(f"spmv2 {nf} rows, {nnz} nnz, {nbytes / 1e6:.0f} MB: {us:.1f} us -> {gbs:.0f} GB/s "
+            f"({gbs / HBM_PEAK_GBS:.2f} of peak); setup {time.perf_counter() - t0:.1f}s")
+        m.close()
+        del x, y
+    # attainable ceiling: a 2 GiB device-to-device elementwise copy
+    n = (2 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        torch.mul(src, 1.0, out=dst)
+    e1.record()
+    e1.synchronize()
+    copy_gbs = 2 * n * 8 / (e0.elapsed_time(e1) / 5 * 1e-3) / 1e9
+    log(f"copy ceiling: {copy_gbs:.0f} GB/s ({copy_gbs / HBM_PEAK_GBS:.2f} of peak)")
+    del src, dst
+    return dict(kernel="k_spmv2 (fine mass matrix, 2 right-hand sides)", points=out, copy_gbs=round(copy_gbs, 1),
+                copy_frac=round(copy_gbs / HBM_PEAK_GBS, 4))
+
+
 def run_batch(args, log):
     """Config-4-style sweep: independent cylinder instances of uneven size stepped together."""
     import numpy as np
@@ -200,6 +253,9 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="instances of the batched sweep (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--only-batch", action="store_true", help="run only the batched sweep")
+    ap.add_argument("--spmv-sweep", type=int, default=1, help="run the SpMV size sweep (0: skip)")
+    ap.add_argument("--spmv-large", action="store_true", help="add a 16.8M-row point to the SpMV sweep")
+    ap.add_argument("--only-spmv", action="store_true", help="run only the SpMV size sweep")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -227,6 +283,9 @@ def main():
     X0 = cgp._native
     if args.only_batch:
         print(json.dumps({"batch": run_batch(args, log)}), flush=True)
+        return
+    if args.only_spmv:
+        print(json.dumps({"spmv_sweep": run_spmv_sweep(args, log)}), flush=True)
         return
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -433,6 +492,12 @@ def main():
         line["cpu_baseline"] = cpu
     for net in models.values():
         net.close()
+    if args.spmv_sweep:
+        try:
+            line["spmv_sweep"] = run_spmv_sweep(args, log)
+        except Exception as e:
+            line["spmv_sweep"] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"SpMV sweep failed: {e}")
     if args.batch > 0:
         try:
             line["batch"] = run_batch(args, log)

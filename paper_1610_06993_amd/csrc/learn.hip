@@ -430,16 +430,15 @@ void backward(cgp_guess *g, hipStream_t s, int B) {
 void jacobi_eigen(int q, std::vector<double> &A, std::vector<double> &V) {
   V.assign((size_t)q * q, 0.0);
   for (int i = 0; i < q; i++) V[(size_t)i * q + i] = 1.0;
-  for (int sweep = 0; sweep < 100; sweep++) {
-    double off = 0.0, diag = 0.0;
-    for (int i = 0; i < q; i++)
-      for (int j = 0; j < q; j++) (i == j ? diag : off) += A[(size_t)i * q + j] * A[(size_t)i * q + j];
-    if (off <= 1e-30 * diag) break;
+  for (int sweep = 0; sweep < 60; sweep++) {
+    int rotations = 0;
     for (int p = 0; p < q - 1; p++)
       for (int r = p + 1; r < q; r++) {
         const double apr = A[(size_t)p * q + r];
-        if (apr == 0.0) continue;
         const double app = A[(size_t)p * q + p], arr = A[(size_t)r * q + r];
+        // an off-diagonal entry below the rounding level of its diagonal pair changes nothing
+        if (std::fabs(apr) <= 1e-18 * std::sqrt(std::fabs(app * arr)) || apr == 0.0) continue;
+        rotations++;
         const double theta = (arr - app) / (2.0 * apr);
         const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
         const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
@@ -459,6 +458,7 @@ void jacobi_eigen(int q, std::vector<double> &A, std::vector<double> &V) {
           V[(size_t)k * q + r] = sn * vkp + c * vkr;
         }
       }
+    if (rotations == 0) break;
   }
 }
 
