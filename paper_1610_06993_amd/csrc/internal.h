@@ -134,7 +134,7 @@ struct cgp_mesh {
   std::vector<void *> allocations;
   double *d_scalar = nullptr;     // device scalar for sums (means)
   double *h_scalar = nullptr;     // pinned [4]
-  cgp_tuning tune{{4, 512, 2}, {4, 512, 1}, 0, 0};  // Krylov launch shapes (fine, coarse), persistent kernel
+  cgp_tuning tune{{4, 512, 4}, {4, 512, 2}, 0, 0};  // Krylov launch shapes (fine, coarse), persistent kernel
   int mom_chunk = 4, p_chunk = 32, p32_chunk = 16, mass_chunk = 8;  // Krylov iterations queued before a poll
   // HIP-event timing of every launch of the Poisson SpMV kernel (cgp_step_opts.timing == 2)
   bool kt_on = false;
