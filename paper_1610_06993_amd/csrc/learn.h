@@ -35,6 +35,10 @@ struct cgp_guess {
   float *d_z1 = nullptr, *d_z2 = nullptr, *d_y = nullptr, *d_t = nullptr, *d_dy = nullptr, *d_dh2 = nullptr,
         *d_dz2 = nullptr, *d_dh1 = nullptr, *d_dz1 = nullptr;
   double *d_part = nullptr, *d_scal = nullptr;  // partials, small scalars/vectors
+  double *scr[5] = {};                           // grown scratch (basis construction, split-K partials)
+  size_t scr_cap[5] = {};
+  double *h_pin = nullptr;                       // pinned staging
+  size_t pin_cap = 0;
   int *d_idx = nullptr;
 };
 

@@ -211,16 +211,30 @@ __global__ void k_sum_chunks(long count, int chunks, const double *__restrict__ 
   C[e] = s;
 }
 
-// Y[i][k] = sum_j K[i][j] Phi[j][k]: one wave per row, lane = mode
+// C[e] = sum over the chunks of Cpart[z][e], one block per output, fixed order
+__global__ void __launch_bounds__(256) k_sum_chunks_blk(long count, int chunks, const double *__restrict__ Cpart,
+                                                        double *__restrict__ C) {
+  const long e = blockIdx.x;
+  double v[1] = {0.0};
+  for (int z = threadIdx.x; z < chunks; z += blockDim.x) v[0] += Cpart[(long)z * count + e];
+  double t[1];
+  dev::block_sum<1>(v, t);
+  if (threadIdx.x == 0) C[e] = t[0];
+}
+
+// Y[i][k] = sum_j K[i][j] Phi[j][k]: a group of LPR lanes per row (lane = mode), 64 / LPR rows per wave
+template <int LPR>
 __global__ void __launch_bounds__(256) k_spmm_modes(int n, int nm, const int *__restrict__ rp,
                                                     const int *__restrict__ col, const double *__restrict__ val,
                                                     const double *__restrict__ Phi, double *__restrict__ Y) {
+  constexpr int RPW = 64 / LPR;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int i = blockIdx.x * 4 + wave; i < n; i += gridDim.x * 4) {
+  const int sub = lane / LPR, l = lane % LPR;
+  for (int i = (blockIdx.x * 4 + wave) * RPW + sub; i < n; i += gridDim.x * 4 * RPW) {
     double acc = 0.0;
-    if (lane < nm)
-      for (int k = rp[i]; k < rp[i + 1]; k++) acc += val[k] * Phi[(long)col[k] * nm + lane];
-    if (lane < nm) Y[(long)i * nm + lane] = acc;
+    if (l < nm)
+      for (int k = rp[i]; k < rp[i + 1]; k++) acc += val[k] * Phi[(long)col[k] * nm + l];
+    if (l < nm) Y[(long)i * nm + l] = acc;
   }
 }
 
@@ -330,6 +344,39 @@ cgp_status galloc(cgp_guess *g, T **p, size_t count) {
   return CGP_OK;
 }
 
+// device scratch slot k of at least `count` doubles (kept and grown; freed with the guess)
+cgp_status scratch(cgp_guess *g, int k, size_t count, double **out) {
+  if (g->scr_cap[k] < count) {
+    double *p = nullptr;
+    cgp_status st = galloc(g, &p, count);
+    if (st) return st;
+    g->scr[k] = p;
+    g->scr_cap[k] = count;
+  }
+  *out = g->scr[k];
+  return CGP_OK;
+}
+
+// pinned host staging of at least `count` doubles
+cgp_status pinned(cgp_guess *g, size_t count, double **out) {
+  if (g->pin_cap < count) {
+    if (g->h_pin) {
+      CGP_HIP(hipStreamSynchronize(g->mesh->stream));  // a copy from the old staging may be in flight
+      (void)hipHostFree(g->h_pin);
+    }
+    g->h_pin = nullptr;
+    g->pin_cap = 0;
+    hipError_t e = hipHostMalloc((void **)&g->h_pin, sizeof(double) * count, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      set_error(std::string("hipHostMalloc: ") + hipGetErrorString(e));
+      return CGP_E_OOM;
+    }
+    g->pin_cap = count;
+  }
+  *out = g->h_pin;
+  return CGP_OK;
+}
+
 #define GTRY(x)                  \
   do {                           \
     cgp_status s_ = (x);         \
@@ -379,13 +426,22 @@ cgp_status gemm64(cgp_guess *g, hipStream_t s, int M, int N, int K, const double
   chunks = std::max(1L, std::min(chunks, (8L << 20) / ((long)M * N)));
   const int kchunk = (int)(((K + chunks - 1) / chunks + 31) / 32 * 32);
   chunks = (K + kchunk - 1) / kchunk;
-  double *part = nullptr;
-  CGP_HIP(hipMallocAsync((void **)&part, sizeof(double) * (size_t)chunks * M * N, s));
   dim3 grid((N + 63) / 64, (M + 63) / 64, chunks);
+  if (chunks == 1) {  // one K chunk: the partial is the result
+    hipLaunchKernelGGL(k_gemm64, grid, dim3(256), 0, s, M, N, K, kchunk, P, spa, spi, w, Y, syi, syb, C);
+    CGP_HIP(hipGetLastError());
+    return CGP_OK;
+  }
+  double *part = nullptr;
+  cgp_status st = scratch(g, 4, (size_t)chunks * M * N, &part);
+  if (st) return st;
   hipLaunchKernelGGL(k_gemm64, grid, dim3(256), 0, s, M, N, K, kchunk, P, spa, spi, w, Y, syi, syb, part);
   const long count = (long)M * N;
-  hipLaunchKernelGGL(k_sum_chunks, dim3((count + 255) / 256), dim3(256), 0, s, count, chunks, (const double *)part, C);
-  CGP_HIP(hipFreeAsync(part, s));
+  if (count <= 65536)  // few outputs, many chunks: one block per output
+    hipLaunchKernelGGL(k_sum_chunks_blk, dim3(count), dim3(256), 0, s, count, (int)chunks, (const double *)part, C);
+  else
+    hipLaunchKernelGGL(k_sum_chunks, dim3((count + 255) / 256), dim3(256), 0, s, count, (int)chunks,
+                       (const double *)part, C);
   CGP_HIP(hipGetLastError());
   return CGP_OK;
 }
@@ -430,14 +486,17 @@ void backward(cgp_guess *g, hipStream_t s, int B) {
 void jacobi_eigen(int q, std::vector<double> &A, std::vector<double> &V) {
   V.assign((size_t)q * q, 0.0);
   for (int i = 0; i < q; i++) V[(size_t)i * q + i] = 1.0;
+  double dmax = 0.0;
+  for (int i = 0; i < q; i++) dmax = std::max(dmax, std::fabs(A[(size_t)i * q + i]));
   for (int sweep = 0; sweep < 60; sweep++) {
     int rotations = 0;
     for (int p = 0; p < q - 1; p++)
       for (int r = p + 1; r < q; r++) {
         const double apr = A[(size_t)p * q + r];
         const double app = A[(size_t)p * q + p], arr = A[(size_t)r * q + r];
-        // an off-diagonal entry below the rounding level of its diagonal pair changes nothing
-        if (std::fabs(apr) <= 1e-18 * std::sqrt(std::fabs(app * arr)) || apr == 0.0) continue;
+        // an off-diagonal entry below the rounding level of its diagonal pair, or of the whole matrix,
+        // changes nothing that the input resolves
+        if (std::fabs(apr) <= std::max(1e-18 * std::sqrt(std::fabs(app * arr)), 1e-16 * dmax)) continue;
         rotations++;
         const double theta = (arr - app) / (2.0 * apr);
         const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
@@ -627,6 +686,7 @@ void cgp_guess_destroy(cgp_guess *g) {
   if (g->mesh && g->mesh->guess == g) g->mesh->guess = nullptr;
   (void)hipDeviceSynchronize();
   for (void *p : g->allocations) (void)hipFree(p);
+  if (g->h_pin) (void)hipHostFree(g->h_pin);
   delete g;
 }
 
@@ -690,43 +750,52 @@ cgp_status cgp_guess_build_pod(cgp_guess *g, const double *snaps, int32_t S, dou
   cgp_mesh *m = g->mesh;
   hipStream_t s = m->stream;
   const int n = g->n, nm = g->nm;
+  // pinned staging: [Gram S*S | Vs S*nm | Phi^T K Phi nm*nm | inverse nm*nm]
+  double *hp = nullptr;
+  GTRY(pinned(g, (size_t)S * S + (size_t)S * nm + 2 * (size_t)nm * nm, &hp));
+  double *hG = hp, *hV = hG + (size_t)S * S, *hK = hV + (size_t)S * nm, *hI = hK + (size_t)nm * nm;
   // Gram matrix G = S M S^T (FP64, device), then to the host
   double *dG = nullptr;
-  CGP_HIP(hipMallocAsync((void **)&dG, sizeof(double) * (size_t)S * S, s));
+  GTRY(scratch(g, 0, (size_t)S * S, &dG));
   GTRY(gemm64(g, s, S, S, n, snaps, n, 1, m->d_mc, snaps, 1, n, dG));
-  std::vector<double> G((size_t)S * S);
-  CGP_HIP(hipMemcpyAsync(G.data(), dG, sizeof(double) * G.size(), hipMemcpyDeviceToHost, s));
-  CGP_HIP(hipFreeAsync(dG, s));
+  CGP_HIP(hipMemcpyAsync(hG, dG, sizeof(double) * S * S, hipMemcpyDeviceToHost, s));
   CGP_HIP(hipStreamSynchronize(s));
-  // randomised subspace iteration for the nm largest eigenpairs (Halko, Martinsson & Tropp 2011)
+  std::vector<double> G(hG, hG + (size_t)S * S);
+  // randomised subspace iteration for the nm largest eigenpairs (Halko, Martinsson & Tropp 2011);
+  // when the oversampled subspace is the whole snapshot space, G itself is decomposed
   const int q = std::min(S, nm + 16);
   std::vector<double> Y((size_t)S * q), Z((size_t)S * q);
-  uint64_t state = g->seed ^ 0xA5A5A5A5ull;
-  for (auto &v : Y) v = 2.0 * uniform01(state) - 1.0;
-  auto mult = [&](const std::vector<double> &X, std::vector<double> &out) {  // out = G X
-    std::fill(out.begin(), out.end(), 0.0);
-    for (int a = 0; a < S; a++)
-      for (int b = 0; b < S; b++) {
-        const double gab = G[(size_t)a * S + b];
-        const double *xb = &X[(size_t)b * q];
-        double *oa = &out[(size_t)a * q];
-        for (int j = 0; j < q; j++) oa[j] += gab * xb[j];
-      }
-  };
-  orthonormalise(S, q, Y);
-  for (int it = 0; it < 6; it++) {
-    mult(Y, Z);
-    Y.swap(Z);
-    orthonormalise(S, q, Y);
-  }
-  mult(Y, Z);  // Z = G Q
   std::vector<double> Bm((size_t)q * q, 0.0), U;
-  for (int i = 0; i < q; i++)
-    for (int j = 0; j < q; j++) {
-      double d = 0.0;
-      for (int a = 0; a < S; a++) d += Y[(size_t)a * q + i] * Z[(size_t)a * q + j];
-      Bm[(size_t)i * q + j] = d;
+  if (q == S) {
+    for (int a = 0; a < S; a++) Y[(size_t)a * q + a] = 1.0;
+    Bm = G;
+  } else {
+    uint64_t state = g->seed ^ 0xA5A5A5A5ull;
+    for (auto &v : Y) v = 2.0 * uniform01(state) - 1.0;
+    auto mult = [&](const std::vector<double> &X, std::vector<double> &out) {  // out = G X
+      std::fill(out.begin(), out.end(), 0.0);
+      for (int a = 0; a < S; a++)
+        for (int b = 0; b < S; b++) {
+          const double gab = G[(size_t)a * S + b];
+          const double *xb = &X[(size_t)b * q];
+          double *oa = &out[(size_t)a * q];
+          for (int j = 0; j < q; j++) oa[j] += gab * xb[j];
+        }
+    };
+    orthonormalise(S, q, Y);
+    for (int it = 0; it < 6; it++) {
+      mult(Y, Z);
+      Y.swap(Z);
+      orthonormalise(S, q, Y);
     }
+    mult(Y, Z);  // Z = G Q
+    for (int i = 0; i < q; i++)
+      for (int j = 0; j < q; j++) {
+        double d = 0.0;
+        for (int a = 0; a < S; a++) d += Y[(size_t)a * q + i] * Z[(size_t)a * q + j];
+        Bm[(size_t)i * q + j] = d;
+      }
+  }
   for (int i = 0; i < q; i++)  // symmetrise
     for (int j = i + 1; j < q; j++) Bm[(size_t)i * q + j] = Bm[(size_t)j * q + i] = 0.5 * (Bm[(size_t)i * q + j] + Bm[(size_t)j * q + i]);
   jacobi_eigen(q, Bm, U);
@@ -761,22 +830,31 @@ cgp_status cgp_guess_build_pod(cgp_guess *g, const double *snaps, int32_t S, dou
   if (energy) std::copy(g->energy.begin(), g->energy.end(), energy);
   // Phi = S^T Vs  ([n][nm])
   double *dV = nullptr;
-  CGP_HIP(hipMallocAsync((void **)&dV, sizeof(double) * Vs.size(), s));
-  CGP_HIP(hipMemcpyAsync(dV, Vs.data(), sizeof(double) * Vs.size(), hipMemcpyHostToDevice, s));
+  GTRY(scratch(g, 1, Vs.size(), &dV));
+  std::copy(Vs.begin(), Vs.end(), hV);
+  CGP_HIP(hipMemcpyAsync(dV, hV, sizeof(double) * Vs.size(), hipMemcpyHostToDevice, s));
   GTRY(gemm64(g, s, n, nm, S, snaps, 1, n, nullptr, dV, nm, 1, g->d_phi));
-  CGP_HIP(hipFreeAsync(dV, s));
   // Phi^T K Phi and its inverse (POD-Galerkin guess)
   double *dKP = nullptr, *dPKP = nullptr;
-  CGP_HIP(hipMallocAsync((void **)&dKP, sizeof(double) * (size_t)n * nm, s));
-  CGP_HIP(hipMallocAsync((void **)&dPKP, sizeof(double) * (size_t)nm * nm, s));
-  hipLaunchKernelGGL(k_spmm_modes, dim3(1024), dim3(256), 0, s, n, nm, m->d_rp_c, m->d_col_c, (const double *)m->d_Kbc,
-                     (const double *)g->d_phi, dKP);
+  GTRY(scratch(g, 2, (size_t)n * nm, &dKP));
+  GTRY(scratch(g, 3, (size_t)nm * nm, &dPKP));
+  {
+    const int rpw = nm <= 16 ? 4 : (nm <= 32 ? 2 : 1);
+    const dim3 grid((unsigned)std::min<long>(65535, ((long)n + 4 * rpw - 1) / (4 * rpw)));
+    if (rpw == 4)
+      hipLaunchKernelGGL((k_spmm_modes<16>), grid, dim3(256), 0, s, n, nm, m->d_rp_c, m->d_col_c,
+                         (const double *)m->d_Kbc, (const double *)g->d_phi, dKP);
+    else if (rpw == 2)
+      hipLaunchKernelGGL((k_spmm_modes<32>), grid, dim3(256), 0, s, n, nm, m->d_rp_c, m->d_col_c,
+                         (const double *)m->d_Kbc, (const double *)g->d_phi, dKP);
+    else
+      hipLaunchKernelGGL((k_spmm_modes<64>), grid, dim3(256), 0, s, n, nm, m->d_rp_c, m->d_col_c,
+                         (const double *)m->d_Kbc, (const double *)g->d_phi, dKP);
+  }
   GTRY(gemm64(g, s, nm, nm, n, g->d_phi, 1, nm, nullptr, dKP, nm, 1, dPKP));
-  std::vector<double> Kc((size_t)nm * nm);
-  CGP_HIP(hipMemcpyAsync(Kc.data(), dPKP, sizeof(double) * Kc.size(), hipMemcpyDeviceToHost, s));
-  CGP_HIP(hipFreeAsync(dKP, s));
-  CGP_HIP(hipFreeAsync(dPKP, s));
+  CGP_HIP(hipMemcpyAsync(hK, dPKP, sizeof(double) * nm * nm, hipMemcpyDeviceToHost, s));
   CGP_HIP(hipStreamSynchronize(s));
+  std::vector<double> Kc(hK, hK + (size_t)nm * nm);
   // inverse of the leading rank x rank block by Gauss-Jordan with partial pivoting (SPD and tiny);
   // rows and columns of the unused modes stay zero
   std::vector<double> inv((size_t)nm * nm, 0.0);
@@ -808,8 +886,9 @@ cgp_status cgp_guess_build_pod(cgp_guess *g, const double *snaps, int32_t S, dou
       }
     }
   }
-  CGP_HIP(hipMemcpyAsync(g->d_kinv, inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice, s));
-  CGP_HIP(hipStreamSynchronize(s));
+  // the staging stays untouched until the next call's first synchronisation, after this copy
+  std::copy(inv.begin(), inv.end(), hI);
+  CGP_HIP(hipMemcpyAsync(g->d_kinv, hI, sizeof(double) * inv.size(), hipMemcpyHostToDevice, s));
   g->pod_ready = true;
   g->trained = false;
   g->rank = rank;
