@@ -158,8 +158,8 @@ def run_batch(args, log):
     log(f"batch: {len(meshes)} instances, {t_fine} fine triangles, {rows} coarse rows, {nnz} coarse nonzeros; "
         f"setup {time.perf_counter() - t0:.1f}s; autotuned {tuned}")
     tol = 1e-8
-    opts = StepOpts(momentum=SolverOpts(tol=tol, max_iter=5000), poisson=SolverOpts(tol=tol, max_iter=100000),
-                    mass=SolverOpts(tol=1e-10, max_iter=2000))
+    opts = StepOpts(momentum=SolverOpts(tol=args.mom_tol, max_iter=5000), poisson=SolverOpts(tol=tol, max_iter=100000),
+                    mass=SolverOpts(tol=args.mass_tol, max_iter=2000))
     for k in range(2):
         batch.step(g, u, pf, pc, opts=opts)
     torch.cuda.synchronize()
@@ -212,8 +212,8 @@ def run_batch(args, log):
     for i in small:
         o = oracle.Problem(cases[i].mesh, 1)
         o.assemble(cases[i].rho, cases[i].mu, cases[i].dt)
-        ur, pfr, pcr, code, _ = o.step(g[i].cpu().numpy(), su[i].cpu().numpy(), spc[i].cpu().numpy(), tol_mom=tol,
-                                       tol_p=tol, tol_mass=1e-10)
+        ur, pfr, pcr, code, _ = o.step(g[i].cpu().numpy(), su[i].cpu().numpy(), spc[i].cpu().numpy(), tol_mom=args.mom_tol,
+                                       tol_p=tol, tol_mass=args.mass_tol)
         err_oracle = max(err_oracle, rel(u[i].cpu().numpy(), ur), rel(pf[i].cpu().numpy(), pfr))
     batch.close()
     out = dict(instances=len(meshes), fine_triangles=t_fine, coarse_rows=rows, coarse_nnz=nnz,
@@ -249,6 +249,12 @@ def main():
     ap.add_argument("--no-instrumented", action="store_true", help="skip the event-timed kernel pass")
     ap.add_argument("--launch", choices=["loop", "persistent", "fused"], default="fused",
                     help="Poisson Krylov launch strategy")
+    ap.add_argument("--mom-x0", choices=["prev", "extrap"], default="extrap",
+                    help="momentum initial guess: U^n, or 2 U~^n - U~^(n-1) from the two previous solves")
+    # the Poisson right-hand side is the divergence of U~, small beside U~ itself: a momentum error of
+    # relative size t reaches it amplified ~100x, so the momentum solve runs two decades below the Poisson's
+    ap.add_argument("--mom-tol", type=float, default=1e-10, help="momentum solve tolerance (relative residual)")
+    ap.add_argument("--mass-tol", type=float, default=1e-10, help="mass solve tolerance of the correction")
     ap.add_argument("--paths", default="all", help="comma-separated subset of the timed paths")
     ap.add_argument("--batch", type=int, default=64, help="instances of the batched sweep (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
@@ -311,11 +317,13 @@ def main():
     tol = 1e-8
     launch = {"loop": 1, "persistent": 2, "fused": 3}[args.launch]
 
+    mom_x0 = {"prev": X0.X0_PREV, "extrap": X0.X0_EXTRAP}[args.mom_x0]
+
     def opts(precision=0, x0=X0.X0_PREV, timing=0):
-        return StepOpts(momentum=SolverOpts(tol=tol, max_iter=5000),
+        return StepOpts(momentum=SolverOpts(tol=args.mom_tol, max_iter=5000, x0_mode=mom_x0),
                         poisson=SolverOpts(tol=tol, max_iter=100000, precision=precision, inner_tol=1e-4,
                                            x0_mode=x0, launch=launch),
-                        mass=SolverOpts(tol=1e-10, max_iter=2000), timing=timing)
+                        mass=SolverOpts(tol=args.mass_tol, max_iter=2000), timing=timing)
 
     for k in range(args.warmup):
         st = mesh.step(g, u, pf, pc, opts=opts())
@@ -455,7 +463,7 @@ def main():
         t2 = time.perf_counter()
         outs = []
         for k in range(args.cpu_steps):
-            ur, pfr, pcr, code, ost = ref.step(gh, ur, pcr, tol_mom=tol, tol_p=tol, tol_mass=1e-10)
+            ur, pfr, pcr, code, ost = ref.step(gh, ur, pcr, tol_mom=args.mom_tol, tol_p=tol, tol_mass=args.mass_tol)
             outs.append((ur.copy(), pfr.copy()))
         el = time.perf_counter() - t2
         err_vs_oracle = max(rel(ub, outs[0][0]), rel(pfb, outs[0][1]))
@@ -473,7 +481,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+f32-ir" if bprec == F32 else "f64", "data": "synthetic",
         "config": {"workload": f"cylinder channel Re=100, coarse {info['t_c']} / fine {info['t_f']} P1 triangles, "
-                               f"l=1, dt=1e-3, PCG tol 1e-8, path {best}",
+                               f"l=1, dt=1e-3, Poisson PCG tol 1e-8 (momentum {args.mom_tol:g}, mass {args.mass_tol:g}), "
+                               f"momentum x0 {args.mom_x0}, path {best}",
                    "path": best, "fine_nodes": info["n_f"], "coarse_nodes": n_c, "nnz_f": info["nnz_f"],
                    "nnz_c": nnz_c, "pod_modes": args.modes, "snapshots": S, "parallelism": "single GPU"},
         "fp64_steps_per_s": results["fp64"]["steps_per_s"],

@@ -9,8 +9,11 @@
  *    rho*M*U^n + dt*M*F^{n+1}, coarse Poisson K P = -(rho/dt) D U, correction
  *    factor dt/rho.
  *  - "boundary conditions enforced in the discrete operators": symmetric
- *    elimination on the fixed sparsity pattern.  Dirichlet rows/columns become
- *    identity, the known values g^{n+1} are moved to the right-hand side.
+ *    elimination on the fixed sparsity pattern.  Dirichlet rows/columns are
+ *    cleared except for the diagonal, which keeps its value a_ii (so that the
+ *    residual norm weighs those rows like the others), the right-hand side
+ *    there is a_ii g_i, and the known values g^{n+1} are moved to the
+ *    right-hand side of the other rows.
  *  - pressure p = 0 on every node of an outflow edge of the Poisson mesh
  *    (Eq. 14); without such nodes the Poisson problem is pure Neumann
  *    (Eq. 13): the right-hand side is made orthogonal to constants by
@@ -35,20 +38,25 @@ static double *dalloc(size_t n) { return (double *)calloc(n ? n : 1, sizeof(doub
 
 /* Symmetric Dirichlet elimination on A (values on pattern P) and rhs for one
  * velocity component c of g: rows j outside D get rhs_j -= sum_{i in D} A_ji g_i,
- * then D rows and columns become identity and rhs_i = g_i. */
+ * then D rows and columns are cleared except for the diagonal a_ii (kept; 1 if
+ * it is not positive) and rhs_i = a_ii g_i. */
 static void eliminate(const orc_csr *P, double *val, double *rhs, const unsigned char *dir, const double *g, int c) {
   for (int j = 0; j < P->n; j++) {
     if (dir[j]) continue;
     for (int k = P->rp[j]; k < P->rp[j + 1]; k++)
       if (dir[P->col[k]]) rhs[j] -= val[k] * g[2 * P->col[k] + c];
   }
-  for (int j = 0; j < P->n; j++)
+  for (int j = 0; j < P->n; j++) {
+    double d = 1.0;
+    if (dir[j])
+      for (int k = P->rp[j]; k < P->rp[j + 1]; k++)
+        if (P->col[k] == j && val[k] > 0.0) d = val[k];
     for (int k = P->rp[j]; k < P->rp[j + 1]; k++) {
       int i = P->col[k];
-      if (dir[j] || dir[i]) val[k] = (i == j) ? 1.0 : 0.0;
+      if (dir[j] || dir[i]) val[k] = (i == j) ? d : 0.0;
     }
-  for (int j = 0; j < P->n; j++)
-    if (dir[j]) rhs[j] = g[2 * j + c];
+    if (dir[j]) rhs[j] = d * g[2 * j + c];
+  }
 }
 
 /* Step 1, Eq. (19): (rho M + dt N(U^n) + dt mu K) U~ = rho M U^n + dt M F, per component */
@@ -73,7 +81,8 @@ int orc_momentum(orc_problem *p, const double *g_next, const double *f_next, con
     }
     memcpy(Ac, A, sizeof(double) * nnz);
     eliminate(P, Ac, rhs, p->vdir, g_next, c);
-    for (int i = 0; i < n; i++) x[i] = u[2 * i + c];
+    /* initial guess U^n with the known values g^{n+1} on the Dirichlet rows */
+    for (int i = 0; i < n; i++) x[i] = p->vdir[i] ? g_next[2 * i + c] : u[2 * i + c];
     int it; double rr;
     int s = orc_bicgstab(P, Ac, rhs, x, tol, maxit, &it, &rr);
     if (st) { st->mom_iters[c] = it; st->mom_relres[c] = rr; }
@@ -200,7 +209,7 @@ static int correct(orc_problem *p, const double *g_next, const double *ut, const
     for (int i = 0; i < n; i++) rhs[i] -= s * gp[i];
     memcpy(Mc, p->Mf, sizeof(double) * nnz);
     eliminate(P, Mc, rhs, p->vdir, g_next, c);
-    memcpy(x, uc, sizeof(double) * (size_t)n);
+    for (int i = 0; i < n; i++) x[i] = p->vdir[i] ? g_next[2 * i + c] : uc[i];
     int it; double rr;
     int q = orc_pcg(P, Mc, rhs, x, tol, maxit, &it, &rr);
     if (st) { st->mass_iters[c] = it; st->mass_relres[c] = rr; }

@@ -106,6 +106,7 @@ cgp_status build_device(cgp_mesh *m) {
   m->d_wlev.assign(m->levels + 1, nullptr);
   for (int k = 0; k <= m->levels; k++) TRY(dalloc(m, &m->d_wlev[k], size_t(m->lev[k].n)));
   TRY(dalloc(m, &m->d_ut, 2 * Nf));
+  TRY(dalloc(m, &m->d_ut_prev, 2 * Nf));
   TRY(dalloc(m, &m->d_bc, Nc));
   TRY(dalloc(m, &m->d_state, 4));
   m->red_grid = std::max(8, m->cu_count);
@@ -118,11 +119,13 @@ cgp_status build_device(cgp_mesh *m) {
   return CGP_OK;
 }
 
-bool valid_opts(const cgp_solver_opts *o, bool poisson) {
+bool valid_opts(const cgp_solver_opts *o, bool poisson, bool allow_extrap = false) {
   if (!o) return false;
   if (!(o->tol > 0.0) || o->max_iter < 1) return false;
   if (o->precision != CGP_PREC_FP64 && !(poisson && o->precision == CGP_PREC_FP32_IR)) return false;
-  if (o->x0_mode < CGP_X0_ZERO || o->x0_mode > (poisson ? CGP_X0_POD_GALERKIN : CGP_X0_PREV)) return false;
+  if (o->x0_mode < CGP_X0_ZERO || o->x0_mode > (poisson ? CGP_X0_POD_GALERKIN : CGP_X0_PREV)) {
+    if (!(allow_extrap && !poisson && o->x0_mode == CGP_X0_EXTRAP)) return false;
+  }
   if (o->launch < CGP_LAUNCH_AUTO || o->launch > CGP_LAUNCH_FUSED) return false;
   return true;
 }
@@ -404,7 +407,7 @@ cgp_status cgp_correct(cgp_mesh *m, const cgp_solver_opts *o, const double *g, c
 cgp_status cgp_step(cgp_mesh *m, const cgp_step_opts *o, const double *g, const double *f, double *u, double *pf,
                     double *pc, cgp_stats *st) {
   TRY(ready(m));
-  if (!o || !valid_opts(&o->momentum, false) || !valid_opts(&o->poisson, true) || !valid_opts(&o->mass, false) ||
+  if (!o || !valid_opts(&o->momentum, false, true) || !valid_opts(&o->poisson, true) || !valid_opts(&o->mass, false) ||
       !g || !u || !pf || !pc) {
     set_error("cgp_step: invalid argument");
     return CGP_E_ARG;

@@ -119,6 +119,8 @@ struct cgp_mesh {
   std::vector<float *> d_wc32;    // 6 coarse float vectors
   std::vector<double *> d_wlev;   // per level scratch [n_k] (prolong/restrict chains)
   double *d_ut = nullptr;         // u-tilde [n_f][2] for cgp_step
+  double *d_ut_prev = nullptr;    // the step before's u-tilde (extrapolated momentum guess)
+  int ut_hist = 0;                // consecutive cgp_step momentum solves kept in d_ut / d_ut_prev
   double *d_bc = nullptr;         // coarse rhs
   cgp::KrylovState *d_state = nullptr;   // 4 solver states
   cgp::KrylovState *h_state = nullptr;   // pinned mirror

@@ -124,7 +124,8 @@ __global__ void k_coarse_bc(int n, const int *__restrict__ rp, const int *__rest
   dinv32[i] = (float)dinv[i];
 }
 
-// Fine mass with velocity-Dirichlet identity rows/columns, its Jacobi inverse, lumped mass.
+// Fine mass with velocity-Dirichlet rows/columns cleared except for the diagonal, which keeps
+// its value; its Jacobi inverse; lumped mass.
 __global__ void k_mass_bc(int n, const int *__restrict__ rp, const int *__restrict__ col,
                           const unsigned char *__restrict__ vdir, const double *__restrict__ M,
                           double *__restrict__ Mbc, double *__restrict__ dinv, double *__restrict__ ml) {
@@ -135,7 +136,7 @@ __global__ void k_mass_bc(int n, const int *__restrict__ rp, const int *__restri
   for (int k = rp[i]; k < rp[i + 1]; k++) {
     const int j = col[k];
     s += M[k];
-    double v = (di || vdir[j]) ? (i == j ? 1.0 : 0.0) : M[k];
+    double v = (di || vdir[j]) ? (i == j ? (M[k] > 0.0 ? M[k] : 1.0) : 0.0) : M[k];
     Mbc[k] = v;
     if (j == i) d = v;
   }
@@ -153,10 +154,14 @@ __global__ void k_mom_rhs_bc(int n, const int *__restrict__ rp, const int *__res
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const int k0 = rp[j], k1 = rp[j + 1];
-  if (vdir[j]) {
-    for (int k = k0; k < k1; k++) A[k] = (col[k] == j) ? 1.0 : 0.0;
-    rhs[j] = g[j];
-    dinv[j] = 1.0;
+  if (vdir[j]) {  // the row keeps its diagonal a_jj (1 if not positive): a_jj u_j = a_jj g_j
+    double d = 1.0;
+    for (int k = k0; k < k1; k++)
+      if (col[k] == j && A[k] > 0.0) d = A[k];
+    for (int k = k0; k < k1; k++) A[k] = (col[k] == j) ? d : 0.0;
+    const double2 gj = g[j];
+    rhs[j] = make_double2(d * gj.x, d * gj.y);
+    dinv[j] = 1.0 / d;
     return;
   }
   double ax = 0.0, ay = 0.0, fx = 0.0, fy = 0.0, d = 1.0;
@@ -234,6 +239,15 @@ __global__ void k_spmv2(int n, const int *__restrict__ rp, const int *__restrict
     sy = group_sum<L>(sy);
     if (lane == 0) y[row] = make_double2(sx, sy);
   }
+}
+
+// x0 = 2 a - b, b = a (element-wise over `count` values)
+__global__ void k_extrapolate(long count, double *__restrict__ a, double *__restrict__ b) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const double ai = a[i];
+  a[i] = 2.0 * ai - b[i];
+  b[i] = ai;
 }
 
 // ------------------------------------------------------------------ pressure path
@@ -317,7 +331,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_reduce_scalar(const double *__res
   if (threadIdx.x == 0) *out = tot[0];
 }
 
-// Correction right-hand side (Eq. 23): M u~ - (dt/rho)(Dx P, Dy P), lifted with g.
+// Correction right-hand side (Eq. 23): M u~ - (dt/rho)(Dx P, Dy P), lifted with g; m_ii g_i on
+// velocity-Dirichlet rows.
 template <int L>
 __global__ void k_correct_rhs(int n, const int *__restrict__ rp, const int *__restrict__ col,
                               const unsigned char *__restrict__ vdir, const double *__restrict__ M,
@@ -327,7 +342,7 @@ __global__ void k_correct_rhs(int n, const int *__restrict__ rp, const int *__re
   const int lane = threadIdx.x & (L - 1);
   const int rows_per_grid = gridDim.x * blockDim.x / L;
   for (int row = (xcd_block() * blockDim.x + threadIdx.x) / L; row < n; row += rows_per_grid) {
-    double mx = 0.0, my = 0.0, gx = 0.0, gy = 0.0, lx = 0.0, ly = 0.0;
+    double mx = 0.0, my = 0.0, gx = 0.0, gy = 0.0, lx = 0.0, ly = 0.0, md = 0.0;
     for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
       const int c = col[k];
       const double m = M[k];
@@ -337,6 +352,7 @@ __global__ void k_correct_rhs(int n, const int *__restrict__ rp, const int *__re
       my += m * u.y;
       gx += d.x * p;
       gy += d.y * p;
+      if (c == row) md = m;
       if (vdir[c]) {
         const double2 gc = g[c];
         lx += m * gc.x;
@@ -346,7 +362,16 @@ __global__ void k_correct_rhs(int n, const int *__restrict__ rp, const int *__re
     mx = group_sum<L>(mx); my = group_sum<L>(my);
     gx = group_sum<L>(gx); gy = group_sum<L>(gy);
     lx = group_sum<L>(lx); ly = group_sum<L>(ly);
-    if (lane == 0) rhs[row] = vdir[row] ? g[row] : make_double2(mx - s * gx - lx, my - s * gy - ly);
+    md = group_sum<L>(md);
+    if (lane == 0) {
+      if (vdir[row]) {  // m_ii u_i = m_ii g_i, as the eliminated mass matrix keeps m_ii
+        const double d = md > 0.0 ? md : 1.0;
+        const double2 gr = g[row];
+        rhs[row] = make_double2(d * gr.x, d * gr.y);
+      } else {
+        rhs[row] = make_double2(mx - s * gx - lx, my - s * gy - ly);
+      }
+    }
   }
 }
 
@@ -432,6 +457,10 @@ void launch_set_dirichlet(cgp_mesh *m, const double *g, double *u) {
   const int n = m->pf.n;
   hipLaunchKernelGGL(k_set_dirichlet, dim3(blocks_1d(n)), dim3(256), 0, m->stream, n, m->d_vdir,
                      (const double2 *)g, (double2 *)u);
+}
+
+void launch_extrapolate(cgp_mesh *m, long count, double *a, double *b) {
+  hipLaunchKernelGGL(dev::k_extrapolate, dim3((count + 255) / 256), dim3(256), 0, m->stream, count, a, b);
 }
 
 void launch_pdir_zero(cgp_mesh *m, double *b, double *x) {

@@ -1053,10 +1053,21 @@ cgp_status drv_momentum(cgp_mesh *m, const cgp_solver_opts *o, const double *g, 
   launch_conv_assembly(m, u);
   double2 *rhs = (double2 *)m->d_wf[0];
   launch_mom_rhs(m, g, u, f, (double *)rhs);
-  if (o->x0_mode == CGP_X0_ZERO)
-    CGP_HIP(hipMemsetAsync(ut, 0, 2 * n * sizeof(double), s));
-  else
-    CGP_HIP(hipMemcpyAsync(ut, u, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  const bool extrap = (o->x0_mode == CGP_X0_EXTRAP && ut == m->d_ut);
+  if (extrap && m->ut_hist >= 2) {
+    // d_ut holds U~^n and d_ut_prev U~^(n-1): x0 = 2 U~^n - U~^(n-1), and U~^n moves to d_ut_prev
+    launch_extrapolate(m, 2 * n, m->d_ut, m->d_ut_prev);
+  } else {
+    if (extrap && m->ut_hist == 1)
+      CGP_HIP(hipMemcpyAsync(m->d_ut_prev, m->d_ut, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (o->x0_mode == CGP_X0_ZERO)
+      CGP_HIP(hipMemsetAsync(ut, 0, 2 * n * sizeof(double), s));
+    else
+      CGP_HIP(hipMemcpyAsync(ut, u, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  m->ut_hist = extrap ? std::min(m->ut_hist + 1, 2) : 0;
+  // known values in the initial guess: the eliminated Dirichlet rows then start (and stay) exact
+  launch_set_dirichlet(m, g, ut);
   double2 *r = (double2 *)m->d_wf[1], *rh = (double2 *)m->d_wf[2], *p = (double2 *)m->d_wf[3];
   double2 *v = (double2 *)m->d_wf[4], *t = (double2 *)m->d_wf[5], *ph = (double2 *)m->d_wf[6];
   KrylovState *st = m->d_state + SLOT_MOM;
@@ -1315,6 +1326,7 @@ cgp_status drv_correct(cgp_mesh *m, const cgp_solver_opts *o, const double *g, c
     CGP_HIP(hipMemsetAsync(u, 0, 2 * n * sizeof(double), s));
   else
     CGP_HIP(hipMemcpyAsync(u, ut, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_set_dirichlet(m, g, u);
   double *w[5] = {m->d_wf[1], m->d_wf[2], m->d_wf[3], m->d_wf[4], m->d_wf[5]};
   KrylovState fin{};
   cgp_status rs = run_pcg64<2>(m, SLOT_MASS, n, m->d_rp_f, m->d_col_f, m->d_Mbc, m->d_dinvM, rhs, u, w, m->tune.fine,

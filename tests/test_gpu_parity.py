@@ -199,6 +199,19 @@ def test_cylinder_steps(env, launch):
     _run_steps(env, case, 1, 5, opts)
 
 
+def test_extrapolated_momentum_guess(env):
+    """x0 = 2 U~^n - U~^(n-1) for the momentum solve changes only the start of the Krylov iteration.
+    A different start moves the converged momentum result by up to cond(A) * tol, which the pressure
+    amplifies, so this test solves the momentum equation to 1e-15 on both sides."""
+    torch, cgp, oracle = env
+    case = make(CYLINDER_CASE)
+    _say("cylinder, momentum x0 extrapolated, 6 steps")
+    opts = tight_opts(cgp)
+    opts.momentum = cgp.SolverOpts(tol=1e-15, max_iter=100000, x0_mode=cgp._native.X0_EXTRAP)
+    opts.mass = cgp.SolverOpts(tol=1e-15, max_iter=100000)
+    _run_steps(env, case, 1, 6, opts, tol=1e-15)
+
+
 def test_fp32_ir_step_within_1e6(env):
     torch, cgp, oracle = env
     case = W.case_cylinder(12000, seed=3)
