@@ -166,7 +166,7 @@ enum { CGP_OP_KBC_C = 0,   /* y[n_c]   = Kbar_bc x           (FP64) */
 
 /* Launch shape of the Krylov kernels on one mesh level (set by hand or by the autotuner). */
 typedef struct {
-  int32_t lanes;   /* threads per CSR row in SpMV-type kernels: 4, 8 or 16 */
+  int32_t lanes;   /* threads per CSR row in SpMV-type kernels: 2, 4, 8 or 16 */
   int32_t block;   /* threads per block of the Krylov kernels: 64, 128, 256, 512 or 1024 */
   int32_t passes;  /* rows (SpMV-type kernels) or entries (vector kernels) per lane group: 1..64 */
 } cgp_tuning_knobs;

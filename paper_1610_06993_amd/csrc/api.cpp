@@ -107,6 +107,7 @@ cgp_status build_device(cgp_mesh *m) {
   for (int k = 0; k <= m->levels; k++) TRY(dalloc(m, &m->d_wlev[k], size_t(m->lev[k].n)));
   TRY(dalloc(m, &m->d_ut, 2 * Nf));
   TRY(dalloc(m, &m->d_ut_prev, 2 * Nf));
+  TRY(dalloc(m, &m->d_rec, 8 * Nc));
   TRY(dalloc(m, &m->d_bc, Nc));
   TRY(dalloc(m, &m->d_state, 4));
   m->red_grid = std::max(8, m->cu_count);
@@ -494,10 +495,10 @@ cgp_status cgp_mesh_set_tuning(cgp_mesh *m, const cgp_tuning *t) {
     return CGP_E_ARG;
   }
   for (const cgp_tuning_knobs *k : {&t->fine, &t->coarse}) {
-    const bool lanes_ok = k->lanes == 4 || k->lanes == 8 || k->lanes == 16;
+    const bool lanes_ok = k->lanes == 2 || k->lanes == 4 || k->lanes == 8 || k->lanes == 16;
     const bool block_ok = k->block == 64 || k->block == 128 || k->block == 256 || k->block == 512 || k->block == 1024;
     if (!lanes_ok || !block_ok || k->passes < 1 || k->passes > 64) {
-      set_error("cgp_mesh_set_tuning: lanes must be 4/8/16, block 64..1024 (power of two), passes 1..64");
+      set_error("cgp_mesh_set_tuning: lanes must be 2/4/8/16, block 64..1024 (power of two), passes 1..64");
       return CGP_E_ARG;
     }
   }

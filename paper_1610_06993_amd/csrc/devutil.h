@@ -99,5 +99,48 @@ __device__ __forceinline__ void sum_partials(const double *__restrict__ P, int G
   block_sum<K>(v, tot);
 }
 
+// Consumer side without LDS or barriers: every wave sums the K partial arrays of length G
+// itself (U loads per lane issued together, the rest in a loop, then the wave butterfly).  The
+// order is fixed, so every wave of every block holds bit-identical totals, and a wave can start
+// work that does not need them while its loads are in flight.
+template <int K, int U>
+__device__ __forceinline__ void wave_partials(const double *__restrict__ P, int G, double (&tot)[K]) {
+  const int l = threadIdx.x & 63;
+  double a[K][U];
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    const int b = l + 64 * u;
+#pragma unroll
+    for (int k = 0; k < K; k++) a[k][u] = b < G ? P[k * G + b] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; u++) s += a[k][u];
+    for (int b = l + 64 * U; b < G; b += 64) s += P[k * G + b];
+    tot[k] = wave_sum(s);
+  }
+}
+
+// Producer side with a single barrier: the block's partials go straight from LDS to P.  It has
+// its own LDS array and must be the block's last reduction.
+template <int K>
+__device__ __forceinline__ void put_partials_last(const double (&v)[K], double *__restrict__ P) {
+  __shared__ double sh[K][kMaxBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const double x = wave_sum(v[k]);
+    if (lane == 0) sh[k][wid] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0.0;
+    for (int w = 0; w < nw; w++) s += sh[threadIdx.x][w];
+    P[threadIdx.x * gridDim.x + blockIdx.x] = s;
+  }
+}
+
 }  // namespace dev
 }  // namespace cgp

@@ -121,6 +121,7 @@ struct cgp_mesh {
   double *d_ut = nullptr;         // u-tilde [n_f][2] for cgp_step
   double *d_ut_prev = nullptr;    // the step before's u-tilde (extrapolated momentum guess)
   int ut_hist = 0;                // consecutive cgp_step momentum solves kept in d_ut / d_ut_prev
+  double *d_rec = nullptr;        // 2 x [n_c] records {r, w, s, D^-1} of the fused Poisson PCG (double4 or float4)
   double *d_bc = nullptr;         // coarse rhs
   cgp::KrylovState *d_state = nullptr;   // 4 solver states
   cgp::KrylovState *h_state = nullptr;   // pinned mirror
@@ -136,7 +137,7 @@ struct cgp_mesh {
   std::vector<void *> allocations;
   double *d_scalar = nullptr;     // device scalar for sums (means)
   double *h_scalar = nullptr;     // pinned [4]
-  cgp_tuning tune{{4, 512, 4}, {4, 512, 2}, 0, 0};  // Krylov launch shapes (fine, coarse), persistent kernel
+  cgp_tuning tune{{4, 512, 4}, {2, 1024, 1}, 0, 0};  // Krylov launch shapes (fine, coarse), persistent kernel
   int mom_chunk = 4, p_chunk = 32, p32_chunk = 16, mass_chunk = 8;  // Krylov iterations queued before a poll
   // HIP-event timing of every launch of the Poisson SpMV kernel (cgp_step_opts.timing == 2)
   bool kt_on = false;

@@ -33,6 +33,7 @@ inline int blocks_1d(long long n) { return int(n < 1 ? 1 : (n + 255) / 256); }
 template <typename F>
 void dispatch_L(int L, F &&f) {
   switch (L) {
+    case 2: f(std::integral_constant<int, 2>{}); break;
     case 4: f(std::integral_constant<int, 4>{}); break;
     case 16: f(std::integral_constant<int, 16>{}); break;
     default: f(std::integral_constant<int, 8>{}); break;

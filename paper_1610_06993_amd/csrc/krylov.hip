@@ -313,22 +313,51 @@ __global__ void k_zero_b_fix(int n, double *__restrict__ x, const KrylovState *_
 //   w_{i+1} = K u_{i+1},  gamma_{i+1} = r_{i+1}.u_{i+1},  delta_{i+1} = w_{i+1}.u_{i+1}
 //   beta_{i+1} = gamma_{i+1}/gamma_i,  alpha_{i+1} = gamma_{i+1}/(delta_{i+1} - beta_{i+1} gamma_{i+1}/alpha_i)
 // One kernel does a whole iteration: the SpMV forms u_{i+1} on the fly for its
-// gathered columns from the previous iteration's r, w and s, which are kept
-// double-buffered (slot it & 1 is read, the other written).  p and x are only
-// touched on their own rows and are updated in place.
+// gathered columns from the previous iteration's r, w and s.  Those live in one
+// record per node, {r, w, s, D^-1} (double4, or float4 for the FP32 inner solve),
+// so a gathered column costs one 32- (16-) byte load; the records are
+// double-buffered (slot it & 1 is read, the other written; D^-1 is filled into
+// both at init and never rewritten).  p and x are only touched on their own rows
+// and are updated in place.
+//
+// Latency, not bandwidth, bounds an iteration at the sizes the method is run at,
+// so the kernel is laid out to overlap its dependent loads: every load that does
+// not need this iteration's scalars (the row pointers, columns and values of the
+// block's first chunk of rows, the gathered records, the own records, x and p) is
+// issued before the scalars are formed, each wave reduces the previous
+// iteration's block partials itself (no barrier before the row work), and the
+// block's partials leave after a single barrier.
+
+template <typename T> struct rec_of;
+template <> struct rec_of<double> { using type = double4; };
+template <> struct rec_of<float> { using type = float4; };
+template <typename T> using rec_t = typename rec_of<T>::type;
+
+__device__ __forceinline__ void store_rws(double4 *q, double r, double w, double s) {
+  *reinterpret_cast<double2 *>(q) = make_double2(r, w);
+  q->z = s;
+}
+__device__ __forceinline__ void store_rws(float4 *q, float r, float w, float s) {
+  *reinterpret_cast<float2 *>(q) = make_float2(r, w);
+  q->z = s;
+}
 
 template <typename T>
 __device__ __forceinline__ T cg1_u_next(T dinv, T r, T w, T s, T alpha, T beta) {
   return dinv * (r - alpha * (w + beta * s));
 }
 
-// init, second kernel: w0 = K u0 with u0 = D^-1 r0 gathered; partials (gamma0, delta0, r0.r0).
-// Reduces the first kernel's partials (b.b) and publishes ||b||.
+// entries per lane loaded ahead of the scalars: ten per row (P1 rows on the meshes here have at
+// most nine); longer rows finish in a loop
+template <int L> constexpr int cg1_ahead() { return (10 + L - 1) / L; }
+
+// init, second kernel: w0 = K u0 with u0 = D^-1 r0 gathered from the records (fields r and D^-1
+// only: this kernel writes field w); partials (gamma0, delta0, r0.r0).  Reduces the first
+// kernel's partials (b.b) and publishes ||b||.
 template <typename T, int L>
 __global__ void __launch_bounds__(kMaxBlock) k_cg1_init_w(int Gin, int n, const int *__restrict__ rp,
                                                          const int *__restrict__ col, const T *__restrict__ A,
-                                                         const T *__restrict__ dinv, const T *__restrict__ r0,
-                                                         T *__restrict__ w0, const double *__restrict__ Pin,
+                                                         rec_t<T> *__restrict__ R0, const double *__restrict__ Pin,
                                                          double *__restrict__ Pout, KrylovState *__restrict__ st) {
   if (st->status || st->done[0]) return;
   double tb[1];
@@ -345,13 +374,13 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg1_init_w(int Gin, int n, const 
     double sum = 0.0;
     for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
       const int j = col[k];
-      sum += (double)(A[k] * (dinv[j] * r0[j]));
+      sum += (double)(A[k] * (R0[j].w * R0[j].x));
     }
     sum = group_sum<L>(sum);
     if (lane == 0) {
-      const T w = (T)sum;
-      const double r = (double)r0[row], u = (double)(dinv[row] * r0[row]);
-      w0[row] = w;
+      const T w = (T)sum, r0 = R0[row].x, d = R0[row].w;
+      const double r = (double)r0, u = (double)(d * r0);
+      R0[row].y = w;
       acc[0] += r * u;
       acc[1] += (double)w * u;
       acc[2] += r * r;
@@ -360,27 +389,78 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg1_init_w(int Gin, int n, const 
   put_partials<3>(acc, Pout);
 }
 
-template <typename T, int L>
+template <typename T, int L, int P, int U>
 __global__ void __launch_bounds__(kMaxBlock) k_cg1_iter(int Gin, int it, int n, const int *__restrict__ rp,
                                                        const int *__restrict__ col, const T *__restrict__ A,
-                                                       const T *__restrict__ dinv, T *__restrict__ x,
-                                                       T *__restrict__ p, const T *__restrict__ r_cur,
-                                                       const T *__restrict__ w_cur, const T *__restrict__ s_cur,
-                                                       T *__restrict__ r_nxt, T *__restrict__ w_nxt,
-                                                       T *__restrict__ s_nxt, const double *__restrict__ Pin,
-                                                       double *__restrict__ Pout, KrylovState *__restrict__ st) {
-  if (st->status || st->done[0]) return;
+                                                       T *__restrict__ x, T *__restrict__ p,
+                                                       const rec_t<T> *__restrict__ Rc, rec_t<T> *__restrict__ Rn,
+                                                       const double *__restrict__ Pin, double *__restrict__ Pout,
+                                                       KrylovState *__restrict__ st) {
+  using R4 = rec_t<T>;
+  constexpr int E = cg1_ahead<L>();
+  // the previous iteration's state and partials, first in the load queue
+  const int stopped = st->status | st->done[0];
+  const double bnorm = st->bnorm[0], tol = st->tol;
+  const double rz_prev = it ? st->rz[(it - 1) & 1][0] : 1.0;
+  const double al_prev = it ? st->alpha[(it - 1) & 1][0] : 1.0;
   double t3[3];
-  sum_partials<3>(Pin, Gin, t3);
+  wave_partials<3, U>(Pin, Gin, t3);
+
+  const int lane = threadIdx.x & (L - 1);
+  const int rpb = blockDim.x / L;  // rows per block and pass
+  const long long rows_chunk = (long long)rpb * P;
+  int k0[P], k1[P];
+  T av[P][E], xo[P], po[P];
+  R4 qv[P][E], own[P];
+  auto load_chunk = [&](int c) {
+#pragma unroll
+    for (int q = 0; q < P; q++) {
+      const long long row = c * rows_chunk + q * rpb + threadIdx.x / L;
+      k0[q] = 0;
+      k1[q] = 0;
+      if (row < n) {
+        k0[q] = rp[row];
+        k1[q] = rp[row + 1];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < P; q++) {
+      const long long row = c * rows_chunk + q * rpb + threadIdx.x / L;
+#pragma unroll
+      for (int e = 0; e < E; e++) {
+        const int k = k0[q] + lane + e * L;
+        if (k < k1[q]) {
+          av[q][e] = A[k];
+          qv[q][e] = Rc[col[k]];
+        } else {
+          av[q][e] = T(0);
+          qv[q][e] = R4{};
+        }
+      }
+      if (row < n && lane == 0) {
+        own[q] = Rc[row];
+        xo[q] = x[row];
+        po[q] = p[row];
+      } else {
+        own[q] = R4{};
+        xo[q] = T(0);
+        po[q] = T(0);
+      }
+    }
+  };
+  int c = xcd_block();
+  load_chunk(c);
+  if (stopped) return;
+
   const double gam = t3[0], del = t3[1], rr = t3[2];
-  const double bb = st->bnorm[0] * st->bnorm[0];
-  const bool done = bb == 0.0 || sqrt(rr) <= st->tol * sqrt(bb);
+  const double bb = bnorm * bnorm;
+  const bool done = bb == 0.0 || sqrt(rr) <= tol * sqrt(bb);
   double beta = 0.0, alpha = 0.0;
   if (it == 0) {
     alpha = gam / del;
   } else {
-    beta = gam / st->rz[(it - 1) & 1][0];
-    alpha = gam / (del - beta * gam / st->alpha[(it - 1) & 1][0]);
+    beta = gam / rz_prev;
+    alpha = gam / (del - beta * gam / al_prev);
   }
   const bool bad = !is_finite(rr) || (!done && (!is_finite(alpha) || !is_finite(beta)));
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -393,34 +473,41 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg1_iter(int Gin, int it, int n, 
   }
   if (done || bad) return;
   const T al = (T)alpha, bt = (T)beta;
-  const int lane = threadIdx.x & (L - 1);
-  const int rows_per_grid = gridDim.x * blockDim.x / L;
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int row = (xcd_block() * blockDim.x + threadIdx.x) / L; row < n; row += rows_per_grid) {
-    double sum = 0.0;
-    for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
-      const int j = col[k];
-      sum += (double)(A[k] * cg1_u_next<T>(dinv[j], r_cur[j], w_cur[j], s_cur[j], al, bt));
+  for (;;) {
+#pragma unroll
+    for (int q = 0; q < P; q++) {
+      const long long row = c * rows_chunk + q * rpb + threadIdx.x / L;
+      double sum = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; e++)
+        if (k0[q] + lane + e * L < k1[q])
+          sum += (double)(av[q][e] * cg1_u_next<T>(qv[q][e].w, qv[q][e].x, qv[q][e].y, qv[q][e].z, al, bt));
+      for (int k = k0[q] + lane + E * L; k < k1[q]; k += L) {
+        const R4 g = Rc[col[k]];
+        sum += (double)(A[k] * cg1_u_next<T>(g.w, g.x, g.y, g.z, al, bt));
+      }
+      sum = group_sum<L>(sum);
+      if (row < n && lane == 0) {
+        const T d = own[q].w, rc = own[q].x, wc = own[q].y, sc = own[q].z;
+        const T si = wc + bt * sc;
+        const T pi = d * rc + bt * po[q];
+        const T rn = rc - al * si;
+        const T un = cg1_u_next<T>(d, rc, wc, sc, al, bt);
+        const T wn = (T)sum;
+        x[row] = xo[q] + al * pi;
+        p[row] = pi;
+        store_rws(&Rn[row], rn, wn, si);
+        acc[0] += (double)rn * (double)un;
+        acc[1] += (double)wn * (double)un;
+        acc[2] += (double)rn * (double)rn;
+      }
     }
-    sum = group_sum<L>(sum);
-    if (lane == 0) {
-      const T d = dinv[row], rc = r_cur[row], wc = w_cur[row], sc = s_cur[row];
-      const T si = wc + bt * sc;
-      const T pi = d * rc + bt * p[row];
-      const T rn = rc - al * si;
-      const T un = cg1_u_next<T>(d, rc, wc, sc, al, bt);
-      const T wn = (T)sum;
-      x[row] = x[row] + al * pi;
-      p[row] = pi;
-      s_nxt[row] = si;
-      r_nxt[row] = rn;
-      w_nxt[row] = wn;
-      acc[0] += (double)rn * (double)un;
-      acc[1] += (double)wn * (double)un;
-      acc[2] += (double)rn * (double)rn;
-    }
+    c += gridDim.x;
+    if (c * rows_chunk >= n) break;
+    load_chunk(c);
   }
-  put_partials<3>(acc, Pout);
+  put_partials_last<3>(acc, Pout);
 }
 
 // after a chunk: convergence and iteration count from the last iteration's partials
@@ -437,13 +524,15 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg1_finish(int it_end, int G, con
   else if (rn <= st->tol * st->bnorm[0]) st->done[0] = 1;
 }
 
-// FP64 init, first kernel: r0 = b - K x0, p = s_{-1} = 0; partials b.b
+// FP64 init, first kernel: r0 = b - K x0, p = s_{-1} = 0, records {r0, -, 0, D^-1} in slot 0 and
+// {-, -, -, D^-1} in slot 1; partials b.b
 template <int L>
 __global__ void __launch_bounds__(kMaxBlock) k_cg1_init_r(int n, const int *__restrict__ rp,
                                                          const int *__restrict__ col, const double *__restrict__ A,
-                                                         const double *__restrict__ b, const double *__restrict__ x,
-                                                         double *__restrict__ r0, double *__restrict__ p,
-                                                         double *__restrict__ s0, double *__restrict__ Pout) {
+                                                         const double *__restrict__ dinv, const double *__restrict__ b,
+                                                         const double *__restrict__ x, double *__restrict__ p,
+                                                         double4 *__restrict__ R0, double4 *__restrict__ R1,
+                                                         double *__restrict__ Pout) {
   const int lane = threadIdx.x & (L - 1);
   const int rows_per_grid = gridDim.x * blockDim.x / L;
   double acc[1] = {0.0};
@@ -452,10 +541,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg1_init_r(int n, const int *__re
     for (int k = rp[row] + lane; k < rp[row + 1]; k += L) sum += A[k] * x[col[k]];
     sum = group_sum<L>(sum);
     if (lane == 0) {
-      const double bb = b[row];
-      r0[row] = bb - sum;
+      const double bb = b[row], d = dinv[row];
+      R0[row] = make_double4(bb - sum, 0.0, 0.0, d);
+      R1[row] = make_double4(0.0, 0.0, 0.0, d);
       p[row] = 0.0;
-      s0[row] = 0.0;
       acc[0] += bb * bb;
     }
   }
@@ -463,13 +552,14 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg1_init_r(int n, const int *__re
 }
 
 // FP32 inner solve of iterative refinement, first kernel: outer convergence test on
-// the FP64 residual partials (r.r, b.b); r0 = r64/||r64|| in FP32, d = p = s_{-1} = 0;
-// partials r0.r0 (the inner right-hand side norm).
+// the FP64 residual partials (r.r, b.b); r0 = r64/||r64|| in FP32, d = p = s_{-1} = 0,
+// records as in k_cg1_init_r with the FP32 D^-1; partials r0.r0 (the inner right-hand side norm).
 __global__ void __launch_bounds__(kMaxBlock) k_cg1_ir_init(int Gin, int n, const double *__restrict__ r64,
-                                                          float *__restrict__ r0, float *__restrict__ d,
-                                                          float *__restrict__ p, float *__restrict__ s0,
-                                                          const double *__restrict__ Pin, double *__restrict__ Pout,
-                                                          KrylovState *__restrict__ so, KrylovState *__restrict__ si) {
+                                                          const float *__restrict__ dinv, float4 *__restrict__ R0,
+                                                          float4 *__restrict__ R1, float *__restrict__ d,
+                                                          float *__restrict__ p, const double *__restrict__ Pin,
+                                                          double *__restrict__ Pout, KrylovState *__restrict__ so,
+                                                          KrylovState *__restrict__ si) {
   double t2[2];
   sum_partials<2>(Pin, Gin, t2);
   const double rn = sqrt(t2[0]), bn = sqrt(t2[1]);
@@ -490,11 +580,11 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg1_ir_init(int Gin, int n, const
   double acc[1] = {0.0};
   const int stride = gridDim.x * blockDim.x;
   for (int i = xcd_block() * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const float rr = (float)(r64[i] * inv);
-    r0[i] = rr;
+    const float rr = (float)(r64[i] * inv), di = dinv[i];
+    R0[i] = make_float4(rr, 0.0f, 0.0f, di);
+    R1[i] = make_float4(0.0f, 0.0f, 0.0f, di);
     d[i] = 0.0f;
     p[i] = 0.0f;
-    s0[i] = 0.0f;
     acc[0] += (double)rr * (double)rr;
   }
   put_partials<1>(acc, Pout);
@@ -992,13 +1082,31 @@ cgp_status run_pcg64(cgp_mesh *m, int slot, int n, const int *rp, const int *col
   return status_of(*out, slot);
 }
 
-// Single-kernel PCG loop.  Precondition: r0 = b - K x0 (or the normalised
-// refinement residual), p = s0 = 0, and the b.b partials in R_INIT from a grid
-// of g_first blocks.
+// Single-kernel PCG loop.  Precondition: records of slot 0 hold {r0, -, 0, D^-1} with
+// r0 = b - K x0 (or the normalised refinement residual), slot 1 holds D^-1, p = 0, and the
+// b.b partials are in R_INIT from a grid of g_first blocks.
+template <typename F>
+void dispatch_cg1(int lanes, int passes, int grid, F &&f) {
+  auto with_LP = [&](auto LC, auto PC) {
+    if (grid > 256) f(LC, PC, std::integral_constant<int, 8>{});
+    else f(LC, PC, std::integral_constant<int, 4>{});
+  };
+  auto with_L = [&](auto LC) {
+    if (passes >= 2) with_LP(LC, std::integral_constant<int, 2>{});
+    else with_LP(LC, std::integral_constant<int, 1>{});
+  };
+  switch (lanes) {
+    case 2: with_L(std::integral_constant<int, 2>{}); break;
+    case 4: with_L(std::integral_constant<int, 4>{}); break;
+    case 16: with_L(std::integral_constant<int, 16>{}); break;
+    default: with_L(std::integral_constant<int, 8>{}); break;
+  }
+}
+
 template <typename T>
-cgp_status cg1_loop(cgp_mesh *m, int slot, int n, const int *rp, const int *col, const T *A, const T *dinv, T *x,
-                    T *p, T *const r[2], T *const w[2], T *const sv[2], const cgp_tuning_knobs &tk, int g_first,
-                    int maxit, int *chunk_hint, bool timed, KrylovState *out) {
+cgp_status cg1_loop(cgp_mesh *m, int slot, int n, const int *rp, const int *col, const T *A, T *x, T *p,
+                    rec_t<T> *const R[2], const cgp_tuning_knobs &tk, int g_first, int maxit, int *chunk_hint,
+                    bool timed, KrylovState *out) {
   KrylovState *st = m->d_state + slot;
   hipStream_t s = m->stream;
   const Shape sh = shape_rows(tk, n, tk.lanes);
@@ -1007,24 +1115,23 @@ cgp_status cg1_loop(cgp_mesh *m, int slot, int n, const int *rp, const int *col,
   auto pout = [&](int it) { return region(m, (it & 1) ? R_C : R_B); };
   dispatch_L(tk.lanes, [&](auto LC) {
     constexpr int LL = decltype(LC)::value;
-    hipLaunchKernelGGL((k_cg1_init_w<T, LL>), dim3(sh.grid), dim3(sh.block), 0, s, g_first, n, rp, col, A, dinv,
-                       (const T *)r[0], w[0], (const double *)region(m, R_INIT), Pw, st);
+    hipLaunchKernelGGL((k_cg1_init_w<T, LL>), dim3(sh.grid), dim3(sh.block), 0, s, g_first, n, rp, col, A, R[0],
+                       (const double *)region(m, R_INIT), Pw, st);
   });
   int it = 0, chunk = std::max(1, std::min(*chunk_hint, maxit));
   for (;;) {
-    dispatch_L(tk.lanes, [&](auto LC) {
-      constexpr int LL = decltype(LC)::value;
+    dispatch_cg1(tk.lanes, tk.passes, sh.grid, [&](auto LC, auto PC, auto UC) {
+      constexpr int LL = decltype(LC)::value, PP = decltype(PC)::value, UU = decltype(UC)::value;
       for (int c = 0; c < chunk && it < maxit; c++, it++) {
         const int cur = it & 1, nxt = cur ^ 1;
         hipEvent_t e0, e1;
         if (timed && kt_slot(m, it, &e0, &e1))
-          hipExtLaunchKernelGGL((k_cg1_iter<T, LL>), dim3(sh.grid), dim3(sh.block), 0, s, e0, e1, 0, sh.grid, it, n,
-                                rp, col, A, dinv, x, p, (const T *)r[cur], (const T *)w[cur], (const T *)sv[cur],
-                                r[nxt], w[nxt], sv[nxt], (const double *)pin(it), pout(it), st);
+          hipExtLaunchKernelGGL((k_cg1_iter<T, LL, PP, UU>), dim3(sh.grid), dim3(sh.block), 0, s, e0, e1, 0, sh.grid,
+                                it, n, rp, col, A, x, p, (const rec_t<T> *)R[cur], R[nxt], (const double *)pin(it),
+                                pout(it), st);
         else
-          hipLaunchKernelGGL((k_cg1_iter<T, LL>), dim3(sh.grid), dim3(sh.block), 0, s, sh.grid, it, n, rp, col, A,
-                             dinv, x, p, (const T *)r[cur], (const T *)w[cur], (const T *)sv[cur], r[nxt], w[nxt],
-                             sv[nxt], (const double *)pin(it), pout(it), st);
+          hipLaunchKernelGGL((k_cg1_iter<T, LL, PP, UU>), dim3(sh.grid), dim3(sh.block), 0, s, sh.grid, it, n, rp,
+                             col, A, x, p, (const rec_t<T> *)R[cur], R[nxt], (const double *)pin(it), pout(it), st);
       }
     });
     hipLaunchKernelGGL(k_cg1_finish, dim3(1), dim3(256), 0, s, it, sh.grid, (const double *)pin(it), st);
@@ -1135,8 +1242,8 @@ cgp_status poisson_ir(cgp_mesh *m, const double *b, double *x, const cgp_solver_
   double *r64 = m->d_wc[1];
   float *r = m->d_wc32[0], *z = m->d_wc32[1], *d = m->d_wc32[2], *p0 = m->d_wc32[3], *p1 = m->d_wc32[4],
         *q = m->d_wc32[5];
-  float *f1r[2] = {m->d_wc32[0], m->d_wc32[1]}, *f1w[2] = {m->d_wc32[3], m->d_wc32[4]},
-        *f1s[2] = {m->d_wc32[5], m->d_wc32[6]}, *f1p = m->d_wc32[7];
+  float4 *f1R[2] = {reinterpret_cast<float4 *>(m->d_rec), reinterpret_cast<float4 *>(m->d_rec) + n};
+  float *f1p = m->d_wc32[7];
   const double inner_tol = o->inner_tol > 0 ? o->inner_tol : 1e-4;
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, so, o->tol, o->max_iter, 1);
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, si, inner_tol, o->max_iter, 1);
@@ -1148,8 +1255,8 @@ cgp_status poisson_ir(cgp_mesh *m, const double *b, double *x, const cgp_solver_
     });
     if (fused)
       hipLaunchKernelGGL(k_cg1_ir_init, dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, sh.rows.grid, n,
-                         (const double *)r64, f1r[0], d, f1p, f1s[0], (const double *)region(m, R_C),
-                         region(m, R_INIT), so, si);
+                         (const double *)r64, (const float *)m->d_dinvK32, f1R[0], f1R[1], d, f1p,
+                         (const double *)region(m, R_C), region(m, R_INIT), so, si);
     else
       hipLaunchKernelGGL(k_ir_inner_init, dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, sh.rows.grid, n,
                          (const double *)r64, (const float *)m->d_dinvK32, r, z, d, p0, p1,
@@ -1176,9 +1283,8 @@ cgp_status poisson_ir(cgp_mesh *m, const double *b, double *x, const cgp_solver_
         if (!m->h_state[SLOT_P].done[0]) m->kt_iters += (long)hi.iters - used;
       }
     } else if (fused) {
-      cgp_status ls = cg1_loop<float>(m, SLOT_PIN, n, m->d_rp_c, m->d_col_c, (const float *)m->d_Kbc32,
-                                      (const float *)m->d_dinvK32, d, f1p, f1r, f1w, f1s, tk, sh.elem.grid, budget,
-                                      &m->p32_chunk, true, &hi);
+      cgp_status ls = cg1_loop<float>(m, SLOT_PIN, n, m->d_rp_c, m->d_col_c, (const float *)m->d_Kbc32, d, f1p, f1R,
+                                      tk, sh.elem.grid, budget, &m->p32_chunk, true, &hi);
       if (ls) return ls;
       cgp_status ps = poll(m, SLOT_P);
       if (ps) return ps;
@@ -1267,18 +1373,17 @@ cgp_status drv_poisson(cgp_mesh *m, const double *b_in, double *x, const cgp_sol
       KrylovState *so = m->d_state + SLOT_P;
       const cgp_tuning_knobs &tk = m->tune.coarse;
       const Shape sh = shape_rows(tk, n, tk.lanes);
-      double *r[2] = {m->d_wc[1], m->d_wc[2]}, *w[2] = {m->d_wc[3], m->d_wc[4]}, *sv[2] = {m->d_wc[5], m->d_wc[6]};
+      double4 *R[2] = {reinterpret_cast<double4 *>(m->d_rec), reinterpret_cast<double4 *>(m->d_rec) + n};
       double *p = m->d_wc[7];
       hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, so, o->tol, o->max_iter, 1);
       dispatch_L(tk.lanes, [&](auto LC) {
         constexpr int LL = decltype(LC)::value;
         hipLaunchKernelGGL((k_cg1_init_r<LL>), dim3(sh.grid), dim3(sh.block), 0, s, n, m->d_rp_c, m->d_col_c,
-                           (const double *)m->d_Kbc, (const double *)b, (const double *)x, r[0], p, sv[0],
-                           region(m, R_INIT));
+                           (const double *)m->d_Kbc, (const double *)m->d_dinvK, (const double *)b,
+                           (const double *)x, p, R[0], R[1], region(m, R_INIT));
       });
-      cgp_status ls = cg1_loop<double>(m, SLOT_P, n, m->d_rp_c, m->d_col_c, (const double *)m->d_Kbc,
-                                       (const double *)m->d_dinvK, x, p, r, w, sv, tk, sh.grid, o->max_iter,
-                                       &m->p_chunk, true, &fin);
+      cgp_status ls = cg1_loop<double>(m, SLOT_P, n, m->d_rp_c, m->d_col_c, (const double *)m->d_Kbc, x, p, R, tk,
+                                       sh.grid, o->max_iter, &m->p_chunk, true, &fin);
       if (ls) return ls;
       hipLaunchKernelGGL((k_zero_b_fix<1>), dim3(blocks_1d(n)), dim3(256), 0, s, n, x, (const KrylovState *)so);
       rs = status_of(fin, SLOT_P);
