@@ -294,7 +294,7 @@ cgp_status cgp_batch_step(cgp_batch *batch, const cgp_step_opts *opts, const dou
                           const double *const *f, double *const *u, double *const *p_fine, double *const *p_coarse,
                           cgp_stats *stats);
 cgp_status cgp_batch_get_tuning(const cgp_batch *batch, cgp_batch_tuning *out);
-/* lanes 4/8/16 per row, block a power of two in 64..1024, passes 1..64, chunk even in 2..256. */
+/* lanes 2/4/8/16 per row, block a power of two in 64..1024, passes 1..64, chunk even in 2..256. */
 cgp_status cgp_batch_set_tuning(cgp_batch *batch, const cgp_batch_tuning *tuning);
 /* Time 12 launch shapes on the batch's own system and keep the fastest; the choice is cached in the JSON
  * file cache_path (NULL: no cache) under the batch's size class and reused without timing. */

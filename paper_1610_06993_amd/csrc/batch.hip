@@ -8,7 +8,11 @@
 // each instance sums its own tiles' partials in a fixed order, so every
 // instance keeps its own Krylov scalars and convergence flag (a converged
 // instance's tiles return at once).  The iteration is the single-kernel
-// Chronopoulos-Gear form of the single-mesh solver.  Chunks of iterations are
+// Chronopoulos-Gear form of the single-mesh solver, with the same node records
+// {r, w, s, D^-1} (a gathered column is one 32-byte load).  At the batch's
+// size the iteration streams from HBM, and each instance's partials are summed
+// per block: a per-wave sum, as in the single-mesh kernel, would read them 16
+// times over.  Chunks of iterations are
 // captured once into HIP graphs and replayed, with one poll of the instance
 // states per chunk.  Launch shapes (lanes per row, block, rows per lane group)
 // come from cgp_batch_set_tuning or from the autotuner, which times each
@@ -40,11 +44,13 @@ struct cgp_batch {
   int *d_rp = nullptr, *d_col = nullptr;
   double *d_A = nullptr, *d_dinv = nullptr;
   // work vectors over all rows
-  double *d_x = nullptr, *d_b = nullptr, *d_p = nullptr, *d_r[2] = {}, *d_w[2] = {}, *d_s[2] = {};
+  double *d_x = nullptr, *d_b = nullptr, *d_p = nullptr;
+  double4 *d_rec[2] = {};             // records {r, w, s, D^-1}, double-buffered
   // tiles
   cgp_batch_tuning tune{4, 512, 1, 1, 16};
   int ntiles = 0;
-  int4 *d_tiles = nullptr;
+  int4 *d_tiles = nullptr;            // {instance, first row, end row, -}
+  int4 *d_tinfo = nullptr;            // per tile: {first tile, tile count} of its instance
   int *d_t0 = nullptr, *d_nt = nullptr;
   double *d_part = nullptr;           // 4 regions of [3][ntiles]
   cgp::KrylovState *d_state = nullptr, *h_state = nullptr;
@@ -81,6 +87,24 @@ __device__ __forceinline__ void inst_sum(const double *__restrict__ P, int G, in
   block_sum<K>(v, tot);
 }
 
+// put_at with a single barrier: must be the block's last reduction
+template <int K>
+__device__ __forceinline__ void put_at_last(const double (&v)[K], double *__restrict__ P, int G, int t) {
+  __shared__ double sh[K][kMaxBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const double x = wave_sum(v[k]);
+    if (lane == 0) sh[k][wid] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0.0;
+    for (int w = 0; w < nw; w++) s += sh[threadIdx.x][w];
+    P[(long)threadIdx.x * G + t] = s;
+  }
+}
+
 __global__ void k_bt_state_init(int ninst, double tol, int maxit, KrylovState *st) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ninst) return;
@@ -91,14 +115,15 @@ __global__ void k_bt_state_init(int ninst, double tol, int maxit, KrylovState *s
   st[i] = s;
 }
 
-// r0 = b - A x, p = s = 0; partial b.b per tile
+// r0 = b - A x, p = s = 0: records {r0, -, 0, D^-1} in slot 0, {-, -, -, D^-1} in slot 1; partial
+// b.b per tile
 template <int L>
 __global__ void __launch_bounds__(kMaxBlock) k_bt_init_r(int G, const int4 *__restrict__ tiles,
                                                         const int *__restrict__ rp, const int *__restrict__ col,
-                                                        const double *__restrict__ A, const double *__restrict__ b,
-                                                        const double *__restrict__ x, double *__restrict__ r0,
-                                                        double *__restrict__ p, double *__restrict__ s0,
-                                                        double *__restrict__ Pout) {
+                                                        const double *__restrict__ A, const double *__restrict__ dinv,
+                                                        const double *__restrict__ b, const double *__restrict__ x,
+                                                        double *__restrict__ p, double4 *__restrict__ R0,
+                                                        double4 *__restrict__ R1, double *__restrict__ Pout) {
   const int t = xcd_block();
   const int4 T = tiles[t];
   const int lane = threadIdx.x & (L - 1), groups = blockDim.x / L;
@@ -108,23 +133,23 @@ __global__ void __launch_bounds__(kMaxBlock) k_bt_init_r(int G, const int4 *__re
     for (int k = rp[row] + lane; k < rp[row + 1]; k += L) sum += A[k] * x[col[k]];
     sum = group_sum<L>(sum);
     if (lane == 0) {
-      const double bb = b[row];
-      r0[row] = bb - sum;
+      const double bb = b[row], d = dinv[row];
+      R0[row] = make_double4(bb - sum, 0.0, 0.0, d);
+      R1[row] = make_double4(0.0, 0.0, 0.0, d);
       p[row] = 0.0;
-      s0[row] = 0.0;
       acc[0] += bb * bb;
     }
   }
   put_at<1>(acc, Pout, G, t);
 }
 
-// w0 = A D^-1 r0; partials (gamma, delta, r.r); publishes ||b|| per instance
+// w0 = A D^-1 r0 into the records' w field (fields r and D^-1 gathered); partials (gamma, delta,
+// r.r); publishes ||b|| per instance
 template <int L>
 __global__ void __launch_bounds__(kMaxBlock) k_bt_init_w(int G, const int4 *__restrict__ tiles,
                                                         const int *__restrict__ t0s, const int *__restrict__ nts,
                                                         const int *__restrict__ rp, const int *__restrict__ col,
-                                                        const double *__restrict__ A, const double *__restrict__ dinv,
-                                                        const double *__restrict__ r0, double *__restrict__ w0,
+                                                        const double *__restrict__ A, double4 *__restrict__ R0,
                                                         const double *__restrict__ Pin, double *__restrict__ Pout,
                                                         KrylovState *__restrict__ st) {
   const int t = xcd_block();
@@ -144,12 +169,12 @@ __global__ void __launch_bounds__(kMaxBlock) k_bt_init_w(int G, const int4 *__re
     double sum = 0.0;
     for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
       const int j = col[k];
-      sum += A[k] * (dinv[j] * r0[j]);
+      sum += A[k] * (R0[j].w * R0[j].x);
     }
     sum = group_sum<L>(sum);
     if (lane == 0) {
-      const double r = r0[row], u = dinv[row] * r;
-      w0[row] = sum;
+      const double r = R0[row].x, u = R0[row].w * r;
+      R0[row].y = sum;
       acc[0] += r * u;
       acc[1] += sum * u;
       acc[2] += r * r;
@@ -162,19 +187,17 @@ __global__ void __launch_bounds__(kMaxBlock) k_bt_init_w(int G, const int4 *__re
 // The first tile's block of each instance publishes its scalars and counts its updates.
 template <int L>
 __global__ void __launch_bounds__(kMaxBlock)
-    k_bt_iter(int it, int G, const int4 *__restrict__ tiles, const int *__restrict__ t0s, const int *__restrict__ nts,
+    k_bt_iter(int it, int G, const int4 *__restrict__ tiles, const int4 *__restrict__ tinfo,
               const int *__restrict__ rp, const int *__restrict__ col, const double *__restrict__ A,
-              const double *__restrict__ dinv, double *__restrict__ x, double *__restrict__ p,
-              const double *__restrict__ r_cur, const double *__restrict__ w_cur, const double *__restrict__ s_cur,
-              double *__restrict__ r_nxt, double *__restrict__ w_nxt, double *__restrict__ s_nxt,
-              const double *__restrict__ Pin, double *__restrict__ Pout, KrylovState *__restrict__ st) {
+              double *__restrict__ x, double *__restrict__ p, const double4 *__restrict__ Rc,
+              double4 *__restrict__ Rn, const double *__restrict__ Pin, double *__restrict__ Pout,
+              KrylovState *__restrict__ st) {
   const int t = xcd_block();
-  const int4 T = tiles[t];
+  const int4 T = tiles[t], I = tinfo[t];
   KrylovState *S = st + T.x;
   if (S->status || S->done[0]) return;
-  const int t0 = t0s[T.x];
   double t3[3];
-  inst_sum<3>(Pin, G, t0, nts[T.x], t3);
+  inst_sum<3>(Pin, G, I.x, I.y, t3);
   const double gam = t3[0], del = t3[1], rr = t3[2];
   const double bb = S->bnorm[0] * S->bnorm[0];
   const bool done = bb == 0.0 || sqrt(rr) <= S->tol * sqrt(bb);
@@ -186,7 +209,7 @@ __global__ void __launch_bounds__(kMaxBlock)
     alpha = gam / (del - beta * gam / S->alpha[(it - 1) & 1][0]);
   }
   const bool bad = !is_finite(rr) || (!done && (!is_finite(alpha) || !is_finite(beta)));
-  if (t == t0 && threadIdx.x == 0) {
+  if (t == I.x && threadIdx.x == 0) {
     S->rz[it & 1][0] = gam;
     S->alpha[it & 1][0] = alpha;
     S->rnorm[0] = sqrt(rr);
@@ -200,27 +223,27 @@ __global__ void __launch_bounds__(kMaxBlock)
   for (int row = T.y + (int)threadIdx.x / L; row < T.z; row += groups) {
     double sum = 0.0;
     for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
-      const int j = col[k];
-      sum += A[k] * (dinv[j] * (r_cur[j] - alpha * (w_cur[j] + beta * s_cur[j])));
+      const double4 g = Rc[col[k]];
+      sum += A[k] * (g.w * (g.x - alpha * (g.y + beta * g.z)));
     }
     sum = group_sum<L>(sum);
     if (lane == 0) {
-      const double d = dinv[row], rc = r_cur[row], wc = w_cur[row], sc = s_cur[row];
+      const double4 o = Rc[row];
+      const double d = o.w, rc = o.x, wc = o.y, sc = o.z;
       const double si = wc + beta * sc;
       const double pi = d * rc + beta * p[row];
       const double rn = rc - alpha * si;
       const double un = d * (rc - alpha * (wc + beta * sc));
       x[row] += alpha * pi;
       p[row] = pi;
-      s_nxt[row] = si;
-      r_nxt[row] = rn;
-      w_nxt[row] = sum;
+      *reinterpret_cast<double2 *>(&Rn[row]) = make_double2(rn, sum);
+      Rn[row].z = si;
       acc[0] += rn * un;
       acc[1] += sum * un;
       acc[2] += rn * rn;
     }
   }
-  put_at<3>(acc, Pout, G, t);
+  put_at_last<3>(acc, Pout, G, t);
 }
 
 // after a chunk (one block per instance): convergence from the last iteration's partials
@@ -314,12 +337,16 @@ cgp_status build_tiles(cgp_batch *B) {
     tiles.push_back(make_int4(last, e, e, 0));
     nt[last]++;
   }
+  std::vector<int4> tinfo(tiles.size());
+  for (size_t k = 0; k < tiles.size(); k++) tinfo[k] = make_int4(t0[tiles[k].x], nt[tiles[k].x], 0, 0);
   if ((int)tiles.size() > B->ntiles) {
     BTRY(balloc(B, &B->d_tiles, tiles.size()));
+    BTRY(balloc(B, &B->d_tinfo, tiles.size()));
     BTRY(balloc(B, &B->d_part, 4 * 3 * tiles.size()));
   }
   B->ntiles = (int)tiles.size();
   CGP_HIP(hipMemcpyAsync(B->d_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, B->stream));
+  CGP_HIP(hipMemcpyAsync(B->d_tinfo, tinfo.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, B->stream));
   CGP_HIP(hipMemcpyAsync(B->d_t0, t0.data(), sizeof(int) * B->ninst, hipMemcpyHostToDevice, B->stream));
   CGP_HIP(hipMemcpyAsync(B->d_nt, nt.data(), sizeof(int) * B->ninst, hipMemcpyHostToDevice, B->stream));
   CGP_HIP(hipStreamSynchronize(B->stream));
@@ -336,11 +363,9 @@ void enqueue_chunk(cgp_batch *B, int it0, int count) {
     for (int it = it0; it < it0 + count; it++) {
       const int cur = it & 1, nxt = cur ^ 1;
       hipLaunchKernelGGL((k_bt_iter<LL>), dim3(G), dim3(blk), 0, s, it, G, (const int4 *)B->d_tiles,
-                         (const int *)B->d_t0, (const int *)B->d_nt, (const int *)B->d_rp, (const int *)B->d_col,
-                         (const double *)B->d_A, (const double *)B->d_dinv, B->d_x, B->d_p,
-                         (const double *)B->d_r[cur], (const double *)B->d_w[cur], (const double *)B->d_s[cur],
-                         B->d_r[nxt], B->d_w[nxt], B->d_s[nxt], (const double *)bpin(B, it), bpout(B, it),
-                         B->d_state);
+                         (const int4 *)B->d_tinfo, (const int *)B->d_rp, (const int *)B->d_col,
+                         (const double *)B->d_A, B->d_x, B->d_p, (const double4 *)B->d_rec[cur], B->d_rec[nxt],
+                         (const double *)bpin(B, it), bpout(B, it), B->d_state);
     }
   });
   hipLaunchKernelGGL(k_bt_finish, dim3(B->ninst), dim3(256), 0, s, G, (const int *)B->d_t0, (const int *)B->d_nt,
@@ -393,12 +418,13 @@ cgp_status solve(cgp_batch *B, double tol, int maxit, int *launched) {
   dispatch_L(B->tune.lanes, [&](auto LC) {
     constexpr int LL = decltype(LC)::value;
     hipLaunchKernelGGL((k_bt_init_r<LL>), dim3(G), dim3(blk), 0, s, G, (const int4 *)B->d_tiles,
-                       (const int *)B->d_rp, (const int *)B->d_col, (const double *)B->d_A, (const double *)B->d_b,
-                       (const double *)B->d_x, B->d_r[0], B->d_p, B->d_s[0], bregion(B, B_INIT));
+                       (const int *)B->d_rp, (const int *)B->d_col, (const double *)B->d_A,
+                       (const double *)B->d_dinv, (const double *)B->d_b, (const double *)B->d_x, B->d_p,
+                       B->d_rec[0], B->d_rec[1], bregion(B, B_INIT));
     hipLaunchKernelGGL((k_bt_init_w<LL>), dim3(G), dim3(blk), 0, s, G, (const int4 *)B->d_tiles,
                        (const int *)B->d_t0, (const int *)B->d_nt, (const int *)B->d_rp, (const int *)B->d_col,
-                       (const double *)B->d_A, (const double *)B->d_dinv, (const double *)B->d_r[0], B->d_w[0],
-                       (const double *)bregion(B, B_INIT), bregion(B, B_A), B->d_state);
+                       (const double *)B->d_A, B->d_rec[0], (const double *)bregion(B, B_INIT), bregion(B, B_A),
+                       B->d_state);
   });
   CGP_HIP(hipGetLastError());
   const int K = B->tune.chunk;
@@ -489,9 +515,8 @@ cgp_status cgp_batch_create(cgp_mesh *const *meshes, int32_t n, cgp_batch **out)
   cgp_status st;
   if ((st = balloc(B, &B->d_rp, rows + 1)) || (st = balloc(B, &B->d_col, nnz)) || (st = balloc(B, &B->d_A, nnz)) ||
       (st = balloc(B, &B->d_dinv, rows)) || (st = balloc(B, &B->d_x, rows)) || (st = balloc(B, &B->d_b, rows)) ||
-      (st = balloc(B, &B->d_p, rows)) || (st = balloc(B, &B->d_r[0], rows)) || (st = balloc(B, &B->d_r[1], rows)) ||
-      (st = balloc(B, &B->d_w[0], rows)) || (st = balloc(B, &B->d_w[1], rows)) ||
-      (st = balloc(B, &B->d_s[0], rows)) || (st = balloc(B, &B->d_s[1], rows)) ||
+      (st = balloc(B, &B->d_p, rows)) || (st = balloc(B, &B->d_rec[0], rows)) ||
+      (st = balloc(B, &B->d_rec[1], rows)) ||
       (st = balloc(B, &B->d_t0, n)) || (st = balloc(B, &B->d_nt, n)) || (st = balloc(B, &B->d_state, n)))
     return fail(st);
   if (hipHostMalloc((void **)&B->h_state, sizeof(KrylovState) * n, hipHostMallocDefault) != hipSuccess) {
@@ -545,10 +570,10 @@ cgp_status cgp_batch_get_tuning(const cgp_batch *B, cgp_batch_tuning *out) {
 }
 
 cgp_status cgp_batch_set_tuning(cgp_batch *B, const cgp_batch_tuning *t) {
-  if (!B || !t || (t->lanes != 4 && t->lanes != 8 && t->lanes != 16) || t->block < 64 || t->block > 1024 ||
+  if (!B || !t || (t->lanes != 2 && t->lanes != 4 && t->lanes != 8 && t->lanes != 16) || t->block < 64 || t->block > 1024 ||
       (t->block & (t->block - 1)) || t->passes < 1 || t->passes > 64 || t->chunk < 2 || t->chunk > 256 ||
       (t->chunk & 1) || (t->use_graph != 0 && t->use_graph != 1)) {
-    set_error("cgp_batch_set_tuning: lanes 4/8/16, block a power of two in 64..1024, passes 1..64, "
+    set_error("cgp_batch_set_tuning: lanes 2/4/8/16, block a power of two in 64..1024, passes 1..64, "
               "chunk even in 2..256, use_graph 0/1");
     return CGP_E_ARG;
   }

@@ -114,7 +114,7 @@ struct cgp_mesh {
   float *d_Kbc32 = nullptr, *d_dinvK32 = nullptr;
   double mc_sum = 0.0;
   // work vectors: fine [n_f][2], coarse [n_c]
-  std::vector<double *> d_wf;     // 10 fine 2-vectors
+  std::vector<double *> d_wf;     // 8 fine 2-vectors
   std::vector<double *> d_wc;     // 8 coarse vectors
   std::vector<float *> d_wc32;    // 6 coarse float vectors
   std::vector<double *> d_wlev;   // per level scratch [n_k] (prolong/restrict chains)
