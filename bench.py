@@ -255,6 +255,7 @@ def main():
     # relative size t reaches it amplified ~100x, so the momentum solve runs two decades below the Poisson's
     ap.add_argument("--mom-tol", type=float, default=1e-10, help="momentum solve tolerance (relative residual)")
     ap.add_argument("--mass-tol", type=float, default=1e-10, help="mass solve tolerance of the correction")
+    ap.add_argument("--inner-tol", type=float, default=1e-4, help="FP32 inner solve tolerance of the refinement")
     ap.add_argument("--paths", default="all", help="comma-separated subset of the timed paths")
     ap.add_argument("--batch", type=int, default=64, help="instances of the batched sweep (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
@@ -321,7 +322,7 @@ def main():
 
     def opts(precision=0, x0=X0.X0_PREV, timing=0):
         return StepOpts(momentum=SolverOpts(tol=args.mom_tol, max_iter=5000, x0_mode=mom_x0),
-                        poisson=SolverOpts(tol=tol, max_iter=100000, precision=precision, inner_tol=1e-4,
+                        poisson=SolverOpts(tol=tol, max_iter=100000, precision=precision, inner_tol=args.inner_tol,
                                            x0_mode=x0, launch=launch),
                         mass=SolverOpts(tol=args.mass_tol, max_iter=2000), timing=timing)
 

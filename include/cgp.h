@@ -107,7 +107,9 @@ typedef struct {
   int32_t precision;          /* CGP_PREC_*; only the Poisson solve honours FP32_IR */
   double tol;                 /* stop when ||b - A x||_2 <= tol ||b||_2 (unpreconditioned) */
   int32_t max_iter;           /* Krylov iterations (inner iterations summed for FP32_IR) */
-  double inner_tol;           /* FP32_IR: relative reduction asked of each inner FP32 solve */
+  double inner_tol;           /* FP32_IR: relative reduction asked of each inner FP32 solve; an inner
+                                 solve asks for less (half the reduction the outer tolerance still needs)
+                                 when that is enough, except under CGP_LAUNCH_PERSISTENT */
   int32_t x0_mode;            /* CGP_X0_* */
   int32_t launch;             /* CGP_LAUNCH_* */
 } cgp_solver_opts;

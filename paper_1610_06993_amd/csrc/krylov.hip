@@ -551,10 +551,18 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg1_init_r(int n, const int *__re
   put_partials<1>(acc, Pout);
 }
 
+// Reduction asked of an inner FP32 solve: `inner_tol`, or half of what the outer tolerance still
+// needs when that is less (a warm start then ends in one refinement step instead of over-solving).
+__device__ __forceinline__ double inner_tol_for(double inner_tol, double outer_tol, double rn, double bn) {
+  const double need = 0.5 * outer_tol * bn / rn;
+  return need > inner_tol ? need : inner_tol;
+}
+
 // FP32 inner solve of iterative refinement, first kernel: outer convergence test on
 // the FP64 residual partials (r.r, b.b); r0 = r64/||r64|| in FP32, d = p = s_{-1} = 0,
 // records as in k_cg1_init_r with the FP32 D^-1; partials r0.r0 (the inner right-hand side norm).
-__global__ void __launch_bounds__(kMaxBlock) k_cg1_ir_init(int Gin, int n, const double *__restrict__ r64,
+__global__ void __launch_bounds__(kMaxBlock) k_cg1_ir_init(int Gin, int n, double inner_tol,
+                                                          const double *__restrict__ r64,
                                                           const float *__restrict__ dinv, float4 *__restrict__ R0,
                                                           float4 *__restrict__ R1, float *__restrict__ d,
                                                           float *__restrict__ p, const double *__restrict__ Pin,
@@ -574,6 +582,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg1_ir_init(int Gin, int n, const
     si->done[0] = done || bad;
     si->status = 0;
     si->iters = 0;
+    si->tol = inner_tol_for(inner_tol, so->tol, rn, bn);
   }
   if (done || bad) return;
   const double inv = 1.0 / rn;
@@ -858,7 +867,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_ir_residual(int n, const int *__r
 
 // Outer convergence test and start of the inner solve K32 d = r64 / ||r64||:
 // r = r64/||r64|| (FP32), z = D^-1 r, d = 0, p0 = p1 = 0; partials (r.z, r.r, r.r).
-__global__ void __launch_bounds__(kMaxBlock) k_ir_inner_init(int Gin, int n, const double *__restrict__ r64,
+__global__ void __launch_bounds__(kMaxBlock) k_ir_inner_init(int Gin, int n, double inner_tol,
+                                                            const double *__restrict__ r64,
                                                             const float *__restrict__ dinv, float *__restrict__ r,
                                                             float *__restrict__ z, float *__restrict__ d,
                                                             float *__restrict__ p0, float *__restrict__ p1,
@@ -878,6 +888,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_ir_inner_init(int Gin, int n, con
     si->done[0] = done || bad;
     si->status = 0;
     si->iters = 0;
+    si->tol = inner_tol_for(inner_tol, so->tol, rn, bn);
   }
   if (done || bad) return;
   const double inv = 1.0 / rn;
@@ -1254,12 +1265,12 @@ cgp_status poisson_ir(cgp_mesh *m, const double *b, double *x, const cgp_solver_
                          m->d_col_c, (const double *)m->d_Kbc, b, (const double *)x, r64, region(m, R_C));
     });
     if (fused)
-      hipLaunchKernelGGL(k_cg1_ir_init, dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, sh.rows.grid, n,
+      hipLaunchKernelGGL(k_cg1_ir_init, dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, sh.rows.grid, n, inner_tol,
                          (const double *)r64, (const float *)m->d_dinvK32, f1R[0], f1R[1], d, f1p,
                          (const double *)region(m, R_C), region(m, R_INIT), so, si);
     else
       hipLaunchKernelGGL(k_ir_inner_init, dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, sh.rows.grid, n,
-                         (const double *)r64, (const float *)m->d_dinvK32, r, z, d, p0, p1,
+                         inner_tol, (const double *)r64, (const float *)m->d_dinvK32, r, z, d, p0, p1,
                          (const double *)region(m, R_C), region(m, R_INIT), so, si);
   };
   int outer = 0;
