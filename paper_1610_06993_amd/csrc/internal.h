@@ -138,7 +138,9 @@ struct cgp_mesh {
   double *d_scalar = nullptr;     // device scalar for sums (means)
   double *h_scalar = nullptr;     // pinned [4]
   cgp_tuning tune{{4, 512, 4}, {2, 1024, 1}, 0, 0};  // Krylov launch shapes (fine, coarse), persistent kernel
-  int mom_chunk = 4, p_chunk = 32, p32_chunk = 16, mass_chunk = 8;  // Krylov iterations queued before a poll
+  // Krylov iterations queued before the first poll of a solve (the last solve's count), per solve
+  // kind; the FP32 inner solves keep one per refinement step, whose lengths differ
+  int mom_chunk = 4, p_chunk = 32, p32_chunk[4] = {16, 16, 16, 16}, mass_chunk = 8;
   // HIP-event timing of every launch of the Poisson SpMV kernel (cgp_step_opts.timing == 2)
   bool kt_on = false;
   std::vector<hipEvent_t> kt_ev;   // event pairs

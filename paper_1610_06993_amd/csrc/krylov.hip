@@ -1066,7 +1066,7 @@ cgp_status pcg_loop(cgp_mesh *m, int slot, int n, const int *rp, const int *col,
     const KrylovState &h = m->h_state[slot];
     if (timed && m->kt_on && (ps = kt_harvest(m, h.iters))) return ps;
     if (h.status || host_all_done(h) || it >= maxit) break;
-    chunk = 8;
+    chunk = std::max(8, it / 16);  // later chunks grow: fewer polls, bounded overshoot
   }
   *out = m->h_state[slot];
   *chunk_hint = std::max(1, out->iters - 2);
@@ -1152,7 +1152,7 @@ cgp_status cg1_loop(cgp_mesh *m, int slot, int n, const int *rp, const int *col,
     const KrylovState &h = m->h_state[slot];
     if (timed && m->kt_on && (ps = kt_harvest(m, h.iters))) return ps;
     if (h.status || h.done[0] || it >= maxit) break;
-    chunk = 8;
+    chunk = std::max(8, it / 16);  // later chunks grow: fewer polls, bounded overshoot
   }
   *out = m->h_state[slot];
   *chunk_hint = std::max(1, out->iters - 2);
@@ -1295,14 +1295,14 @@ cgp_status poisson_ir(cgp_mesh *m, const double *b, double *x, const cgp_solver_
       }
     } else if (fused) {
       cgp_status ls = cg1_loop<float>(m, SLOT_PIN, n, m->d_rp_c, m->d_col_c, (const float *)m->d_Kbc32, d, f1p, f1R,
-                                      tk, sh.elem.grid, budget, &m->p32_chunk, true, &hi);
+                                      tk, sh.elem.grid, budget, &m->p32_chunk[std::min(outer, 3)], true, &hi);
       if (ls) return ls;
       cgp_status ps = poll(m, SLOT_P);
       if (ps) return ps;
     } else {
       cgp_status ls = pcg_loop<float, 1>(m, SLOT_PIN, n, m->d_rp_c, m->d_col_c, (const float *)m->d_Kbc32,
                                          (const float *)m->d_dinvK32, d, r, z, p0, p1, q, tk, sh.elem.grid, budget,
-                                         &m->p32_chunk, true, &hi);
+                                         &m->p32_chunk[std::min(outer, 3)], true, &hi);
       if (ls) return ls;
       cgp_status ps = poll(m, SLOT_P);
       if (ps) return ps;
