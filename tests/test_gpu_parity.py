@@ -146,6 +146,55 @@ def test_poisson_solve(env, which, precision, launch):
         assert st["p_outer"] >= 2
 
 
+# launch shapes of the fused PCG kernel: the default; one-wave blocks whose grid exceeds the partial
+# sums a wave reads unrolled (512); several chunks of rows per block (passes above 2); 16 lanes; and a
+# grid at the cap of 8192 blocks on a larger mesh
+SHAPES = [((2, 1024, 1), 8000), ((2, 64, 1), 8000), ((4, 512, 2), 8000), ((8, 256, 3), 8000),
+          ((16, 1024, 4), 8000), ((16, 64, 1), 8000), ((4, 128, 7), 8000), ((16, 64, 1), 70000)]
+
+
+@pytest.mark.parametrize("shape,tris", SHAPES)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_poisson_launch_shapes(env, shape, tris, precision):
+    torch, cgp, oracle = env
+    mesh = W.cylinder_channel(tris, seed=2)
+    _say("poisson launch shape", shape, "triangles", tris, "precision", precision)
+    g, o = make_pair(env, mesh, 1, 1.0, 1e-3, 1e-3)
+    g.set_tuning(coarse=shape)
+    assert g.get_tuning()["coarse"] == shape
+    rng = np.random.default_rng(11)
+    b = rng.normal(size=g.info["n_c"])
+    x = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
+    tol = TIGHT if precision == 0 else 1e-10
+    st = g.poisson_solve(dev(torch, b), x, cgp.SolverOpts(tol=tol, precision=precision, x0_mode=0, max_iter=100000))
+    ref, code, it, rr = o.poisson_solve(b, tol=1e-14)
+    assert code == 0
+    err = rel(x.cpu().numpy(), ref)
+    assert err <= (1e-10 if precision == 0 else 1e-6), (err, st)
+
+
+def test_fp32_refinement_from_warm_start(env):
+    """From an initial guess already within 1e-5 of the solution, the FP32 inner solves are asked only
+    for the reduction the outer tolerance still needs: far fewer inner iterations than from a zero
+    guess, and the result meets the same bar."""
+    torch, cgp, oracle = env
+    mesh = W.cylinder_channel(8000, seed=2)
+    g, o = make_pair(env, mesh, 1, 1.0, 1e-3, 1e-3)
+    rng = np.random.default_rng(5)
+    b = rng.normal(size=g.info["n_c"])
+    ref, code, it, rr = o.poisson_solve(b, tol=1e-14)
+    assert code == 0
+    opts = cgp.SolverOpts(tol=1e-8, precision=1, x0_mode=cgp._native.X0_PREV, inner_tol=1e-4, max_iter=100000)
+    x = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
+    cold = g.poisson_solve(dev(torch, b), x, opts)
+    x = dev(torch, ref * (1.0 + 1e-5 * rng.uniform(-1.0, 1.0, ref.shape)))
+    warm = g.poisson_solve(dev(torch, b), x, opts)
+    _say("FP32 refinement: cold", cold["p_outer"], "checks,", cold["p_iters"], "inner iterations; warm",
+         warm["p_outer"], "checks,", warm["p_iters"], "inner iterations")
+    assert warm["p_relres"] <= 1e-8 and rel(x.cpu().numpy(), ref) <= 1e-6
+    assert warm["p_outer"] <= 3 and warm["p_iters"] < 0.5 * cold["p_iters"]
+
+
 def _run_steps(env, case, levels, nsteps, opts_gpu, restrict_mode=0, mass_mode=0, check_every=True, bar=1e-10,
                tol=TIGHT):
     torch, cgp, oracle = env
