@@ -158,7 +158,10 @@ def run_batch(args, log):
     log(f"batch: {len(meshes)} instances, {t_fine} fine triangles, {rows} coarse rows, {nnz} coarse nonzeros; "
         f"setup {time.perf_counter() - t0:.1f}s; autotuned {tuned}")
     tol = 1e-8
-    opts = StepOpts(momentum=SolverOpts(tol=args.mom_tol, max_iter=5000), poisson=SolverOpts(tol=tol, max_iter=100000),
+    X0 = cgp._native
+    mom = SolverOpts(tol=args.mom_tol, max_iter=5000,
+                     x0_mode={"prev": X0.X0_PREV, "extrap": X0.X0_EXTRAP}[args.mom_x0])
+    opts = StepOpts(momentum=mom, poisson=SolverOpts(tol=tol, max_iter=100000),
                     mass=SolverOpts(tol=args.mass_tol, max_iter=2000))
     for k in range(2):
         batch.step(g, u, pf, pc, opts=opts)
@@ -215,6 +218,29 @@ def run_batch(args, log):
         ur, pfr, pcr, code, _ = o.step(g[i].cpu().numpy(), su[i].cpu().numpy(), spc[i].cpu().numpy(), tol_mom=args.mom_tol,
                                        tol_p=tol, tol_mass=args.mass_tol)
         err_oracle = max(err_oracle, rel(u[i].cpu().numpy(), ur), rel(pf[i].cpu().numpy(), pfr))
+    # every instance with its own online POD basis (the last `batch_window` solutions), which fills during
+    # window + 1 untimed batched steps; then the same timed steps
+    guesses = []
+    for m in meshes:
+        gs = cgp.Guess(m, n_modes=args.batch_window, hidden=16, seed=5)
+        gs.set_online(args.batch_window, 1)
+        gs.attach()
+        guesses.append(gs)
+    oopts = StepOpts(momentum=mom, poisson=SolverOpts(tol=tol, max_iter=100000, x0_mode=X0.X0_POD_GALERKIN),
+                     mass=SolverOpts(tol=args.mass_tol, max_iter=2000))
+    restore()
+    for k in range(args.batch_window + 1):
+        batch.step(g, u, pf, pc, opts=oopts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(args.batch_steps):
+        st_on = batch.step(g, u, pf, pc, opts=oopts)
+    torch.cuda.synchronize()
+    el_on = time.perf_counter() - t1
+    iters_on = [s["p_iters"] for s in st_on]
+    for gs in guesses:
+        gs.detach()
+        gs.close()
     batch.close()
     out = dict(instances=len(meshes), fine_triangles=t_fine, coarse_rows=rows, coarse_nnz=nnz,
                instance_steps_per_s=round(len(meshes) * args.batch_steps / el, 3),
@@ -226,11 +252,18 @@ def run_batch(args, log):
                tuning=tuned, batched_kernel_us_per_iteration_all_active=round(us_it, 2),
                batched_kernel_bytes_per_iteration=kbytes,
                batched_kernel_gbs=round(kbytes / (us_it * 1e-6) / 1e9, 1),
-               batched_kernel_frac_of_hbm_peak=round(kbytes / (us_it * 1e-6) / 1e9 / HBM_PEAK_GBS, 4))
+               batched_kernel_frac_of_hbm_peak=round(kbytes / (us_it * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+               online_pod=dict(window=args.batch_window,
+                               instance_steps_per_s=round(len(meshes) * args.batch_steps / el_on, 3),
+                               ms_per_batch_step=round(1e3 * el_on / args.batch_steps, 2),
+                               poisson_iters_min_max=[min(iters_on), max(iters_on)]))
     log(f"batch: {out['instance_steps_per_s']} instance-steps/s ({out['ms_per_batch_step']} ms per batch step) vs "
         f"{out['sequential_instance_steps_per_s']} sequential; Poisson iterations {min(iters)}..{max(iters)}; "
         f"batched PCG kernel {us_it:.1f} us/iteration for {kbytes / 1e6:.0f} MB -> {out['batched_kernel_gbs']} GB/s; "
         f"rel err vs single-instance {err:.1e}, vs oracle {err_oracle:.1e}")
+    log(f"batch with per-instance online POD guesses (window {args.batch_window}): "
+        f"{out['online_pod']['instance_steps_per_s']} instance-steps/s ({out['online_pod']['ms_per_batch_step']} ms "
+        f"per batch step); Poisson iterations {min(iters_on)}..{max(iters_on)}")
     return out
 
 
@@ -259,6 +292,7 @@ def main():
     ap.add_argument("--paths", default="all", help="comma-separated subset of the timed paths")
     ap.add_argument("--batch", type=int, default=64, help="instances of the batched sweep (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--batch-window", type=int, default=16, help="online POD window per batched instance")
     ap.add_argument("--only-batch", action="store_true", help="run only the batched sweep")
     ap.add_argument("--spmv-sweep", type=int, default=1, help="run the SpMV size sweep (0: skip)")
     ap.add_argument("--spmv-large", action="store_true", help="add a 16.8M-row point to the SpMV sweep")

@@ -287,8 +287,12 @@ typedef struct { int32_t lanes, block, passes, use_graph, chunk; } cgp_batch_tun
 cgp_status cgp_batch_create(cgp_mesh *const *meshes, int32_t n, cgp_batch **out);
 void cgp_batch_destroy(cgp_batch *batch);
 /* rhs[i], x[i]: instance i's coarse right-hand side and solution (x: initial guess when x0_mode =
- * CGP_X0_PREV); FP64 only.  stats: host [n] or NULL (p_iters, p_relres per instance; n_dominant =
- * iteration launches).  CGP_E_NOCONV when max_iter launches pass before every instance converged. */
+ * CGP_X0_PREV, base of the guess for the learned and POD-Galerkin modes); FP64 only.  With
+ * x0_mode >= CGP_X0_LEARNED every mesh forms its initial guess from its own attached model or online
+ * basis (cgp_guess_attach; CGP_E_STATE as in cgp_poisson_solve when one is missing), and a mesh with
+ * an online window records its converged solution.  stats: host [n] or NULL (p_iters, p_relres per
+ * instance; n_dominant = iteration launches).  CGP_E_NOCONV when max_iter launches pass before every
+ * instance converged. */
 cgp_status cgp_batch_poisson_solve(cgp_batch *batch, const double *const *rhs, double *const *x,
                                    const cgp_solver_opts *opts, cgp_stats *stats);
 /* One IFE-CGP step of every instance (arguments as cgp_step, one pointer per instance; f may be NULL). */

@@ -31,6 +31,7 @@
 
 #include "devutil.h"
 #include "kernels.h"
+#include "learn.h"
 
 struct cgp_batch {
   std::vector<cgp_mesh *> meshes;
@@ -588,8 +589,8 @@ cgp_status cgp_batch_set_tuning(cgp_batch *B, const cgp_batch_tuning *t) {
 cgp_status cgp_batch_poisson_solve(cgp_batch *B, const double *const *rhs, double *const *x,
                                    const cgp_solver_opts *o, cgp_stats *stats) {
   if (!B || !rhs || !x || !o || !(o->tol > 0.0) || o->max_iter < 1 || o->precision != CGP_PREC_FP64 ||
-      (o->x0_mode != CGP_X0_ZERO && o->x0_mode != CGP_X0_PREV)) {
-    set_error("cgp_batch_poisson_solve: bad argument (FP64, x0 zero or previous)");
+      o->x0_mode < CGP_X0_ZERO || o->x0_mode > CGP_X0_POD_GALERKIN) {
+    set_error("cgp_batch_poisson_solve: bad argument (FP64; x0 zero, previous, learned or POD-Galerkin)");
     return CGP_E_ARG;
   }
   for (int i = 0; i < B->ninst; i++)
@@ -608,6 +609,11 @@ cgp_status cgp_batch_poisson_solve(cgp_batch *B, const double *const *rhs, doubl
     else CGP_HIP(hipMemcpyAsync(B->d_x + off, x[i], bytes, hipMemcpyDeviceToDevice, ms));
     if (m->n_pdir > 0) launch_pdir_zero(m, B->d_b + off, B->d_x + off);
     else launch_mean_shift(m, B->d_b + off, nullptr, double(m->pc.n), m->red.partials);
+    if (o->x0_mode >= CGP_X0_LEARNED) {
+      // the instance's own attached model or online basis, as in its single solve
+      BTRY(guess_initial(m, o->x0_mode, B->d_b + off, B->d_x + off));
+      if (m->n_pdir > 0) launch_pdir_zero(m, B->d_b + off, B->d_x + off);
+    }
   }
   CGP_HIP(hipGetLastError());
   CGP_HIP(hipEventRecord(B->ev_in, ms));
@@ -624,6 +630,8 @@ cgp_status cgp_batch_poisson_solve(cgp_batch *B, const double *const *rhs, doubl
     const long off = B->row_off[i];
     if (m->n_pdir == 0) launch_mean_shift(m, B->d_x + off, m->d_mc, m->mc_sum, m->red.partials);
     CGP_HIP(hipMemcpyAsync(x[i], B->d_x + off, sizeof(double) * m->pc.n, hipMemcpyDeviceToDevice, ms));
+    const KrylovState &h = B->h_state[i];
+    if (h.done[0] && !h.status) BTRY(guess_record(m, x[i]));  // online window of a converged instance
   }
   CGP_HIP(hipGetLastError());
   if (stats)

@@ -148,6 +148,59 @@ def test_batch_step_matches_single_steps(env, instances):
         assert rel(ub, us_) <= 1e-10 and rel(pb, ps) <= 1e-10
 
 
+def test_batch_step_online_guess_matches_single_steps(env, instances):
+    """Every instance keeps its own online POD basis (window 4); inside the batched solve each instance's
+    initial guess comes from it exactly as in its single solve.  After the windows fill, the batched
+    steps agree with single-instance steps, and the guess cuts the Poisson iterations."""
+    torch, cgp, oracle = env
+    sub = [instances[0], instances[2], instances[4]]
+    X0 = cgp._native
+
+    def opts(x0):
+        return cgp.StepOpts(momentum=cgp.SolverOpts(tol=TIGHT, max_iter=100000),
+                            poisson=cgp.SolverOpts(tol=1e-12, max_iter=100000, x0_mode=x0),
+                            mass=cgp.SolverOpts(tol=TIGHT, max_iter=100000))
+
+    states, iters = {}, {}
+    for mode in ("batch", "single", "batch_prev"):
+        guesses, us, pfs, pcs = [], [], [], []
+        for case, g, o in sub:
+            gs = cgp.Guess(g, n_modes=4, hidden=16, seed=3)
+            gs.set_online(4, 1)
+            gs.attach()
+            guesses.append(gs)
+            us.append(dev(torch, case.initial(g.export("xy"), g.export("vdir"))))
+            pfs.append(torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda"))
+            pcs.append(torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda"))
+        x0 = X0.X0_PREV if mode == "batch_prev" else X0.X0_POD_GALERKIN
+        batch = cgp.Batch([g for _, g, _ in sub]) if mode != "single" else None
+        last = []
+        try:
+            for k in range(9):
+                gds = [dev(torch, case.dirichlet(g.export("xy"), (k + 1) * case.dt)) for case, g, _ in sub]
+                if batch:
+                    st = batch.step(gds, us, pfs, pcs, opts=opts(x0))
+                else:
+                    st = [g.step(gd, u, pf, pc, opts=opts(x0)) for (case, g, o), gd, u, pf, pc in
+                          zip(sub, gds, us, pfs, pcs)]
+                if k >= 6:
+                    last.append([s["p_iters"] for s in st])
+        finally:
+            if batch:
+                batch.close()
+            for gs in guesses:
+                gs.detach()
+                gs.close()
+        states[mode] = [(u.cpu().numpy(), pf.cpu().numpy()) for u, pf in zip(us, pfs)]
+        iters[mode] = np.sum(last, axis=0)
+    _say("  Poisson iterations of the last 3 steps: batch+online", iters["batch"], "single+online",
+         iters["single"], "batch, previous pressure", iters["batch_prev"])
+    for (ub, pb), (us_, ps) in zip(states["batch"], states["single"]):
+        assert rel(ub, us_) <= 1e-9 and rel(pb, ps) <= 1e-9
+    assert np.all(np.abs(iters["batch"] - iters["single"]) <= 6)
+    assert iters["batch"].sum() < iters["batch_prev"].sum()
+
+
 def test_autotune_cache(env, instances, tmp_path):
     torch, cgp, oracle = env
     batch = cgp.Batch([g for _, g, _ in instances])
