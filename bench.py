@@ -238,6 +238,18 @@ def run_batch(args, log):
     torch.cuda.synchronize()
     el_on = time.perf_counter() - t1
     iters_on = [s["p_iters"] for s in st_on]
+    # the same with every instance's FP32 inner solves batched inside its FP64 refinement
+    mopts = StepOpts(momentum=mom, poisson=SolverOpts(tol=tol, max_iter=100000, precision=cgp._native.PREC_FP32_IR,
+                                                      inner_tol=args.inner_tol, x0_mode=X0.X0_POD_GALERKIN),
+                     mass=SolverOpts(tol=args.mass_tol, max_iter=2000))
+    batch.step(g, u, pf, pc, opts=mopts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(args.batch_steps):
+        st_mx = batch.step(g, u, pf, pc, opts=mopts)
+    torch.cuda.synchronize()
+    el_mx = time.perf_counter() - t1
+    iters_mx = [s["p_iters"] for s in st_mx]
     for gs in guesses:
         gs.detach()
         gs.close()
@@ -256,7 +268,10 @@ def run_batch(args, log):
                online_pod=dict(window=args.batch_window,
                                instance_steps_per_s=round(len(meshes) * args.batch_steps / el_on, 3),
                                ms_per_batch_step=round(1e3 * el_on / args.batch_steps, 2),
-                               poisson_iters_min_max=[min(iters_on), max(iters_on)]))
+                               poisson_iters_min_max=[min(iters_on), max(iters_on)]),
+               mixed_online_pod=dict(instance_steps_per_s=round(len(meshes) * args.batch_steps / el_mx, 3),
+                                     ms_per_batch_step=round(1e3 * el_mx / args.batch_steps, 2),
+                                     inner_iters_min_max=[min(iters_mx), max(iters_mx)]))
     log(f"batch: {out['instance_steps_per_s']} instance-steps/s ({out['ms_per_batch_step']} ms per batch step) vs "
         f"{out['sequential_instance_steps_per_s']} sequential; Poisson iterations {min(iters)}..{max(iters)}; "
         f"batched PCG kernel {us_it:.1f} us/iteration for {kbytes / 1e6:.0f} MB -> {out['batched_kernel_gbs']} GB/s; "
@@ -264,6 +279,9 @@ def run_batch(args, log):
     log(f"batch with per-instance online POD guesses (window {args.batch_window}): "
         f"{out['online_pod']['instance_steps_per_s']} instance-steps/s ({out['online_pod']['ms_per_batch_step']} ms "
         f"per batch step); Poisson iterations {min(iters_on)}..{max(iters_on)}")
+    log(f"batch with online POD guesses and batched FP32 refinement: {out['mixed_online_pod']['instance_steps_per_s']} "
+        f"instance-steps/s ({out['mixed_online_pod']['ms_per_batch_step']} ms per batch step); inner iterations "
+        f"{min(iters_mx)}..{max(iters_mx)}")
     return out
 
 

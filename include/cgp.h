@@ -287,7 +287,9 @@ typedef struct { int32_t lanes, block, passes, use_graph, chunk; } cgp_batch_tun
 cgp_status cgp_batch_create(cgp_mesh *const *meshes, int32_t n, cgp_batch **out);
 void cgp_batch_destroy(cgp_batch *batch);
 /* rhs[i], x[i]: instance i's coarse right-hand side and solution (x: initial guess when x0_mode =
- * CGP_X0_PREV, base of the guess for the learned and POD-Galerkin modes); FP64 only.  With
+ * CGP_X0_PREV, base of the guess for the learned and POD-Galerkin modes).  precision CGP_PREC_FP64,
+ * or CGP_PREC_FP32_IR: every instance's FP32 inner solves run batched inside its own FP64 iterative
+ * refinement (p_iters = inner iterations, p_outer = residual checks; graphs are not used).  With
  * x0_mode >= CGP_X0_LEARNED every mesh forms its initial guess from its own attached model or online
  * basis (cgp_guess_attach; CGP_E_STATE as in cgp_poisson_solve when one is missing), and a mesh with
  * an online window records its converged solution.  stats: host [n] or NULL (p_iters, p_relres per

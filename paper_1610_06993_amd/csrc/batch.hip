@@ -46,6 +46,9 @@ struct cgp_batch {
   double *d_A = nullptr, *d_dinv = nullptr;
   // work vectors over all rows
   double *d_x = nullptr, *d_b = nullptr, *d_p = nullptr;
+  // FP32 refinement: operator and D^-1 in FP32, FP64 residual, FP32 inner iterate and direction
+  float *d_A32 = nullptr, *d_dinv32 = nullptr, *d_d32 = nullptr, *d_p32 = nullptr;
+  double *d_r64 = nullptr;
   double4 *d_rec[2] = {};             // records {r, w, s, D^-1}, double-buffered
   // tiles
   cgp_batch_tuning tune{4, 512, 1, 1, 16};
@@ -145,20 +148,21 @@ __global__ void __launch_bounds__(kMaxBlock) k_bt_init_r(int G, const int4 *__re
 }
 
 // w0 = A D^-1 r0 into the records' w field (fields r and D^-1 gathered); partials (gamma, delta,
-// r.r); publishes ||b|| per instance
-template <int L>
+// r.r); publishes ||b|| per instance.  T = double (the FP64 solve) or float (an FP32 inner solve).
+template <typename T, int L>
 __global__ void __launch_bounds__(kMaxBlock) k_bt_init_w(int G, const int4 *__restrict__ tiles,
                                                         const int *__restrict__ t0s, const int *__restrict__ nts,
                                                         const int *__restrict__ rp, const int *__restrict__ col,
-                                                        const double *__restrict__ A, double4 *__restrict__ R0,
+                                                        const T *__restrict__ A, rec_t<T> *__restrict__ R0,
                                                         const double *__restrict__ Pin, double *__restrict__ Pout,
                                                         KrylovState *__restrict__ st) {
   const int t = xcd_block();
-  const int4 T = tiles[t];
-  KrylovState *S = st + T.x;
-  const int t0 = t0s[T.x];
+  const int4 Tl = tiles[t];
+  KrylovState *S = st + Tl.x;
+  if (S->status || S->done[0]) return;
+  const int t0 = t0s[Tl.x];
   double tb[1];
-  inst_sum<1>(Pin, G, t0, nts[T.x], tb);
+  inst_sum<1>(Pin, G, t0, nts[Tl.x], tb);
   if (t == t0 && threadIdx.x == 0) {
     S->bnorm[0] = sqrt(tb[0]);
     S->zero_b[0] = (tb[0] == 0.0);
@@ -166,18 +170,19 @@ __global__ void __launch_bounds__(kMaxBlock) k_bt_init_w(int G, const int4 *__re
   }
   const int lane = threadIdx.x & (L - 1), groups = blockDim.x / L;
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int row = T.y + (int)threadIdx.x / L; row < T.z; row += groups) {
+  for (int row = Tl.y + (int)threadIdx.x / L; row < Tl.z; row += groups) {
     double sum = 0.0;
     for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
       const int j = col[k];
-      sum += A[k] * (R0[j].w * R0[j].x);
+      sum += (double)(A[k] * (R0[j].w * R0[j].x));
     }
     sum = group_sum<L>(sum);
     if (lane == 0) {
-      const double r = R0[row].x, u = R0[row].w * r;
-      R0[row].y = sum;
+      const T w = (T)sum, r0 = R0[row].x;
+      const double r = (double)r0, u = (double)(R0[row].w * r0);
+      R0[row].y = w;
       acc[0] += r * u;
-      acc[1] += sum * u;
+      acc[1] += (double)w * u;
       acc[2] += r * r;
     }
   }
@@ -186,16 +191,17 @@ __global__ void __launch_bounds__(kMaxBlock) k_bt_init_w(int G, const int4 *__re
 
 // One PCG iteration of every unconverged instance (recurrences as in the single-mesh kernel).
 // The first tile's block of each instance publishes its scalars and counts its updates.
-template <int L>
+template <typename T, int L>
 __global__ void __launch_bounds__(kMaxBlock)
     k_bt_iter(int it, int G, const int4 *__restrict__ tiles, const int4 *__restrict__ tinfo,
-              const int *__restrict__ rp, const int *__restrict__ col, const double *__restrict__ A,
-              double *__restrict__ x, double *__restrict__ p, const double4 *__restrict__ Rc,
-              double4 *__restrict__ Rn, const double *__restrict__ Pin, double *__restrict__ Pout,
+              const int *__restrict__ rp, const int *__restrict__ col, const T *__restrict__ A,
+              T *__restrict__ x, T *__restrict__ p, const rec_t<T> *__restrict__ Rc,
+              rec_t<T> *__restrict__ Rn, const double *__restrict__ Pin, double *__restrict__ Pout,
               KrylovState *__restrict__ st) {
+  using R4 = rec_t<T>;
   const int t = xcd_block();
-  const int4 T = tiles[t], I = tinfo[t];
-  KrylovState *S = st + T.x;
+  const int4 Tl = tiles[t], I = tinfo[t];
+  KrylovState *S = st + Tl.x;
   if (S->status || S->done[0]) return;
   double t3[3];
   inst_sum<3>(Pin, G, I.x, I.y, t3);
@@ -219,32 +225,117 @@ __global__ void __launch_bounds__(kMaxBlock)
     if (!done && !bad) S->iters += 1;
   }
   if (done || bad) return;
+  const T al = (T)alpha, bt = (T)beta;
   const int lane = threadIdx.x & (L - 1), groups = blockDim.x / L;
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int row = T.y + (int)threadIdx.x / L; row < T.z; row += groups) {
+  for (int row = Tl.y + (int)threadIdx.x / L; row < Tl.z; row += groups) {
     double sum = 0.0;
     for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
-      const double4 g = Rc[col[k]];
-      sum += A[k] * (g.w * (g.x - alpha * (g.y + beta * g.z)));
+      const R4 g = Rc[col[k]];
+      sum += (double)(A[k] * (g.w * (g.x - al * (g.y + bt * g.z))));
     }
     sum = group_sum<L>(sum);
     if (lane == 0) {
-      const double4 o = Rc[row];
-      const double d = o.w, rc = o.x, wc = o.y, sc = o.z;
-      const double si = wc + beta * sc;
-      const double pi = d * rc + beta * p[row];
-      const double rn = rc - alpha * si;
-      const double un = d * (rc - alpha * (wc + beta * sc));
-      x[row] += alpha * pi;
+      const R4 o = Rc[row];
+      const T d = o.w, rc = o.x, wc = o.y, sc = o.z;
+      const T si = wc + bt * sc;
+      const T pi = d * rc + bt * p[row];
+      const T rn = rc - al * si;
+      const T un = d * (rc - al * (wc + bt * sc));
+      const T wn = (T)sum;
+      x[row] = x[row] + al * pi;
       p[row] = pi;
-      *reinterpret_cast<double2 *>(&Rn[row]) = make_double2(rn, sum);
-      Rn[row].z = si;
-      acc[0] += rn * un;
-      acc[1] += sum * un;
-      acc[2] += rn * rn;
+      store_rws(&Rn[row], rn, wn, si);
+      acc[0] += (double)rn * (double)un;
+      acc[1] += (double)wn * (double)un;
+      acc[2] += (double)rn * (double)rn;
     }
   }
   put_at_last<3>(acc, Pout, G, t);
+}
+
+// ---- FP32 inner solves inside FP64 iterative refinement, per instance (as the single-mesh solve)
+// r64 = b - A x in FP64; partials (r.r, b.b) per tile
+template <int L>
+__global__ void __launch_bounds__(kMaxBlock) k_bt_ir_residual(int G, const int4 *__restrict__ tiles,
+                                                             const int *__restrict__ rp, const int *__restrict__ col,
+                                                             const double *__restrict__ A,
+                                                             const double *__restrict__ b, const double *__restrict__ x,
+                                                             double *__restrict__ r64, double *__restrict__ Pout) {
+  const int t = xcd_block();
+  const int4 Tl = tiles[t];
+  const int lane = threadIdx.x & (L - 1), groups = blockDim.x / L;
+  double acc[2] = {0.0, 0.0};
+  for (int row = Tl.y + (int)threadIdx.x / L; row < Tl.z; row += groups) {
+    double sum = 0.0;
+    for (int k = rp[row] + lane; k < rp[row + 1]; k += L) sum += A[k] * x[col[k]];
+    sum = group_sum<L>(sum);
+    if (lane == 0) {
+      const double bb = b[row], rr = bb - sum;
+      r64[row] = rr;
+      acc[0] += rr * rr;
+      acc[1] += bb * bb;
+    }
+  }
+  put_at<2>(acc, Pout, G, t);
+}
+
+// Outer convergence test of each instance and the start of its inner solve K32 d = r64/||r64||:
+// records {r0, -, 0, D^-1} (FP32) in slot 0 and D^-1 in slot 1, d = p = 0; partial r0.r0 per tile.
+// The instance's first tile publishes the outer state and resets the inner one, whose tolerance is
+// the reduction still needed (at least inner_tol).
+__global__ void __launch_bounds__(kMaxBlock) k_bt_ir_init(int G, const int4 *__restrict__ tiles,
+                                                         const int4 *__restrict__ tinfo, double inner_tol,
+                                                         const double *__restrict__ r64,
+                                                         const float *__restrict__ dinv, float4 *__restrict__ R0,
+                                                         float4 *__restrict__ R1, float *__restrict__ d,
+                                                         float *__restrict__ p, const double *__restrict__ Pin,
+                                                         double *__restrict__ Pout, KrylovState *__restrict__ so,
+                                                         KrylovState *__restrict__ si) {
+  const int t = xcd_block();
+  const int4 Tl = tiles[t], I = tinfo[t];
+  KrylovState *O = so + Tl.x, *S = si + Tl.x;
+  double t2[2];
+  inst_sum<2>(Pin, G, I.x, I.y, t2);
+  const double rn = sqrt(t2[0]), bn = sqrt(t2[1]);
+  const bool bad = !is_finite(rn) || !is_finite(bn) || O->status;
+  const bool done = bn == 0.0 || rn <= O->tol * bn;
+  if (t == I.x && threadIdx.x == 0) {
+    O->rnorm[0] = rn;
+    O->bnorm[0] = bn;
+    O->zero_b[0] = (bn == 0.0);
+    O->done[0] = done;
+    if (bad && !O->status) O->status = CGP_E_NONFINITE;
+    S->done[0] = done || bad;
+    S->status = 0;
+    S->iters = 0;
+    const double need = 0.5 * O->tol * bn / rn;
+    S->tol = need > inner_tol ? need : inner_tol;
+  }
+  if (done || bad) return;
+  const double inv = 1.0 / rn;
+  const int groups = blockDim.x;
+  double acc[1] = {0.0};
+  for (int row = Tl.y + (int)threadIdx.x; row < Tl.z; row += groups) {
+    const float rr = (float)(r64[row] * inv), di = dinv[row];
+    R0[row] = make_float4(rr, 0.0f, 0.0f, di);
+    R1[row] = make_float4(0.0f, 0.0f, 0.0f, di);
+    d[row] = 0.0f;
+    p[row] = 0.0f;
+    acc[0] += (double)rr * (double)rr;
+  }
+  put_at<1>(acc, Pout, G, t);
+}
+
+// x += ||r64|| d for every instance whose outer solve goes on and whose inner solve ended cleanly
+__global__ void k_bt_ir_update(const int4 *__restrict__ tiles, const KrylovState *__restrict__ so,
+                               const KrylovState *__restrict__ si, double *__restrict__ x,
+                               const float *__restrict__ d) {
+  const int4 Tl = tiles[blockIdx.x];
+  const KrylovState *O = so + Tl.x, *S = si + Tl.x;
+  if (O->done[0] || O->status || S->status) return;
+  const double s = O->rnorm[0];
+  for (int row = Tl.y + (int)threadIdx.x; row < Tl.z; row += blockDim.x) x[row] += s * (double)d[row];
 }
 
 // after a chunk (one block per instance): convergence from the last iteration's partials
@@ -355,22 +446,31 @@ cgp_status build_tiles(cgp_batch *B) {
   return CGP_OK;
 }
 
-// enqueue `count` iterations starting at `it0`, then the chunk's convergence check
-void enqueue_chunk(cgp_batch *B, int it0, int count) {
+// enqueue `count` iterations starting at `it0`, then the chunk's convergence check: the FP64 solve
+// (fp32 = false) or the FP32 inner solves of the refinement (states si = d_state + ninst)
+void enqueue_chunk(cgp_batch *B, int it0, int count, bool fp32 = false) {
   const int G = B->ntiles, blk = B->tune.block;
   hipStream_t s = B->stream;
+  KrylovState *st = fp32 ? B->d_state + B->ninst : B->d_state;
+  float4 *R32[2] = {reinterpret_cast<float4 *>(B->d_rec[0]), reinterpret_cast<float4 *>(B->d_rec[0]) + B->rows};
   dispatch_L(B->tune.lanes, [&](auto LC) {
     constexpr int LL = decltype(LC)::value;
     for (int it = it0; it < it0 + count; it++) {
       const int cur = it & 1, nxt = cur ^ 1;
-      hipLaunchKernelGGL((k_bt_iter<LL>), dim3(G), dim3(blk), 0, s, it, G, (const int4 *)B->d_tiles,
-                         (const int4 *)B->d_tinfo, (const int *)B->d_rp, (const int *)B->d_col,
-                         (const double *)B->d_A, B->d_x, B->d_p, (const double4 *)B->d_rec[cur], B->d_rec[nxt],
-                         (const double *)bpin(B, it), bpout(B, it), B->d_state);
+      if (fp32)
+        hipLaunchKernelGGL((k_bt_iter<float, LL>), dim3(G), dim3(blk), 0, s, it, G, (const int4 *)B->d_tiles,
+                           (const int4 *)B->d_tinfo, (const int *)B->d_rp, (const int *)B->d_col,
+                           (const float *)B->d_A32, B->d_d32, B->d_p32, (const float4 *)R32[cur], R32[nxt],
+                           (const double *)bpin(B, it), bpout(B, it), st);
+      else
+        hipLaunchKernelGGL((k_bt_iter<double, LL>), dim3(G), dim3(blk), 0, s, it, G, (const int4 *)B->d_tiles,
+                           (const int4 *)B->d_tinfo, (const int *)B->d_rp, (const int *)B->d_col,
+                           (const double *)B->d_A, B->d_x, B->d_p, (const double4 *)B->d_rec[cur], B->d_rec[nxt],
+                           (const double *)bpin(B, it), bpout(B, it), st);
     }
   });
   hipLaunchKernelGGL(k_bt_finish, dim3(B->ninst), dim3(256), 0, s, G, (const int *)B->d_t0, (const int *)B->d_nt,
-                     (const double *)bpin(B, it0 + count), B->d_state);
+                     (const double *)bpin(B, it0 + count), st);
 }
 
 cgp_status run_chunk(cgp_batch *B, int which) {
@@ -398,14 +498,18 @@ cgp_status run_chunk(cgp_batch *B, int which) {
   return CGP_OK;
 }
 
-cgp_status poll_states(cgp_batch *B, bool *all_done, int *bad) {
-  CGP_HIP(hipMemcpyAsync(B->h_state, B->d_state, sizeof(KrylovState) * B->ninst, hipMemcpyDeviceToHost, B->stream));
+// copy both state arrays (the FP64 or outer states, then the inner ones) to the host; report on the
+// array that starts at `first` (0 or ninst)
+cgp_status poll_states(cgp_batch *B, bool *all_done, int *bad, int first = 0) {
+  CGP_HIP(hipMemcpyAsync(B->h_state, B->d_state, sizeof(KrylovState) * 2 * B->ninst, hipMemcpyDeviceToHost,
+                         B->stream));
   CGP_HIP(hipStreamSynchronize(B->stream));
   *all_done = true;
   *bad = -1;
   for (int i = 0; i < B->ninst; i++) {
-    if (B->h_state[i].status && *bad < 0) *bad = i;
-    if (!B->h_state[i].done[0]) *all_done = false;
+    const KrylovState &h = B->h_state[first + i];
+    if (h.status && *bad < 0) *bad = i;
+    if (!h.done[0]) *all_done = false;
   }
   return CGP_OK;
 }
@@ -422,7 +526,7 @@ cgp_status solve(cgp_batch *B, double tol, int maxit, int *launched) {
                        (const int *)B->d_rp, (const int *)B->d_col, (const double *)B->d_A,
                        (const double *)B->d_dinv, (const double *)B->d_b, (const double *)B->d_x, B->d_p,
                        B->d_rec[0], B->d_rec[1], bregion(B, B_INIT));
-    hipLaunchKernelGGL((k_bt_init_w<LL>), dim3(G), dim3(blk), 0, s, G, (const int4 *)B->d_tiles,
+    hipLaunchKernelGGL((k_bt_init_w<double, LL>), dim3(G), dim3(blk), 0, s, G, (const int4 *)B->d_tiles,
                        (const int *)B->d_t0, (const int *)B->d_nt, (const int *)B->d_rp, (const int *)B->d_col,
                        (const double *)B->d_A, B->d_rec[0], (const double *)bregion(B, B_INIT), bregion(B, B_A),
                        B->d_state);
@@ -448,6 +552,80 @@ cgp_status solve(cgp_batch *B, double tol, int maxit, int *launched) {
   }
   if (!all) {
     set_error("batched Poisson PCG: iteration limit reached before every instance converged");
+    return CGP_E_NOCONV;
+  }
+  return CGP_OK;
+}
+
+// FP32 Jacobi-PCG inside FP64 iterative refinement for every instance at once (as the single-mesh
+// refinement): per refinement step one FP64 residual launch, one init launch, then the FP32 inner
+// iterations of all instances whose outer solve goes on, and one update launch.  iters[i]: inner
+// iterations of instance i; outers[i]: residual checks it took.
+cgp_status solve_ir(cgp_batch *B, const cgp_solver_opts *o, int *launched, std::vector<int> &iters,
+                    std::vector<int> &outers) {
+  hipStream_t s = B->stream;
+  const int G = B->ntiles, blk = B->tune.block, n = B->ninst, K = B->tune.chunk;
+  const double inner_tol = o->inner_tol > 0 ? o->inner_tol : 1e-4;
+  KrylovState *so = B->d_state, *si = B->d_state + n;
+  float4 *R32[2] = {reinterpret_cast<float4 *>(B->d_rec[0]), reinterpret_cast<float4 *>(B->d_rec[0]) + B->rows};
+  hipLaunchKernelGGL(k_bt_state_init, dim3((n + 255) / 256), dim3(256), 0, s, n, o->tol, o->max_iter, so);
+  hipLaunchKernelGGL(k_bt_state_init, dim3((n + 255) / 256), dim3(256), 0, s, n, inner_tol, o->max_iter, si);
+  iters.assign(n, 0);
+  outers.assign(n, 0);
+  int total = 0;
+  bool all = false;
+  int bad = -1;
+  for (int outer = 0; outer < 200; outer++) {
+    dispatch_L(B->tune.lanes, [&](auto LC) {
+      constexpr int LL = decltype(LC)::value;
+      hipLaunchKernelGGL((k_bt_ir_residual<LL>), dim3(G), dim3(blk), 0, s, G, (const int4 *)B->d_tiles,
+                         (const int *)B->d_rp, (const int *)B->d_col, (const double *)B->d_A,
+                         (const double *)B->d_b, (const double *)B->d_x, B->d_r64, bregion(B, B_B));
+      hipLaunchKernelGGL(k_bt_ir_init, dim3(G), dim3(blk), 0, s, G, (const int4 *)B->d_tiles,
+                         (const int4 *)B->d_tinfo, inner_tol, (const double *)B->d_r64, (const float *)B->d_dinv32,
+                         R32[0], R32[1], B->d_d32, B->d_p32, (const double *)bregion(B, B_B), bregion(B, B_INIT),
+                         so, si);
+    });
+    CGP_HIP(hipGetLastError());
+    BTRY(poll_states(B, &all, &bad, 0));
+    for (int i = 0; i < n; i++)
+      if (!outers[i] && (B->h_state[i].done[0] || B->h_state[i].status)) outers[i] = outer + 1;
+    if (all || bad >= 0 || total >= o->max_iter) break;
+    dispatch_L(B->tune.lanes, [&](auto LC) {
+      constexpr int LL = decltype(LC)::value;
+      hipLaunchKernelGGL((k_bt_init_w<float, LL>), dim3(G), dim3(blk), 0, s, G, (const int4 *)B->d_tiles,
+                         (const int *)B->d_t0, (const int *)B->d_nt, (const int *)B->d_rp, (const int *)B->d_col,
+                         (const float *)B->d_A32, R32[0], (const double *)bregion(B, B_INIT), bregion(B, B_A), si);
+    });
+    bool inner_all = false;
+    int inner_bad = -1;
+    for (int it0 = 0; total < o->max_iter; it0 += K) {
+      enqueue_chunk(B, it0, K, true);
+      CGP_HIP(hipGetLastError());
+      total += K;
+      BTRY(poll_states(B, &inner_all, &inner_bad, n));
+      if (inner_all || inner_bad >= 0) break;
+    }
+    for (int i = 0; i < n; i++) iters[i] += B->h_state[n + i].iters;
+    if (inner_bad >= 0) {
+      bad = inner_bad;
+      break;
+    }
+    hipLaunchKernelGGL(k_bt_ir_update, dim3(G), dim3(256), 0, s, (const int4 *)B->d_tiles,
+                       (const KrylovState *)so, (const KrylovState *)si, B->d_x, (const float *)B->d_d32);
+    CGP_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_bt_zero_b, dim3(G), dim3(256), 0, s, (const int4 *)B->d_tiles, (const KrylovState *)so,
+                     B->d_x);
+  CGP_HIP(hipGetLastError());
+  *launched = total;
+  if (bad >= 0) {
+    set_error("batched FP32-refinement Poisson solve: instance " + std::to_string(bad) +
+              " produced a non-finite residual");
+    return CGP_E_NONFINITE;
+  }
+  if (!all) {
+    set_error("batched FP32-refinement Poisson solve: iteration limit reached before every instance converged");
     return CGP_E_NOCONV;
   }
   return CGP_OK;
@@ -518,9 +696,15 @@ cgp_status cgp_batch_create(cgp_mesh *const *meshes, int32_t n, cgp_batch **out)
       (st = balloc(B, &B->d_dinv, rows)) || (st = balloc(B, &B->d_x, rows)) || (st = balloc(B, &B->d_b, rows)) ||
       (st = balloc(B, &B->d_p, rows)) || (st = balloc(B, &B->d_rec[0], rows)) ||
       (st = balloc(B, &B->d_rec[1], rows)) ||
-      (st = balloc(B, &B->d_t0, n)) || (st = balloc(B, &B->d_nt, n)) || (st = balloc(B, &B->d_state, n)))
+      (st = balloc(B, &B->d_A32, nnz)) || (st = balloc(B, &B->d_dinv32, rows)) ||
+      (st = balloc(B, &B->d_d32, rows)) || (st = balloc(B, &B->d_p32, rows)) || (st = balloc(B, &B->d_r64, rows)) ||
+      (st = balloc(B, &B->d_t0, n)) || (st = balloc(B, &B->d_nt, n)) || (st = balloc(B, &B->d_state, 2 * n)))
     return fail(st);
-  if (hipHostMalloc((void **)&B->h_state, sizeof(KrylovState) * n, hipHostMallocDefault) != hipSuccess) {
+  if (hipMemset(B->d_state, 0, sizeof(KrylovState) * 2 * n) != hipSuccess) {
+    set_error("cgp_batch_create: state initialisation failed");
+    return fail(CGP_E_DEVICE);
+  }
+  if (hipHostMalloc((void **)&B->h_state, sizeof(KrylovState) * 2 * n, hipHostMallocDefault) != hipSuccess) {
     set_error("cgp_batch_create: pinned allocation failed");
     return fail(CGP_E_OOM);
   }
@@ -551,6 +735,10 @@ cgp_status cgp_batch_create(cgp_mesh *const *meshes, int32_t n, cgp_batch **out)
     if (hipMemcpyAsync(B->d_A + B->nnz_off[i], m->d_Kbc, sizeof(double) * m->pc.nnz, hipMemcpyDeviceToDevice,
                        B->stream) != hipSuccess ||
         hipMemcpyAsync(B->d_dinv + B->row_off[i], m->d_dinvK, sizeof(double) * m->pc.n, hipMemcpyDeviceToDevice,
+                       B->stream) != hipSuccess ||
+        hipMemcpyAsync(B->d_A32 + B->nnz_off[i], m->d_Kbc32, sizeof(float) * m->pc.nnz, hipMemcpyDeviceToDevice,
+                       B->stream) != hipSuccess ||
+        hipMemcpyAsync(B->d_dinv32 + B->row_off[i], m->d_dinvK32, sizeof(float) * m->pc.n, hipMemcpyDeviceToDevice,
                        B->stream) != hipSuccess) {
       set_error("cgp_batch_create: operator copy failed");
       return fail(CGP_E_DEVICE);
@@ -588,9 +776,10 @@ cgp_status cgp_batch_set_tuning(cgp_batch *B, const cgp_batch_tuning *t) {
 
 cgp_status cgp_batch_poisson_solve(cgp_batch *B, const double *const *rhs, double *const *x,
                                    const cgp_solver_opts *o, cgp_stats *stats) {
-  if (!B || !rhs || !x || !o || !(o->tol > 0.0) || o->max_iter < 1 || o->precision != CGP_PREC_FP64 ||
-      o->x0_mode < CGP_X0_ZERO || o->x0_mode > CGP_X0_POD_GALERKIN) {
-    set_error("cgp_batch_poisson_solve: bad argument (FP64; x0 zero, previous, learned or POD-Galerkin)");
+  if (!B || !rhs || !x || !o || !(o->tol > 0.0) || o->max_iter < 1 ||
+      (o->precision != CGP_PREC_FP64 && o->precision != CGP_PREC_FP32_IR) || o->x0_mode < CGP_X0_ZERO ||
+      o->x0_mode > CGP_X0_POD_GALERKIN) {
+    set_error("cgp_batch_poisson_solve: bad argument (FP64 or FP32_IR; x0 zero, previous, learned or POD-Galerkin)");
     return CGP_E_ARG;
   }
   for (int i = 0; i < B->ninst; i++)
@@ -620,7 +809,9 @@ cgp_status cgp_batch_poisson_solve(cgp_batch *B, const double *const *rhs, doubl
   CGP_HIP(hipStreamWaitEvent(B->stream, B->ev_in, 0));
   int launched = 0;
   const auto t0 = std::chrono::steady_clock::now();
-  cgp_status rs = solve(B, o->tol, o->max_iter, &launched);
+  const bool ir = (o->precision == CGP_PREC_FP32_IR);
+  std::vector<int> ir_iters, ir_outers;
+  cgp_status rs = ir ? solve_ir(B, o, &launched, ir_iters, ir_outers) : solve(B, o->tol, o->max_iter, &launched);
   const double ms_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (rs != CGP_OK && rs != CGP_E_NOCONV) return rs;
   CGP_HIP(hipEventRecord(B->ev_out, B->stream));
@@ -638,8 +829,8 @@ cgp_status cgp_batch_poisson_solve(cgp_batch *B, const double *const *rhs, doubl
     for (int i = 0; i < B->ninst; i++) {
       const KrylovState &h = B->h_state[i];
       stats[i] = cgp_stats{};
-      stats[i].p_iters = h.iters;
-      stats[i].p_outer = 1;
+      stats[i].p_iters = ir ? ir_iters[i] : h.iters;
+      stats[i].p_outer = ir ? ir_outers[i] : 1;
       stats[i].p_relres = h.bnorm[0] > 0 ? h.rnorm[0] / h.bnorm[0] : 0.0;
       stats[i].ms_poisson = (float)ms_solve;
       stats[i].n_dominant = launched;  // launches of the batched iteration kernel (all instances)

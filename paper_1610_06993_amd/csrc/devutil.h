@@ -99,6 +99,22 @@ __device__ __forceinline__ void sum_partials(const double *__restrict__ P, int G
   block_sum<K>(v, tot);
 }
 
+// Per-node records of the single-kernel PCG: {r, w, s, D^-1} in double4 (FP64) or float4 (FP32).
+template <typename T> struct rec_of;
+template <> struct rec_of<double> { using type = double4; };
+template <> struct rec_of<float> { using type = float4; };
+template <typename T> using rec_t = typename rec_of<T>::type;
+
+// store the r, w, s fields of a record (D^-1 stays)
+__device__ __forceinline__ void store_rws(double4 *q, double r, double w, double s) {
+  *reinterpret_cast<double2 *>(q) = make_double2(r, w);
+  q->z = s;
+}
+__device__ __forceinline__ void store_rws(float4 *q, float r, float w, float s) {
+  *reinterpret_cast<float2 *>(q) = make_float2(r, w);
+  q->z = s;
+}
+
 // Consumer side without LDS or barriers: every wave sums the K partial arrays of length G
 // itself (U loads per lane issued together, the rest in a loop, then the wave butterfly).  The
 // order is fixed, so every wave of every block holds bit-identical totals, and a wave can start

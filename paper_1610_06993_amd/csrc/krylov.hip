@@ -328,20 +328,6 @@ __global__ void k_zero_b_fix(int n, double *__restrict__ x, const KrylovState *_
 // iteration's block partials itself (no barrier before the row work), and the
 // block's partials leave after a single barrier.
 
-template <typename T> struct rec_of;
-template <> struct rec_of<double> { using type = double4; };
-template <> struct rec_of<float> { using type = float4; };
-template <typename T> using rec_t = typename rec_of<T>::type;
-
-__device__ __forceinline__ void store_rws(double4 *q, double r, double w, double s) {
-  *reinterpret_cast<double2 *>(q) = make_double2(r, w);
-  q->z = s;
-}
-__device__ __forceinline__ void store_rws(float4 *q, float r, float w, float s) {
-  *reinterpret_cast<float2 *>(q) = make_float2(r, w);
-  q->z = s;
-}
-
 template <typename T>
 __device__ __forceinline__ T cg1_u_next(T dinv, T r, T w, T s, T alpha, T beta) {
   return dinv * (r - alpha * (w + beta * s));

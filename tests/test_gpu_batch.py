@@ -95,6 +95,28 @@ def test_batch_equals_single_instance_solves(env, instances):
     batch.close()
 
 
+def test_batch_fp32_refinement(env, instances):
+    """Every instance's FP32 inner solves batched inside its own FP64 refinement: each solution within
+    1e-6 of the oracle, refinement counts close to the single-instance refinement."""
+    torch, cgp, oracle = env
+    batch = cgp.Batch([g for _, g, _ in instances])
+    bs = _rhs(instances, 5)
+    opts = cgp.SolverOpts(tol=1e-10, max_iter=100000, precision=cgp._native.PREC_FP32_IR,
+                          x0_mode=cgp._native.X0_ZERO)
+    xs = [torch.zeros(len(b), dtype=torch.float64, device="cuda") for b in bs]
+    st = batch.poisson_solve([dev(torch, b) for b in bs], xs, opts)
+    for (case, g, o), b, x, s in zip(instances, bs, xs, st):
+        ref, code, its, rr = o.poisson_solve(b, tol=1e-14)
+        y = torch.zeros_like(x)
+        s1 = g.poisson_solve(dev(torch, b), y, opts)
+        err = rel(x.cpu().numpy(), ref)
+        _say(f"  n_c {len(b)}: batched refinement {s['p_outer']} checks / {s['p_iters']} inner iterations, "
+             f"single {s1['p_outer']} / {s1['p_iters']}; rel err vs oracle {err:.2e}")
+        assert code == 0 and s["p_relres"] <= 1e-10 and err <= 1e-6
+        assert abs(s["p_outer"] - s1["p_outer"]) <= 1
+    batch.close()
+
+
 def test_graph_replays_equal_eager(env, instances):
     torch, cgp, oracle = env
     batch = cgp.Batch([g for _, g, _ in instances])
