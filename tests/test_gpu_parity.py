@@ -290,6 +290,28 @@ def test_deterministic_bitwise(env):
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_zero_right_hand_side(env, precision):
+    """b = 0: the solve returns x = 0 exactly without iterating, whatever the initial guess."""
+    torch, cgp, oracle = env
+    g = cgp.Mesh(W.cylinder_channel(3000, seed=2), 1)
+    g.assemble(1.0, 1e-3, 1e-3)
+    b = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
+    x = torch.ones_like(b)
+    st = g.poisson_solve(b, x, cgp.SolverOpts(tol=1e-10, precision=precision, x0_mode=cgp._native.X0_PREV))
+    assert torch.count_nonzero(x).item() == 0 and st["p_iters"] == 0
+
+
+@pytest.mark.parametrize("n,levels", [(1, 1), (2, 1), (1, 2), (3, 0)])
+def test_tiny_meshes(env, n, levels):
+    """The smallest meshes: an n x n Taylor-Green square (2 n^2 coarse triangles, every node but the
+    interior ones velocity-Dirichlet, pure-Neumann pressure), 5 steps against the oracle."""
+    torch, cgp, oracle = env
+    case = W.case_tg(n=n, levels=levels)
+    _say("tiny mesh", n, "levels", levels)
+    _run_steps(env, case, levels, 5, tight_opts(cgp))
+
+
 def test_failure_paths(env):
     torch, cgp, oracle = env
     case = W.case_bfs(nx=40, ny=8)
