@@ -107,6 +107,7 @@ cgp_status build_device(cgp_mesh *m) {
   for (int k = 0; k <= m->levels; k++) TRY(dalloc(m, &m->d_wlev[k], size_t(m->lev[k].n)));
   TRY(dalloc(m, &m->d_ut, 2 * Nf));
   TRY(dalloc(m, &m->d_ut_prev, 2 * Nf));
+  TRY(dalloc(m, &m->d_ut_prev2, 2 * Nf));
   TRY(dalloc(m, &m->d_rec, 8 * Nc));
   TRY(dalloc(m, &m->d_bc, Nc));
   TRY(dalloc(m, &m->d_state, 4));

@@ -120,7 +120,8 @@ struct cgp_mesh {
   std::vector<double *> d_wlev;   // per level scratch [n_k] (prolong/restrict chains)
   double *d_ut = nullptr;         // u-tilde [n_f][2] for cgp_step
   double *d_ut_prev = nullptr;    // the step before's u-tilde (extrapolated momentum guess)
-  int ut_hist = 0;                // consecutive cgp_step momentum solves kept in d_ut / d_ut_prev
+  double *d_ut_prev2 = nullptr;   // and the one before that
+  int ut_hist = 0;                // consecutive cgp_step momentum solves kept in d_ut / d_ut_prev / d_ut_prev2
   double *d_rec = nullptr;        // 2 x [n_c] records {r, w, s, D^-1} of the fused Poisson PCG (double4 or float4)
   double *d_bc = nullptr;         // coarse rhs
   cgp::KrylovState *d_state = nullptr;   // 4 solver states

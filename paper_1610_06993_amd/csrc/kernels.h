@@ -60,6 +60,7 @@ void launch_set_dirichlet(cgp_mesh *m, const double *g, double *u);
 void launch_pdir_zero(cgp_mesh *m, double *b, double *x);
 // a <- 2 a - b and b <- a (old), element-wise
 void launch_extrapolate(cgp_mesh *m, long count, double *a, double *b);
+void launch_extrapolate3(cgp_mesh *m, long count, double *a, double *b, double *c);
 // x -= (sum_i w_i x_i) / den over the coarse vector (w = NULL: plain sum); P: partial scratch
 void launch_mean_shift(cgp_mesh *m, double *x, const double *w, double den, double *P);
 

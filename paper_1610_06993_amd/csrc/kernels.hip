@@ -250,6 +250,16 @@ __global__ void k_extrapolate(long count, double *__restrict__ a, double *__rest
   b[i] = ai;
 }
 
+// x0 = 3 a - 3 b + c, then c = b, b = a (element-wise over `count` values)
+__global__ void k_extrapolate3(long count, double *__restrict__ a, double *__restrict__ b, double *__restrict__ c) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const double ai = a[i], bi = b[i];
+  a[i] = 3.0 * (ai - bi) + c[i];
+  c[i] = bi;
+  b[i] = ai;
+}
+
 // ------------------------------------------------------------------ pressure path
 // INJECT (Eqs. 20-21, 30): b_c[i] = s * sum_k (Dbar_x u~_x + Dbar_y u~_y) at coarse
 // column j, which is fine node j (coarse nodes are the prefix of the fine numbering).
@@ -461,6 +471,10 @@ void launch_set_dirichlet(cgp_mesh *m, const double *g, double *u) {
 
 void launch_extrapolate(cgp_mesh *m, long count, double *a, double *b) {
   hipLaunchKernelGGL(dev::k_extrapolate, dim3((count + 255) / 256), dim3(256), 0, m->stream, count, a, b);
+}
+
+void launch_extrapolate3(cgp_mesh *m, long count, double *a, double *b, double *c) {
+  hipLaunchKernelGGL(dev::k_extrapolate3, dim3((count + 255) / 256), dim3(256), 0, m->stream, count, a, b, c);
 }
 
 void launch_pdir_zero(cgp_mesh *m, double *b, double *x) {

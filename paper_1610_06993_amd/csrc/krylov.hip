@@ -1158,8 +1158,13 @@ cgp_status drv_momentum(cgp_mesh *m, const cgp_solver_opts *o, const double *g, 
   double2 *rhs = (double2 *)m->d_wf[0];
   launch_mom_rhs(m, g, u, f, (double *)rhs);
   const bool extrap = (o->x0_mode == CGP_X0_EXTRAP && ut == m->d_ut);
-  if (extrap && m->ut_hist >= 2) {
-    // d_ut holds U~^n and d_ut_prev U~^(n-1): x0 = 2 U~^n - U~^(n-1), and U~^n moves to d_ut_prev
+  if (extrap && m->ut_hist >= 3) {
+    // d_ut, d_ut_prev, d_ut_prev2 hold U~^n, U~^(n-1), U~^(n-2): x0 = 3 U~^n - 3 U~^(n-1) + U~^(n-2)
+    // (quadratic in time), and the history shifts by one step
+    launch_extrapolate3(m, 2 * n, m->d_ut, m->d_ut_prev, m->d_ut_prev2);
+  } else if (extrap && m->ut_hist == 2) {
+    // x0 = 2 U~^n - U~^(n-1); U~^(n-1) moves to d_ut_prev2, U~^n to d_ut_prev
+    CGP_HIP(hipMemcpyAsync(m->d_ut_prev2, m->d_ut_prev, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
     launch_extrapolate(m, 2 * n, m->d_ut, m->d_ut_prev);
   } else {
     if (extrap && m->ut_hist == 1)
@@ -1169,7 +1174,7 @@ cgp_status drv_momentum(cgp_mesh *m, const cgp_solver_opts *o, const double *g, 
     else
       CGP_HIP(hipMemcpyAsync(ut, u, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
-  m->ut_hist = extrap ? std::min(m->ut_hist + 1, 2) : 0;
+  m->ut_hist = extrap ? std::min(m->ut_hist + 1, 3) : 0;
   // known values in the initial guess: the eliminated Dirichlet rows then start (and stay) exact
   launch_set_dirichlet(m, g, ut);
   double2 *r = (double2 *)m->d_wf[1], *rh = (double2 *)m->d_wf[2], *p = (double2 *)m->d_wf[3];
