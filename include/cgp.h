@@ -118,7 +118,8 @@ typedef struct {
 typedef struct {
   cgp_solver_opts momentum;   /* step 1, Eq. (19): Jacobi-BiCGStab, both components together */
   cgp_solver_opts poisson;    /* step 3, Eq. (21): Jacobi-PCG on the coarse mesh */
-  cgp_solver_opts mass;       /* step 5, Eq. (23): Jacobi-PCG with the consistent mass matrix */
+  cgp_solver_opts mass;       /* step 5, Eq. (23): Jacobi-PCG with the consistent mass matrix, started
+                                 from the lumped-mass correction (from 0 when x0_mode = CGP_X0_ZERO) */
   int32_t timing;             /* 1: per-phase HIP-event times in cgp_stats; 2: also bracket every launch of
                                  the Poisson Krylov kernel with HIP events (slows the step; for measurement) */
 } cgp_step_opts;

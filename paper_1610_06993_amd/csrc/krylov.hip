@@ -1429,11 +1429,14 @@ cgp_status drv_correct(cgp_mesh *m, const cgp_solver_opts *o, const double *g, c
   }
   double *rhs = m->d_wf[0];
   launch_correct_rhs(m, g, ut, pf, rhs);
-  if (o->x0_mode == CGP_X0_ZERO)
+  if (o->x0_mode == CGP_X0_ZERO) {
     CGP_HIP(hipMemsetAsync(u, 0, 2 * n * sizeof(double), s));
-  else
-    CGP_HIP(hipMemcpyAsync(u, ut, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
-  launch_set_dirichlet(m, g, u);
+    launch_set_dirichlet(m, g, u);
+  } else {
+    // start from the lumped-mass correction (g on the Dirichlet rows): the consistent solve then
+    // only removes the difference between the two mass matrices
+    launch_correct_lumped(m, g, ut, pf, u);
+  }
   double *w[5] = {m->d_wf[1], m->d_wf[2], m->d_wf[3], m->d_wf[4], m->d_wf[5]};
   KrylovState fin{};
   cgp_status rs = run_pcg64<2>(m, SLOT_MASS, n, m->d_rp_f, m->d_col_f, m->d_Mbc, m->d_dinvM, rhs, u, w, m->tune.fine,
