@@ -128,6 +128,43 @@ def run_spmv_sweep(args, log):
                 copy_frac=round(copy_gbs / HBM_PEAK_GBS, 4))
 
 
+def run_cg_sweep(args, log):
+    """The fused FP64 PCG iteration on coarse operators of growing size (cylinder meshes without
+    refinement): microseconds per iteration and algorithmic GB/s, from the small latency-bound sizes to
+    sizes that stream from HBM."""
+    import numpy as np
+    import torch
+
+    import paper_1610_06993_amd as cgp
+    import workloads as W
+    from paper_1610_06993_amd import SolverOpts
+    iters = 400
+    points = []
+    for tris in (250_000, 1_000_000, 4_000_000):
+        t0 = time.perf_counter()
+        mesh = cgp.Mesh(W.cylinder_channel(tris, seed=3), 0)
+        mesh.assemble(1.0, 1e-3, 1e-3)
+        n, nnz = mesh.info["n_c"], mesh.info["nnz_c"]
+        b = torch.from_numpy(np.random.default_rng(1).normal(size=n)).cuda()
+        x = torch.zeros_like(b)
+        opts = SolverOpts(tol=1e-300, max_iter=iters, x0_mode=cgp._native.X0_ZERO)
+        mesh.poisson_solve(b, x, opts, allow_noconv=True)  # sizes the first chunk: one poll per solve
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        mesh.poisson_solve(b, x, opts, allow_noconv=True)
+        torch.cuda.synchronize()
+        us = 1e6 * (time.perf_counter() - t1) / iters
+        mbytes = (12 * nnz + 92 * n) / 1e6
+        gbs = mbytes * 1e3 / us
+        points.append(dict(rows=n, nnz=nnz, mbytes=round(mbytes, 1), us_per_iteration=round(us, 2),
+                           gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4)))
+        log(f"cg sweep {n} rows, {nnz} nnz, {mbytes:.0f} MB per iteration: {us:.2f} us -> {gbs:.0f} GB/s "
+            f"({gbs / HBM_PEAK_GBS:.2f} of peak); setup {t1 - t0:.1f}s")
+        mesh.close()
+    return dict(kernel="k_cg1_iter<double> (whole PCG iteration, wall time over 400 iterations, host polls included)",
+                points=points)
+
+
 def run_batch(args, log):
     """Config-4-style sweep: independent cylinder instances of uneven size stepped together."""
     import numpy as np
@@ -316,6 +353,8 @@ def main():
     ap.add_argument("--spmv-sweep", type=int, default=1, help="run the SpMV size sweep (0: skip)")
     ap.add_argument("--spmv-large", action="store_true", help="add a 16.8M-row point to the SpMV sweep")
     ap.add_argument("--only-spmv", action="store_true", help="run only the SpMV size sweep")
+    ap.add_argument("--cg-sweep", type=int, default=1, help="run the PCG iteration size sweep (0: skip)")
+    ap.add_argument("--only-cg", action="store_true", help="run only the PCG iteration size sweep")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -346,6 +385,9 @@ def main():
         return
     if args.only_spmv:
         print(json.dumps({"spmv_sweep": run_spmv_sweep(args, log)}), flush=True)
+        return
+    if args.only_cg:
+        print(json.dumps({"cg_sweep": run_cg_sweep(args, log)}), flush=True)
         return
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -561,6 +603,12 @@ def main():
         except Exception as e:
             line["spmv_sweep"] = {"error": f"{type(e).__name__}: {e}"}
             log(f"SpMV sweep failed: {e}")
+    if args.cg_sweep:
+        try:
+            line["cg_sweep"] = run_cg_sweep(args, log)
+        except Exception as e:
+            line["cg_sweep"] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"PCG sweep failed: {e}")
     if args.batch > 0:
         try:
             line["batch"] = run_batch(args, log)

@@ -375,7 +375,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg1_init_w(int Gin, int n, const 
   put_partials<3>(acc, Pout);
 }
 
-template <typename T, int L, int P, int U>
+template <typename T, int L, int P, int U, int E>
 __global__ void __launch_bounds__(kMaxBlock) k_cg1_iter(int Gin, int it, int n, const int *__restrict__ rp,
                                                        const int *__restrict__ col, const T *__restrict__ A,
                                                        T *__restrict__ x, T *__restrict__ p,
@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg1_iter(int Gin, int it, int n, 
                                                        const double *__restrict__ Pin, double *__restrict__ Pout,
                                                        KrylovState *__restrict__ st) {
   using R4 = rec_t<T>;
-  constexpr int E = cg1_ahead<L>();
+  constexpr int EA = E > 0 ? E : 1;  // E = 0: no entries ahead (bandwidth-bound sizes, fewer registers)
   // the previous iteration's state and partials, first in the load queue
   const int stopped = st->status | st->done[0];
   const double bnorm = st->bnorm[0], tol = st->tol;
@@ -396,8 +396,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg1_iter(int Gin, int it, int n, 
   const int rpb = blockDim.x / L;  // rows per block and pass
   const long long rows_chunk = (long long)rpb * P;
   int k0[P], k1[P];
-  T av[P][E], xo[P], po[P];
-  R4 qv[P][E], own[P];
+  T av[P][EA], xo[P], po[P];
+  R4 qv[P][EA], own[P];
   auto load_chunk = [&](int c) {
 #pragma unroll
     for (int q = 0; q < P; q++) {
@@ -494,6 +494,17 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg1_iter(int Gin, int it, int n, 
     load_chunk(c);
   }
   put_partials_last<3>(acc, Pout);
+}
+
+// Large grids: one block sums an iteration's G block partials into 3 totals in a fixed order, so that
+// the next iteration's waves read 3 values instead of 3 G each (that read grows as G squared).
+__global__ void __launch_bounds__(kMaxBlock) k_cg1_total(int G, const double *__restrict__ Pin,
+                                                        double *__restrict__ Ptot,
+                                                        const KrylovState *__restrict__ st) {
+  if (st->status || st->done[0]) return;
+  double t3[3];
+  sum_partials<3>(Pin, G, t3);
+  if (threadIdx.x < 3) Ptot[threadIdx.x] = t3[threadIdx.x];
 }
 
 // after a chunk: convergence and iteration count from the last iteration's partials
@@ -1082,11 +1093,19 @@ cgp_status run_pcg64(cgp_mesh *m, int slot, int n, const int *rp, const int *col
 // Single-kernel PCG loop.  Precondition: records of slot 0 hold {r0, -, 0, D^-1} with
 // r0 = b - K x0 (or the normalised refinement residual), slot 1 holds D^-1, p = 0, and the
 // b.b partials are in R_INIT from a grid of g_first blocks.
+constexpr int kCg1DirectGrid = 256;  // largest grid whose partials every wave of the next iteration sums itself
+
+// Kernel variant for a launch shape: lanes L, rows per lane group P (1 or 2, more by looping), partial
+// sums read U per lane ahead, E entries per lane ahead of the scalars.  `tree`: the partials arrive
+// summed (one value per total) and the sizes are bandwidth-bound, so nothing is loaded ahead and the
+// kernel keeps its registers low for occupancy.
 template <typename F>
-void dispatch_cg1(int lanes, int passes, int grid, F &&f) {
+void dispatch_cg1(int lanes, int passes, int grid, bool tree, F &&f) {
   auto with_LP = [&](auto LC, auto PC) {
-    if (grid > 256) f(LC, PC, std::integral_constant<int, 8>{});
-    else f(LC, PC, std::integral_constant<int, 4>{});
+    constexpr int LL = decltype(LC)::value;
+    if (tree) f(LC, PC, std::integral_constant<int, 1>{}, std::integral_constant<int, 0>{});
+    else if (grid > 256) f(LC, PC, std::integral_constant<int, 8>{}, std::integral_constant<int, cg1_ahead<LL>()>{});
+    else f(LC, PC, std::integral_constant<int, 4>{}, std::integral_constant<int, cg1_ahead<LL>()>{});
   };
   auto with_L = [&](auto LC) {
     if (passes >= 2) with_LP(LC, std::integral_constant<int, 2>{});
@@ -1108,30 +1127,41 @@ cgp_status cg1_loop(cgp_mesh *m, int slot, int n, const int *rp, const int *col,
   hipStream_t s = m->stream;
   const Shape sh = shape_rows(tk, n, tk.lanes);
   double *Pw = region(m, R_A);
-  auto pin = [&](int it) { return it == 0 ? Pw : region(m, ((it - 1) & 1) ? R_C : R_B); };
+  // above 256 blocks the partials of each iteration are first summed by one block (k_cg1_total)
+  const bool tree = sh.grid > kCg1DirectGrid;
+  double *Ptot = region(m, R_INIT) + 4 * kMaxRedGrid;  // 3 totals, clear of the init partials
+  const int gin = tree ? 1 : sh.grid;
+  auto pin = [&](int it) {
+    if (tree) return Ptot;
+    return it == 0 ? Pw : region(m, ((it - 1) & 1) ? R_C : R_B);
+  };
   auto pout = [&](int it) { return region(m, (it & 1) ? R_C : R_B); };
   dispatch_L(tk.lanes, [&](auto LC) {
     constexpr int LL = decltype(LC)::value;
     hipLaunchKernelGGL((k_cg1_init_w<T, LL>), dim3(sh.grid), dim3(sh.block), 0, s, g_first, n, rp, col, A, R[0],
                        (const double *)region(m, R_INIT), Pw, st);
   });
+  if (tree) hipLaunchKernelGGL(k_cg1_total, dim3(1), dim3(1024), 0, s, sh.grid, (const double *)Pw, Ptot, st);
   int it = 0, chunk = std::max(1, std::min(*chunk_hint, maxit));
   for (;;) {
-    dispatch_cg1(tk.lanes, tk.passes, sh.grid, [&](auto LC, auto PC, auto UC) {
+    dispatch_cg1(tk.lanes, tk.passes, sh.grid, tree, [&](auto LC, auto PC, auto UC, auto EC) {
       constexpr int LL = decltype(LC)::value, PP = decltype(PC)::value, UU = decltype(UC)::value;
+      constexpr int EE = decltype(EC)::value;
       for (int c = 0; c < chunk && it < maxit; c++, it++) {
         const int cur = it & 1, nxt = cur ^ 1;
         hipEvent_t e0, e1;
         if (timed && kt_slot(m, it, &e0, &e1))
-          hipExtLaunchKernelGGL((k_cg1_iter<T, LL, PP, UU>), dim3(sh.grid), dim3(sh.block), 0, s, e0, e1, 0, sh.grid,
-                                it, n, rp, col, A, x, p, (const rec_t<T> *)R[cur], R[nxt], (const double *)pin(it),
+          hipExtLaunchKernelGGL((k_cg1_iter<T, LL, PP, UU, EE>), dim3(sh.grid), dim3(sh.block), 0, s, e0, e1, 0, gin, it,
+                                n, rp, col, A, x, p, (const rec_t<T> *)R[cur], R[nxt], (const double *)pin(it),
                                 pout(it), st);
         else
-          hipLaunchKernelGGL((k_cg1_iter<T, LL, PP, UU>), dim3(sh.grid), dim3(sh.block), 0, s, sh.grid, it, n, rp,
-                             col, A, x, p, (const rec_t<T> *)R[cur], R[nxt], (const double *)pin(it), pout(it), st);
+          hipLaunchKernelGGL((k_cg1_iter<T, LL, PP, UU, EE>), dim3(sh.grid), dim3(sh.block), 0, s, gin, it, n, rp, col,
+                             A, x, p, (const rec_t<T> *)R[cur], R[nxt], (const double *)pin(it), pout(it), st);
+        if (tree)
+          hipLaunchKernelGGL(k_cg1_total, dim3(1), dim3(1024), 0, s, sh.grid, (const double *)pout(it), Ptot, st);
       }
     });
-    hipLaunchKernelGGL(k_cg1_finish, dim3(1), dim3(256), 0, s, it, sh.grid, (const double *)pin(it), st);
+    hipLaunchKernelGGL(k_cg1_finish, dim3(1), dim3(256), 0, s, it, gin, (const double *)pin(it), st);
     CGP_HIP(hipGetLastError());
     cgp_status ps = poll(m, slot);
     if (ps) return ps;
