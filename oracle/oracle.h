@@ -3,7 +3,7 @@
  * time step of Kashefi & Staples, "A Finite-Element Coarse-Grid Projection
  * Method" (Sections 2.1-2.2, Eqs. 16-23; Remark 2.2, Eqs. 29-30).
  *
- * TEST INFRASTRUCTURE ONLY.  This library is the judge of the GPU path: only
+ * TEST INFRASTRUCTURE ONLY.  This library is the reference the GPU path is checked against: only
  * the test suite, the package smoke check and the benchmark's CPU-baseline leg
  * may load it.  It shares no code, header or table with the GPU library, and
  * is written to be read against the paper, not to be fast: element loops in
