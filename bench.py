@@ -333,6 +333,7 @@ def main():
     ap.add_argument("--hidden", type=int, default=128, help="hidden width of the guess networks")
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--window", type=int, default=32, help="solutions kept for the online POD basis")
+    ap.add_argument("--refresh", type=int, default=1, help="Poisson solves between online basis rebuilds")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps timed for the CPU baseline (0: skip)")
     ap.add_argument("--no-instrumented", action="store_true", help="skip the event-timed kernel pass")
     ap.add_argument("--launch", choices=["loop", "persistent", "fused"], default="fused",
@@ -462,7 +463,7 @@ def main():
         pc.copy_(snap_pc)
         pf.zero_()
         if model == "online":
-            online.set_online(args.window, 1)
+            online.set_online(args.window, args.refresh)
             online.attach()
             for k in range(S - args.window, S):  # the newest recorded solves fill the window
                 mesh.poisson_solve(rhs[k], ps[k].clone(), SolverOpts(tol=tol, x0_mode=X0.X0_PREV))

@@ -1066,7 +1066,7 @@ cgp_status pcg_loop(cgp_mesh *m, int slot, int n, const int *rp, const int *col,
     chunk = std::max(8, it / 16);  // later chunks grow: fewer polls, bounded overshoot
   }
   *out = m->h_state[slot];
-  *chunk_hint = std::max(1, out->iters - 2);
+  *chunk_hint = out->iters + 1;  // stable counts (mass solves): the next solve usually needs one poll
   return CGP_OK;
 }
 
@@ -1250,7 +1250,7 @@ cgp_status drv_momentum(cgp_mesh *m, const cgp_solver_opts *o, const double *g, 
   }
   hipLaunchKernelGGL((k_zero_b_fix<2>), dim3(blocks_1d(n)), dim3(256), 0, s, n, ut, (const KrylovState *)st);
   const KrylovState h = m->h_state[SLOT_MOM];
-  m->mom_chunk = std::max(1, h.iters - 1);
+  m->mom_chunk = std::max(1, h.iters + 1);  // one iteration of slack: usually a single poll per solve
   if (stats) {
     stats->mom_iters = h.iters;
     stats->mom_relres = 0.0;
