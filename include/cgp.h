@@ -283,7 +283,10 @@ cgp_status cgp_last_poisson_rhs(const cgp_mesh *mesh, double *dst);
  * concatenated block-diagonal system, one kernel launch per iteration for all instances, each instance
  * with its own scalars and convergence test; chunks of `chunk` iterations are captured into HIP graphs
  * (use_graph = 1) and replayed, with one poll per chunk.  The other phases of cgp_batch_step run per
- * instance as in cgp_step.  Pointer arrays are host arrays of n device pointers. */
+ * instance as in cgp_step, on up to 4 streams of the batch driven from as many host threads (each
+ * mesh runs on one of them for the phase; the meshes' stream waits for all of them afterwards), so
+ * the meshes must not be used elsewhere during the call.  Pointer arrays are host arrays of n
+ * device pointers. */
 typedef struct cgp_batch cgp_batch;
 typedef struct { int32_t lanes, block, passes, use_graph, chunk; } cgp_batch_tuning;
 cgp_status cgp_batch_create(cgp_mesh *const *meshes, int32_t n, cgp_batch **out);

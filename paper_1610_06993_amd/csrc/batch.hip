@@ -27,16 +27,23 @@
 #include <fstream>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "devutil.h"
 #include "kernels.h"
 #include "learn.h"
 
+constexpr int kBatchLanes = 4;  // host threads / streams for the per-instance phases of a batch step
+
 struct cgp_batch {
   std::vector<cgp_mesh *> meshes;
   hipStream_t mstream = nullptr;     // the meshes' stream
   hipStream_t stream = nullptr;      // the batch's own stream (graphs are captured on it)
+  // per-instance phases of cgp_batch_step run on these streams from as many host threads, so that the
+  // small instances' latency-bound solves overlap (default priority, like every stream here)
+  std::vector<hipStream_t> aux;
+  std::vector<hipEvent_t> aux_ev;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   int ninst = 0;
   long rows = 0, nnz = 0;
@@ -646,6 +653,8 @@ void cgp_batch_destroy(cgp_batch *B) {
   if (B->h_state) (void)hipHostFree(B->h_state);
   if (B->ev_in) (void)hipEventDestroy(B->ev_in);
   if (B->ev_out) (void)hipEventDestroy(B->ev_out);
+  for (hipStream_t a : B->aux) (void)hipStreamDestroy(a);
+  for (hipEvent_t e : B->aux_ev) (void)hipEventDestroy(e);
   if (B->stream) (void)hipStreamDestroy(B->stream);
   delete B;
 }
@@ -685,6 +694,19 @@ cgp_status cgp_batch_create(cgp_mesh *const *meshes, int32_t n, cgp_batch **out)
   B->rows = rows;
   B->nnz = nnz;
   B->mstream = meshes[0]->stream;
+  const int naux = std::min(n, kBatchLanes);
+  B->aux.assign(naux, nullptr);
+  B->aux_ev.assign(naux + 1, nullptr);
+  for (int k = 0; k < naux; k++)
+    if (hipStreamCreateWithFlags(&B->aux[k], hipStreamNonBlocking) != hipSuccess) {
+      set_error("cgp_batch_create: stream creation failed");
+      return fail(CGP_E_DEVICE);
+    }
+  for (auto &e : B->aux_ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      set_error("cgp_batch_create: event creation failed");
+      return fail(CGP_E_DEVICE);
+    }
   if (hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming) != hipSuccess) {
@@ -847,31 +869,81 @@ cgp_status cgp_batch_step(cgp_batch *B, const cgp_step_opts *o, const double *co
   const int n = B->ninst;
   std::vector<cgp_stats> S(n);
   std::vector<const double *> bc(n);
+  // phases 1-2 and 4-5 per instance, on the auxiliary streams from one host thread per stream (each
+  // mesh is touched by one thread; its stream is swapped for the phase and restored)
+  auto per_instance = [&](auto &&body) -> cgp_status {
+    const int T = (int)B->aux.size();
+    CGP_HIP(hipEventRecord(B->aux_ev[T], B->mstream));
+    for (int k = 0; k < T; k++) CGP_HIP(hipStreamWaitEvent(B->aux[k], B->aux_ev[T], 0));
+    std::vector<cgp_status> st(T, CGP_OK);
+    std::vector<std::string> msg(T);
+    int dev = 0;
+    CGP_HIP(hipGetDevice(&dev));
+    auto work = [&](int k) {
+      if (hipSetDevice(dev) != hipSuccess) {  // the current device is per host thread
+        st[k] = CGP_E_DEVICE;
+        msg[k] = "cgp_batch_step: hipSetDevice failed in a worker thread";
+        return;
+      }
+      for (int i = k; i < n; i += T) {
+        cgp_mesh *m = B->meshes[i];
+        m->stream = B->aux[k];
+        const cgp_status r = body(i, m);
+        m->stream = B->mstream;
+        if (r != CGP_OK && (st[k] == CGP_OK || st[k] == CGP_E_NOCONV)) {
+          st[k] = r;
+          msg[k] = cgp_last_error();
+        }
+        if (r != CGP_OK && r != CGP_E_NOCONV) return;
+      }
+    };
+    std::vector<std::thread> pool;
+    int started = 1;
+    try {
+      for (int k = 1; k < T; k++, started++) pool.emplace_back(work, k);
+    } catch (const std::exception &) {  // no more threads: the rest run on this one
+    }
+    work(0);
+    for (int k = started; k < T; k++) work(k);
+    for (auto &t : pool) t.join();
+    for (int k = 0; k < T; k++) {
+      CGP_HIP(hipEventRecord(B->aux_ev[k], B->aux[k]));
+      CGP_HIP(hipStreamWaitEvent(B->mstream, B->aux_ev[k], 0));
+    }
+    cgp_status worst = CGP_OK;
+    for (int k = 0; k < T; k++)
+      if (st[k] != CGP_OK && (worst == CGP_OK || worst == CGP_E_NOCONV)) {
+        worst = st[k];
+        set_error(msg[k]);
+      }
+    return worst;
+  };
   cgp_status worst = CGP_OK;
   auto note = [&](cgp_status s) {
     if (s == CGP_E_NOCONV && worst == CGP_OK) worst = s;
     return s == CGP_OK || s == CGP_E_NOCONV;
   };
   // steps 1-2 (Eqs. 19-21) per instance
-  for (int i = 0; i < n; i++) {
-    cgp_mesh *m = B->meshes[i];
-    cgp_status s = drv_momentum(m, &o->momentum, g[i], f ? f[i] : nullptr, u[i], m->d_ut, &S[i]);
-    if (!note(s)) return s;
-    s = drv_restrict(m, m->d_ut, m->d_bc);
-    if (!note(s)) return s;
-    bc[i] = m->d_bc;
-  }
+  cgp_status s = per_instance([&](int i, cgp_mesh *m) {
+    cgp_status r = drv_momentum(m, &o->momentum, g[i], f ? f[i] : nullptr, u[i], m->d_ut, &S[i]);
+    if (r != CGP_OK && r != CGP_E_NOCONV) return r;
+    const cgp_status r2 = drv_restrict(m, m->d_ut, m->d_bc);
+    return r2 != CGP_OK ? r2 : r;
+  });
+  if (!note(s)) return s;
+  for (int i = 0; i < n; i++) bc[i] = B->meshes[i]->d_bc;
   // step 3 (Eq. 21): every instance's Poisson solve in one PCG
   std::vector<cgp_stats> P(n);
-  cgp_status s = cgp_batch_poisson_solve(B, bc.data(), pc, &o->poisson, P.data());
+  s = cgp_batch_poisson_solve(B, bc.data(), pc, &o->poisson, P.data());
   if (!note(s)) return s;
   // steps 4-5 (Eqs. 22-23) per instance
+  s = per_instance([&](int i, cgp_mesh *m) {
+    const cgp_status r = drv_prolong(m, pc[i], pf[i]);
+    if (r != CGP_OK) return r;
+    return drv_correct(m, &o->mass, g[i], m->d_ut, pf[i], u[i], &S[i]);
+  });
+  if (!note(s)) return s;
   for (int i = 0; i < n; i++) {
-    cgp_mesh *m = B->meshes[i];
-    s = drv_prolong(m, pc[i], pf[i]);
-    if (!note(s)) return s;
-    s = drv_correct(m, &o->mass, g[i], m->d_ut, pf[i], u[i], &S[i]);
-    if (!note(s)) return s;
     S[i].p_iters = P[i].p_iters;
     S[i].p_outer = P[i].p_outer;
     S[i].p_relres = P[i].p_relres;
