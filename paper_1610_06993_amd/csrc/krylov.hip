@@ -938,6 +938,7 @@ enum { R_INIT = 0, R_A = 1, R_B = 2, R_C = 3 };
 inline double *region(cgp_mesh *m, int k) { return m->red.partials + size_t(k) * 8 * kMaxRedGrid; }
 
 cgp_status poll(cgp_mesh *m, int slot, int count = 1) {
+  guess_progress(m);  // host work of a pending online rebuild, while the queued kernels run
   CGP_HIP(hipMemcpyAsync(&m->h_state[slot], m->d_state + slot, sizeof(KrylovState) * count, hipMemcpyDeviceToHost,
                          m->stream));
   CGP_HIP(hipStreamSynchronize(m->stream));

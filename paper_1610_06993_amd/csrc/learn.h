@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -21,6 +22,15 @@ struct cgp_guess {
   double *d_ring = nullptr;           // [ring_cap][n]
   int ring_cap = 0, win = 0, refresh = 1, head = 0, filled = 0;
   long recorded = 0;
+  // an online rebuild runs in stages on its own stream, overlapping the next step's momentum solve:
+  // 0 idle, 1 Gram matrix queued, 2 basis queued (the host finishes each stage when its event is done)
+  int stage = 0;
+  cgp_status stage_err = CGP_OK;
+  std::string stage_msg;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_in = nullptr, ev_gram = nullptr, ev_basis = nullptr, ev_done = nullptr;
+  const double *pend_snaps = nullptr;  // snapshots of the rebuild in progress
+  int pend_S = 0;
   // network: parameters [W1 nh*nm | b1 nh | W2 nh*nh | b2 nh | W3 nm*nh | b3 nm]
   long nparams = 0;
   float *d_w = nullptr, *d_g = nullptr, *d_m = nullptr, *d_v = nullptr;
@@ -49,6 +59,10 @@ constexpr int kMaxBatch = 256;
 // the incremental model applied to Phi^T (b - K x);
 // CGP_X0_POD_GALERKIN: x0 = x + Phi (Phi^T K Phi)^-1 Phi^T (b - K x).  x holds the previous pressure.
 cgp_status guess_initial(cgp_mesh *m, int mode, const double *b, double *x);
-// After a converged Poisson solve: keep x in the attached guess's window and refresh its basis when due.
+// After a converged Poisson solve: keep x in the attached guess's window and start the refresh of its
+// basis when due (completed by guess_progress or at the next guess_initial).
 cgp_status guess_record(cgp_mesh *m, const double *x);
+// Called by the solvers before they wait on the mesh's stream: moves a pending online rebuild on
+// (host eigen-decomposition) when its Gram matrix is ready, without blocking.
+void guess_progress(cgp_mesh *m);
 }  // namespace cgp

@@ -24,6 +24,11 @@
 #include "learn.h"
 
 namespace cgp {
+namespace {
+cgp_status pod_events(cgp_guess *g);
+cgp_status pod_finish(cgp_guess *g);
+cgp_status pod_stage_gram(cgp_guess *g, hipStream_t st, const double *snaps, int S);
+}  // namespace
 namespace ldev {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
@@ -362,6 +367,7 @@ cgp_status pinned(cgp_guess *g, size_t count, double **out) {
   if (g->pin_cap < count) {
     if (g->h_pin) {
       CGP_HIP(hipStreamSynchronize(g->mesh->stream));  // a copy from the old staging may be in flight
+      if (g->side) CGP_HIP(hipStreamSynchronize(g->side));
       (void)hipHostFree(g->h_pin);
     }
     g->h_pin = nullptr;
@@ -541,6 +547,10 @@ void orthonormalise(int S, int q, std::vector<double> &Y) {
 
 cgp_status guess_initial(cgp_mesh *m, int mode, const double *b, double *x) {
   cgp_guess *g = m->guess;
+  if (g) {
+    cgp_status ps = pod_finish(g);  // an online rebuild started after the last solve
+    if (ps) return ps;
+  }
   if (g && g->win > 0 && mode == CGP_X0_POD_GALERKIN && !g->pod_ready) return CGP_OK;  // window still filling
   if (!g || !g->pod_ready || (mode != CGP_X0_POD_GALERKIN && !g->trained)) {
     set_error("learned initial guess requested but no trained model is attached");
@@ -585,15 +595,21 @@ cgp_status guess_initial(cgp_mesh *m, int mode, const double *b, double *x) {
 cgp_status guess_record(cgp_mesh *m, const double *x) {
   cgp_guess *g = m->guess;
   if (!g || g->win <= 0) return CGP_OK;
+  cgp_status st = pod_finish(g);  // a rebuild still reading the window ends before a slot is replaced
+  if (st) return st;
   CGP_HIP(hipMemcpyAsync(g->d_ring + (size_t)g->head * g->n, x, sizeof(double) * g->n, hipMemcpyDeviceToDevice,
                          m->stream));
   g->head = (g->head + 1) % g->win;
   g->filled = std::min(g->filled + 1, g->win);
   g->recorded++;
   if (g->filled >= g->nm && g->recorded % g->refresh == 0) {
-    // the basis of the newest window (slot order does not matter to the POD)
-    cgp_status st = cgp_guess_build_pod(g, g->d_ring, g->filled, nullptr);
+    // the basis of the newest window (slot order does not matter to the POD), built on the guess's
+    // own stream: the Gram matrix now, the rest as the solvers poll and at the next guess
+    CGP_HIP(hipEventRecord(g->ev_in, m->stream));
+    CGP_HIP(hipStreamWaitEvent(g->side, g->ev_in, 0));
+    st = pod_stage_gram(g, g->side, g->d_ring, g->filled);
     if (st) return st;
+    g->stage = 1;
   }
   return CGP_OK;
 }
@@ -608,6 +624,16 @@ cgp_status cgp_guess_set_online(cgp_guess *g, int32_t window, int32_t refresh) {
   if (!g || window < 0 || (window > 0 && (window < g->nm || window > 1024 || refresh < 1))) {
     set_error("cgp_guess_set_online: window must be 0 (off) or in n_modes..1024, refresh >= 1");
     return CGP_E_ARG;
+  }
+  cgp_status ps = pod_finish(g);
+  if (ps) return ps;
+  if (window > 0) {
+    ps = pod_events(g);
+    if (ps) return ps;
+    if (!g->side && hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking) != hipSuccess) {
+      set_error("cgp_guess_set_online: stream creation failed");
+      return CGP_E_DEVICE;
+    }
   }
   if (window > g->ring_cap) {
     double *r = nullptr;
@@ -687,6 +713,9 @@ void cgp_guess_destroy(cgp_guess *g) {
   (void)hipDeviceSynchronize();
   for (void *p : g->allocations) (void)hipFree(p);
   if (g->h_pin) (void)hipHostFree(g->h_pin);
+  for (hipEvent_t e : {g->ev_in, g->ev_gram, g->ev_basis, g->ev_done})
+    if (e) (void)hipEventDestroy(e);
+  if (g->side) (void)hipStreamDestroy(g->side);
   delete g;
 }
 
@@ -742,24 +771,38 @@ cgp_status cgp_guess_export_norm(const cgp_guess *g, double *host, size_t count)
   return CGP_OK;
 }
 
-cgp_status cgp_guess_build_pod(cgp_guess *g, const double *snaps, int32_t S, double *energy) {
-  if (!g || !snaps || S < g->nm) {
-    set_error("cgp_guess_build_pod: need at least n_modes snapshots");
-    return CGP_E_ARG;
-  }
-  cgp_mesh *m = g->mesh;
-  hipStream_t s = m->stream;
+}  // extern "C"
+
+namespace cgp {
+namespace {
+
+// ---- the POD build in three stages on a stream `st` (the mesh's stream for an explicit build, the
+// guess's own stream for an online rebuild).  Pinned staging: [Gram S*S | Vs S*nm | Phi^T K Phi nm*nm |
+// inverse nm*nm].
+
+// stage 1: Gram matrix G = S M S^T (FP64, device) copied to the host; event ev_gram
+cgp_status pod_stage_gram(cgp_guess *g, hipStream_t st, const double *snaps, int S) {
   const int n = g->n, nm = g->nm;
-  // pinned staging: [Gram S*S | Vs S*nm | Phi^T K Phi nm*nm | inverse nm*nm]
   double *hp = nullptr;
   GTRY(pinned(g, (size_t)S * S + (size_t)S * nm + 2 * (size_t)nm * nm, &hp));
-  double *hG = hp, *hV = hG + (size_t)S * S, *hK = hV + (size_t)S * nm, *hI = hK + (size_t)nm * nm;
-  // Gram matrix G = S M S^T (FP64, device), then to the host
   double *dG = nullptr;
   GTRY(scratch(g, 0, (size_t)S * S, &dG));
-  GTRY(gemm64(g, s, S, S, n, snaps, n, 1, m->d_mc, snaps, 1, n, dG));
-  CGP_HIP(hipMemcpyAsync(hG, dG, sizeof(double) * S * S, hipMemcpyDeviceToHost, s));
-  CGP_HIP(hipStreamSynchronize(s));
+  GTRY(gemm64(g, st, S, S, n, snaps, n, 1, g->mesh->d_mc, snaps, 1, n, dG));
+  CGP_HIP(hipMemcpyAsync(hp, dG, sizeof(double) * S * S, hipMemcpyDeviceToHost, st));
+  CGP_HIP(hipEventRecord(g->ev_gram, st));
+  g->pend_snaps = snaps;
+  g->pend_S = S;
+  return CGP_OK;
+}
+
+// stage 2 (host, once the Gram matrix is there): top nm eigenpairs, Vs = V Lambda^-1/2 to the device,
+// Phi = S^T Vs, K Phi and Phi^T K Phi, the latter to the host; event ev_basis
+cgp_status pod_stage_basis(cgp_guess *g, hipStream_t st) {
+  cgp_mesh *m = g->mesh;
+  const int n = g->n, nm = g->nm, S = g->pend_S;
+  const double *snaps = g->pend_snaps;
+  CGP_HIP(hipEventSynchronize(g->ev_gram));
+  double *hG = g->h_pin, *hV = hG + (size_t)S * S, *hK = hV + (size_t)S * nm;
   std::vector<double> G(hG, hG + (size_t)S * S);
   // randomised subspace iteration for the nm largest eigenpairs (Halko, Martinsson & Tropp 2011);
   // when the oversampled subspace is the whole snapshot space, G itself is decomposed
@@ -827,14 +870,14 @@ cgp_status cgp_guess_build_pod(cgp_guess *g, const double *snaps, int32_t S, dou
       Vs[(size_t)a * nm + k] = v * inv;
     }
   }
-  if (energy) std::copy(g->energy.begin(), g->energy.end(), energy);
+  g->rank = rank;
   // Phi = S^T Vs  ([n][nm])
   double *dV = nullptr;
   GTRY(scratch(g, 1, Vs.size(), &dV));
   std::copy(Vs.begin(), Vs.end(), hV);
-  CGP_HIP(hipMemcpyAsync(dV, hV, sizeof(double) * Vs.size(), hipMemcpyHostToDevice, s));
-  GTRY(gemm64(g, s, n, nm, S, snaps, 1, n, nullptr, dV, nm, 1, g->d_phi));
-  // Phi^T K Phi and its inverse (POD-Galerkin guess)
+  CGP_HIP(hipMemcpyAsync(dV, hV, sizeof(double) * Vs.size(), hipMemcpyHostToDevice, st));
+  GTRY(gemm64(g, st, n, nm, S, snaps, 1, n, nullptr, dV, nm, 1, g->d_phi));
+  // Phi^T K Phi (POD-Galerkin guess) to the host
   double *dKP = nullptr, *dPKP = nullptr;
   GTRY(scratch(g, 2, (size_t)n * nm, &dKP));
   GTRY(scratch(g, 3, (size_t)nm * nm, &dPKP));
@@ -842,18 +885,26 @@ cgp_status cgp_guess_build_pod(cgp_guess *g, const double *snaps, int32_t S, dou
     const int rpw = nm <= 16 ? 4 : (nm <= 32 ? 2 : 1);
     const dim3 grid((unsigned)std::min<long>(65535, ((long)n + 4 * rpw - 1) / (4 * rpw)));
     if (rpw == 4)
-      hipLaunchKernelGGL((k_spmm_modes<16>), grid, dim3(256), 0, s, n, nm, m->d_rp_c, m->d_col_c,
+      hipLaunchKernelGGL((k_spmm_modes<16>), grid, dim3(256), 0, st, n, nm, m->d_rp_c, m->d_col_c,
                          (const double *)m->d_Kbc, (const double *)g->d_phi, dKP);
     else if (rpw == 2)
-      hipLaunchKernelGGL((k_spmm_modes<32>), grid, dim3(256), 0, s, n, nm, m->d_rp_c, m->d_col_c,
+      hipLaunchKernelGGL((k_spmm_modes<32>), grid, dim3(256), 0, st, n, nm, m->d_rp_c, m->d_col_c,
                          (const double *)m->d_Kbc, (const double *)g->d_phi, dKP);
     else
-      hipLaunchKernelGGL((k_spmm_modes<64>), grid, dim3(256), 0, s, n, nm, m->d_rp_c, m->d_col_c,
+      hipLaunchKernelGGL((k_spmm_modes<64>), grid, dim3(256), 0, st, n, nm, m->d_rp_c, m->d_col_c,
                          (const double *)m->d_Kbc, (const double *)g->d_phi, dKP);
   }
-  GTRY(gemm64(g, s, nm, nm, n, g->d_phi, 1, nm, nullptr, dKP, nm, 1, dPKP));
-  CGP_HIP(hipMemcpyAsync(hK, dPKP, sizeof(double) * nm * nm, hipMemcpyDeviceToHost, s));
-  CGP_HIP(hipStreamSynchronize(s));
+  GTRY(gemm64(g, st, nm, nm, n, g->d_phi, 1, nm, nullptr, dKP, nm, 1, dPKP));
+  CGP_HIP(hipMemcpyAsync(hK, dPKP, sizeof(double) * nm * nm, hipMemcpyDeviceToHost, st));
+  CGP_HIP(hipEventRecord(g->ev_basis, st));
+  return CGP_OK;
+}
+
+// stage 3 (host, once Phi^T K Phi is there): its inverse to the device; the mesh's stream waits for st
+cgp_status pod_stage_inverse(cgp_guess *g, hipStream_t st) {
+  const int nm = g->nm, S = g->pend_S, rank = g->rank;
+  CGP_HIP(hipEventSynchronize(g->ev_basis));
+  double *hK = g->h_pin + (size_t)S * S + (size_t)S * nm, *hI = hK + (size_t)nm * nm;
   std::vector<double> Kc(hK, hK + (size_t)nm * nm);
   // inverse of the leading rank x rank block by Gauss-Jordan with partial pivoting (SPD and tiny);
   // rows and columns of the unused modes stay zero
@@ -886,17 +937,86 @@ cgp_status cgp_guess_build_pod(cgp_guess *g, const double *snaps, int32_t S, dou
       }
     }
   }
-  // the staging stays untouched until the next call's first synchronisation, after this copy
+  // the staging stays untouched until the next build's first synchronisation, after this copy
   std::copy(inv.begin(), inv.end(), hI);
-  CGP_HIP(hipMemcpyAsync(g->d_kinv, hI, sizeof(double) * inv.size(), hipMemcpyHostToDevice, s));
+  CGP_HIP(hipMemcpyAsync(g->d_kinv, hI, sizeof(double) * inv.size(), hipMemcpyHostToDevice, st));
+  if (st != g->mesh->stream) {
+    CGP_HIP(hipEventRecord(g->ev_done, st));
+    CGP_HIP(hipStreamWaitEvent(g->mesh->stream, g->ev_done, 0));
+  }
   g->pod_ready = true;
   g->trained = false;
-  g->rank = rank;
   return CGP_OK;
+}
+
+cgp_status pod_events(cgp_guess *g) {
+  if (g->ev_gram) return CGP_OK;
+  for (hipEvent_t *e : {&g->ev_in, &g->ev_gram, &g->ev_basis, &g->ev_done})
+    CGP_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  return CGP_OK;
+}
+
+// finish an online rebuild in progress (blocking); an error from a stage run inside a solver's poll is
+// reported here
+cgp_status pod_finish(cgp_guess *g) {
+  if (g->stage_err) {
+    const cgp_status e = g->stage_err;
+    g->stage_err = CGP_OK;
+    g->stage = 0;
+    set_error(g->stage_msg);
+    return e;
+  }
+  if (g->stage == 1) {
+    cgp_status st = pod_stage_basis(g, g->side);
+    if (st) {
+      g->stage = 0;
+      return st;
+    }
+    g->stage = 2;
+  }
+  if (g->stage == 2) {
+    g->stage = 0;
+    return pod_stage_inverse(g, g->side);
+  }
+  return CGP_OK;
+}
+
+}  // namespace
+
+void guess_progress(cgp_mesh *m) {
+  cgp_guess *g = m->guess;
+  if (!g || g->stage != 1 || g->stage_err) return;
+  if (hipEventQuery(g->ev_gram) != hipSuccess) return;  // not there yet: a later poll or the next guess
+  const cgp_status st = pod_stage_basis(g, g->side);
+  if (st) {
+    g->stage_err = st;
+    g->stage_msg = cgp_last_error();
+    return;
+  }
+  g->stage = 2;
+}
+
+}  // namespace cgp
+
+extern "C" {
+
+cgp_status cgp_guess_build_pod(cgp_guess *g, const double *snaps, int32_t S, double *energy) {
+  if (!g || !snaps || S < g->nm) {
+    set_error("cgp_guess_build_pod: need at least n_modes snapshots");
+    return CGP_E_ARG;
+  }
+  GTRY(pod_events(g));
+  GTRY(pod_finish(g));
+  hipStream_t s = g->mesh->stream;
+  GTRY(pod_stage_gram(g, s, snaps, S));
+  GTRY(pod_stage_basis(g, s));
+  if (energy) std::copy(g->energy.begin(), g->energy.end(), energy);
+  return pod_stage_inverse(g, s);
 }
 
 cgp_status cgp_guess_train(cgp_guess *g, const double *rhs, const double *p, int32_t S, const cgp_train_opts *o,
                            cgp_train_stats *stats) {
+  if (g) GTRY(pod_finish(g));
   if (!g || !rhs || !p || !o || S < 2 || S > 65536 || !g->pod_ready || o->batch < 1 || o->batch > kMaxBatch ||
       o->epochs < 1 || !(o->lr > 0)) {
     set_error("cgp_guess_train: bad argument (basis built? 2 <= S <= 65536, batch in 1..256, epochs >= 1, lr > 0)");
