@@ -986,7 +986,11 @@ cgp_status pod_finish(cgp_guess *g) {
 void guess_progress(cgp_mesh *m) {
   cgp_guess *g = m->guess;
   if (!g || g->stage != 1 || g->stage_err) return;
-  if (hipEventQuery(g->ev_gram) != hipSuccess) return;  // not there yet: a later poll or the next guess
+  const bool clean = hipPeekAtLastError() == hipSuccess;
+  if (hipEventQuery(g->ev_gram) != hipSuccess) {  // not there yet: a later poll or the next guess
+    if (clean) (void)hipGetLastError();            // "not ready" is no error of the caller's launches
+    return;
+  }
   const cgp_status st = pod_stage_basis(g, g->side);
   if (st) {
     g->stage_err = st;
