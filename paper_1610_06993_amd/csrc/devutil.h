@@ -49,7 +49,9 @@ __device__ __forceinline__ float group_sumf(float x) {
   return x;
 }
 
-__device__ __forceinline__ bool is_finite(double x) { return x == x && x - x == 0.0; }
+// A classification test, not x - x == 0: with floating-point contraction (the HIP default) a
+// product's x - x can become fma(a, b, -(a b)), its rounding error, and reject finite values.
+__device__ __forceinline__ bool is_finite(double x) { return __builtin_isfinite(x); }
 
 // Sum K values over the block in a fixed order; every thread gets the totals.
 template <int K>

@@ -112,7 +112,8 @@ __device__ __forceinline__ void grid_allreduce(double (&v)[K], double *buf, Grid
   for (int k = 0; k < K; k++) tot[k] = res[k];
 }
 
-__device__ __forceinline__ bool finite(double x) { return x == x && x - x == 0.0; }
+// a classification test: x - x == 0 can contract into an fma that rejects finite products
+__device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
 
 template <typename T, int L, bool IR, int BAR>
 __global__ void __launch_bounds__(kBlock) k_pcg_persistent(PersistArgs args) {
