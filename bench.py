@@ -197,7 +197,7 @@ def run_batch(args, log):
     tol = 1e-8
     X0 = cgp._native
     mom = SolverOpts(tol=args.mom_tol, max_iter=5000,
-                     x0_mode={"prev": X0.X0_PREV, "extrap": X0.X0_EXTRAP}[args.mom_x0])
+                     x0_mode={"prev": X0.X0_PREV, "extrap": X0.X0_EXTRAP, "project": X0.X0_PROJECT}[args.mom_x0])
     opts = StepOpts(momentum=mom, poisson=SolverOpts(tol=tol, max_iter=100000),
                     mass=SolverOpts(tol=args.mass_tol, max_iter=2000))
     for k in range(2):
@@ -338,8 +338,9 @@ def main():
     ap.add_argument("--no-instrumented", action="store_true", help="skip the event-timed kernel pass")
     ap.add_argument("--launch", choices=["loop", "persistent", "fused"], default="fused",
                     help="Poisson Krylov launch strategy")
-    ap.add_argument("--mom-x0", choices=["prev", "extrap"], default="extrap",
-                    help="momentum initial guess: U^n, or the quadratic extrapolation of the three previous solves")
+    ap.add_argument("--mom-x0", choices=["prev", "extrap", "project"], default="project",
+                    help="momentum initial guess: U^n, the quadratic extrapolation of the three previous solves, or "
+                         "the residual-minimising combination of the last eight")
     # the Poisson right-hand side is the divergence of U~, small beside U~ itself: a momentum error of
     # relative size t reaches it amplified ~100-300x, so the momentum solve runs 2.5 decades below the
     # Poisson's (sweep on the online-POD path: 1e-9 -> 90, 3e-10 -> 105, 1e-10 -> 114, 3e-11 -> 118 steps/s)
@@ -414,7 +415,7 @@ def main():
     tol = 1e-8
     launch = {"loop": 1, "persistent": 2, "fused": 3}[args.launch]
 
-    mom_x0 = {"prev": X0.X0_PREV, "extrap": X0.X0_EXTRAP}[args.mom_x0]
+    mom_x0 = {"prev": X0.X0_PREV, "extrap": X0.X0_EXTRAP, "project": X0.X0_PROJECT}[args.mom_x0]
 
     def opts(precision=0, x0=X0.X0_PREV, timing=0):
         return StepOpts(momentum=SolverOpts(tol=args.mom_tol, max_iter=5000, x0_mode=mom_x0),

@@ -74,10 +74,18 @@ enum { CGP_X0_ZERO = 0,            /* Krylov initial guess zero */
        CGP_X0_LEARNED = 2,         /* Poisson only: x0 = Phi c, c from the attached POD/MLP model */
        CGP_X0_LEARNED_CORR = 3,    /* Poisson only: x0 = x + Phi dc, dc from the incremental model and b - K x */
        CGP_X0_POD_GALERKIN = 4,    /* Poisson only: previous pressure plus the Galerkin correction in span(Phi) */
-       CGP_X0_EXTRAP = 5 };        /* cgp_step momentum only: x0 = 3 U~^n - 3 U~^(n-1) + U~^(n-2), the quadratic
+       CGP_X0_EXTRAP = 5,          /* cgp_step momentum only: x0 = 3 U~^n - 3 U~^(n-1) + U~^(n-2), the quadratic
                                       extrapolation of this mesh's three previous intermediate velocities
                                       (U^n after no such step, linear 2 U~^n - U~^(n-1) after one); the solve
                                       still meets its tolerance */
+       CGP_X0_PROJECT = 6 };       /* cgp_step momentum only: per velocity component, x0 = the combination of
+                                      this mesh's last (up to 8) intermediate velocities from consecutive
+                                      cgp_step calls in this mode that minimises ||b - A x0||_2 over the
+                                      non-Dirichlet rows of the current system (normal equations, scaled to a
+                                      unit diagonal, ridge 1e-13, solved on the device); U^n before the first
+                                      such step.  The span holds the quadratic extrapolation, so the starting
+                                      residual is never larger than that of CGP_X0_EXTRAP beyond rounding.
+                                      The first use allocates 128 bytes per fine node for the history. */
 
 enum { CGP_LAUNCH_AUTO = 0,        /* library choice (FUSED for the Poisson solve) */
        CGP_LAUNCH_LOOP = 1,        /* two kernels per PCG iteration (textbook recurrences), host polls every chunk */

@@ -17,7 +17,7 @@ VEL_DIRICHLET, OUTFLOW = 1, 2
 RESTRICT_INJECT, RESTRICT_GALERKIN = 0, 1
 MASS_CONSISTENT, MASS_LUMPED = 0, 1
 PREC_FP64, PREC_FP32_IR = 0, 1
-X0_ZERO, X0_PREV, X0_LEARNED, X0_LEARNED_CORR, X0_POD_GALERKIN, X0_EXTRAP = 0, 1, 2, 3, 4, 5
+X0_ZERO, X0_PREV, X0_LEARNED, X0_LEARNED_CORR, X0_POD_GALERKIN, X0_EXTRAP, X0_PROJECT = 0, 1, 2, 3, 4, 5, 6
 LAUNCH_AUTO, LAUNCH_LOOP, LAUNCH_PERSISTENT, LAUNCH_FUSED = 0, 1, 2, 3
 OP_KBC_C, OP_M_F, OP_A_F, OP_KBC_C32 = 0, 1, 2, 3
 

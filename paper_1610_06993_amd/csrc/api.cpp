@@ -126,7 +126,7 @@ bool valid_opts(const cgp_solver_opts *o, bool poisson, bool allow_extrap = fals
   if (!(o->tol > 0.0) || o->max_iter < 1) return false;
   if (o->precision != CGP_PREC_FP64 && !(poisson && o->precision == CGP_PREC_FP32_IR)) return false;
   if (o->x0_mode < CGP_X0_ZERO || o->x0_mode > (poisson ? CGP_X0_POD_GALERKIN : CGP_X0_PREV)) {
-    if (!(allow_extrap && !poisson && o->x0_mode == CGP_X0_EXTRAP)) return false;
+    if (!(allow_extrap && !poisson && (o->x0_mode == CGP_X0_EXTRAP || o->x0_mode == CGP_X0_PROJECT))) return false;
   }
   if (o->launch < CGP_LAUNCH_AUTO || o->launch > CGP_LAUNCH_FUSED) return false;
   return true;

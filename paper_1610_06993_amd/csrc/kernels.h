@@ -10,6 +10,15 @@ namespace cgp {
 constexpr int kMaxGrid = 2048;        // cap on blocks of non-reducing row kernels (grid-stride loops)
 constexpr int kMaxRedGrid = 8192;     // cap on blocks of reducing kernels (one partial each)
 
+// projected momentum guess (CGP_X0_PROJECT): ring of the last kProj momentum solutions; per
+// component the Gram matrix's upper triangle (kProjTri entries) and kProj right-hand-side entries;
+// ridge added to the unit-diagonal scaled Gram matrix; blocks of the Gram kernel
+constexpr int kProj = 8;
+constexpr int kProjTri = kProj * (kProj + 1) / 2;
+constexpr int kProjPer = kProjTri + kProj;
+constexpr double kProjRidge = 1e-13;
+constexpr int kProjGrid = 512;
+
 // Launch shape of a reducing kernel: `lanes` threads per CSR row (row kernels),
 // `block` threads per block, each lane group covering `passes` rows.
 struct Shape {

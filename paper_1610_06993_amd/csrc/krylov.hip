@@ -838,6 +838,194 @@ __global__ void __launch_bounds__(kMaxBlock) k_bi_finish(int it_end, int G, cons
   if (bad) st->status = CGP_E_NONFINITE;
 }
 
+// ------------------------------------------------------------------ projected momentum guess
+// The momentum solutions of the last kProj consecutive steps are kept per node, hist[j][i] =
+// (U_i,x, U_i,y) of ring slot i at node j: 128 bytes a node, so one gathered column brings all
+// of them.  The initial guess is, per component, the combination x0 = sum_i c_i U_i that
+// minimises ||b - A x0||_2 over the free rows (A and b after the Dirichlet elimination, whose
+// free rows do not read the Dirichlet columns): the normal equations (AU)^T (AU) c = (AU)^T b.
+
+// Per block: partial sums of the two Gram matrices (upper triangles) and right-hand sides over
+// its row tiles, one array of gridDim.x partials per entry.  Entry e of component c sits at
+// c * kProjPer + e: the triangle row by row (i <= j), then (AU_i)^T b for i < kProj.
+template <int L>
+__global__ void __launch_bounds__(256) k_proj_gram(int n, const int *__restrict__ rp, const int *__restrict__ col,
+                                                  const double *__restrict__ A, const unsigned char *__restrict__ vdir,
+                                                  const double2 *__restrict__ hist, const double2 *__restrict__ b,
+                                                  double *__restrict__ P) {
+  constexpr int R = 256 / L;  // rows per tile
+  __shared__ double sw[R][2 * kProj + 3];
+  const int lane = threadIdx.x & (L - 1), g = threadIdx.x / L;
+  int ci = -1, cj = -1;  // the two LDS columns whose product this thread accumulates
+  if (threadIdx.x < 2 * kProjPer) {
+    const int c = threadIdx.x / kProjPer;
+    int e = threadIdx.x % kProjPer;
+    if (e < kProjTri) {
+      int i = 0;
+      while (e >= kProj - i) {
+        e -= kProj - i;
+        i++;
+      }
+      ci = c * kProj + i;
+      cj = c * kProj + i + e;
+    } else {
+      ci = c * kProj + (e - kProjTri);
+      cj = 2 * kProj + c;
+    }
+  }
+  double acc = 0.0;
+  const int tiles = (n + R - 1) / R;
+  for (int tile = xcd_block(); tile < tiles; tile += gridDim.x) {
+    const int row = tile * R + g;
+    double wx[kProj], wy[kProj];
+#pragma unroll
+    for (int i = 0; i < kProj; i++) wx[i] = wy[i] = 0.0;
+    if (row < n) {
+      for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
+        const double a = A[k];
+        const double2 *h = hist + (size_t)col[k] * kProj;
+#pragma unroll
+        for (int i = 0; i < kProj; i++) {
+          const double2 v = h[i];
+          wx[i] += a * v.x;
+          wy[i] += a * v.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kProj; i++) {
+      wx[i] = group_sum<L>(wx[i]);
+      wy[i] = group_sum<L>(wy[i]);
+    }
+    if (lane == 0) {
+      const bool fr = row < n && !vdir[row];
+      const double2 bb = fr ? b[row] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < kProj; i++) {
+        sw[g][i] = fr ? wx[i] : 0.0;
+        sw[g][kProj + i] = fr ? wy[i] : 0.0;
+      }
+      sw[g][2 * kProj] = bb.x;
+      sw[g][2 * kProj + 1] = bb.y;
+    }
+    __syncthreads();
+    if (ci >= 0)
+      for (int r = 0; r < R; r++) acc += sw[r][ci] * sw[r][cj];
+    __syncthreads();
+  }
+  if (ci >= 0) P[threadIdx.x * gridDim.x + blockIdx.x] = acc;
+}
+
+// Sums the G partials of every entry (fixed order), then one thread per component solves the
+// normal equations over the k filled ring slots: diagonal scaling to a unit diagonal, a ridge of
+// kProjRidge (the solutions of consecutive steps are close to collinear; the ridge keeps every
+// direction with a damped weight), Cholesky.  Unfilled slots and zero columns become identity
+// rows with a zero right-hand side, and a pivot that does not stay above half the ridge drops its
+// direction, so their coefficients are 0.  If anything is not finite the guess falls back to the
+// newest solution alone.  Every loop has a constant trip count, so the arrays live in registers.
+__global__ void __launch_bounds__(64) k_proj_solve(int G, int k, int newest, const double *__restrict__ P,
+                                                  double *__restrict__ coef) {
+  __shared__ double S[2 * kProjPer];
+  for (int e = threadIdx.x; e < 2 * kProjPer; e += blockDim.x) {
+    double s = 0.0;
+    for (int q = 0; q < G; q++) s += P[e * G + q];
+    S[e] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x >= 2) return;
+  const int c = threadIdx.x;
+  const double *T = S + c * kProjPer;
+  double a[kProj][kProj], h[kProj], sc[kProj], y[kProj];
+  bool use[kProj];
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < kProj; i++) {
+#pragma unroll
+    for (int j = 0; j < kProj; j++) {
+      const int lo = i < j ? i : j, hi = i < j ? j : i;
+      a[i][j] = T[lo * kProj - lo * (lo - 1) / 2 + (hi - lo)];  // upper triangle, row by row
+    }
+    h[i] = T[kProjTri + i];
+  }
+#pragma unroll
+  for (int i = 0; i < kProj; i++) {
+    const bool live = i < k;
+    ok = ok && (!live || (is_finite(a[i][i]) && is_finite(h[i])));
+    sc[i] = (live && a[i][i] > 0.0) ? 1.0 / sqrt(a[i][i]) : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < kProj; i++) {
+#pragma unroll
+    for (int j = 0; j < kProj; j++)
+      a[i][j] = (sc[i] > 0.0 && sc[j] > 0.0) ? a[i][j] * sc[i] * sc[j] : (i == j ? 1.0 : 0.0);
+    a[i][i] += sc[i] > 0.0 ? kProjRidge : 0.0;
+    h[i] = sc[i] > 0.0 ? h[i] * sc[i] : 0.0;
+  }
+  // L L^T in the lower triangle
+#pragma unroll
+  for (int j = 0; j < kProj; j++) {
+    double d = a[j][j];
+#pragma unroll
+    for (int q = 0; q < j; q++) d -= a[j][q] * a[j][q];
+    use[j] = d > 0.5 * kProjRidge;
+    const double lj = use[j] ? sqrt(d) : 1.0;
+    a[j][j] = lj;
+#pragma unroll
+    for (int i = j + 1; i < kProj; i++) {
+      double v = a[i][j];
+#pragma unroll
+      for (int q = 0; q < j; q++) v -= a[i][q] * a[j][q];
+      a[i][j] = use[j] ? v / lj : 0.0;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kProj; i++) {  // L z = h
+    double v = h[i];
+#pragma unroll
+    for (int q = 0; q < i; q++) v -= a[i][q] * y[q];
+    y[i] = use[i] ? v / a[i][i] : 0.0;
+  }
+#pragma unroll
+  for (int i = kProj - 1; i >= 0; i--) {  // L^T w = z
+    double v = y[i];
+#pragma unroll
+    for (int q = i + 1; q < kProj; q++) v -= a[q][i] * y[q];
+    y[i] = use[i] ? v / a[i][i] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < kProj; i++) {
+    y[i] *= sc[i];
+    ok = ok && is_finite(y[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < kProj; i++) coef[c * kProj + i] = ok ? y[i] : (i == newest ? 1.0 : 0.0);
+}
+
+// x0 = sum_{i<k} c_i U_i per component
+__global__ void k_proj_x0(int n, int k, const double2 *__restrict__ hist, const double *__restrict__ coef,
+                          double2 *__restrict__ x) {
+  __shared__ double cs[2 * kProj];
+  if (threadIdx.x < 2 * kProj) cs[threadIdx.x] = coef[threadIdx.x];
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 *h = hist + (size_t)i * kProj;
+  double sx = 0.0, sy = 0.0;
+  for (int s = 0; s < k; s++) {
+    const double2 v = h[s];
+    sx += cs[s] * v.x;
+    sy += cs[kProj + s] * v.y;
+  }
+  x[i] = make_double2(sx, sy);
+}
+
+// ring slot `slot` of every node <- the new solution
+__global__ void k_proj_push(int n, const double2 *__restrict__ ut, double2 *__restrict__ hist, int slot) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  hist[(size_t)i * kProj + slot] = ut[i];
+}
+
 // ------------------------------------------------------------------ iterative refinement (FP32 inner PCG)
 // r64 = b - K x in FP64; partials (r.r, b.b)
 template <int L>
@@ -1189,7 +1377,35 @@ cgp_status drv_momentum(cgp_mesh *m, const cgp_solver_opts *o, const double *g, 
   double2 *rhs = (double2 *)m->d_wf[0];
   launch_mom_rhs(m, g, u, f, (double *)rhs);
   const bool extrap = (o->x0_mode == CGP_X0_EXTRAP && ut == m->d_ut);
-  if (extrap && m->ut_hist >= 3) {
+  const bool project = (o->x0_mode == CGP_X0_PROJECT && ut == m->d_ut);
+  if (project && !m->d_uhist) {
+    const size_t hb = (size_t)kProj * 2 * n * sizeof(double);
+    const size_t pb = (2 * (size_t)kProjPer * kProjGrid + 2 * kProj) * sizeof(double);
+    void *q = nullptr;
+    CGP_HIP(hipMalloc(&q, hb));
+    m->allocations.push_back(q);
+    m->d_uhist = (double *)q;
+    CGP_HIP(hipMalloc(&q, pb));
+    m->allocations.push_back(q);
+    m->d_proj = (double *)q;
+    CGP_HIP(hipMemsetAsync(m->d_uhist, 0, hb, s));  // unused slots hold finite values
+    m->uh_count = m->uh_head = 0;
+  }
+  if (!project) m->uh_count = m->uh_head = 0;  // the ring fills from slot 0 again
+  if (project && m->uh_count > 0) {
+    // x0 from the ring (A and rhs above are the eliminated system of this step)
+    const int k = m->uh_count, newest = (m->uh_head + kProj - 1) % kProj;
+    const int tiles = (n + 63) / 64;
+    const int G = std::max(8, std::min(kProjGrid, (tiles + 7) / 8 * 8));
+    double *coef = m->d_proj + 2 * (size_t)kProjPer * kProjGrid;
+    hipLaunchKernelGGL((k_proj_gram<4>), dim3(G), dim3(256), 0, s, n, m->d_rp_f, m->d_col_f, (const double *)m->d_A,
+                       m->d_vdir, (const double2 *)m->d_uhist, (const double2 *)rhs, m->d_proj);
+    hipLaunchKernelGGL(k_proj_solve, dim3(1), dim3(64), 0, s, G, k, newest, (const double *)m->d_proj, coef);
+    hipLaunchKernelGGL(k_proj_x0, dim3(blocks_1d(n)), dim3(256), 0, s, n, k, (const double2 *)m->d_uhist,
+                       (const double *)coef, (double2 *)ut);
+  } else if (project) {
+    CGP_HIP(hipMemcpyAsync(ut, u, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else if (extrap && m->ut_hist >= 3) {
     // d_ut, d_ut_prev, d_ut_prev2 hold U~^n, U~^(n-1), U~^(n-2): x0 = 3 U~^n - 3 U~^(n-1) + U~^(n-2)
     // (quadratic in time), and the history shifts by one step
     launch_extrapolate3(m, 2 * n, m->d_ut, m->d_ut_prev, m->d_ut_prev2);
@@ -1252,6 +1468,14 @@ cgp_status drv_momentum(cgp_mesh *m, const cgp_solver_opts *o, const double *g, 
   hipLaunchKernelGGL((k_zero_b_fix<2>), dim3(blocks_1d(n)), dim3(256), 0, s, n, ut, (const KrylovState *)st);
   const KrylovState h = m->h_state[SLOT_MOM];
   m->mom_chunk = std::max(1, h.iters + 1);  // one iteration of slack: usually a single poll per solve
+  if (project && status_of(h, SLOT_MOM) == CGP_OK) {
+    hipLaunchKernelGGL(k_proj_push, dim3(blocks_1d(n)), dim3(256), 0, s, n, (const double2 *)ut,
+                       (double2 *)m->d_uhist, m->uh_head);
+    m->uh_head = (m->uh_head + 1) % kProj;
+    m->uh_count = std::min(m->uh_count + 1, kProj);
+  } else {
+    m->uh_count = m->uh_head = 0;
+  }
   if (stats) {
     stats->mom_iters = h.iters;
     stats->mom_relres = 0.0;

@@ -261,6 +261,60 @@ def test_extrapolated_momentum_guess(env):
     _run_steps(env, case, 1, 6, opts, tol=1e-15)
 
 
+def test_projected_momentum_guess(env):
+    """The residual-minimising combination of the last momentum solutions as x0: 11 steps (the ring
+    of 8 fills and wraps), one extrapolated step (the ring restarts), 3 more; every step against the
+    oracle with both sides' momentum solves at 1e-15."""
+    torch, cgp, oracle = env
+    case = make(CYLINDER_CASE)
+    _say("cylinder, momentum x0 projected, 11 + 1 + 3 steps")
+    X0 = cgp._native
+    g, o = make_pair(env, case.mesh, 1, case.rho, case.mu, case.dt)
+    xy = g.export("xy")
+    u0 = case.initial(xy, g.export("vdir"))
+    u = dev(torch, u0.copy())
+    pf = torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda")
+    pc = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
+    ur, pcr = u0.copy(), None
+    modes = [X0.X0_PROJECT] * 11 + [X0.X0_EXTRAP] + [X0.X0_PROJECT] * 3
+    for k, mode in enumerate(modes):
+        opts = tight_opts(cgp)
+        opts.momentum = cgp.SolverOpts(tol=1e-15, max_iter=100000, x0_mode=mode)
+        opts.mass = cgp.SolverOpts(tol=1e-15, max_iter=100000)
+        gd = case.dirichlet(xy, (k + 1) * case.dt)
+        g.step(dev(torch, gd), u, pf, pc, opts=opts)
+        ur, pfr, pcr, code, _ = o.step(gd, ur, pcr, tol_mom=1e-15, tol_p=TIGHT_P, tol_mass=1e-15)
+        assert code == 0
+        eu, ep = rel(u.cpu().numpy(), ur), rel(pf.cpu().numpy(), pfr)
+        assert eu <= 1e-10 and ep <= 1e-10, (k, mode, eu, ep)
+
+
+def test_projected_guess_fewer_iterations(env):
+    """From the same state, once the ring is full, the projected start needs no more momentum
+    iterations than the quadratic extrapolation (its span holds the extrapolant)."""
+    torch, cgp, oracle = env
+    case = W.case_cylinder(12000, seed=3)
+    _say("cylinder 12k, momentum iterations projected vs extrapolated")
+    X0 = cgp._native
+    iters = {}
+    for mode in (X0.X0_EXTRAP, X0.X0_PROJECT):
+        g = cgp.Mesh(case.mesh, 1)
+        g.assemble(case.rho, case.mu, case.dt)
+        xy = g.export("xy")
+        u = dev(torch, case.initial(xy, g.export("vdir")))
+        pf = torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda")
+        pc = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
+        gd = dev(torch, case.dirichlet(xy, 0.0))
+        opts = cgp.StepOpts(momentum=cgp.SolverOpts(tol=3e-11, max_iter=5000, x0_mode=mode),
+                            poisson=cgp.SolverOpts(tol=1e-8, max_iter=100000),
+                            mass=cgp.SolverOpts(tol=1e-10, max_iter=2000))
+        its = [g.step(gd, u, pf, pc, opts=opts)["mom_iters"] for _ in range(14)]
+        iters[mode] = its
+        g.close()
+    _say("extrapolated", iters[X0.X0_EXTRAP], "projected", iters[X0.X0_PROJECT])
+    assert sum(iters[X0.X0_PROJECT][9:]) <= sum(iters[X0.X0_EXTRAP][9:])
+
+
 def test_fp32_ir_step_within_1e6(env):
     torch, cgp, oracle = env
     case = W.case_cylinder(12000, seed=3)
