@@ -433,7 +433,13 @@ def main():
     rhs = torch.zeros((S, n_c), dtype=torch.float64, device=dev)
     ps = torch.zeros_like(rhs)
     pprev = torch.zeros_like(rhs)
+    # each path restarts REPLAY recorded steps before the end and steps them again, so that the
+    # momentum guess's history (the last 8 solves) is this trajectory's own when the path starts
+    REPLAY = 9
+    assert S >= REPLAY, "--snapshots must be at least 9"
     for k in range(S):
+        if k == S - REPLAY:
+            replay_u, replay_pc = u.clone(), pc.clone()
         pprev[k].copy_(pc)
         mesh.step(g, u, pf, pc, opts=opts())
         mesh.last_poisson_rhs(rhs[k])
@@ -456,13 +462,20 @@ def main():
     # restarting a path refills its window from the recorded pressures
     online = cgp.Guess(mesh, n_modes=args.window, hidden=16, seed=5)
     models["online"] = online
-    snap_u, snap_pc = u.clone(), pc.clone()
 
     def restore(model=None):
-        """Back to the recorded state with `model` attached (None: no guess model)."""
-        u.copy_(snap_u)
-        pc.copy_(snap_pc)
+        """Back to the recorded state with `model` attached (None: no guess model): the last REPLAY
+        recorded steps are stepped again with plain FP64 Poisson solves and no model, the first with
+        the momentum solve started from U^n (which empties the momentum guess's history)."""
+        online.detach()
+        u.copy_(replay_u)
+        pc.copy_(replay_pc)
         pf.zero_()
+        for k in range(REPLAY):
+            o = opts()
+            if k == 0:
+                o.momentum.x0_mode = X0.X0_PREV
+            mesh.step(g, u, pf, pc, opts=o)
         if model == "online":
             online.set_online(args.window, args.refresh)
             online.attach()
@@ -500,19 +513,22 @@ def main():
         restore(model)
         mesh.step(g, u, pf, pc, opts=opts(prec, x0))  # untimed: solver chunk sizes adapt
         restore(model)
-        iters = []
+        iters, miters = [], []
         t1 = time.perf_counter()
         for k in range(args.steps):
             st = mesh.step(g, u, pf, pc, opts=opts(prec, x0))
             iters.append(st["p_iters"])
+            miters.append(st["mom_iters"])
         torch.cuda.synchronize()
         el = time.perf_counter() - t1
         results[name] = dict(steps_per_s=round(args.steps / el, 3), ms_per_step=round(1e3 * el / args.steps, 3),
-                             poisson_iters_mean=float(np.mean(iters)), rel_err_vs_fp64=err,
+                             poisson_iters_mean=float(np.mean(iters)), momentum_iters_mean=float(np.mean(miters)),
+                             rel_err_vs_fp64=err,
                              phase_ms={k: round(st1[k], 4) for k in ("ms_momentum", "ms_restrict", "ms_poisson",
                                                                      "ms_prolong", "ms_correct")})
         log(f"{name}: {args.steps / el:.2f} steps/s ({1e3 * el / args.steps:.2f} ms/step), Poisson iterations "
-            f"{np.mean(iters):.0f}, one-step rel err vs fp64 {err:.1e}; phases (ms) mom {st1['ms_momentum']:.2f} "
+            f"{np.mean(iters):.0f}, momentum iterations {np.mean(miters):.1f}, one-step rel err vs fp64 {err:.1e}; "
+            f"phases (ms) mom {st1['ms_momentum']:.2f} "
             f"poisson {st1['ms_poisson']:.2f} correct {st1['ms_correct']:.2f}")
     restore()
 
@@ -552,9 +568,9 @@ def main():
         import oracle
         ref = oracle.Problem(case.mesh, 1)
         ref.assemble(case.rho, case.mu, case.dt)
-        ur, pcr = snap_u.cpu().numpy(), snap_pc.cpu().numpy()
         gh = g.cpu().numpy()
         restore(bmodel)
+        ur, pcr = u.cpu().numpy(), pc.cpu().numpy()
         mesh.step(g, u, pf, pc, opts=opts(bprec, bx0))
         ub, pfb = u.cpu().numpy(), pf.cpu().numpy()
         restore()

@@ -17,7 +17,7 @@ constexpr int kProj = 8;
 constexpr int kProjTri = kProj * (kProj + 1) / 2;
 constexpr int kProjPer = kProjTri + kProj;
 constexpr double kProjRidge = 1e-13;
-constexpr int kProjGrid = 512;
+constexpr int kProjGrid = 1024;
 
 // Launch shape of a reducing kernel: `lanes` threads per CSR row (row kernels),
 // `block` threads per block, each lane group covering `passes` rows.

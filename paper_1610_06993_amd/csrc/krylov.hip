@@ -909,29 +909,39 @@ __global__ void __launch_bounds__(256) k_proj_gram(int n, const int *__restrict_
       sw[g][2 * kProj + 1] = bb.y;
     }
     __syncthreads();
-    if (ci >= 0)
-      for (int r = 0; r < R; r++) acc += sw[r][ci] * sw[r][cj];
+    if (ci >= 0) {  // four independent chains over the tile's rows
+      double a4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int r = 0; r < R; r += 4) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) a4[q] += sw[r + q][ci] * sw[r + q][cj];
+      }
+      acc += (a4[0] + a4[1]) + (a4[2] + a4[3]);
+    }
     __syncthreads();
   }
   if (ci >= 0) P[threadIdx.x * gridDim.x + blockIdx.x] = acc;
 }
 
-// Sums the G partials of every entry (fixed order), then one thread per component solves the
-// normal equations over the k filled ring slots: diagonal scaling to a unit diagonal, a ridge of
-// kProjRidge (the solutions of consecutive steps are close to collinear; the ridge keeps every
-// direction with a damped weight), Cholesky.  Unfilled slots and zero columns become identity
-// rows with a zero right-hand side, and a pivot that does not stay above half the ridge drops its
-// direction, so their coefficients are 0.  If anything is not finite the guess falls back to the
-// newest solution alone.  Every loop has a constant trip count, so the arrays live in registers.
-__global__ void __launch_bounds__(64) k_proj_solve(int G, int k, int newest, const double *__restrict__ P,
+// One block per Gram entry: the G block partials summed in a fixed order into S[entry].
+__global__ void __launch_bounds__(256) k_proj_sum(int G, const double *__restrict__ P, double *__restrict__ S) {
+  const double *p = P + (size_t)blockIdx.x * G;
+  double v[1] = {0.0};
+  for (int q = threadIdx.x; q < G; q += blockDim.x) v[0] += p[q];
+  double tot[1];
+  block_sum<1>(v, tot);
+  if (threadIdx.x == 0) S[blockIdx.x] = tot[0];
+}
+
+// One thread per component solves the normal equations over the k filled ring slots: diagonal
+// scaling to a unit diagonal, a ridge of kProjRidge (the solutions of consecutive steps are close
+// to collinear; the ridge keeps every direction with a damped weight), Cholesky.  Unfilled slots
+// and zero columns become identity rows with a zero right-hand side, and a pivot that does not
+// stay above half the ridge drops its direction, so their coefficients are 0.  If anything is not
+// finite the guess falls back to the newest solution alone.  Every loop has a constant trip count,
+// so the arrays live in registers.
+__global__ void __launch_bounds__(64) k_proj_solve(int k, int newest, const double *__restrict__ S,
                                                   double *__restrict__ coef) {
-  __shared__ double S[2 * kProjPer];
-  for (int e = threadIdx.x; e < 2 * kProjPer; e += blockDim.x) {
-    double s = 0.0;
-    for (int q = 0; q < G; q++) s += P[e * G + q];
-    S[e] = s;
-  }
-  __syncthreads();
   if (threadIdx.x >= 2) return;
   const int c = threadIdx.x;
   const double *T = S + c * kProjPer;
@@ -1380,7 +1390,7 @@ cgp_status drv_momentum(cgp_mesh *m, const cgp_solver_opts *o, const double *g, 
   const bool project = (o->x0_mode == CGP_X0_PROJECT && ut == m->d_ut);
   if (project && !m->d_uhist) {
     const size_t hb = (size_t)kProj * 2 * n * sizeof(double);
-    const size_t pb = (2 * (size_t)kProjPer * kProjGrid + 2 * kProj) * sizeof(double);
+    const size_t pb = (2 * (size_t)kProjPer * kProjGrid + 2 * kProj + 2 * kProjPer) * sizeof(double);
     void *q = nullptr;
     CGP_HIP(hipMalloc(&q, hb));
     m->allocations.push_back(q);
@@ -1400,7 +1410,9 @@ cgp_status drv_momentum(cgp_mesh *m, const cgp_solver_opts *o, const double *g, 
     double *coef = m->d_proj + 2 * (size_t)kProjPer * kProjGrid;
     hipLaunchKernelGGL((k_proj_gram<4>), dim3(G), dim3(256), 0, s, n, m->d_rp_f, m->d_col_f, (const double *)m->d_A,
                        m->d_vdir, (const double2 *)m->d_uhist, (const double2 *)rhs, m->d_proj);
-    hipLaunchKernelGGL(k_proj_solve, dim3(1), dim3(64), 0, s, G, k, newest, (const double *)m->d_proj, coef);
+    double *sums = coef + 2 * kProj;
+    hipLaunchKernelGGL(k_proj_sum, dim3(2 * kProjPer), dim3(256), 0, s, G, (const double *)m->d_proj, sums);
+    hipLaunchKernelGGL(k_proj_solve, dim3(1), dim3(64), 0, s, k, newest, (const double *)sums, coef);
     hipLaunchKernelGGL(k_proj_x0, dim3(blocks_1d(n)), dim3(256), 0, s, n, k, (const double2 *)m->d_uhist,
                        (const double *)coef, (double2 *)ut);
   } else if (project) {
