@@ -65,6 +65,21 @@ cgp_status build_device(cgp_mesh *m) {
   TRY(upload(m, &m->d_xy_c, C.xy.data(), C.xy.size()));
   TRY(upload(m, &m->d_tri_f, trif.data(), trif.size()));
   TRY(upload(m, &m->d_slot_f, slotf.data(), slotf.size()));
+  {  // fine node i -> the vertex triples {v0, v1, v2, 0} of its elements, in element order, row after row
+    const int nf = F.n, tf = F.t;
+    std::vector<int> ptr(nf + 1, 0);
+    for (int v : F.tri) ptr[v + 1]++;
+    for (int i = 0; i < nf; i++) ptr[i + 1] += ptr[i];
+    std::vector<int> pos(ptr.begin(), ptr.end() - 1), incv(4 * (size_t)ptr[nf]);
+    for (int e = 0; e < tf; e++)
+      for (int a = 0; a < 3; a++) {
+        const size_t q = (size_t)pos[F.tri[3 * e + a]]++;
+        for (int b = 0; b < 3; b++) incv[4 * q + b] = F.tri[3 * e + b];
+        incv[4 * q + 3] = 0;
+      }
+    TRY(upload(m, &m->d_inc_ptr_f, ptr.data(), ptr.size()));
+    TRY(upload(m, &m->d_incv_f, incv.data(), incv.size()));
+  }
   TRY(upload(m, &m->d_tri_c, tric.data(), tric.size()));
   TRY(upload(m, &m->d_slot_c, slotc.data(), slotc.size()));
   TRY(upload(m, &m->d_rp_f, m->pf.rp.data(), m->pf.rp.size()));

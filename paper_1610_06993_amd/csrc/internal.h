@@ -102,6 +102,7 @@ struct cgp_mesh {
   // device topology
   double *d_xy_f = nullptr, *d_xy_c = nullptr;
   int *d_tri_f = nullptr, *d_slot_f = nullptr;      // permuted by colour
+  int *d_inc_ptr_f = nullptr, *d_incv_f = nullptr;  // fine node -> vertex triples {v0, v1, v2, 0} of its elements
   int *d_tri_c = nullptr, *d_slot_c = nullptr;
   int *d_rp_f = nullptr, *d_col_f = nullptr, *d_rp_c = nullptr, *d_col_c = nullptr;
   unsigned char *d_vdir = nullptr, *d_pdir = nullptr;

@@ -61,7 +61,7 @@ cgp_status drv_correct(cgp_mesh *m, const cgp_solver_opts *o, const double *g, c
 cgp_status drv_spmv(cgp_mesh *m, int op, const void *x, void *y);
 
 // launchers of kernels.hip used by the Krylov drivers (enqueue only)
-void launch_conv_assembly(cgp_mesh *m, const double *u);
+void launch_conv_assembly(cgp_mesh *m, const double *u);  // d_A = S + dt N(u), every entry
 void launch_mom_rhs(cgp_mesh *m, const double *g, const double *u, const double *f, double *rhs);
 void launch_correct_rhs(cgp_mesh *m, const double *g, const double *ut, const double *pf, double *rhs);
 void launch_correct_lumped(cgp_mesh *m, const double *g, const double *ut, const double *pf, double *u);

@@ -2,9 +2,11 @@
 // CSR SpMV and the grid-transfer / pressure-path kernels, with their host
 // launchers.  The Krylov solvers live in krylov.hip.
 //
-// Everything here is memory-bound.  Element assembly scatters into CSR values
-// colour by colour (elements of one colour share no node, so no atomics and a
-// fixed summation order); CSR kernels give each row a group of L lanes so that
+// Everything here is memory-bound.  The static element assembly scatters into
+// CSR values colour by colour (elements of one colour share no node, so no
+// atomics and a fixed summation order); the per-step momentum matrix is formed
+// entry by entry from a node-to-element list instead (one launch, no scatter);
+// CSR kernels give each row a group of L lanes so that
 // one wavefront streams 64/L consecutive rows with coalesced value and column
 // loads; grid-transfer kernels are gathers over index tables.
 #include <hip/hip_runtime.h>
@@ -84,23 +86,48 @@ __global__ void k_asm_coarse_static(int begin, int count, const int *__restrict_
   }
 }
 
-// Convection: A += dt * N(U^n), N_ab = rho/24 [(u_a + sum u) b_b + (v_a + sum v) c_b].
-__global__ void k_asm_conv(int begin, int count, const int *__restrict__ tri, const int *__restrict__ slot,
-                           const double2 *__restrict__ xy, const double2 *__restrict__ u, double dtrho24,
-                           double *__restrict__ A) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  const int e = begin + i;
-  const int v[3] = {tri[3 * e], tri[3 * e + 1], tri[3 * e + 2]};
-  Geo g = geometry(xy, v[0], v[1], v[2]);
-  const double2 u0 = u[v[0]], u1 = u[v[1]], u2 = u[v[2]];
-  const double su = u0.x + u1.x + u2.x, sv = u0.y + u1.y + u2.y;
-  const double ua[3] = {u0.x + su, u1.x + su, u2.x + su};
-  const double va[3] = {u0.y + sv, u1.y + sv, u2.y + sv};
+// Momentum matrix A = S + dt N(U^n), N_ab = rho/24 [(u_a + sum u) b_b + (v_a + sum v) c_b], formed
+// per row: a group of L lanes takes row i, each lane one element around i (vertex triples,
+// contiguous per row in element order; more than L elements are taken L at a time) and forms
+// that element's row (u_i + sum u) b + (v_i + sum v) c.  For each entry (i, j) of the row the
+// group sums, in a fixed butterfly order, what the elements containing j contribute, and lane
+// (s mod L) keeps the total of the row's s-th entry; every entry is written once, from S.
+template <int L>
+__global__ void k_asm_conv_rows(int n, const int *__restrict__ rp, const int *__restrict__ col,
+                                const double *__restrict__ S, const int *__restrict__ inc_ptr,
+                                const int4 *__restrict__ incv, const double2 *__restrict__ xy,
+                                const double2 *__restrict__ u, double dtrho24, double *__restrict__ A) {
+  const int lane = threadIdx.x & (L - 1);
+  const int row = (blockIdx.x * blockDim.x + threadIdx.x) / L;
+  if (row >= n) return;  // the whole group
+  const int k0 = rp[row], deg = rp[row + 1] - k0, p0 = inc_ptr[row], p1 = inc_ptr[row + 1];
+  const double2 ui = u[row];
+  for (int s0 = 0; s0 < deg; s0 += 2 * L) {  // entries s0 .. s0 + 2L - 1 of the row
+    double acc0 = 0.0, acc1 = 0.0;          // totals of entries s0 + lane and s0 + L + lane
+    for (int q0 = p0; q0 < p1; q0 += L) {
+      const int q = q0 + lane;
+      int4 v = make_int4(-1, -1, -1, 0);
+      double cb[3] = {0.0, 0.0, 0.0};
+      if (q < p1) {
+        v = incv[q];
+        const Geo g = geometry(xy, v.x, v.y, v.z);
+        const double2 u0 = u[v.x], u1 = u[v.y], u2 = u[v.z];
+        const double ua = ui.x + (u0.x + u1.x + u2.x), va = ui.y + (u0.y + u1.y + u2.y);
 #pragma unroll
-  for (int a = 0; a < 3; a++)
-#pragma unroll
-    for (int b = 0; b < 3; b++) A[slot[9 * e + 3 * a + b]] += dtrho24 * (ua[a] * g.b[b] + va[a] * g.c[b]);
+        for (int b = 0; b < 3; b++) cb[b] = ua * g.b[b] + va * g.c[b];
+      }
+      const int s1 = min(deg, s0 + 2 * L);
+      for (int s = s0; s < s1; s++) {
+        const int j = col[k0 + s];
+        double c = (v.x == j) ? cb[0] : (v.y == j) ? cb[1] : (v.z == j) ? cb[2] : 0.0;
+        c = group_sum<L>(c);
+        if (s - s0 == lane) acc0 += c;
+        if (s - s0 == L + lane) acc1 += c;
+      }
+    }
+    if (s0 + lane < deg) A[k0 + s0 + lane] = S[k0 + s0 + lane] + dtrho24 * acc0;
+    if (s0 + L + lane < deg) A[k0 + s0 + L + lane] = S[k0 + s0 + L + lane] + dtrho24 * acc1;
+  }
 }
 
 // Coarse p = 0 elimination (Eq. 14): rows/columns of pressure-Dirichlet nodes
@@ -426,12 +453,12 @@ __global__ void k_set_dirichlet(int n, const unsigned char *__restrict__ vdir, c
 using namespace dev;
 
 void launch_conv_assembly(cgp_mesh *m, const double *u) {
+  constexpr int L = 8;  // lanes per row: P1 rows hold about seven entries
   const double dtrho24 = m->params.dt * m->params.rho / 24.0;
-  for (int c = 0; c < m->col_f.ncol; c++) {
-    const int b0 = m->col_f.cptr[c], cnt = m->col_f.cptr[c + 1] - b0;
-    hipLaunchKernelGGL(k_asm_conv, dim3(blocks_1d(cnt)), dim3(256), 0, m->stream, b0, cnt, m->d_tri_f, m->d_slot_f,
-                       (const double2 *)m->d_xy_f, (const double2 *)u, dtrho24, m->d_A);
-  }
+  const int n = m->pf.n;
+  hipLaunchKernelGGL((k_asm_conv_rows<L>), dim3(blocks_1d((long long)n * L)), dim3(256), 0, m->stream, n, m->d_rp_f,
+                     m->d_col_f, (const double *)m->d_S, m->d_inc_ptr_f, (const int4 *)m->d_incv_f,
+                     (const double2 *)m->d_xy_f, (const double2 *)u, dtrho24, m->d_A);
 }
 
 void launch_mom_rhs(cgp_mesh *m, const double *g, const double *u, const double *f, double *rhs) {

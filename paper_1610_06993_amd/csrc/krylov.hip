@@ -1381,9 +1381,7 @@ cgp_status drv_momentum(cgp_mesh *m, const cgp_solver_opts *o, const double *g, 
                         double *ut, cgp_stats *stats) {
   hipStream_t s = m->stream;
   const int n = m->pf.n;
-  const size_t nnz = m->pf.nnz;
-  CGP_HIP(hipMemcpyAsync(m->d_A, m->d_S, nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
-  launch_conv_assembly(m, u);
+  launch_conv_assembly(m, u);  // A = S + dt N(U^n), every entry
   double2 *rhs = (double2 *)m->d_wf[0];
   launch_mom_rhs(m, g, u, f, (double *)rhs);
   const bool extrap = (o->x0_mode == CGP_X0_EXTRAP && ut == m->d_ut);
