@@ -171,54 +171,72 @@ __global__ void k_mass_bc(int n, const int *__restrict__ rp, const int *__restri
   ml[i] = s;
 }
 
-// Momentum right-hand side rho M U^n + dt M F with symmetric Dirichlet
-// elimination of g on the fixed pattern, and the Jacobi inverse of A.
+// Momentum right-hand side rho M U^n + dt M F with symmetric Dirichlet elimination of g on the
+// fixed pattern, and the Jacobi inverse of A; a group of L lanes per row, group sums in a fixed order.
+template <int L>
 __global__ void k_mom_rhs_bc(int n, const int *__restrict__ rp, const int *__restrict__ col,
                              const unsigned char *__restrict__ vdir, const double *__restrict__ M,
                              double *__restrict__ A, const double2 *__restrict__ g, const double2 *__restrict__ u,
                              const double2 *__restrict__ f, double rho, double dt, double2 *__restrict__ rhs,
                              double *__restrict__ dinv) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+  const int lane = threadIdx.x & (L - 1);
+  const int j = (blockIdx.x * blockDim.x + threadIdx.x) / L;
+  if (j >= n) return;  // the whole group
   const int k0 = rp[j], k1 = rp[j + 1];
   if (vdir[j]) {  // the row keeps its diagonal a_jj (1 if not positive): a_jj u_j = a_jj g_j
-    double d = 1.0;
-    for (int k = k0; k < k1; k++)
-      if (col[k] == j && A[k] > 0.0) d = A[k];
-    for (int k = k0; k < k1; k++) A[k] = (col[k] == j) ? d : 0.0;
-    const double2 gj = g[j];
-    rhs[j] = make_double2(d * gj.x, d * gj.y);
-    dinv[j] = 1.0 / d;
+    double a = 0.0;
+    for (int k = k0 + lane; k < k1; k += L)
+      if (col[k] == j) a = A[k];
+    a = group_sum<L>(a);
+    const double d = a > 0.0 ? a : 1.0;
+    for (int k = k0 + lane; k < k1; k += L) A[k] = (col[k] == j) ? d : 0.0;
+    if (lane == 0) {
+      const double2 gj = g[j];
+      rhs[j] = make_double2(d * gj.x, d * gj.y);
+      dinv[j] = 1.0 / d;
+    }
     return;
   }
-  double ax = 0.0, ay = 0.0, fx = 0.0, fy = 0.0, d = 1.0;
-  for (int k = k0; k < k1; k++) {
+  double ax = 0.0, ay = 0.0, fx = 0.0, fy = 0.0, gx = 0.0, gy = 0.0, d = 0.0;
+  for (int k = k0 + lane; k < k1; k += L) {
+    const int c = col[k];
     const double m = M[k];
-    const double2 uc = u[col[k]];
+    const double2 uc = u[c];
     ax += m * uc.x;
     ay += m * uc.y;
     if (f) {
-      const double2 fc = f[col[k]];
+      const double2 fc = f[c];
       fx += m * fc.x;
       fy += m * fc.y;
     }
-  }
-  double rx = rho * ax, ry = rho * ay;
-  if (f) { rx += dt * fx; ry += dt * fy; }
-  for (int k = k0; k < k1; k++) {
-    const int c = col[k];
     if (vdir[c]) {
       const double a = A[k];
       const double2 gc = g[c];
-      rx -= a * gc.x;
-      ry -= a * gc.y;
+      gx += a * gc.x;
+      gy += a * gc.y;
       A[k] = 0.0;
     } else if (c == j) {
       d = A[k];
     }
   }
-  rhs[j] = make_double2(rx, ry);
-  dinv[j] = d != 0.0 ? 1.0 / d : 1.0;
+  ax = group_sum<L>(ax);
+  ay = group_sum<L>(ay);
+  gx = group_sum<L>(gx);
+  gy = group_sum<L>(gy);
+  d = group_sum<L>(d);  // one lane holds the diagonal
+  if (f) {
+    fx = group_sum<L>(fx);
+    fy = group_sum<L>(fy);
+  }
+  if (lane == 0) {
+    double rx = rho * ax, ry = rho * ay;
+    if (f) {
+      rx += dt * fx;
+      ry += dt * fy;
+    }
+    rhs[j] = make_double2(rx - gx, ry - gy);
+    dinv[j] = d != 0.0 ? 1.0 / d : 1.0;
+  }
 }
 
 // ------------------------------------------------------------------ SpMV
@@ -463,7 +481,9 @@ void launch_conv_assembly(cgp_mesh *m, const double *u) {
 
 void launch_mom_rhs(cgp_mesh *m, const double *g, const double *u, const double *f, double *rhs) {
   const int n = m->pf.n;
-  hipLaunchKernelGGL(k_mom_rhs_bc, dim3(blocks_1d(n)), dim3(256), 0, m->stream, n, m->d_rp_f, m->d_col_f, m->d_vdir,
+  constexpr int L = 8;
+  hipLaunchKernelGGL(k_mom_rhs_bc<L>, dim3(blocks_1d((long long)n * L)), dim3(256), 0, m->stream, n, m->d_rp_f,
+                     m->d_col_f, m->d_vdir,
                      m->d_M, m->d_A, (const double2 *)g, (const double2 *)u, (const double2 *)f, m->params.rho,
                      m->params.dt, (double2 *)rhs, m->d_dinvA);
 }

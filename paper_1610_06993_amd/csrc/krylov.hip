@@ -926,8 +926,13 @@ __global__ void __launch_bounds__(256) k_proj_gram(int n, const int *__restrict_
 // One block per Gram entry: the G block partials summed in a fixed order into S[entry].
 __global__ void __launch_bounds__(256) k_proj_sum(int G, const double *__restrict__ P, double *__restrict__ S) {
   const double *p = P + (size_t)blockIdx.x * G;
-  double v[1] = {0.0};
-  for (int q = threadIdx.x; q < G; q += blockDim.x) v[0] += p[q];
+  double a[4] = {0.0, 0.0, 0.0, 0.0};  // four chains, so that the loads overlap
+  int q = threadIdx.x;
+  for (; q + 3 * (int)blockDim.x < G; q += 4 * blockDim.x)
+#pragma unroll
+    for (int r = 0; r < 4; r++) a[r] += p[q + r * blockDim.x];
+  for (; q < G; q += blockDim.x) a[0] += p[q];
+  double v[1] = {(a[0] + a[1]) + (a[2] + a[3])};
   double tot[1];
   block_sum<1>(v, tot);
   if (threadIdx.x == 0) S[blockIdx.x] = tot[0];

@@ -24,6 +24,8 @@
 #include "learn.h"
 
 namespace cgp {
+// blocks of the POD projection (one partial per block and mode) and of the expansion
+constexpr int kProjectGrid = 1024, kExpandGrid = 2048;
 namespace {
 cgp_status pod_events(cgp_guess *g);
 cgp_status pod_finish(cgp_guess *g);
@@ -267,41 +269,55 @@ __global__ void k_pair_residual(int n, const int *__restrict__ rp, const int *__
   R[k * n + i] = B[k * n + i] - s;
 }
 
-// per-block partials of out[k] = sum_i Phi[i][k] w_i v_i for the nm <= 64 modes: lane k of each wave
-// accumulates mode k over the wave's rows; waves combine in LDS; partials laid out [nm][grid]
+// Lanes of a wave cover (row, mode) pairs of the row-major Phi [n][nm]: a span of 16, 32 or 64
+// lanes per row (the next power of two >= nm), so one wave instruction reads 64 / span whole rows.
+__device__ __forceinline__ int mode_span(int nm) { return nm <= 16 ? 16 : nm <= 32 ? 32 : 64; }
+
+// per-block partials of out[k] = sum_i Phi[i][k] w_i v_i for the nm <= 64 modes; partials laid out
+// [nm][grid]
 __global__ void __launch_bounds__(256) k_project(int n, int nm, const double *__restrict__ Phi,
                                                  const double *__restrict__ w, const double *__restrict__ v,
                                                  double *__restrict__ P) {
   __shared__ double sh[4][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int span = mode_span(nm), sub = lane / span, k = lane % span, rpw = 64 / span;
+  const long step = (long)gridDim.x * 4 * rpw;
   double acc = 0.0;
-  const int gw = blockIdx.x * 4 + wave, nw = gridDim.x * 4;
-  if (lane < nm)
-    for (int i = gw; i < n; i += nw) acc += Phi[(long)i * nm + lane] * (w ? w[i] : 1.0) * v[i];
+  if (k < nm) {
+#pragma unroll 4
+    for (long i = (long)(blockIdx.x * 4 + wave) * rpw + sub; i < n; i += step)
+      acc += Phi[i * nm + k] * (w ? w[i] : 1.0) * v[i];
+  }
+  for (int off = span; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);  // the wave's rows of mode k
   sh[wave][lane] = acc;
   __syncthreads();
   if (threadIdx.x < nm) P[threadIdx.x * gridDim.x + blockIdx.x] = sh[0][threadIdx.x] + sh[1][threadIdx.x] +
                                                                      sh[2][threadIdx.x] + sh[3][threadIdx.x];
 }
 
-// out[k] = sum over the G partials of mode k (one block, one thread per mode, fixed order)
-__global__ void k_project_finish(int G, int nm, const double *__restrict__ P, double *__restrict__ out) {
-  const int k = threadIdx.x;
-  if (k >= nm) return;
-  double s = 0.0;
-  for (int b = 0; b < G; b++) s += P[k * G + b];
-  out[k] = s;
+// out[k] = sum over the G partials of mode k (one block per mode, fixed order)
+__global__ void __launch_bounds__(256) k_project_finish(int G, const double *__restrict__ P, double *__restrict__ out) {
+  const double *p = P + (size_t)blockIdx.x * G;
+  double v[1] = {0.0};
+  for (int b = threadIdx.x; b < G; b += blockDim.x) v[0] += p[b];
+  double tot[1];
+  dev::block_sum<1>(v, tot);
+  if (threadIdx.x == 0) out[blockIdx.x] = tot[0];
 }
 
-// x[i] = base[i] + sum_k Phi[i][k] c[k]  (base may be NULL or equal to x); one wave per row, lane k = mode k
+// x[i] = base[i] + sum_k Phi[i][k] c[k]  (base may be NULL or equal to x); the span of lanes of a row
+// sums its modes
 __global__ void __launch_bounds__(256) k_expand(int n, int nm, const double *__restrict__ Phi,
                                                 const double *__restrict__ c, const double *base, double *x) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const double ck = lane < nm ? c[lane] : 0.0;
-  for (int i = blockIdx.x * 4 + wave; i < n; i += gridDim.x * 4) {
-    double v = lane < nm ? Phi[(long)i * nm + lane] * ck : 0.0;
-    v = dev::wave_sum(v);
-    if (lane == 0) x[i] = (base ? base[i] : 0.0) + v;
+  const int span = mode_span(nm), sub = lane / span, k = lane % span, rpw = 64 / span;
+  const double ck = k < nm ? c[k] : 0.0;
+  const long step = (long)gridDim.x * 4 * rpw;
+  for (long i0 = (long)(blockIdx.x * 4 + wave) * rpw; i0 < n; i0 += step) {  // uniform over the wave
+    const long i = i0 + sub;
+    double v = (k < nm && i < n) ? Phi[i * nm + k] * ck : 0.0;
+    for (int off = span >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (k == 0 && i < n) x[i] = (base ? base[i] : 0.0) + v;
   }
 }
 
@@ -562,12 +578,12 @@ cgp_status guess_initial(cgp_mesh *m, int mode, const double *b, double *x) {
     return CGP_E_STATE;
   }
   hipStream_t s = m->stream;
-  const int n = g->n, nm = g->nm, G = 256;
+  const int n = g->n, nm = g->nm, G = kProjectGrid;
   double *a = g->d_scal, *c = g->d_scal + 64;
   const double *mu_a = g->d_stats, *sd_a = g->d_stats + nm, *mu_c = g->d_stats + 2 * nm, *sd_c = g->d_stats + 3 * nm;
   auto project = [&](const double *w, const double *v, double *out) {
     hipLaunchKernelGGL(k_project, dim3(G), dim3(256), 0, s, n, nm, (const double *)g->d_phi, w, v, g->d_part);
-    hipLaunchKernelGGL(k_project_finish, dim3(1), dim3(64), 0, s, G, nm, (const double *)g->d_part, out);
+    hipLaunchKernelGGL(k_project_finish, dim3(nm), dim3(256), 0, s, G, (const double *)g->d_part, out);
   };
   // features: Phi^T b (absolute model) or Phi^T (b - K x) (incremental model and POD-Galerkin)
   const bool from_residual = (mode != CGP_X0_LEARNED);
@@ -586,7 +602,7 @@ cgp_status guess_initial(cgp_mesh *m, int mode, const double *b, double *x) {
     forward(g, s, 1);
     hipLaunchKernelGGL(k_feat_out, dim3(1), dim3(64), 0, s, nm, (const float *)g->d_y, mu_c, sd_c, c);
   }
-  hipLaunchKernelGGL(k_expand, dim3(512), dim3(256), 0, s, n, nm, (const double *)g->d_phi, (const double *)c,
+  hipLaunchKernelGGL(k_expand, dim3(kExpandGrid), dim3(256), 0, s, n, nm, (const double *)g->d_phi, (const double *)c,
                      from_residual ? (const double *)x : (const double *)nullptr, x);
   CGP_HIP(hipGetLastError());
   return CGP_OK;
@@ -686,7 +702,7 @@ cgp_status cgp_guess_create(cgp_mesh *m, const cgp_guess_desc *d, cgp_guess **ou
       (st = galloc(g, &g->d_t, (size_t)B * nm)) || (st = galloc(g, &g->d_dy, (size_t)B * nm)) ||
       (st = galloc(g, &g->d_dh2, (size_t)B * nh)) || (st = galloc(g, &g->d_dz2, (size_t)B * nh)) ||
       (st = galloc(g, &g->d_dh1, (size_t)B * nh)) || (st = galloc(g, &g->d_dz1, (size_t)B * nh)) ||
-      (st = galloc(g, &g->d_part, (size_t)64 * 256)) || (st = galloc(g, &g->d_scal, 256)) ||
+      (st = galloc(g, &g->d_part, (size_t)64 * kProjectGrid)) || (st = galloc(g, &g->d_scal, 256)) ||
       (st = galloc(g, &g->d_idx, 65536)))
     return fail(st);
   // uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) initialisation from a SplitMix64 stream
