@@ -326,15 +326,15 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=32,
-                    help="untimed steps of each path before its timed steps (an online window of 32 then holds "
+    ap.add_argument("--warmup", type=int, default=64,
+                    help="untimed steps of each path before its timed steps (an online window of 64 then holds "
                          "only the path's own solves)")
     ap.add_argument("--target-tris", type=int, default=250_000, help="coarse triangles (fine = 4x)")
     ap.add_argument("--snapshots", type=int, default=64, help="plain-FP64 steps recorded as training data")
     ap.add_argument("--modes", type=int, default=32, help="POD modes of the learned guess")
     ap.add_argument("--hidden", type=int, default=128, help="hidden width of the guess networks")
     ap.add_argument("--epochs", type=int, default=300)
-    ap.add_argument("--window", type=int, default=32, help="solutions kept for the online POD basis")
+    ap.add_argument("--window", type=int, default=64, help="solutions kept for the online POD basis (at most 64)")
     ap.add_argument("--refresh", type=int, default=1, help="Poisson solves between online basis rebuilds")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps timed for the CPU baseline (0: skip)")
     ap.add_argument("--no-instrumented", action="store_true", help="skip the event-timed kernel pass")
@@ -482,7 +482,7 @@ def main():
         if model == "online":
             online.set_online(args.window, args.refresh)
             online.attach()
-            for k in range(S - args.window, S):  # the newest recorded solves fill the window
+            for k in range(max(0, S - args.window), S):  # the newest recorded solves fill the window
                 mesh.poisson_solve(rhs[k], ps[k].clone(), SolverOpts(tol=tol, x0_mode=X0.X0_PREV))
         elif model:
             models[model].attach()
