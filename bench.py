@@ -352,7 +352,7 @@ def main():
     ap.add_argument("--paths", default="all", help="comma-separated subset of the timed paths")
     ap.add_argument("--batch", type=int, default=64, help="instances of the batched sweep (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
-    ap.add_argument("--batch-window", type=int, default=16, help="online POD window per batched instance")
+    ap.add_argument("--batch-window", type=int, default=64, help="online POD window per batched instance (at most 64)")
     ap.add_argument("--only-batch", action="store_true", help="run only the batched sweep")
     ap.add_argument("--spmv-sweep", type=int, default=1, help="run the SpMV size sweep (0: skip)")
     ap.add_argument("--spmv-large", action="store_true", help="add a 16.8M-row point to the SpMV sweep")
