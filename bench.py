@@ -165,6 +165,60 @@ def run_cg_sweep(args, log):
                 points=points)
 
 
+def run_steady(args, log):
+    """One continuous run of the online-POD path (not a restart from recorded state): 74 plain steps
+    from the impulsive start, then the guess with an empty window that fills as it goes, for each
+    Poisson precision; 20-step means of Poisson iterations and steps/s."""
+    import numpy as np
+    import torch
+
+    import paper_1610_06993_amd as cgp
+    import workloads as W
+    from paper_1610_06993_amd import SolverOpts, StepOpts
+    X0 = cgp._native
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    case = W.case_cylinder(args.target_tris)
+    out = {}
+    for name, prec in (("fp64+online_pod", cgp._native.PREC_FP64), ("mixed+online_pod", cgp._native.PREC_FP32_IR)):
+        mesh = cgp.Mesh(case.mesh, 1)
+        mesh.assemble(case.rho, case.mu, case.dt)
+        xy, vdir = mesh.export("xy"), mesh.export("vdir")
+        g = torch.from_numpy(case.dirichlet(xy, 0.0)).to(dev)
+        u = torch.from_numpy(case.initial(xy, vdir)).to(dev)
+        pf = torch.zeros(mesh.info["n_f"], dtype=torch.float64, device=dev)
+        pc = torch.zeros(mesh.info["n_c"], dtype=torch.float64, device=dev)
+
+        def opts(x0):
+            return StepOpts(momentum=SolverOpts(tol=args.mom_tol, max_iter=5000, x0_mode=X0.X0_PROJECT),
+                            poisson=SolverOpts(tol=1e-8, max_iter=100000, x0_mode=x0, inner_tol=args.inner_tol,
+                                               precision=prec if x0 != X0.X0_PREV else cgp._native.PREC_FP64),
+                            mass=SolverOpts(tol=args.mass_tol, max_iter=2000))
+        for k in range(74):
+            mesh.step(g, u, pf, pc, opts=opts(X0.X0_PREV))
+        online = cgp.Guess(mesh, n_modes=args.window, hidden=16, seed=5)
+        online.set_online(args.window, args.refresh)
+        online.attach()
+        torch.cuda.synchronize()
+        means = []
+        its = []
+        t = time.perf_counter()
+        for k in range(args.only_steady):
+            its.append(mesh.step(g, u, pf, pc, opts=opts(X0.X0_POD_GALERKIN))["p_iters"])
+            if (k + 1) % 20 == 0:
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                means.append(dict(steps=[k - 18, k + 1], poisson_iters=float(np.mean(its[-20:])),
+                                  max_iters=int(max(its[-20:])), steps_per_s=round(20 / (t1 - t), 1)))
+                log(f"steady {name}: steps {k - 18}-{k + 1}: Poisson iterations {np.mean(its[-20:]):.0f} "
+                    f"(max {max(its[-20:])}), {20 / (t1 - t):.1f} steps/s")
+                t = t1
+        out[name] = means
+        online.close()
+        mesh.close()
+    return dict(window=args.window, plain_steps_first=74, blocks=out)
+
+
 def run_batch(args, log):
     """Config-4-style sweep: independent cylinder instances of uneven size stepped together."""
     import numpy as np
@@ -359,6 +413,8 @@ def main():
     ap.add_argument("--only-spmv", action="store_true", help="run only the SpMV size sweep")
     ap.add_argument("--cg-sweep", type=int, default=1, help="run the PCG iteration size sweep (0: skip)")
     ap.add_argument("--only-cg", action="store_true", help="run only the PCG iteration size sweep")
+    ap.add_argument("--only-steady", type=int, default=0, metavar="STEPS",
+                    help="run only a continuous online-POD run of STEPS steps per precision (20-step means)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -392,6 +448,9 @@ def main():
         return
     if args.only_cg:
         print(json.dumps({"cg_sweep": run_cg_sweep(args, log)}), flush=True)
+        return
+    if args.only_steady:
+        print(json.dumps({"steady": run_steady(args, log)}), flush=True)
         return
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
