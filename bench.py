@@ -190,7 +190,8 @@ def run_steady(args, log):
         pc = torch.zeros(mesh.info["n_c"], dtype=torch.float64, device=dev)
 
         def opts(x0):
-            return StepOpts(momentum=SolverOpts(tol=args.mom_tol, max_iter=5000, x0_mode=X0.X0_PROJECT),
+            mx0 = {"prev": X0.X0_PREV, "extrap": X0.X0_EXTRAP, "project": X0.X0_PROJECT}[args.mom_x0]
+            return StepOpts(momentum=SolverOpts(tol=args.mom_tol, max_iter=5000, x0_mode=mx0),
                             poisson=SolverOpts(tol=1e-8, max_iter=100000, x0_mode=x0, inner_tol=args.inner_tol,
                                                precision=prec if x0 != X0.X0_PREV else cgp._native.PREC_FP64),
                             mass=SolverOpts(tol=args.mass_tol, max_iter=2000))
