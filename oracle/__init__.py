@@ -87,6 +87,8 @@ def _declare(L):
                                       C.c_int, C.POINTER(Stats)]
     L.orc_momentum.restype = C.c_int
     L.orc_momentum.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, C.c_double, C.c_int, C.POINTER(Stats)]
+    L.orc_convection.restype = None
+    L.orc_convection.argtypes = [C.c_void_p, _dp, _dp]
     L.orc_restrict.restype = C.c_int
     L.orc_restrict.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
     L.orc_prolong.argtypes = [C.c_void_p, _dp, _dp]
@@ -224,6 +226,13 @@ class Problem:
         out = np.zeros(n)
         if lib().orc_export_values(self._h, code, _d(out)):
             raise ValueError("not assembled")
+        return out
+
+    def convection(self, u):
+        """Values of the convection matrix N(u) of Eq. (16) on the fine CSR pattern (rho included)."""
+        u = np.ascontiguousarray(u, np.float64)
+        out = np.zeros(self.info["nnz_f"])
+        lib().orc_convection(self._h, _d(u), _d(out))
         return out
 
     def momentum(self, g, u, f=None, tol=1e-12, maxit=100000):

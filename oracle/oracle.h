@@ -108,6 +108,8 @@ int orc_projection_step(orc_problem *p, const double *g_next, const double *f_ne
                         orc_stats *st);
 int orc_momentum(orc_problem *p, const double *g_next, const double *f_next, const double *u, double *ut,
                  double tol, int maxit, orc_stats *st);
+/* values of the convection matrix N(u) of Eq. (16) (rho included) on the fine CSR pattern */
+void orc_convection(const orc_problem *p, const double *u, double *Nval);
 
 /* ---- learned guess network (oracle/learn.c) */
 double orc_bf16(double x);

@@ -124,6 +124,35 @@ def test_momentum_solve(env):
     assert rel(ut.cpu().numpy(), ref) <= 1e-10, (st, ost)
 
 
+def test_momentum_matrix(env):
+    """The momentum matrix a step forms (A = rho M + dt mu K + dt N(U^n) with the velocity-Dirichlet
+    rows reduced to their diagonal and the Dirichlet columns of the other rows cleared, Eq. 19)
+    against the same matrix built here from the oracle's M, K and N(U^n), applied to random vectors."""
+    torch, cgp, oracle = env
+    case = W.case_bfs(nx=80, ny=10)
+    _say("momentum matrix bfs 80x10")
+    g, o = make_pair(env, case.mesh, 1, case.rho, case.mu, case.dt)
+    n = g.info["n_f"]
+    xy, vdir = g.export("xy"), g.export("vdir").astype(bool)
+    rng = np.random.default_rng(5)
+    u = case.initial(xy, vdir) + 0.1 * rng.normal(size=(n, 2))
+    ut = torch.zeros(n, 2, dtype=torch.float64, device="cuda")
+    g.momentum(dev(torch, case.dirichlet(xy, case.dt)), dev(torch, u), ut,
+               opts=cgp.SolverOpts(tol=1e-8, max_iter=5000))
+    rp, col = o.export("rowptr_f"), o.export("col_f")
+    A = case.rho * o.values("M_f") + case.dt * case.mu * o.values("K_f") + case.dt * o.convection(u)
+    row = np.repeat(np.arange(n), np.diff(rp))
+    diag = row == col
+    d = np.where(A[diag] > 0.0, A[diag], 1.0)  # the diagonal a Dirichlet row keeps (1 if not positive)
+    A = np.where(vdir[row] | vdir[col], 0.0, A)
+    A[diag & vdir[row]] = d[vdir]
+    x = rng.normal(size=(n, 2))
+    y = torch.zeros(n, 2, dtype=torch.float64, device="cuda")
+    g.spmv(cgp._native.OP_A_F, dev(torch, x), y)
+    ref = np.stack([np.bincount(row, A * x[col, c], minlength=n) for c in range(2)], 1)
+    assert rel(y.cpu().numpy(), ref) <= 1e-13
+
+
 @pytest.mark.parametrize("which", ["neumann", "dirichlet"])
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("launch", [1, 2, 3])
