@@ -15,7 +15,7 @@ import numpy as np
 
 _DIR = Path(__file__).resolve().parent
 _LIB_PATH = _DIR / "liboracle.so"
-_SOURCES = ["mesh.c", "fem.c", "krylov.c", "cgp.c", "learn.c"]
+_SOURCES = ["mesh.c", "fem.c", "krylov.c", "cgp.c", "learn.c", "pod.c", "norms.c"]
 _lib = None
 
 ERRORS = {0: "ok", 1: "bad argument", 2: "invalid mesh", 3: "no convergence", 4: "non-finite value"}
@@ -101,6 +101,17 @@ def _declare(L):
         f.restype = C.c_int
         f.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double, C.c_int, _ip, _dp]
     L.orc_spmv.argtypes = [C.c_void_p, _dp, _dp, _dp]
+    L.orc_correct.restype = C.c_int
+    L.orc_correct.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, C.c_double, C.c_int, C.POINTER(Stats)]
+    L.orc_jacobi_eigen.restype = None
+    L.orc_jacobi_eigen.argtypes = [C.c_int, _dp, _dp]
+    L.orc_pod.restype = C.c_int
+    L.orc_pod.argtypes = [C.c_int, C.c_int, _dp, _dp, C.c_int, _dp, _dp]
+    L.orc_quad_npts.restype = C.c_int
+    L.orc_quad_points.restype = C.c_int
+    L.orc_quad_points.argtypes = [C.c_void_p, C.c_int, _dp]
+    L.orc_error_norms.restype = C.c_int
+    L.orc_error_norms.argtypes = [C.c_void_p, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp]
     if hasattr(L, "orc_mlp_forward_backward"):
         _declare_learn(L)
 
@@ -277,6 +288,38 @@ class Problem:
                               tol_p, tol_mass, maxit, int(x0_prev), C.byref(st))
         return u, pf, pc, code, st.asdict()
 
+    def correct(self, g, ut, pf, tol=1e-12, maxit=100000):
+        """Step 5 alone (Eq. 23): U^{n+1} from U~ and the fine pressure, with the assembled mass mode."""
+        g = np.ascontiguousarray(g, np.float64)
+        ut = np.ascontiguousarray(ut, np.float64)
+        pf = np.ascontiguousarray(pf, np.float64)
+        u = np.zeros_like(ut)
+        st = Stats()
+        code = lib().orc_correct(self._h, _d(g), _d(ut), _d(pf), _d(u), tol, maxit, C.byref(st))
+        return u, code, st.asdict()
+
+    def quad_points(self, level=None):
+        """Quadrature points [t][q][2] of the error-norm rule on a level (default: the fine level)."""
+        lv = self.levels if level is None else level
+        q = int(lib().orc_quad_npts())
+        out = np.zeros((self.level_sizes(lv)["t"], q, 2))
+        if lib().orc_quad_points(self._h, lv, _d(out)):
+            raise ValueError("bad level")
+        return out
+
+    def error_norms(self, A, exact, level=None):
+        """Eqs. (32)-(33) of the nodal field A ([n] or [n][2]) against the callable exact(xy) -> values."""
+        lv = self.levels if level is None else level
+        A = np.ascontiguousarray(A, np.float64)
+        nc = 1 if A.ndim == 1 else A.shape[1]
+        xq = self.quad_points(lv)
+        aq = np.ascontiguousarray(exact(xq.reshape(-1, 2)), np.float64)
+        an = np.ascontiguousarray(exact(self.export("xy", lv)), np.float64)
+        l2, linf = C.c_double(), C.c_double()
+        if lib().orc_error_norms(self._h, lv, nc, _d(A), _d(aq), _d(an), C.byref(l2), C.byref(linf)):
+            raise ValueError("bad arguments")
+        return l2.value, linf.value
+
     def projection_step(self, g, u, f=None, tol_mom=1e-12, tol_p=1e-12, tol_mass=1e-12, maxit=100000):
         g = np.ascontiguousarray(g, np.float64)
         u = np.array(u, np.float64, order="C")
@@ -298,6 +341,27 @@ def _declare_learn(L):
     fp = C.POINTER(C.c_float)
     L.orc_mlp_forward_backward.argtypes = [C.c_int, C.c_int, C.c_int, fp, fp, fp, C.c_int, _dp, _dp, _dp]
     L.orc_adam.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double]
+
+
+def jacobi_eigen(A):
+    """Eigenvalues (unsorted) and eigenvectors (columns) of a symmetric matrix by the oracle's cyclic Jacobi."""
+    A = np.array(A, np.float64, order="C")
+    V = np.zeros_like(A)
+    lib().orc_jacobi_eigen(A.shape[0], _d(A), _d(V))
+    return np.diag(A).copy(), V
+
+
+def pod(snaps, w, m):
+    """POD of the rows of snaps [S][n] in the w-weighted inner product: basis [n][m], energies [m], rank."""
+    snaps = np.ascontiguousarray(snaps, np.float64)
+    w = np.ascontiguousarray(w, np.float64)
+    S, n = snaps.shape
+    phi = np.zeros((n, m))
+    energy = np.zeros(m)
+    rank = lib().orc_pod(S, n, _d(snaps), _d(w), m, _d(phi), _d(energy))
+    if rank < 0:
+        raise ValueError("bad POD arguments")
+    return phi, energy, rank
 
 
 def bf16(x: float) -> float:

@@ -186,7 +186,7 @@ int orc_poisson_solve(const orc_problem *p, const double *b, double *x, double t
 }
 
 /* Step 5, Eq. (23): M U = M U~ - (dt/rho) G P_f, velocity data lifted as in step 1. */
-static int correct(orc_problem *p, const double *g_next, const double *ut, const double *pf, double *u,
+int orc_correct(orc_problem *p, const double *g_next, const double *ut, const double *pf, double *u,
                    double tol, int maxit, orc_stats *st) {
   const orc_csr *P = &p->pf;
   int n = P->n;
@@ -242,7 +242,7 @@ int orc_step(orc_problem *p, const double *g_next, const double *f_next, double 
   if (!x0_prev) memset(p_c, 0, sizeof(double) * (size_t)nc);
   int s3 = orc_poisson_solve(p, bc, p_c, tol_p, maxit, &st->p_iters, &st->p_relres); /* step 3 */
   orc_prolong(p, p_c, p_f);                                                          /* step 4 */
-  int s5 = correct(p, g_next, ut, p_f, u, tol_mass, maxit, st);                      /* step 5 */
+  int s5 = orc_correct(p, g_next, ut, p_f, u, tol_mass, maxit, st);                      /* step 5 */
   if (status == ORC_OK) status = s2;
   if (status == ORC_OK) status = s3;
   if (status == ORC_OK) status = s5;
@@ -292,7 +292,7 @@ int orc_projection_step(orc_problem *p, const double *g_next, const double *f_ne
     for (int i = 0; i < n; i++) { wm += p->mc[i] * p_f[i]; ws += p->mc[i]; }
     for (int i = 0; i < n; i++) p_f[i] -= wm / ws;
   }
-  int s5 = correct(p, g_next, ut, p_f, u, tol_mass, maxit, st);
+  int s5 = orc_correct(p, g_next, ut, p_f, u, tol_mass, maxit, st);
   if (status == ORC_OK) status = s3;
   if (status == ORC_OK) status = s5;
   free(ut); free(b); free(K);

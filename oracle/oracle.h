@@ -108,6 +108,8 @@ int orc_projection_step(orc_problem *p, const double *g_next, const double *f_ne
                         orc_stats *st);
 int orc_momentum(orc_problem *p, const double *g_next, const double *f_next, const double *u, double *ut,
                  double tol, int maxit, orc_stats *st);
+int orc_correct(orc_problem *p, const double *g_next, const double *ut, const double *pf, double *u, double tol,
+                int maxit, orc_stats *st);
 /* values of the convection matrix N(u) of Eq. (16) (rho included) on the fine CSR pattern */
 void orc_convection(const orc_problem *p, const double *u, double *Nval);
 
@@ -119,5 +121,15 @@ void orc_mlp_forward_backward(int m, int h, int B, const float *params, const fl
                               double *loss, double *Y, double *grad);
 void orc_adam(int n, double *w, const double *g, double *m1, double *m2, int t, double lr, double b1, double b2,
               double eps);
+
+/* ---- POD of snapshots (oracle/pod.c) */
+void orc_jacobi_eigen(int q, double *A, double *V);
+int orc_pod(int S, int n, const double *snaps, const double *w, int m, double *phi, double *energy);
+
+/* ---- the paper's error norms, Eqs. (31)-(33) (oracle/norms.c) */
+int orc_quad_npts(void);
+int orc_quad_points(const orc_problem *p, int level, double *xyq);
+int orc_error_norms(const orc_problem *p, int level, int nc, const double *A, const double *aq, const double *an,
+                    double *l2, double *linf);
 
 #endif
