@@ -101,6 +101,10 @@ def _declare(L):
         f.restype = C.c_int
         f.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double, C.c_int, _ip, _dp]
     L.orc_spmv.argtypes = [C.c_void_p, _dp, _dp, _dp]
+    L.orc_set_pressure_mode.restype = C.c_int
+    L.orc_set_pressure_mode.argtypes = [C.c_void_p, C.c_int]
+    L.orc_pressure_update.restype = C.c_int
+    L.orc_pressure_update.argtypes = [C.c_void_p, _dp, _dp, _dp]
     L.orc_correct.restype = C.c_int
     L.orc_correct.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, C.c_double, C.c_int, C.POINTER(Stats)]
     L.orc_jacobi_eigen.restype = None
@@ -222,11 +226,13 @@ class Problem:
             raise ValueError(f"export {what} failed")
         return out
 
-    def assemble(self, rho, mu, dt, restrict_mode=0, mass_mode=0):
+    def assemble(self, rho, mu, dt, restrict_mode=0, mass_mode=0, pressure_mode=0):
+        """pressure_mode: 0 non-incremental (the paper's scheme), 1 standard incremental, 2 rotational."""
         st = lib().orc_assemble(self._h, rho, mu, dt, restrict_mode, mass_mode)
-        if st:
+        if st or lib().orc_set_pressure_mode(self._h, pressure_mode):
             raise ValueError("assemble failed")
-        self.params = dict(rho=rho, mu=mu, dt=dt, restrict_mode=restrict_mode, mass_mode=mass_mode)
+        self.params = dict(rho=rho, mu=mu, dt=dt, restrict_mode=restrict_mode, mass_mode=mass_mode,
+                           pressure_mode=pressure_mode)
 
     def values(self, what: str):
         names = ["M_f", "K_f", "Dx_f", "Dy_f", "ml_f", "K_c", "K_c_bc", "Dx_c", "Dy_c", "m_c"]
@@ -297,6 +303,15 @@ class Problem:
         st = Stats()
         code = lib().orc_correct(self._h, _d(g), _d(ut), _d(pf), _d(u), tol, maxit, C.byref(st))
         return u, code, st.asdict()
+
+    def pressure_update(self, bc, phi, pc):
+        """New coarse pressure of the incremental schemes from the restricted right-hand side, the increment
+        and the previous pressure."""
+        out = np.array(pc, np.float64)
+        if lib().orc_pressure_update(self._h, _d(np.ascontiguousarray(bc, np.float64)),
+                                     _d(np.ascontiguousarray(phi, np.float64)), _d(out)):
+            raise ValueError("not an incremental pressure mode")
+        return out
 
     def quad_points(self, level=None):
         """Quadrature points [t][q][2] of the error-norm rule on a level (default: the fine level)."""

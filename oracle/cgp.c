@@ -25,6 +25,17 @@
  *    the levels.
  *  - correction (Eq. 23) solves with the consistent mass matrix (mode 0) or
  *    divides by the lumped mass (mode 1); velocity data are re-imposed last.
+ *  - incremental pressure correction (the extension Remark 3.1 and the
+ *    conclusions point to; pressure_mode 1 = standard, 2 = rotational form):
+ *    the momentum right-hand side gains -dt G P_f^n with P_f^n the prolonged
+ *    previous pressure; the coarse Poisson equation of Eq. (21) is solved for
+ *    the increment phi with the same right-hand side and boundary conditions;
+ *    Eq. (23) corrects with the prolonged increment; the new coarse pressure is
+ *    P^n + phi (standard), or P^n + phi - mu q (rotational), where q is the
+ *    restricted divergence of U~ divided by the coarse lumped mass (a lumped
+ *    L2 projection of div U~ onto the coarse pressure space), zero on the
+ *    pressure-Dirichlet nodes, and the result is shifted to zero
+ *    lumped-mass-weighted mean when there are none.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -59,9 +70,10 @@ static void eliminate(const orc_csr *P, double *val, double *rhs, const unsigned
   }
 }
 
-/* Step 1, Eq. (19): (rho M + dt N(U^n) + dt mu K) U~ = rho M U^n + dt M F, per component */
-int orc_momentum(orc_problem *p, const double *g_next, const double *f_next, const double *u, double *ut,
-                 double tol, int maxit, orc_stats *st) {
+/* Step 1, Eq. (19): (rho M + dt N(U^n) + dt mu K) U~ = rho M U^n + dt M F, per component;
+ * with pn (the incremental schemes) the right-hand side also gets -dt G P_f^n. */
+static int momentum(orc_problem *p, const double *g_next, const double *f_next, const double *u, const double *pn,
+                    double *ut, double tol, int maxit, orc_stats *st) {
   const orc_csr *P = &p->pf;
   int n = P->n;
   size_t nnz = (size_t)P->nnz;
@@ -79,6 +91,10 @@ int orc_momentum(orc_problem *p, const double *g_next, const double *f_next, con
       orc_spmv(P, p->Mf, uc, tmp);
       for (int i = 0; i < n; i++) rhs[i] += p->dt * tmp[i];
     }
+    if (pn) {
+      orc_spmv(P, c == 0 ? p->Dxf : p->Dyf, pn, tmp);
+      for (int i = 0; i < n; i++) rhs[i] -= p->dt * tmp[i];
+    }
     memcpy(Ac, A, sizeof(double) * nnz);
     eliminate(P, Ac, rhs, p->vdir, g_next, c);
     /* initial guess U^n with the known values g^{n+1} on the Dirichlet rows */
@@ -91,6 +107,17 @@ int orc_momentum(orc_problem *p, const double *g_next, const double *f_next, con
   }
   free(Nv); free(A); free(Ac); free(uc); free(tmp); free(rhs); free(x);
   return status;
+}
+
+int orc_momentum(orc_problem *p, const double *g_next, const double *f_next, const double *u, double *ut,
+                 double tol, int maxit, orc_stats *st) {
+  return momentum(p, g_next, f_next, u, NULL, ut, tol, maxit, st);
+}
+
+int orc_set_pressure_mode(orc_problem *p, int mode) {
+  if (!p || mode < 0 || mode > 2) return ORC_E_ARG;
+  p->pressure_mode = mode;
+  return ORC_OK;
 }
 
 /* Step 2 (+ right-hand side of step 3), Eqs. (20)-(21):
@@ -228,6 +255,25 @@ static int check_finite(const double *v, size_t n) {
   return 1;
 }
 
+/* New coarse pressure of the incremental schemes from the restricted right-hand side b_c of step 2
+ * (before boundary conditions), the increment phi and P^n (in p_c). */
+int orc_pressure_update(const orc_problem *p, const double *bc, const double *phi, double *p_c) {
+  if (!p || p->pressure_mode < 1) return ORC_E_ARG;
+  int nc = p->lev[0].n;
+  for (int i = 0; i < nc; i++) {
+    double q = 0.0;
+    if (p->pressure_mode == 2) /* bc = -(rho/dt) (restricted div U~); q = (restricted div U~) / m_c */
+      q = -(p->dt / p->rho) * bc[i] / p->mc[i];
+    p_c[i] = (p->n_pdir > 0 && p->pdir[i]) ? 0.0 : p_c[i] + phi[i] - p->mu * q;
+  }
+  if (p->pressure_mode == 2 && p->n_pdir == 0) {
+    double wm = 0.0, ws = 0.0;
+    for (int i = 0; i < nc; i++) { wm += p->mc[i] * p_c[i]; ws += p->mc[i]; }
+    for (int i = 0; i < nc; i++) p_c[i] -= wm / ws;
+  }
+  return ORC_OK;
+}
+
 int orc_step(orc_problem *p, const double *g_next, const double *f_next, double *u, double *p_f, double *p_c,
              double tol_mom, double tol_p, double tol_mass, int maxit, int x0_prev, orc_stats *st) {
   if (!p || !p->assembled || !g_next || !u || !p_f || !p_c) return ORC_E_ARG;
@@ -237,12 +283,27 @@ int orc_step(orc_problem *p, const double *g_next, const double *f_next, double 
   if (!st) st = &local;
   memset(st, 0, sizeof *st);
   double *ut = dalloc(2 * (size_t)nf), *bc = dalloc((size_t)nc);
-  int status = orc_momentum(p, g_next, f_next, u, ut, tol_mom, maxit, st);          /* step 1 */
-  int s2 = orc_restrict(p, p->restrict_mode, ut, bc);                                 /* step 2 */
-  if (!x0_prev) memset(p_c, 0, sizeof(double) * (size_t)nc);
-  int s3 = orc_poisson_solve(p, bc, p_c, tol_p, maxit, &st->p_iters, &st->p_relres); /* step 3 */
-  orc_prolong(p, p_c, p_f);                                                          /* step 4 */
-  int s5 = orc_correct(p, g_next, ut, p_f, u, tol_mass, maxit, st);                      /* step 5 */
+  int status, s2, s3, s5;
+  if (p->pressure_mode == 0) {
+    status = orc_momentum(p, g_next, f_next, u, ut, tol_mom, maxit, st);              /* step 1 */
+    s2 = orc_restrict(p, p->restrict_mode, ut, bc);                                     /* step 2 */
+    if (!x0_prev) memset(p_c, 0, sizeof(double) * (size_t)nc);
+    s3 = orc_poisson_solve(p, bc, p_c, tol_p, maxit, &st->p_iters, &st->p_relres);     /* step 3 */
+    orc_prolong(p, p_c, p_f);                                                          /* step 4 */
+    s5 = orc_correct(p, g_next, ut, p_f, u, tol_mass, maxit, st);                      /* step 5 */
+  } else {
+    /* incremental schemes: p_c holds P^n on entry */
+    double *pn = dalloc((size_t)nf), *phi = dalloc((size_t)nc), *phif = dalloc((size_t)nf);
+    orc_prolong(p, p_c, pn);
+    status = momentum(p, g_next, f_next, u, pn, ut, tol_mom, maxit, st);              /* step 1 */
+    s2 = orc_restrict(p, p->restrict_mode, ut, bc);                                     /* step 2 */
+    s3 = orc_poisson_solve(p, bc, phi, tol_p, maxit, &st->p_iters, &st->p_relres);     /* step 3: increment */
+    orc_prolong(p, phi, phif);                                                         /* step 4 */
+    s5 = orc_correct(p, g_next, ut, phif, u, tol_mass, maxit, st);                     /* step 5 */
+    orc_pressure_update(p, bc, phi, p_c);
+    orc_prolong(p, p_c, p_f);
+    free(pn); free(phi); free(phif);
+  }
   if (status == ORC_OK) status = s2;
   if (status == ORC_OK) status = s3;
   if (status == ORC_OK) status = s5;

@@ -60,6 +60,7 @@ typedef struct {
   double rho, mu, dt;
   int restrict_mode;           /* 0 inject (Eq. 20/30), 1 transpose of prolongation */
   int mass_mode;               /* 0 consistent mass in Eq. 23, 1 lumped */
+  int pressure_mode;           /* 0 non-incremental (Eqs. 9-15), 1 standard incremental, 2 rotational */
   int assembled;
   /* fine operators, values on pf */
   double *Mf, *Kf, *Dxf, *Dyf, *mlf;
@@ -108,6 +109,8 @@ int orc_projection_step(orc_problem *p, const double *g_next, const double *f_ne
                         orc_stats *st);
 int orc_momentum(orc_problem *p, const double *g_next, const double *f_next, const double *u, double *ut,
                  double tol, int maxit, orc_stats *st);
+int orc_set_pressure_mode(orc_problem *p, int mode);
+int orc_pressure_update(const orc_problem *p, const double *bc, const double *phi, double *p_c);
 int orc_correct(orc_problem *p, const double *g_next, const double *ut, const double *pf, double *u, double tol,
                 int maxit, orc_stats *st);
 /* values of the convection matrix N(u) of Eq. (16) (rho included) on the fine CSR pattern */
