@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define CGP_ABI_VERSION 1
+#define CGP_ABI_VERSION 2
 
 typedef enum {
   CGP_OK = 0,
@@ -65,6 +65,15 @@ enum { CGP_RESTRICT_INJECT = 0,    /* Eqs. (20), (30): values at shared nodes (t
 
 enum { CGP_MASS_CONSISTENT = 0,    /* Eq. (23) solved with the consistent mass matrix */
        CGP_MASS_LUMPED = 1 };      /* Eq. (23) with the row-sum lumped mass matrix */
+
+enum { CGP_PRESSURE_NONINCREMENTAL = 0, /* Eqs. (9)-(15), (19)-(23): the paper's scheme; p^n is not used */
+       CGP_PRESSURE_INCREMENTAL = 1,    /* standard incremental correction (the extension of Remark 3.1 and the
+                                           conclusions): momentum right-hand side -dt G P_f^n, Eq. (21) solved for
+                                           the increment, Eq. (23) corrected with the prolonged increment,
+                                           P^{n+1} = P^n + increment */
+       CGP_PRESSURE_ROTATIONAL = 2 };   /* as INCREMENTAL, and P^{n+1} also gets -mu times the restricted
+                                           divergence of U~ divided by the coarse lumped mass (zero on
+                                           pressure-Dirichlet nodes; zero lumped-mass mean without them) */
 
 enum { CGP_PREC_FP64 = 0,          /* all Krylov arithmetic in FP64 */
        CGP_PREC_FP32_IR = 1 };     /* Poisson: FP32 Jacobi-PCG inside FP64 iterative refinement */
@@ -110,6 +119,7 @@ typedef struct {
   double rho, mu, dt;         /* density, dynamic viscosity, time step (Eqs. 5-15) */
   int32_t restrict_mode;      /* CGP_RESTRICT_* */
   int32_t mass_mode;          /* CGP_MASS_* */
+  int32_t pressure_mode;      /* CGP_PRESSURE_*; the incremental modes are cgp_step-only (not cgp_batch_step) */
 } cgp_params;
 
 typedef struct {
@@ -187,7 +197,11 @@ typedef struct {
   cgp_tuning_knobs fine;    /* momentum and mass solves */
   cgp_tuning_knobs coarse;  /* pressure Poisson solve */
   int32_t pcg_barrier;      /* persistent Poisson kernel: 0 = library grid barrier, 1 = HIP cooperative-groups sync */
-  int32_t pcg_grid;         /* persistent Poisson kernel: blocks of 1024 threads (0 = one per compute unit) */
+  int32_t pcg_grid;         /* persistent Poisson kernel: blocks of 1024 threads, 0 = one per compute unit (the
+                               default); at most one per compute unit (256 on a host-only mesh), since a grid of
+                               two blocks per CU was not all resident and never passed its first barrier */
+  int32_t pcg_spin_log2;    /* persistent Poisson kernel: a grid-barrier wait gives up after 2^pcg_spin_log2 polls
+                               and the solve returns CGP_E_DEVICE (0 = 2^24; 1..30) */
 } cgp_tuning;
 
 int32_t cgp_abi_version(void);
@@ -214,7 +228,9 @@ cgp_status cgp_assemble(cgp_mesh *mesh, const cgp_params *params);
  *   f_next   dev [n_f][2]  body force F^{n+1}, or NULL for F = 0
  *   u        dev [n_f][2]  in: U^n, out: U^{n+1}
  *   p_fine   dev [n_f]     out: P_f^{n+1} (prolonged pressure)
- *   p_coarse dev [n_c]     in: initial guess when poisson.x0_mode = CGP_X0_PREV, out: P_c^{n+1}
+ *   p_coarse dev [n_c]     in: initial guess when poisson.x0_mode = CGP_X0_PREV (incremental pressure
+ *                          modes: P_c^n, required; the increment's solve then starts from the previous
+ *                          increment, kept by the library, under CGP_X0_PREV), out: P_c^{n+1}
  *   stats    host or NULL
  * Returns CGP_E_NOCONV if a solve hits its iteration limit (the step is still
  * completed with the last iterates), CGP_E_NONFINITE on NaN/Inf residuals. */
@@ -328,6 +344,7 @@ cgp_status cgp_mesh_set_tuning(cgp_mesh *mesh, const cgp_tuning *tuning);
 
 /* y = op x on device vectors (layouts listed with CGP_OP_*). */
 cgp_status cgp_spmv(cgp_mesh *mesh, int32_t op, const void *x, void *y);
+
 
 #ifdef __cplusplus
 }

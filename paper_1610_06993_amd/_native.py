@@ -16,6 +16,7 @@ OK, E_ARG, E_MESH, E_NOCONV, E_NONFINITE, E_DEVICE, E_OOM, E_STATE = range(8)
 VEL_DIRICHLET, OUTFLOW = 1, 2
 RESTRICT_INJECT, RESTRICT_GALERKIN = 0, 1
 MASS_CONSISTENT, MASS_LUMPED = 0, 1
+PRESSURE_NONINCREMENTAL, PRESSURE_INCREMENTAL, PRESSURE_ROTATIONAL = 0, 1, 2
 PREC_FP64, PREC_FP32_IR = 0, 1
 X0_ZERO, X0_PREV, X0_LEARNED, X0_LEARNED_CORR, X0_POD_GALERKIN, X0_EXTRAP, X0_PROJECT = 0, 1, 2, 3, 4, 5, 6
 LAUNCH_AUTO, LAUNCH_LOOP, LAUNCH_PERSISTENT, LAUNCH_FUSED = 0, 1, 2, 3
@@ -41,7 +42,7 @@ class _Desc(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("rho", C.c_double), ("mu", C.c_double), ("dt", C.c_double), ("restrict_mode", C.c_int32),
-                ("mass_mode", C.c_int32)]
+                ("mass_mode", C.c_int32), ("pressure_mode", C.c_int32)]
 
 
 class _SolverOpts(C.Structure):
@@ -69,7 +70,8 @@ class _Knobs(C.Structure):
 
 
 class _Tuning(C.Structure):
-    _fields_ = [("fine", _Knobs), ("coarse", _Knobs), ("pcg_barrier", C.c_int32), ("pcg_grid", C.c_int32)]
+    _fields_ = [("fine", _Knobs), ("coarse", _Knobs), ("pcg_barrier", C.c_int32), ("pcg_grid", C.c_int32),
+                ("pcg_spin_log2", C.c_int32)]
 
 
 class _GuessDesc(C.Structure):
@@ -275,10 +277,11 @@ class Mesh:
 
     # ---------------------------------------------------------------- compute
     def assemble(self, rho: float, mu: float, dt: float, restrict_mode: int = RESTRICT_INJECT,
-                 mass_mode: int = MASS_CONSISTENT):
-        p = _Params(rho, mu, dt, restrict_mode, mass_mode)
+                 mass_mode: int = MASS_CONSISTENT, pressure_mode: int = PRESSURE_NONINCREMENTAL):
+        p = _Params(rho, mu, dt, restrict_mode, mass_mode, pressure_mode)
         _check(lib().cgp_assemble(self._h, C.byref(p)))
-        self.params = dict(rho=rho, mu=mu, dt=dt, restrict_mode=restrict_mode, mass_mode=mass_mode)
+        self.params = dict(rho=rho, mu=mu, dt=dt, restrict_mode=restrict_mode, mass_mode=mass_mode,
+                           pressure_mode=pressure_mode)
 
     def step(self, g, u, p_fine, p_coarse, f=None, opts: StepOpts | None = None, allow_noconv=False):
         """One IFE-CGP step in place on device tensors; returns the stats dict."""
@@ -324,15 +327,17 @@ class Mesh:
         d = {lvl: (getattr(t, lvl).lanes, getattr(t, lvl).block, getattr(t, lvl).passes) for lvl in ("fine", "coarse")}
         d["pcg_barrier"] = t.pcg_barrier
         d["pcg_grid"] = t.pcg_grid
+        d["pcg_spin_log2"] = t.pcg_spin_log2
         return d
 
-    def set_tuning(self, fine=None, coarse=None, pcg_barrier=None, pcg_grid=None):
+    def set_tuning(self, fine=None, coarse=None, pcg_barrier=None, pcg_grid=None, pcg_spin_log2=None):
         cur = self.get_tuning()
         f = fine or cur["fine"]
         c = coarse or cur["coarse"]
         b = cur["pcg_barrier"] if pcg_barrier is None else pcg_barrier
         g = cur["pcg_grid"] if pcg_grid is None else pcg_grid
-        t = _Tuning(_Knobs(*f), _Knobs(*c), b, g)
+        sp = cur["pcg_spin_log2"] if pcg_spin_log2 is None else pcg_spin_log2
+        t = _Tuning(_Knobs(*f), _Knobs(*c), b, g, sp)
         _check(lib().cgp_mesh_set_tuning(self._h, C.byref(t)))
 
     def last_poisson_rhs(self, dst):

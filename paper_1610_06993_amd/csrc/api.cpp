@@ -359,7 +359,8 @@ cgp_status cgp_assemble(cgp_mesh *m, const cgp_params *p) {
   }
   if (!(p->rho > 0.0) || !(p->mu >= 0.0) || !(p->dt > 0.0) || !std::isfinite(p->rho) || !std::isfinite(p->mu) ||
       !std::isfinite(p->dt) || (p->restrict_mode != CGP_RESTRICT_INJECT && p->restrict_mode != CGP_RESTRICT_GALERKIN) ||
-      (p->mass_mode != CGP_MASS_CONSISTENT && p->mass_mode != CGP_MASS_LUMPED)) {
+      (p->mass_mode != CGP_MASS_CONSISTENT && p->mass_mode != CGP_MASS_LUMPED) ||
+      p->pressure_mode < CGP_PRESSURE_NONINCREMENTAL || p->pressure_mode > CGP_PRESSURE_ROTATIONAL) {
     set_error("cgp_assemble: invalid parameters");
     return CGP_E_ARG;
   }
@@ -421,6 +422,23 @@ cgp_status cgp_correct(cgp_mesh *m, const cgp_solver_opts *o, const double *g, c
   return drv_correct(m, o, g, ut, pf, u, st);
 }
 
+// buffers of the incremental pressure modes, allocated at their first step (the increment starts at 0)
+static cgp_status incremental_buffers(cgp_mesh *m) {
+  if (m->d_phi) return CGP_OK;
+  void *p = nullptr;
+  for (double **dst : {&m->d_pfn, &m->d_phif, &m->d_phi}) {
+    const size_t n = (dst == &m->d_phi) ? size_t(m->pc.n) : size_t(m->pf.n);
+    if (hipMalloc(&p, n * sizeof(double)) != hipSuccess) {
+      set_error("cgp_step: out of device memory for the incremental pressure buffers");
+      return CGP_E_OOM;
+    }
+    m->allocations.push_back(p);
+    *dst = static_cast<double *>(p);
+    CGP_HIP(hipMemsetAsync(p, 0, n * sizeof(double), m->stream));
+  }
+  return CGP_OK;
+}
+
 cgp_status cgp_step(cgp_mesh *m, const cgp_step_opts *o, const double *g, const double *f, double *u, double *pf,
                     double *pc, cgp_stats *st) {
   TRY(ready(m));
@@ -450,8 +468,15 @@ cgp_status cgp_step(cgp_mesh *m, const cgp_step_opts *o, const double *g, const 
   m->kt_count = 0;
   m->kt_iters = 0;
   m->kt_used = 0;
+  if (m->params.pressure_mode != CGP_PRESSURE_NONINCREMENTAL) {
+    s = incremental_buffers(m);
+    if (s) goto out;
+    // P_f^n for the momentum right-hand side
+    s = drv_prolong(m, pc, m->d_pfn);
+    if (s) goto out;
+  }
   // step 1 (Eq. 19): momentum on the fine mesh
-  s = drv_momentum(m, &o->momentum, g, f, u, m->d_ut, S);
+  s = drv_momentum(m, &o->momentum, g, f, u, m->d_ut, S, m->params.pressure_mode ? m->d_pfn : nullptr);
   if (!note(s)) goto out;
   if (s) msg = g_err;
   if (timing) CGP_HIP(hipEventRecord(ev[2], m->stream));
@@ -459,19 +484,39 @@ cgp_status cgp_step(cgp_mesh *m, const cgp_step_opts *o, const double *g, const 
   s = drv_restrict(m, m->d_ut, m->d_bc);
   if (!note(s)) goto out;
   if (timing) CGP_HIP(hipEventRecord(ev[3], m->stream));
-  // step 3 (Eq. 21): coarse pressure Poisson
-  s = drv_poisson(m, m->d_bc, pc, &o->poisson, S);
-  if (!note(s)) goto out;
-  if (s) msg = g_err;
-  if (timing) CGP_HIP(hipEventRecord(ev[4], m->stream));
-  // step 4 (Eq. 22): prolongation
-  s = drv_prolong(m, pc, pf);
-  if (!note(s)) goto out;
-  if (timing) CGP_HIP(hipEventRecord(ev[5], m->stream));
-  // step 5 (Eq. 23): velocity correction
-  s = drv_correct(m, &o->mass, g, m->d_ut, pf, u, S);
-  if (!note(s)) goto out;
-  if (s) msg = g_err;
+  if (m->params.pressure_mode == CGP_PRESSURE_NONINCREMENTAL) {
+    // step 3 (Eq. 21): coarse pressure Poisson
+    s = drv_poisson(m, m->d_bc, pc, &o->poisson, S);
+    if (!note(s)) goto out;
+    if (s) msg = g_err;
+    if (timing) CGP_HIP(hipEventRecord(ev[4], m->stream));
+    // step 4 (Eq. 22): prolongation
+    s = drv_prolong(m, pc, pf);
+    if (!note(s)) goto out;
+    if (timing) CGP_HIP(hipEventRecord(ev[5], m->stream));
+    // step 5 (Eq. 23): velocity correction
+    s = drv_correct(m, &o->mass, g, m->d_ut, pf, u, S);
+    if (!note(s)) goto out;
+    if (s) msg = g_err;
+  } else {
+    // step 3: Eq. (21) for the pressure increment (d_bc is left as restricted: the rotational term reads it)
+    s = drv_poisson(m, m->d_bc, m->d_phi, &o->poisson, S);
+    if (!note(s)) goto out;
+    if (s) msg = g_err;
+    if (timing) CGP_HIP(hipEventRecord(ev[4], m->stream));
+    // step 4: the prolonged increment
+    s = drv_prolong(m, m->d_phi, m->d_phif);
+    if (!note(s)) goto out;
+    if (timing) CGP_HIP(hipEventRecord(ev[5], m->stream));
+    // step 5: Eq. (23) with the increment, then the new pressure and its prolongation
+    s = drv_correct(m, &o->mass, g, m->d_ut, m->d_phif, u, S);
+    if (!note(s)) goto out;
+    if (s) msg = g_err;
+    launch_pressure_update(m, pc, m->d_phi, m->d_bc);
+    CGP_HIP(hipGetLastError());
+    s = drv_prolong(m, pc, pf);
+    if (s) goto out;
+  }
   if (timing) {
     CGP_HIP(hipEventRecord(ev[6], m->stream));
     CGP_HIP(hipEventSynchronize(ev[6]));
@@ -518,8 +563,16 @@ cgp_status cgp_mesh_set_tuning(cgp_mesh *m, const cgp_tuning *t) {
       return CGP_E_ARG;
     }
   }
-  if ((t->pcg_barrier != 0 && t->pcg_barrier != 1) || t->pcg_grid < 0) {
-    set_error("cgp_mesh_set_tuning: pcg_barrier must be 0 or 1 and pcg_grid >= 0");
+  if ((t->pcg_barrier != 0 && t->pcg_barrier != 1) || t->pcg_grid < 0 || t->pcg_spin_log2 < 0 ||
+      t->pcg_spin_log2 > 30) {
+    set_error("cgp_mesh_set_tuning: pcg_barrier must be 0 or 1, pcg_grid >= 0 and pcg_spin_log2 in 0..30");
+    return CGP_E_ARG;
+  }
+  // one block per compute unit at most: the persistent kernel needs every block resident at once
+  const int max_grid = m->cu_count > 0 ? m->cu_count : 256;
+  if (t->pcg_grid > max_grid) {
+    set_error("cgp_mesh_set_tuning: pcg_grid " + std::to_string(t->pcg_grid) + " exceeds one block per compute unit (" +
+              std::to_string(max_grid) + ")");
     return CGP_E_ARG;
   }
   m->tune = *t;

@@ -867,6 +867,11 @@ cgp_status cgp_batch_step(cgp_batch *B, const cgp_step_opts *o, const double *co
     return CGP_E_ARG;
   }
   const int n = B->ninst;
+  for (int i = 0; i < n; i++)
+    if (B->meshes[i]->params.pressure_mode != CGP_PRESSURE_NONINCREMENTAL) {
+      set_error("cgp_batch_step: the incremental pressure modes are served by cgp_step only");
+      return CGP_E_ARG;
+    }
   std::vector<cgp_stats> S(n);
   std::vector<const double *> bc(n);
   // phases 1-2 and 4-5 per instance, on the auxiliary streams from one host thread per stream (each

@@ -128,6 +128,9 @@ struct cgp_mesh {
   int uh_count = 0, uh_head = 0;  // filled ring slots (consecutive cgp_step solves) and the next slot to write
   double *d_rec = nullptr;        // 2 x [n_c] records {r, w, s, D^-1} of the fused Poisson PCG (double4 or float4)
   double *d_bc = nullptr;         // coarse rhs
+  double *d_pfn = nullptr;        // incremental pressure modes: prolonged P^n [n_f], allocated on first use
+  double *d_phi = nullptr;        //   the last pressure increment [n_c] (its solve's initial guess)
+  double *d_phif = nullptr;       //   the prolonged increment [n_f]
   cgp::KrylovState *d_state = nullptr;   // 4 solver states
   cgp::KrylovState *h_state = nullptr;   // pinned mirror
   cgp::ReduceScratch red;

@@ -51,8 +51,9 @@ void dispatch_L(int L, F &&f) {
 
 // drivers (implemented in kernels.hip); all enqueue on mesh->stream
 cgp_status drv_assemble(cgp_mesh *m);
+// pn: prolonged previous pressure P_f^n (incremental pressure modes: the right-hand side gets -dt G P_f^n) or NULL
 cgp_status drv_momentum(cgp_mesh *m, const cgp_solver_opts *o, const double *g, const double *f, const double *u,
-                        double *ut, cgp_stats *st);
+                        double *ut, cgp_stats *st, const double *pn = nullptr);
 cgp_status drv_restrict(cgp_mesh *m, const double *ut, double *bc);
 cgp_status drv_poisson(cgp_mesh *m, const double *b, double *x, const cgp_solver_opts *o, cgp_stats *st);
 cgp_status drv_prolong(cgp_mesh *m, const double *pc, double *pf);
@@ -62,7 +63,9 @@ cgp_status drv_spmv(cgp_mesh *m, int op, const void *x, void *y);
 
 // launchers of kernels.hip used by the Krylov drivers (enqueue only)
 void launch_conv_assembly(cgp_mesh *m, const double *u);  // d_A = S + dt N(u), every entry
-void launch_mom_rhs(cgp_mesh *m, const double *g, const double *u, const double *f, double *rhs);
+void launch_mom_rhs(cgp_mesh *m, const double *g, const double *u, const double *f, const double *pn, double *rhs);
+// incremental pressure modes: pc <- pc + phi (- mu dt/rho ... rotational term), pressure-Dirichlet nodes 0
+void launch_pressure_update(cgp_mesh *m, double *pc, const double *phi, const double *bc);
 void launch_correct_rhs(cgp_mesh *m, const double *g, const double *ut, const double *pf, double *rhs);
 void launch_correct_lumped(cgp_mesh *m, const double *g, const double *ut, const double *pf, double *u);
 void launch_set_dirichlet(cgp_mesh *m, const double *g, double *u);

@@ -171,13 +171,15 @@ __global__ void k_mass_bc(int n, const int *__restrict__ rp, const int *__restri
   ml[i] = s;
 }
 
-// Momentum right-hand side rho M U^n + dt M F with symmetric Dirichlet elimination of g on the
-// fixed pattern, and the Jacobi inverse of A; a group of L lanes per row, group sums in a fixed order.
-template <int L>
+// Momentum right-hand side rho M U^n + dt M F (- dt G P_f^n with GRAD, the incremental pressure
+// modes) with symmetric Dirichlet elimination of g on the fixed pattern, and the Jacobi inverse of A;
+// a group of L lanes per row, group sums in a fixed order.
+template <int L, bool GRAD>
 __global__ void k_mom_rhs_bc(int n, const int *__restrict__ rp, const int *__restrict__ col,
                              const unsigned char *__restrict__ vdir, const double *__restrict__ M,
                              double *__restrict__ A, const double2 *__restrict__ g, const double2 *__restrict__ u,
-                             const double2 *__restrict__ f, double rho, double dt, double2 *__restrict__ rhs,
+                             const double2 *__restrict__ f, const double2 *__restrict__ D,
+                             const double *__restrict__ pn, double rho, double dt, double2 *__restrict__ rhs,
                              double *__restrict__ dinv) {
   const int lane = threadIdx.x & (L - 1);
   const int j = (blockIdx.x * blockDim.x + threadIdx.x) / L;
@@ -197,13 +199,19 @@ __global__ void k_mom_rhs_bc(int n, const int *__restrict__ rp, const int *__res
     }
     return;
   }
-  double ax = 0.0, ay = 0.0, fx = 0.0, fy = 0.0, gx = 0.0, gy = 0.0, d = 0.0;
+  double ax = 0.0, ay = 0.0, fx = 0.0, fy = 0.0, gx = 0.0, gy = 0.0, d = 0.0, px = 0.0, py = 0.0;
   for (int k = k0 + lane; k < k1; k += L) {
     const int c = col[k];
     const double m = M[k];
     const double2 uc = u[c];
     ax += m * uc.x;
     ay += m * uc.y;
+    if (GRAD) {
+      const double2 dk = D[k];
+      const double pc = pn[c];
+      px += dk.x * pc;
+      py += dk.y * pc;
+    }
     if (f) {
       const double2 fc = f[c];
       fx += m * fc.x;
@@ -228,11 +236,19 @@ __global__ void k_mom_rhs_bc(int n, const int *__restrict__ rp, const int *__res
     fx = group_sum<L>(fx);
     fy = group_sum<L>(fy);
   }
+  if (GRAD) {
+    px = group_sum<L>(px);
+    py = group_sum<L>(py);
+  }
   if (lane == 0) {
     double rx = rho * ax, ry = rho * ay;
     if (f) {
       rx += dt * fx;
       ry += dt * fy;
+    }
+    if (GRAD) {
+      rx -= dt * px;
+      ry -= dt * py;
     }
     rhs[j] = make_double2(rx - gx, ry - gy);
     dinv[j] = d != 0.0 ? 1.0 / d : 1.0;
@@ -457,6 +473,17 @@ __global__ void k_correct_lumped(int n, const int *__restrict__ rp, const int *_
   }
 }
 
+// New coarse pressure of the incremental modes: pc + phi, minus (rotational) mu times the restricted
+// divergence of U~ over the lumped mass; bc = -(rho/dt) (restricted divergence), so the rotational
+// term is + (mu dt / rho) bc / m_c.  Pressure-Dirichlet nodes stay 0.
+__global__ void k_pressure_update(int n, const unsigned char *__restrict__ pdir, const double *__restrict__ phi,
+                                  const double *__restrict__ bc, const double *__restrict__ mc, double rot,
+                                  double *__restrict__ pc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  pc[i] = pdir[i] ? 0.0 : pc[i] + phi[i] + rot * bc[i] / mc[i];
+}
+
 __global__ void k_set_dirichlet(int n, const unsigned char *__restrict__ vdir, const double2 *__restrict__ g,
                                 double2 *__restrict__ u) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -479,13 +506,23 @@ void launch_conv_assembly(cgp_mesh *m, const double *u) {
                      (const double2 *)m->d_xy_f, (const double2 *)u, dtrho24, m->d_A);
 }
 
-void launch_mom_rhs(cgp_mesh *m, const double *g, const double *u, const double *f, double *rhs) {
+void launch_mom_rhs(cgp_mesh *m, const double *g, const double *u, const double *f, const double *pn, double *rhs) {
   const int n = m->pf.n;
   constexpr int L = 8;
-  hipLaunchKernelGGL(k_mom_rhs_bc<L>, dim3(blocks_1d((long long)n * L)), dim3(256), 0, m->stream, n, m->d_rp_f,
+  auto kern = pn ? k_mom_rhs_bc<L, true> : k_mom_rhs_bc<L, false>;
+  hipLaunchKernelGGL(kern, dim3(blocks_1d((long long)n * L)), dim3(256), 0, m->stream, n, m->d_rp_f,
                      m->d_col_f, m->d_vdir,
-                     m->d_M, m->d_A, (const double2 *)g, (const double2 *)u, (const double2 *)f, m->params.rho,
-                     m->params.dt, (double2 *)rhs, m->d_dinvA);
+                     m->d_M, m->d_A, (const double2 *)g, (const double2 *)u, (const double2 *)f,
+                     (const double2 *)m->d_D, pn, m->params.rho, m->params.dt, (double2 *)rhs, m->d_dinvA);
+}
+
+void launch_pressure_update(cgp_mesh *m, double *pc, const double *phi, const double *bc) {
+  const int n = m->pc.n;
+  const double rot = m->params.pressure_mode == CGP_PRESSURE_ROTATIONAL
+                         ? m->params.mu * m->params.dt / m->params.rho : 0.0;
+  hipLaunchKernelGGL(k_pressure_update, dim3(blocks_1d(n)), dim3(256), 0, m->stream, n, m->d_pdir, phi, bc,
+                     (const double *)m->d_mc, rot, pc);
+  if (rot != 0.0 && m->n_pdir == 0) launch_mean_shift(m, pc, m->d_mc, m->mc_sum, m->red.partials);
 }
 
 void launch_correct_rhs(cgp_mesh *m, const double *g, const double *ut, const double *pf, double *rhs) {

@@ -1383,12 +1383,12 @@ cgp_status cg1_loop(cgp_mesh *m, int slot, int n, const int *rp, const int *col,
 
 // ------------------------------------------------------------------ step 1
 cgp_status drv_momentum(cgp_mesh *m, const cgp_solver_opts *o, const double *g, const double *f, const double *u,
-                        double *ut, cgp_stats *stats) {
+                        double *ut, cgp_stats *stats, const double *pn) {
   hipStream_t s = m->stream;
   const int n = m->pf.n;
   launch_conv_assembly(m, u);  // A = S + dt N(U^n), every entry
   double2 *rhs = (double2 *)m->d_wf[0];
-  launch_mom_rhs(m, g, u, f, (double *)rhs);
+  launch_mom_rhs(m, g, u, f, pn, (double *)rhs);
   const bool extrap = (o->x0_mode == CGP_X0_EXTRAP && ut == m->d_ut);
   const bool project = (o->x0_mode == CGP_X0_PROJECT && ut == m->d_ut);
   if (project && !m->d_uhist) {

@@ -18,6 +18,7 @@ struct PersistArgs {
   const KrylovState *outer;   // FP32 solve: the refinement state holding ||r64||
   double tol;
   int maxit;
+  long long spin_limit;       // bounded wait of each grid barrier (polls before giving up)
 };
 
 int persistent_block();

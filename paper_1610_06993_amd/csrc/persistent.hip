@@ -16,7 +16,13 @@
 // The same kernel serves the FP64 solve (T = double) and the inner FP32 solve
 // of iterative refinement (T = float, right-hand side r64/||r64||, zero guess);
 // dot products are accumulated in FP64 in both.  Every barrier wait is bounded:
-// a block that spins too long sets an abort flag, and all blocks leave.
+// a block that spins too long sets an abort flag; a block that finds the flag
+// set after a barrier leaves before it uses the (possibly stale) reduction, and
+// every block that left that way raises the solve's status to CGP_E_DEVICE
+// (atomic maximum, so no later write can hide it).  The grid is at most one
+// block per compute unit: a launch of two blocks per CU, which the occupancy
+// query allowed, did not have every block resident and never passed the first
+// barrier.
 #include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
@@ -27,7 +33,6 @@ namespace cgp {
 namespace pdev {
 
 constexpr int kBlock = 1024;
-constexpr long long kSpinLimit = 1ll << 24;
 
 struct GridBar {
   unsigned count;
@@ -49,12 +54,15 @@ __device__ __forceinline__ double wave_sum(double x) {
 // after the wait); the workgroup barriers around it cover the block's other
 // waves, so a block pays one L2 writeback and one invalidate per barrier.
 // BAR = 1: the HIP cooperative-groups grid barrier.
+// Returns true in every thread of the block when the solve is being abandoned:
+// this block gave up waiting, or another block did before this one passed.
 template <int BAR>
-__device__ __forceinline__ void grid_sync(GridBar *bar, unsigned &epoch) {
+__device__ __forceinline__ bool grid_sync(GridBar *bar, unsigned &epoch, long long spin_limit) {
   if (BAR == 1) {
     cooperative_groups::this_grid().sync();
-    return;
+    return false;
   }
+  __shared__ int gave_up;
   epoch += 1;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -62,22 +70,25 @@ __device__ __forceinline__ void grid_sync(GridBar *bar, unsigned &epoch) {
     __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     long long spins = 0;
     while (__hip_atomic_load(&bar->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > kSpinLimit) {
+      if (++spins > spin_limit) {
         __hip_atomic_store(&bar->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
+      __builtin_amdgcn_s_sleep(1);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see every block's writes made before the barrier
+    gave_up = __hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
+  return gave_up != 0;
 }
 
 // Block-reduce K values, publish one partial per block in buf[k][grid], barrier,
 // then sum all partials in a fixed order; tot[] is identical in every block.
+// Returns true (tot[] not formed) when the solve is being abandoned.
 template <int K, int BAR>
-__device__ __forceinline__ void grid_allreduce(double (&v)[K], double *buf, GridBar *bar, unsigned &epoch,
-                                               double (&tot)[K]) {
+__device__ __forceinline__ bool grid_allreduce(double (&v)[K], double *buf, GridBar *bar, unsigned &epoch,
+                                               long long spin_limit, double (&tot)[K]) {
   __shared__ double sh[K][kBlock / 64];
   __shared__ double res[K];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -92,7 +103,7 @@ __device__ __forceinline__ void grid_allreduce(double (&v)[K], double *buf, Grid
     for (int w = 0; w < nw; w++) s += sh[threadIdx.x][w];
     buf[threadIdx.x * gridDim.x + blockIdx.x] = s;
   }
-  grid_sync<BAR>(bar, epoch);
+  if (grid_sync<BAR>(bar, epoch, spin_limit)) return true;
 #pragma unroll
   for (int k = 0; k < K; k++) {
     double x = 0.0;
@@ -110,6 +121,7 @@ __device__ __forceinline__ void grid_allreduce(double (&v)[K], double *buf, Grid
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < K; k++) tot[k] = res[k];
+  return false;
 }
 
 // a classification test: x - x == 0 can contract into an fma that rejects finite products
@@ -164,21 +176,17 @@ __global__ void __launch_bounds__(kBlock) k_pcg_persistent(PersistArgs args) {
     acc3[1] += rr * rr;
     acc3[2] += bb * bb;
   }
-  double tot3[3];
-  grid_allreduce<3, BAR>(acc3, buf(), bar, epoch, tot3);
+  double tot3[3] = {0.0, 1.0, 1.0};
+  const bool gave_up = grid_allreduce<3, BAR>(acc3, buf(), bar, epoch, a.spin_limit, tot3);
   double rz = tot3[0], rnorm = sqrt(tot3[1]);
   const double bnorm = sqrt(tot3[2]);
   const double tol = a.tol;
-  int status = (finite(rnorm) && finite(bnorm)) ? 0 : CGP_E_NONFINITE;
-  bool done = (bnorm == 0.0) || (rnorm <= tol * bnorm);
+  int status = gave_up ? CGP_E_DEVICE : ((finite(rnorm) && finite(bnorm)) ? 0 : CGP_E_NONFINITE);
+  bool done = !gave_up && ((bnorm == 0.0) || (rnorm <= tol * bnorm));
   if (IR && (a.outer->done[0] || a.outer->status)) done = true;  // refinement already converged
   double beta = 0.0;
   int it = 0;
   while (!done && status == 0 && it < a.maxit) {
-    if (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-      status = CGP_E_DEVICE;
-      break;
-    }
     T *p_old = pv[it & 1], *p_new = pv[(it + 1) & 1];
     const T bt = (T)beta;
     // ---- phase A
@@ -199,7 +207,10 @@ __global__ void __launch_bounds__(kBlock) k_pcg_persistent(PersistArgs args) {
       }
     }
     double tot1[1];
-    grid_allreduce<1, BAR>(acc1, buf(), bar, epoch, tot1);
+    if (grid_allreduce<1, BAR>(acc1, buf(), bar, epoch, a.spin_limit, tot1)) {
+      status = CGP_E_DEVICE;
+      break;
+    }
     const double alpha = rz / tot1[0];
     if (!finite(alpha)) {
       status = CGP_E_NONFINITE;
@@ -219,7 +230,10 @@ __global__ void __launch_bounds__(kBlock) k_pcg_persistent(PersistArgs args) {
       acc2[1] += (double)rr * (double)rr;
     }
     double tot2[2];
-    grid_allreduce<2, BAR>(acc2, buf(), bar, epoch, tot2);
+    if (grid_allreduce<2, BAR>(acc2, buf(), bar, epoch, a.spin_limit, tot2)) {
+      status = CGP_E_DEVICE;
+      break;
+    }
     beta = tot2[0] / rz;
     rz = tot2[0];
     rnorm = sqrt(tot2[1]);
@@ -227,14 +241,19 @@ __global__ void __launch_bounds__(kBlock) k_pcg_persistent(PersistArgs args) {
     if (!finite(rnorm)) status = CGP_E_NONFINITE;
     done = rnorm <= tol * bnorm;
   }
+  // status codes order by severity (NOCONV 3 < NONFINITE 4 < DEVICE 5); the state was set to 0
+  // before the launch, so an abandoning block's CGP_E_DEVICE survives block 0's own report
+  KrylovState *st = a.state;
+  if (threadIdx.x == 0 && status == CGP_E_DEVICE)
+    __hip_atomic_fetch_max(&st->status, (int)CGP_E_DEVICE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    KrylovState *st = a.state;
     st->iters = it;
     st->rnorm[0] = rnorm;
     st->bnorm[0] = bnorm;
-    st->done[0] = done;
+    st->done[0] = done && status == 0;
     st->zero_b[0] = (bnorm == 0.0);
-    st->status = status ? status : ((!done && !IR) ? CGP_E_NOCONV : 0);
+    const int mine = status ? status : ((!done && !IR) ? CGP_E_NOCONV : 0);
+    __hip_atomic_fetch_max(&st->status, mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -282,7 +301,7 @@ cgp_status persistent_setup(cgp_mesh *m) {
   }
   const int n = m->pc.n;
   int grid = m->tune.pcg_grid > 0 ? m->tune.pcg_grid : m->cu_count;
-  grid = std::min(grid, m->coop_max);
+  grid = std::min(grid, std::min(m->coop_max, m->cu_count));  // at most one block per compute unit
   grid = std::max(1, std::min(grid, (n + 255) / 256));
   if (grid == m->coop_blocks) return CGP_OK;
   // rows split by nonzeros: block b owns rows [rb[b], rb[b+1])
@@ -335,6 +354,7 @@ cgp_status persistent_pcg(cgp_mesh *m, bool fp32_inner, const double *b, void *x
   a.outer = outer;
   a.tol = tol;
   a.maxit = maxit;
+  a.spin_limit = 1ll << (m->tune.pcg_spin_log2 > 0 ? m->tune.pcg_spin_log2 : 24);
   void *args[] = {&a};
   const int bar = m->tune.pcg_barrier;
   const void *fn = fp32_inner ? kernel_ptr<float, true>(m->tune.coarse.lanes, bar)

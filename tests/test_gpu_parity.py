@@ -44,12 +44,12 @@ def dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
-def make_pair(env, mesh, levels, rho, mu, dt, restrict_mode=0, mass_mode=0):
+def make_pair(env, mesh, levels, rho, mu, dt, restrict_mode=0, mass_mode=0, pressure_mode=0):
     torch, cgp, oracle = env
     g = cgp.Mesh(mesh, levels)
-    g.assemble(rho, mu, dt, restrict_mode, mass_mode)
+    g.assemble(rho, mu, dt, restrict_mode, mass_mode, pressure_mode)
     o = oracle.Problem(mesh, levels)
-    o.assemble(rho, mu, dt, restrict_mode, mass_mode)
+    o.assemble(rho, mu, dt, restrict_mode, mass_mode, pressure_mode)
     return g, o
 
 
@@ -175,6 +175,35 @@ def test_poisson_solve(env, which, precision, launch):
         assert st["p_outer"] >= 2
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_persistent_barrier_give_up_is_reported(env, precision):
+    """The persistent kernel's grid-barrier wait is bounded.  With the bound forced down to two polls from
+    the host, blocks give up waiting; every block then leaves at its next barrier and the solve reports
+    CGP_E_DEVICE instead of a converged result.  With the default bound the same mesh solves normally."""
+    torch, cgp, oracle = env
+    mesh = W.cylinder_channel(8000, seed=2)
+    _say("persistent give-up, precision", precision)
+    g, o = make_pair(env, mesh, 1, 1.0, 1e-3, 1e-3)
+    assert (g.info["n_c"] + 255) // 256 >= 8  # several blocks, so that barriers have waiters
+    rng = np.random.default_rng(5)
+    b = rng.normal(size=g.info["n_c"])
+    opts = cgp.SolverOpts(tol=TIGHT if precision == 0 else 1e-10, precision=precision, x0_mode=0,
+                          max_iter=100000, launch=2)
+    g.set_tuning(pcg_spin_log2=1)
+    x = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
+    with pytest.raises(cgp.CGPError) as e:
+        g.poisson_solve(dev(torch, b), x, opts)
+    assert e.value.status == cgp._native.E_DEVICE, str(e.value)
+    g.set_tuning(pcg_spin_log2=0)
+    x.zero_()
+    g.poisson_solve(dev(torch, b), x, opts)
+    ref, code, it, rr = o.poisson_solve(b, tol=1e-14)
+    assert code == 0
+    assert rel(x.cpu().numpy(), ref) <= (1e-10 if precision == 0 else 1e-6)
+    with pytest.raises(cgp.CGPError):
+        g.set_tuning(pcg_grid=g.get_tuning()["pcg_grid"] + 100000)
+
+
 # launch shapes of the fused PCG kernel: the default; one-wave blocks whose grid exceeds the partial
 # sums a wave reads unrolled (512); several chunks of rows per block (passes above 2); 16 lanes; and a
 # grid at the cap of 8192 blocks on a larger mesh
@@ -225,15 +254,18 @@ def test_fp32_refinement_from_warm_start(env):
 
 
 def _run_steps(env, case, levels, nsteps, opts_gpu, restrict_mode=0, mass_mode=0, check_every=True, bar=1e-10,
-               tol=TIGHT):
+               tol=TIGHT, pressure_mode=0, pc0=None):
     torch, cgp, oracle = env
-    g, o = make_pair(env, case.mesh, levels, case.rho, case.mu, case.dt, restrict_mode, mass_mode)
+    g, o = make_pair(env, case.mesh, levels, case.rho, case.mu, case.dt, restrict_mode, mass_mode, pressure_mode)
     xy = g.export("xy")
     u0 = case.initial(xy, g.export("vdir"))
     u = dev(torch, u0.copy())
     pf = torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda")
     pc = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
     ur, pcr = u0.copy(), None
+    if pc0 is not None:
+        pc.copy_(dev(torch, pc0))
+        pcr = pc0.copy()
     worst = 0.0
     for k in range(nsteps):
         gd = case.dirichlet(xy, (k + 1) * case.dt)
@@ -265,6 +297,24 @@ def test_step_variants(env, restrict_mode, mass_mode, levels):
     case = make(STEP_VARIANT_CASE)
     _say("bfs step variant", restrict_mode, mass_mode, levels)
     _run_steps(env, case, levels, 5, tight_opts(cgp), restrict_mode, mass_mode)
+
+
+@pytest.mark.parametrize("which,restrict_mode,pressure_mode",
+                         [("tg", 1, 1), ("tg", 1, 2), ("tg", 0, 2), ("bfs", 0, 1), ("bfs", 1, 2), ("cyl", 1, 1),
+                          ("cyl", 0, 2)])
+def test_incremental_pressure_steps(env, which, restrict_mode, pressure_mode):
+    """Standard and rotational incremental pressure correction, every step against the oracle: pure
+    Neumann pressure (Taylor-Green from its exact initial pressure), outflow p = 0 (backward-facing
+    step), and a cylinder; both restrictions."""
+    torch, cgp, oracle = env
+    case = {"tg": lambda: W.case_tg(16), "bfs": lambda: make(STEP_VARIANT_CASE),
+            "cyl": lambda: make(CYLINDER_CASE)}[which]()
+    _say("incremental pressure", which, "restrict", restrict_mode, "mode", pressure_mode)
+    pc0 = None
+    if which == "tg":
+        pc0 = W.tg_pressure(W.unit_square_tg(16).xy, 0.0, case.mu)
+    opts = tight_opts(cgp)
+    _run_steps(env, case, 1, 8, opts, restrict_mode, 0, pressure_mode=pressure_mode, pc0=pc0)
 
 
 @pytest.mark.parametrize("launch", [1, 2, 3])
