@@ -3,9 +3,10 @@
 
 Workload: flow past a cylinder (radius 0.05 at (0.2, 0.2)) in a 2.2 x 0.41
 channel, Re = 100, dt = 1e-3; seeded coarse mesh of ~250k P1 triangles, fine
-mesh of ~1M triangles after one 1:4 subdivision (l = 1).  A step is one pass
-of the whole CGP path: convective assembly and momentum solve on the fine
-mesh, restriction and coarse divergence, coarse pressure Poisson solve,
+mesh of ~1M triangles after one 1:4 subdivision (l = 1), injection
+restriction and consistent-mass correction (the paper's scheme).  A step is
+one pass of the whole CGP path: convective assembly and momentum solve on the
+fine mesh, restriction and coarse divergence, coarse pressure Poisson solve,
 prolongation, velocity correction.
 
 Warm-up steps develop the flow from an impulsive start with the plain FP64
@@ -19,11 +20,16 @@ path is then timed from the same state, all with PCG to a relative residual of
   * fp64+learned:        x0 from the absolute network;
   * fp64+learned_corr:   x0 = previous pressure + the incremental network's correction;
   * fp64+online_pod:     Galerkin guess in a POD basis rebuilt after every solve from the last
-                         32 solutions (a recycled Krylov subspace);
-  * mixed, mixed+online_pod: FP32 PCG inside FP64 iterative refinement.
-Each path's one-step output is compared with the plain FP64 path's (and the
-FP64 CPU oracle's) from the same state.  ``value`` is the steps/s of the
-fastest path within 1e-6 relative error of plain FP64; every path is listed.
+                         solutions (a recycled Krylov subspace);
+  * mixed, mixed+online_pod, mixed+learned_corr: FP32 PCG inside FP64 iterative refinement.
+Per path: steps/s over the timed steps, per-phase times averaged over them,
+max |u| and kinetic energy at the first and last timed step (the flow stays
+bounded), and the one-step error against plain FP64 from the same state both
+right after the restart and at the end of the timed window.  ``value`` is the
+steps/s of the fastest path whose errors are within 1e-6; every path is listed.
+Beside it: the paper's coarsening levels l = 0..3 on one fine mesh, the
+backward-facing step at l = 1 and l = 0, SpMV and PCG size sweeps, the batched
+sweep, and the FP64 oracle on the host cores (one thread and OpenMP).
 One JSON line goes to stdout.
 """
 from __future__ import annotations
@@ -40,6 +46,8 @@ sys.path.insert(0, str(ROOT))
 
 HBM_PEAK_GBS = 8000.0
 ERR_BAR = 1e-6
+# measured launch shapes of the batched Poisson kernel per size class (cgp_batch_autotune's cache)
+TUNING_CACHE = ROOT / "paper_1610_06993_amd" / "tuning" / "batch_tuning.json"
 
 
 def log(*a):
@@ -165,6 +173,314 @@ def run_cg_sweep(args, log):
                 points=points)
 
 
+def refined_coarse(coarse, k):
+    """The coarse mesh subdivided k times, as a coarse-mesh description (the library's own subdivision,
+    read back from a host-only mesh), so that meshes with different l share one fine mesh."""
+    import paper_1610_06993_amd as cgp
+    import workloads as W
+    if k == 0:
+        return coarse
+    h = cgp.Mesh(coarse, k, host_only=True)
+    out = W.CoarseMesh(h.export("xy", k), h.export("tri", k), h.export("bedge", k), h.export("bkind", k),
+                       name=f"{coarse.name}_refined{k}", meta=dict(coarse.meta))
+    h.close()
+    return out
+
+
+def time_plain_steps(case, coarse, levels, warm, steps, mom_tol, mass_tol, log, label):
+    """Plain FP64 CGP (the paper's scheme) from the impulsive start: `warm` untimed steps, then `steps`
+    timed ones with per-phase events; steps/s, phase means, Poisson iterations, flow bound."""
+    import numpy as np
+    import torch
+
+    import paper_1610_06993_amd as cgp
+    from paper_1610_06993_amd import SolverOpts, StepOpts
+    X0 = cgp._native
+    t0 = time.perf_counter()
+    mesh = cgp.Mesh(coarse, levels)
+    mesh.assemble(case.rho, case.mu, case.dt)
+    info = mesh.info
+    xy, vd = mesh.export("xy"), mesh.export("vdir")
+    g = torch.from_numpy(case.dirichlet(xy, 0.0)).cuda()
+    u = torch.from_numpy(case.initial(xy, vd)).cuda()
+    pf = torch.zeros(info["n_f"], dtype=torch.float64, device="cuda")
+    pc = torch.zeros(info["n_c"], dtype=torch.float64, device="cuda")
+    setup = time.perf_counter() - t0
+
+    def opts(timing=0):
+        return StepOpts(momentum=SolverOpts(tol=mom_tol, max_iter=5000, x0_mode=X0.X0_PROJECT),
+                        poisson=SolverOpts(tol=1e-8, max_iter=200000),
+                        mass=SolverOpts(tol=mass_tol, max_iter=2000), timing=timing)
+    for _ in range(warm):
+        mesh.step(g, u, pf, pc, opts=opts())
+    torch.cuda.synchronize()
+    keys = ("ms_momentum", "ms_restrict", "ms_poisson", "ms_prolong", "ms_correct")
+    ph = {k: 0.0 for k in keys}
+    its = []
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        st = mesh.step(g, u, pf, pc, opts=opts(timing=1))
+        its.append(st["p_iters"])
+        for k in keys:
+            ph[k] += st[k]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    umax = float(torch.sqrt((u * u).sum(1).max()))
+    out = dict(levels=levels, resolution=f"{info['t_f']}:{info['t_c']}", fine_nodes=info["n_f"],
+               coarse_nodes=info["n_c"], steps_per_s=round(steps / el, 3), ms_per_step=round(1e3 * el / steps, 3),
+               poisson_iters_mean=float(np.mean(its)), phase_ms_mean={k: round(v / steps, 4) for k, v in ph.items()},
+               max_abs_u_last=round(umax, 6), timed_steps=[warm + 1, warm + steps], setup_s=round(setup, 2))
+    log(f"{label} l={levels} ({out['resolution']}): {out['steps_per_s']} steps/s, Poisson {np.mean(its):.0f} "
+        f"iterations / {ph['ms_poisson'] / steps:.2f} ms, momentum {ph['ms_momentum'] / steps:.2f} ms per step; "
+        f"max|u| {umax:.3f}")
+    mesh.close()
+    return out
+
+
+def run_levels(args, log):
+    """The paper's M:N comparison (Section 3, Tables 1 and 4): one fine mesh of ~1M triangles, the
+    Poisson equation on the mesh coarsened l = 3, 2, 1 times and on the fine mesh itself (l = 0, the
+    standard projection method)."""
+    import workloads as W
+    base = W.case_cylinder(max(1000, args.target_tris * 4 // 64))
+    pts = []
+    for l in (3, 2, 1, 0):
+        coarse = refined_coarse(base.mesh, 3 - l)
+        pts.append(time_plain_steps(base, coarse, l, args.level_warmup, args.level_steps, args.mom_tol, args.mass_tol,
+                                    log, "cylinder"))
+    l0 = next(p for p in pts if p["levels"] == 0)["steps_per_s"]
+    for p in pts:
+        p["speedup_vs_l0"] = round(p["steps_per_s"] / l0, 3)
+    return dict(workload=f"cylinder channel Re=100, dt=1e-3, plain FP64 CGP (injection, consistent mass), one fine "
+                         f"mesh of {pts[0]['resolution'].split(':')[0]} triangles", points=pts)
+
+
+def run_bfs(args, log):
+    """Backward-facing step (Section 3.2): ~51k coarse / ~206k fine triangles, Re = 400, dt = 5e-3,
+    CGP with l = 1 and the standard method (l = 0) on the same fine mesh."""
+    import workloads as W
+    ny = max(4, 2 * round(args.bfs_nx * 21 / 612))
+    case = W.case_bfs(nx=args.bfs_nx, ny=ny)
+    pts = [time_plain_steps(case, case.mesh, 1, args.level_warmup, args.level_steps, args.mom_tol, args.mass_tol, log,
+                            "backward step"),
+           time_plain_steps(case, refined_coarse(case.mesh, 1), 0, args.level_warmup, args.level_steps, args.mom_tol,
+                            args.mass_tol, log, "backward step")]
+    pts[0]["speedup_vs_l0"] = round(pts[0]["steps_per_s"] / pts[1]["steps_per_s"], 3)
+    return dict(workload=f"backward-facing step [0,30]x[0,2], {args.bfs_nx}x{ny} cells, Re=400, dt=5e-3, plain FP64",
+                points=pts)
+
+
+def _body_edges(mesh, center=(0.2, 0.2), radius=0.05):
+    import numpy as np
+    xy, be = mesh.xy, mesh.bedge
+    mid = 0.5 * (xy[be[:, 0]] + xy[be[:, 1]])
+    return np.where(np.hypot(mid[:, 0] - center[0], mid[:, 1] - center[1]) < 1.2 * radius)[0]
+
+
+def strouhal(times, lift, diameter=0.1, speed=1.0):
+    """Shedding frequency from the upward zero crossings of the lift (linear interpolation) over the
+    given history, as St = f D / U; None without two full periods."""
+    import numpy as np
+    t, c = np.asarray(times), np.asarray(lift) - np.mean(lift)
+    ups = [t[k] - c[k] * (t[k + 1] - t[k]) / (c[k + 1] - c[k]) for k in range(len(c) - 1) if c[k] < 0 <= c[k + 1]]
+    if len(ups) < 3:
+        return None
+    return float((len(ups) - 1) / (ups[-1] - ups[0]) * diameter / speed)
+
+
+def run_functionals(args, log):
+    """Flow functionals from long runs (Section 3.3, Eq. 42, Table 6, Fig. 13; Section 3.2, Fig. 7):
+    drag and lift coefficients (pressure and viscous parts) and the Strouhal number of the cylinder
+    flow, and the reattachment length behind the backward-facing step."""
+    import numpy as np
+    import torch
+
+    import paper_1610_06993_amd as cgp
+    import workloads as W
+    from paper_1610_06993_amd import SolverOpts, StepOpts
+    X0 = cgp._native
+    out = {}
+    # cylinder: C = 2 F / (rho U^2 D) with the mean inflow speed U = 1 and D = 0.1
+    case = W.case_cylinder(args.target_tris)
+    mesh = cgp.Mesh(case.mesh, 1)
+    mesh.assemble(case.rho, case.mu, case.dt, args.func_restrict)
+    mesh.surface_set(_body_edges(case.mesh))
+    xy, vd = mesh.export("xy"), mesh.export("vdir")
+    g = torch.from_numpy(case.dirichlet(xy, 0.0)).cuda()
+    u = torch.from_numpy(case.initial(xy, vd)).cuda()
+    pf = torch.zeros(mesh.info["n_f"], dtype=torch.float64, device="cuda")
+    pc = torch.zeros(mesh.info["n_c"], dtype=torch.float64, device="cuda")
+    online = cgp.Guess(mesh, n_modes=args.window, hidden=16, seed=5)
+    online.set_online(args.window, 1)
+    online.attach()
+    o = StepOpts(momentum=SolverOpts(tol=args.mom_tol, max_iter=5000, x0_mode=X0.X0_PROJECT),
+                 poisson=SolverOpts(tol=1e-8, max_iter=100000, x0_mode=X0.X0_POD_GALERKIN),
+                 mass=SolverOpts(tol=args.mass_tol, max_iter=2000))
+    hist = []
+    t0 = time.perf_counter()
+    scale = 2.0 / (case.rho * 1.0 * 1.0 * 0.1)
+    for k in range(1, args.func_steps + 1):
+        mesh.step(g, u, pf, pc, opts=o)
+        if k % args.func_every == 0:
+            f = mesh.surface_force(u, pf)
+            umax = float(torch.sqrt((u * u).sum(1).max()))
+            hist.append([k * case.dt] + [scale * v for v in f] + [umax])
+            if k % (50 * args.func_every) == 0:
+                log(f"cylinder step {k}: C_D {scale * (f[0] + f[2]):.4f} (pressure {scale * f[0]:.4f}), C_L "
+                    f"{scale * (f[1] + f[3]):.4f}, max|u| {umax:.3f}; {time.perf_counter() - t0:.0f}s")
+    online.close()
+    mesh.close()
+    H = np.array(hist)
+    tail = H[H[:, 0] >= args.func_steps * case.dt / 2]
+    cd, cl = tail[:, 1] + tail[:, 3], tail[:, 2] + tail[:, 4]
+    out["cylinder"] = dict(
+        workload=f"cylinder channel Re=100, coarse {case.mesh.n_tris} / fine {4 * case.mesh.n_tris} triangles, "
+                 f"dt=1e-3, {args.func_steps} steps, restriction {'Galerkin' if args.func_restrict else 'injection'}",
+        steps_per_s=round(args.func_steps / (time.perf_counter() - t0), 2),
+        second_half=dict(cd_mean=float(cd.mean()), cd_min=float(cd.min()), cd_max=float(cd.max()),
+                         cl_min=float(cl.min()), cl_max=float(cl.max()),
+                         cl_pressure_max=float(tail[:, 2].max()), cl_viscous_max=float(tail[:, 4].max()),
+                         strouhal=strouhal(tail[:, 0], cl), max_abs_u=float(tail[:, 5].max())),
+        history_every=args.func_every, history_cd_cl=[[round(r[0], 4), round(r[1] + r[3], 5), round(r[2] + r[4], 5)]
+                                                      for r in H[::10]])
+    log(f"cylinder: {out['cylinder']['second_half']}")
+    # backward-facing step: reattachment point from the floor's viscous traction
+    case = W.case_bfs()
+    mesh = cgp.Mesh(case.mesh, 1)
+    mesh.assemble(case.rho, case.mu, case.dt, args.func_restrict)
+    xc, be = case.mesh.xy, case.mesh.bedge
+    mesh.surface_set(np.where((xc[be[:, 0], 1] == 0.0) & (xc[be[:, 1], 1] == 0.0))[0])
+    xy, vd = mesh.export("xy"), mesh.export("vdir")
+    g = torch.from_numpy(case.dirichlet(xy, 0.0)).cuda()
+    u = torch.from_numpy(case.initial(xy, vd)).cuda()
+    pf = torch.zeros(mesh.info["n_f"], dtype=torch.float64, device="cuda")
+    pc = torch.zeros(mesh.info["n_c"], dtype=torch.float64, device="cuda")
+    online = cgp.Guess(mesh, n_modes=args.window, hidden=16, seed=5)
+    online.set_online(args.window, 1)
+    online.attach()
+    reat = []
+    t0 = time.perf_counter()
+    for k in range(1, args.bfs_steps + 1):
+        mesh.step(g, u, pf, pc, opts=o)
+        if k % 500 == 0:
+            rows = mesh.surface_traction(u, pf).cpu().numpy()
+            rows = rows[np.argsort(rows[:, 0])]
+            tau = rows[:, 5] / rows[:, 2]  # viscous x-traction per unit length on the floor
+            r = None
+            for q in range(len(tau) - 1):
+                if tau[q] < 0.0 <= tau[q + 1] and rows[q, 0] > 0.05:
+                    r = float(rows[q, 0] - tau[q] * (rows[q + 1, 0] - rows[q, 0]) / (tau[q + 1] - tau[q]))
+                    break
+            reat.append([round(k * case.dt, 3), r])
+            log(f"backward step step {k}: reattachment x/h {r}; {time.perf_counter() - t0:.0f}s")
+    online.close()
+    mesh.close()
+    out["backward_step"] = dict(
+        workload=f"backward-facing step Re=400, coarse {case.mesh.n_tris} / fine {4 * case.mesh.n_tris} triangles, "
+                 f"dt=5e-3, {args.bfs_steps} steps", reattachment_x_over_h=reat)
+    return out
+
+
+def run_learned(args, log):
+    """The learned initial guess at the shape of the configuration it is specified for: pressure
+    snapshots from plain CGP runs of the cylinder at Re drawn uniformly in [60, 160] (seeded), 64 POD
+    modes, MLPs 64-256-256-64 (GELU, BF16 on the matrix cores) trained on the GPU with Adam (lr 1e-3,
+    batch 256); Poisson iterations and solve times on held-out Re from x0 = 0, the previous pressure,
+    the POD-Galerkin correction, the absolute network and the incremental network (whose basis spans
+    the pressure increments), in FP64 and with FP32 inner solves."""
+    import numpy as np
+    import torch
+
+    import paper_1610_06993_amd as cgp
+    import workloads as W
+    from paper_1610_06993_amd import SolverOpts, StepOpts
+    X0 = cgp._native
+    n_re, n_test, settle, rec = args.learn_re, args.learn_test_re, args.learn_settle, args.learn_record
+    res = 60.0 + 100.0 * W.uniform01(7, 0, n_re)
+    case = W.case_cylinder(args.target_tris)
+    mesh = cgp.Mesh(case.mesh, 1)
+    n = mesh.info["n_c"]
+    xy, vd = mesh.export("xy"), mesh.export("vdir")
+    g = torch.from_numpy(case.dirichlet(xy, 0.0)).cuda()
+    S = n_re * rec
+    B = torch.zeros((S, n), dtype=torch.float64, device="cuda")
+    P = torch.zeros_like(B)
+    Pp = torch.zeros_like(B)
+    o = StepOpts(momentum=SolverOpts(tol=args.mom_tol, max_iter=5000, x0_mode=X0.X0_PROJECT),
+                 poisson=SolverOpts(tol=1e-8, max_iter=100000), mass=SolverOpts(tol=args.mass_tol, max_iter=2000))
+    t0 = time.perf_counter()
+    for r, re in enumerate(res):
+        mesh.assemble(case.rho, 0.1 / re, case.dt)
+        u = torch.from_numpy(case.initial(xy, vd)).cuda()
+        pf = torch.zeros(mesh.info["n_f"], dtype=torch.float64, device="cuda")
+        pc = torch.zeros(n, dtype=torch.float64, device="cuda")
+        for k in range(settle + rec):
+            if k >= settle:
+                Pp[r * rec + k - settle].copy_(pc)
+            mesh.step(g, u, pf, pc, opts=o)
+            if k >= settle:
+                mesh.last_poisson_rhs(B[r * rec + k - settle])
+                P[r * rec + k - settle].copy_(pc)
+        torch.cuda.synchronize()
+        log(f"learned study: Re {re:.1f} recorded ({r + 1}/{n_re}), {time.perf_counter() - t0:.0f}s")
+    ntr = (n_re - n_test) * rec
+    tr = slice(0, ntr)
+    models, train = {}, {}
+    for name, incr in (("abs", False), ("incr", True)):
+        net = cgp.Guess(mesh, n_modes=64, hidden=256, seed=11)
+        snaps = (P[tr] - Pp[tr]).contiguous() if incr else P[tr].contiguous()
+        t1 = time.perf_counter()
+        net.build_pod(snaps)
+        st = net.train(B[tr].contiguous(), P[tr].contiguous(), epochs=args.learn_epochs, batch=256, lr=1e-3,
+                       p_prev=Pp[tr].contiguous() if incr else None)
+        torch.cuda.synchronize()
+        train[name] = dict(loss_first=st["loss_first"], loss_last=st["loss_last"], adam_steps=st["steps"],
+                           train_ms=round(st["ms"], 1), pod_and_train_s=round(time.perf_counter() - t1, 2))
+        models[name] = net
+        log(f"learned study: {name} model loss {st['loss_first']:.3e} -> {st['loss_last']:.3e} in {st['steps']} "
+            f"Adam steps ({st['ms']:.0f} ms)")
+    # held-out Re: every `learn_eval_every`-th recorded step of each, solved from each initial guess
+    test_idx = [i for i in range(ntr, S) if (i - ntr) % args.learn_eval_every == 0]
+    modes = {"zero": (X0.X0_ZERO, None, 0), "prev": (X0.X0_PREV, None, 0),
+             "pod_galerkin": (X0.X0_POD_GALERKIN, "abs", 0), "learned": (X0.X0_LEARNED, "abs", 0),
+             "learned_corr": (X0.X0_LEARNED_CORR, "incr", 0), "mixed+prev": (X0.X0_PREV, None, 1),
+             "mixed+learned_corr": (X0.X0_LEARNED_CORR, "incr", 1)}
+    mesh.assemble(case.rho, 0.1 / res[ntr // rec], case.dt)
+    out = {}
+    for name, (mode, model, prec) in modes.items():
+        if model:
+            models[model].attach()
+        its, ms, errs = [], [], []
+        for i in test_idx:
+            re_i = res[i // rec]
+            if abs(mesh.params["mu"] - 0.1 / re_i) > 0:
+                mesh.assemble(case.rho, 0.1 / re_i, case.dt)  # K does not depend on mu; b does, and is recorded
+            x = Pp[i].clone() if mode != X0.X0_ZERO else torch.zeros(n, dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st = mesh.poisson_solve(B[i], x, SolverOpts(tol=1e-8, max_iter=100000, x0_mode=mode,
+                                                        precision=X0.PREC_FP32_IR if prec else X0.PREC_FP64,
+                                                        inner_tol=args.inner_tol))
+            ms.append(1e3 * (time.perf_counter() - t1))
+            its.append(st["p_iters"])
+            errs.append(float(torch.linalg.norm(x - P[i]) / torch.linalg.norm(P[i])))
+        if model:
+            models[model].detach()
+        out[name] = dict(poisson_iters_mean=round(float(np.mean(its)), 1), solve_ms_mean=round(float(np.mean(ms)), 3),
+                         rel_err_vs_recorded_max=float(np.max(errs)))
+        log(f"learned study, held-out Re: {name}: {np.mean(its):.1f} iterations, {np.mean(ms):.2f} ms per solve, "
+            f"max rel diff from the recorded pressure {np.max(errs):.1e}")
+    for net in models.values():
+        net.close()
+    mesh.close()
+    return dict(workload=f"cylinder channel, coarse {case.mesh.n_tris} / fine {4 * case.mesh.n_tris} triangles, dt=1e-3; "
+                         f"{n_re} Re values in [60,160] (seed 7), steps {settle + 1}-{settle + rec} of each recorded "
+                         f"({S} snapshots); the last {n_test} Re held out; Poisson tol 1e-8",
+                train_re=[round(float(v), 2) for v in res[:n_re - n_test]],
+                test_re=[round(float(v), 2) for v in res[n_re - n_test:]], samples_evaluated=len(test_idx),
+                training=train, guesses=out)
+
+
 def run_steady(args, log):
     """One continuous run of the online-POD path (not a restart from recorded state): 74 plain steps
     from the impulsive start, then the guess with an empty window that fills as it goes, for each
@@ -244,9 +560,8 @@ def run_batch(args, log):
     nnz = sum(m.info["nnz_c"] for m in meshes)
     t_fine = sum(m.info["t_f"] for m in meshes)
     batch = cgp.Batch(meshes)
-    cache = ROOT / "gpurun_out" / "batch_tuning.json"
-    cache.parent.mkdir(exist_ok=True)
-    tuned = batch.autotune(cache)
+    TUNING_CACHE.parent.mkdir(exist_ok=True)
+    tuned = batch.autotune(TUNING_CACHE)
     log(f"batch: {len(meshes)} instances, {t_fine} fine triangles, {rows} coarse rows, {nnz} coarse nonzeros; "
         f"setup {time.perf_counter() - t0:.1f}s; autotuned {tuned}")
     tol = 1e-8
@@ -298,18 +613,6 @@ def run_batch(args, log):
     torch.cuda.synchronize()
     us_it = 1e6 * (time.perf_counter() - t2) / 64
     kbytes = 12 * nnz + 92 * rows
-    # per-instance error against the FP64 oracle for the two smallest instances (one step from the same state)
-    import oracle
-    small = sorted(range(len(meshes)), key=lambda i: meshes[i].info["n_c"])[:2]
-    restore()
-    batch.step(g, u, pf, pc, opts=opts)
-    err_oracle = 0.0
-    for i in small:
-        o = oracle.Problem(cases[i].mesh, 1)
-        o.assemble(cases[i].rho, cases[i].mu, cases[i].dt)
-        ur, pfr, pcr, code, _ = o.step(g[i].cpu().numpy(), su[i].cpu().numpy(), spc[i].cpu().numpy(), tol_mom=args.mom_tol,
-                                       tol_p=tol, tol_mass=args.mass_tol)
-        err_oracle = max(err_oracle, rel(u[i].cpu().numpy(), ur), rel(pf[i].cpu().numpy(), pfr))
     # every instance with its own online POD basis (the last `batch_window` solutions), which fills during
     # window + 1 untimed batched steps; then the same timed steps
     guesses = []
@@ -352,7 +655,7 @@ def run_batch(args, log):
                sequential_instance_steps_per_s=round(len(meshes) / seq_s, 3),
                speedup_vs_sequential=round(len(meshes) * args.batch_steps / el / (len(meshes) / seq_s), 3),
                poisson_iters_min_max=[min(iters), max(iters)], batched_launches_per_step=launches,
-               rel_err_vs_single_instance_gpu=err, rel_err_vs_fp64_oracle_2_smallest=err_oracle,
+               rel_err_vs_single_instance_gpu=err,
                tuning=tuned, batched_kernel_us_per_iteration_all_active=round(us_it, 2),
                batched_kernel_bytes_per_iteration=kbytes,
                batched_kernel_gbs=round(kbytes / (us_it * 1e-6) / 1e9, 1),
@@ -367,7 +670,7 @@ def run_batch(args, log):
     log(f"batch: {out['instance_steps_per_s']} instance-steps/s ({out['ms_per_batch_step']} ms per batch step) vs "
         f"{out['sequential_instance_steps_per_s']} sequential; Poisson iterations {min(iters)}..{max(iters)}; "
         f"batched PCG kernel {us_it:.1f} us/iteration for {kbytes / 1e6:.0f} MB -> {out['batched_kernel_gbs']} GB/s; "
-        f"rel err vs single-instance {err:.1e}, vs oracle {err_oracle:.1e}")
+        f"rel err vs single-instance {err:.1e}")
     log(f"batch with per-instance online POD guesses (window {args.batch_window}): "
         f"{out['online_pod']['instance_steps_per_s']} instance-steps/s ({out['online_pod']['ms_per_batch_step']} ms "
         f"per batch step); Poisson iterations {min(iters_on)}..{max(iters_on)}")
@@ -409,6 +712,28 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--batch-window", type=int, default=64, help="online POD window per batched instance (at most 64)")
     ap.add_argument("--only-batch", action="store_true", help="run only the batched sweep")
+    ap.add_argument("--levels-sweep", type=int, default=1, help="run the l = 0..3 comparison on one fine mesh (0: skip)")
+    ap.add_argument("--bfs", type=int, default=1, help="run the backward-facing step at l = 1 and l = 0 (0: skip)")
+    ap.add_argument("--only-levels", action="store_true", help="run only the l = 0..3 comparison")
+    ap.add_argument("--only-learned", action="store_true",
+                    help="run only the learned-guess study (Re sweep, 64 modes, 64-256-256-64, held-out Re)")
+    ap.add_argument("--learn-re", type=int, default=20, help="Re values of the learned-guess study")
+    ap.add_argument("--learn-test-re", type=int, default=4, help="of them held out for evaluation")
+    ap.add_argument("--learn-settle", type=int, default=100, help="unrecorded steps per Re")
+    ap.add_argument("--learn-record", type=int, default=100, help="recorded steps per Re")
+    ap.add_argument("--learn-epochs", type=int, default=200, help="training epochs")
+    ap.add_argument("--learn-eval-every", type=int, default=5, help="held-out recorded steps between evaluations")
+    ap.add_argument("--only-functionals", action="store_true",
+                    help="run only the long flow-functional runs (cylinder drag, lift, Strouhal; backward-step reattachment)")
+    ap.add_argument("--func-steps", type=int, default=8000, help="cylinder steps of the functional run")
+    ap.add_argument("--func-every", type=int, default=10, help="steps between force evaluations")
+    ap.add_argument("--func-restrict", type=int, default=1,
+                    help="restriction of the functional runs: 0 inject, 1 Galerkin (energy-stable; the default)")
+    ap.add_argument("--bfs-steps", type=int, default=10000, help="backward-step steps of the functional run")
+    ap.add_argument("--level-warmup", type=int, default=10, help="untimed steps per level / backward-step run")
+    ap.add_argument("--level-steps", type=int, default=10, help="timed steps per level / backward-step run")
+    ap.add_argument("--only-bfs", action="store_true", help="run only the backward-facing step")
+    ap.add_argument("--bfs-nx", type=int, default=612, help="cells along the backward-step channel (42 across at 612)")
     ap.add_argument("--spmv-sweep", type=int, default=1, help="run the SpMV size sweep (0: skip)")
     ap.add_argument("--spmv-large", action="store_true", help="add a 16.8M-row point to the SpMV sweep")
     ap.add_argument("--only-spmv", action="store_true", help="run only the SpMV size sweep")
@@ -446,6 +771,18 @@ def main():
         return
     if args.only_spmv:
         print(json.dumps({"spmv_sweep": run_spmv_sweep(args, log)}), flush=True)
+        return
+    if args.only_levels:
+        print(json.dumps({"levels": run_levels(args, log)}), flush=True)
+        return
+    if args.only_learned:
+        print(json.dumps({"learned": run_learned(args, log)}), flush=True)
+        return
+    if args.only_functionals:
+        print(json.dumps({"functionals": run_functionals(args, log)}), flush=True)
+        return
+    if args.only_bfs:
+        print(json.dumps({"backward_step": run_bfs(args, log)}), flush=True)
         return
     if args.only_cg:
         print(json.dumps({"cg_sweep": run_cg_sweep(args, log)}), flush=True)
@@ -513,7 +850,8 @@ def main():
     for name, prev in (("abs", None), ("incr", pprev)):
         net = cgp.Guess(mesh, n_modes=args.modes, hidden=args.hidden, seed=11)
         t1 = time.perf_counter()
-        net.build_pod(ps)
+        # the incremental model's basis spans the recorded pressure increments, the quantity it predicts
+        net.build_pod(ps if prev is None else (ps - prev).contiguous())
         tr = net.train(rhs, ps, epochs=args.epochs, batch=64, lr=2e-3, p_prev=prev)
         torch.cuda.synchronize()
         train[name] = dict(loss_first=tr["loss_first"], loss_last=tr["loss_last"], adam_steps=tr["steps"],
@@ -558,42 +896,78 @@ def main():
         "fp64+learned_corr": (F64, X0.X0_LEARNED_CORR, "incr"),
         "fp64+online_pod": (F64, X0.X0_POD_GALERKIN, "online"),
         "mixed": (F32, X0.X0_PREV, None),
+        "mixed+learned_corr": (F32, X0.X0_LEARNED_CORR, "incr"),
         "mixed+online_pod": (F32, X0.X0_POD_GALERKIN, "online"),
     }
     if args.paths != "all":
         keep = set(args.paths.split(",")) | {"fp64"}
         paths = {k: v for k, v in paths.items() if k in keep}
 
-    # one step of every path from the same state: accuracy against plain FP64 and the phase breakdown
+    ml = torch.from_numpy(mesh.export("ml_f")).to(dev)
+
+    def flow_stats():
+        """max |u| and the kinetic energy (1/2) u^T M_L u of the current velocity"""
+        sp = u[:, 0] * u[:, 0] + u[:, 1] * u[:, 1]
+        return float(torch.sqrt(sp.max())), float(0.5 * (ml * sp).sum())
+
+    def one_step_error(prec, x0, model):
+        """From the current state: one step of the path against one plain FP64 step (state restored
+        between them); the path's step is the one kept."""
+        su, spc, spf = u.clone(), pc.clone(), pf.clone()
+        if model:
+            (online if model == "online" else models[model]).detach()
+        mesh.step(g, u, pf, pc, opts=opts())
+        ref_u, ref_pf = u.clone(), pf.clone()
+        u.copy_(su)
+        pc.copy_(spc)
+        pf.copy_(spf)
+        if model:
+            (online if model == "online" else models[model]).attach()
+        mesh.step(g, u, pf, pc, opts=opts(prec, x0))
+        return max(rel(u.cpu().numpy(), ref_u.cpu().numpy()), rel(pf.cpu().numpy(), ref_pf.cpu().numpy()))
+
+    # the plain FP64 trajectory of the timed window, for each path's trajectory difference (reported)
     restore()
-    mesh.step(g, u, pf, pc, opts=opts(timing=1))
-    u_ref, pf_ref = u.cpu().numpy(), pf.cpu().numpy()
+    for k in range(args.warmup + args.steps):
+        mesh.step(g, u, pf, pc, opts=opts())
+    traj_u, traj_pf = u.cpu().numpy(), pf.cpu().numpy()
     results = {}
+    phase_keys = ("ms_momentum", "ms_restrict", "ms_poisson", "ms_prolong", "ms_correct")
     for name, (prec, x0, model) in paths.items():
         restore(model)
-        st1 = mesh.step(g, u, pf, pc, opts=opts(prec, x0, timing=1))
-        err = max(rel(u.cpu().numpy(), u_ref), rel(pf.cpu().numpy(), pf_ref))
+        err_start = one_step_error(prec, x0, model)
         restore(model)
         for k in range(args.warmup):  # untimed: solver chunk sizes adapt, guess windows turn over
             mesh.step(g, u, pf, pc, opts=opts(prec, x0))
         torch.cuda.synchronize()
-        iters, miters = [], []
+        iters, miters, phases, flow = [], [], {k: 0.0 for k in phase_keys}, []
         t1 = time.perf_counter()
         for k in range(args.steps):
-            st = mesh.step(g, u, pf, pc, opts=opts(prec, x0))
+            st = mesh.step(g, u, pf, pc, opts=opts(prec, x0, timing=1))
             iters.append(st["p_iters"])
             miters.append(st["mom_iters"])
+            for key in phase_keys:
+                phases[key] += st[key]
+            if k == 0:
+                flow.append(flow_stats())
         torch.cuda.synchronize()
         el = time.perf_counter() - t1
+        flow.append(flow_stats())
+        err_traj = max(rel(u.cpu().numpy(), traj_u), rel(pf.cpu().numpy(), traj_pf))
+        err_end = one_step_error(prec, x0, model)
         results[name] = dict(steps_per_s=round(args.steps / el, 3), ms_per_step=round(1e3 * el / args.steps, 3),
                              poisson_iters_mean=float(np.mean(iters)), momentum_iters_mean=float(np.mean(miters)),
-                             rel_err_vs_fp64=err,
-                             phase_ms={k: round(st1[k], 4) for k in ("ms_momentum", "ms_restrict", "ms_poisson",
-                                                                     "ms_prolong", "ms_correct")})
+                             rel_err_vs_fp64=max(err_start, err_end), rel_err_vs_fp64_at_restart=err_start,
+                             rel_err_vs_fp64_after_timed_steps=err_end,
+                             trajectory_diff_vs_fp64=err_traj,
+                             max_abs_u_first_last=[round(flow[0][0], 6), round(flow[-1][0], 6)],
+                             kinetic_energy_first_last=[round(flow[0][1], 8), round(flow[-1][1], 8)],
+                             phase_ms_mean={k: round(v / args.steps, 4) for k, v in phases.items()})
         log(f"{name}: {args.steps / el:.2f} steps/s ({1e3 * el / args.steps:.2f} ms/step), Poisson iterations "
-            f"{np.mean(iters):.0f}, momentum iterations {np.mean(miters):.1f}, one-step rel err vs fp64 {err:.1e}; "
-            f"phases (ms) mom {st1['ms_momentum']:.2f} "
-            f"poisson {st1['ms_poisson']:.2f} correct {st1['ms_correct']:.2f}")
+            f"{np.mean(iters):.0f}, momentum iterations {np.mean(miters):.1f}; one-step rel err vs fp64 "
+            f"{err_start:.1e} at restart, {err_end:.1e} after the timed steps; trajectory diff {err_traj:.1e}; "
+            f"max|u| {flow[0][0]:.3f} -> {flow[-1][0]:.3f}; phases (ms) mom {phases['ms_momentum'] / args.steps:.2f} "
+            f"poisson {phases['ms_poisson'] / args.steps:.2f} correct {phases['ms_correct'] / args.steps:.2f}")
     restore()
 
     eligible = {k: v for k, v in results.items() if v["rel_err_vs_fp64"] <= ERR_BAR}
@@ -625,10 +999,15 @@ def main():
         log(f"dominant kernel {kname}: {cnt} launches, avg {dom['avg_us']:.2f} us, {bytes_per_iter} algorithmic "
             f"bytes per launch, {achieved:.0f} GB/s")
 
-    # CPU baseline: the FP64 oracle from the same state, and the best path's accuracy against it
+    # CPU baseline: the FP64 oracle from the same state (one thread, and the OpenMP build on every host
+    # core, in child processes), and the best path's one-step accuracy against it
     cpu = None
     err_vs_oracle = None
     if args.cpu_steps > 0:
+        import os
+        import subprocess
+        import tempfile
+
         import oracle
         ref = oracle.Problem(case.mesh, 1)
         ref.assemble(case.rho, case.mu, case.dt)
@@ -639,16 +1018,48 @@ def main():
         ub, pfb = u.cpu().numpy(), pf.cpu().numpy()
         restore()
         t2 = time.perf_counter()
-        outs = []
-        for k in range(args.cpu_steps):
-            ur, pfr, pcr, code, ost = ref.step(gh, ur, pcr, tol_mom=args.mom_tol, tol_p=tol, tol_mass=args.mass_tol)
-            outs.append((ur.copy(), pfr.copy()))
-        el = time.perf_counter() - t2
-        err_vs_oracle = max(rel(ub, outs[0][0]), rel(pfb, outs[0][1]))
-        cpu = dict(value=round(args.cpu_steps / el, 5), unit="CGP steps/s", cores=1, kind="oracle",
-                   sample=f"{args.cpu_steps} FP64 oracle steps (single thread) of the same cylinder workload "
-                          f"from the post-training state; {el:.1f} s")
-        log(f"oracle: {el / args.cpu_steps:.2f} s/step; {best} step vs oracle rel err {err_vs_oracle:.2e}")
+        ur1, pfr1, _, code, _ = ref.step(gh, ur, pcr, tol_mom=args.mom_tol, tol_p=tol, tol_mass=args.mass_tol)
+        el1 = time.perf_counter() - t2
+        err_vs_oracle = max(rel(ub, ur1), rel(pfb, pfr1))
+        nproc = os.cpu_count() or 1
+        try:
+            nproc = len(os.sched_getaffinity(0))
+        except AttributeError:
+            pass
+        model_name = "unknown"
+        try:
+            for ln in open("/proc/cpuinfo"):
+                if ln.startswith("model name"):
+                    model_name = ln.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+        timed = {}
+        with tempfile.TemporaryDirectory() as td:
+            state = os.path.join(td, "state.npz")
+            np.savez(state, u=ur, pc=pcr, g=gh)
+            for label, env_extra in (("single", {"CGP_ORACLE_OPENMP": "0", "OMP_NUM_THREADS": "1"}),
+                                     ("openmp", {"CGP_ORACLE_OPENMP": "1", "OMP_NUM_THREADS": str(nproc)})):
+                env = dict(os.environ, **env_extra)
+                cmd = [sys.executable, "-m", "oracle.timing", state, str(args.target_tris), str(args.cpu_steps),
+                       repr(args.mom_tol), repr(tol), repr(args.mass_tol)]
+                r = subprocess.run(cmd, cwd=str(ROOT), env=env, capture_output=True, text=True, timeout=900)
+                if r.returncode == 0:
+                    timed[label] = json.loads(r.stdout.strip().splitlines()[-1])
+                else:
+                    log(f"oracle timing ({label}) failed: {r.stderr[-400:]}")
+        single = timed.get("single", dict(s_per_step=el1, steps=1, threads=1))
+        cpu = dict(value=round(1.0 / single["s_per_step"], 5), unit="CGP steps/s", cores=1, kind="oracle",
+                   sample=f"{single['steps']} FP64 oracle steps (single thread) of the same cylinder workload "
+                          f"from the post-training state; {single['s_per_step']:.2f} s per step",
+                   nproc=nproc, cpu_model=model_name)
+        if "openmp" in timed:
+            om = timed["openmp"]
+            cpu["openmp"] = dict(value=round(1.0 / om["s_per_step"], 5), unit="CGP steps/s", cores=om["threads"],
+                                 s_per_step=round(om["s_per_step"], 3))
+        log(f"oracle: {single['s_per_step']:.2f} s/step on one thread"
+            + (f", {timed['openmp']['s_per_step']:.2f} s/step on {timed['openmp']['threads']} threads" if "openmp" in
+               timed else "") + f" ({model_name}, {nproc} cores); {best} step vs oracle rel err {err_vs_oracle:.2e}")
 
     line = {
         "metric": "CGP steps/s (1M-tri fine mesh) vs plain FP64 at <=1e-6 rel err; SpMV HBM GB/s",
@@ -659,13 +1070,16 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+f32-ir" if bprec == F32 else "f64", "data": "synthetic",
         "config": {"workload": f"cylinder channel Re=100, coarse {info['t_c']} / fine {info['t_f']} P1 triangles, "
-                               f"l=1, dt=1e-3, Poisson PCG tol 1e-8 (momentum {args.mom_tol:g}, mass {args.mass_tol:g}), "
-                               f"momentum x0 {args.mom_x0}, path {best}",
+                               f"l=1, injection restriction, consistent-mass correction, dt=1e-3, Poisson PCG tol 1e-8 "
+                               f"(momentum {args.mom_tol:g}, mass {args.mass_tol:g}), momentum x0 {args.mom_x0}, "
+                               f"path {best}",
                    "path": best, "fine_nodes": info["n_f"], "coarse_nodes": n_c, "nnz_f": info["nnz_f"],
                    "nnz_c": nnz_c, "pod_modes": args.modes, "snapshots": S, "parallelism": "single GPU"},
         "fp64_steps_per_s": results["fp64"]["steps_per_s"],
         "speedup_vs_fp64": round(res["steps_per_s"] / results["fp64"]["steps_per_s"], 3),
         "rel_err_vs_fp64_gpu": res["rel_err_vs_fp64"],
+        "max_abs_u_first_last": res["max_abs_u_first_last"],
+        "kinetic_energy_first_last": res["kinetic_energy_first_last"],
         "rel_err_vs_fp64_oracle": err_vs_oracle,
         "paths": results,
         "training": train,
@@ -679,6 +1093,18 @@ def main():
         line["cpu_baseline"] = cpu
     for net in models.values():
         net.close()
+    if args.levels_sweep:
+        try:
+            line["levels"] = run_levels(args, log)
+        except Exception as e:
+            line["levels"] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"levels sweep failed: {e}")
+    if args.bfs:
+        try:
+            line["backward_step"] = run_bfs(args, log)
+        except Exception as e:
+            line["backward_step"] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"backward-facing step failed: {e}")
     if args.spmv_sweep:
         try:
             line["spmv_sweep"] = run_spmv_sweep(args, log)

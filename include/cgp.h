@@ -96,6 +96,11 @@ enum { CGP_X0_ZERO = 0,            /* Krylov initial guess zero */
                                       residual is never larger than that of CGP_X0_EXTRAP beyond rounding.
                                       The first use allocates 128 bytes per fine node for the history. */
 
+enum { CGP_METHOD_DEFAULT = 0,     /* Jacobi-PCG (Poisson, mass), Jacobi-BiCGStab (momentum) */
+       CGP_METHOD_ILU_GMRES = 1 };  /* Poisson only: GMRES(restart) preconditioned by ILU(0) of Kbar, the paper's solver
+                                       (Section 2.3); FP64; factorised on the device at the first such solve
+                                       after cgp_assemble */
+
 enum { CGP_LAUNCH_AUTO = 0,        /* library choice (FUSED for the Poisson solve) */
        CGP_LAUNCH_LOOP = 1,        /* two kernels per PCG iteration (textbook recurrences), host polls every chunk */
        CGP_LAUNCH_PERSISTENT = 2,  /* Poisson: one cooperative kernel for the whole Krylov loop */
@@ -130,7 +135,9 @@ typedef struct {
                                  solve asks for less (half the reduction the outer tolerance still needs)
                                  when that is enough, except under CGP_LAUNCH_PERSISTENT */
   int32_t x0_mode;            /* CGP_X0_* */
-  int32_t launch;             /* CGP_LAUNCH_* */
+  int32_t launch;             /* CGP_LAUNCH_* (the default method only) */
+  int32_t method;             /* CGP_METHOD_* */
+  int32_t restart;            /* CGP_METHOD_ILU_GMRES: Krylov vectors per cycle, 1..200 (0 = 30) */
 } cgp_solver_opts;
 
 typedef struct {
@@ -177,7 +184,9 @@ enum {
   CGP_X_DX_C = 26, CGP_X_DY_C = 27,
   CGP_X_MC = 28,         /* coarse lumped mass [n_c] */
   CGP_X_A_F = 29,        /* momentum matrix of the last step, after Dirichlet elimination */
-  CGP_X_ML_F = 30        /* fine lumped mass [n_f] */
+  CGP_X_ML_F = 30,       /* fine lumped mass [n_f] */
+  CGP_X_ILU_C = 31       /* ILU(0) factors of the coarse Poisson matrix on its pattern [nnz_c] (unit L below the
+                            diagonal, U on and above), after the first CGP_METHOD_ILU_GMRES solve */
 };
 
 /* operators for cgp_spmv */
@@ -336,6 +345,24 @@ cgp_status cgp_batch_set_tuning(cgp_batch *batch, const cgp_batch_tuning *tuning
 /* Time 12 launch shapes on the batch's own system and keep the fastest; the choice is cached in the JSON
  * file cache_path (NULL: no cache) under the batch's size class and reused without timing. */
 cgp_status cgp_batch_autotune(cgp_batch *batch, const char *cache_path, cgp_batch_tuning *chosen);
+
+/* ---- flow functionals: the force of the fluid on a marked part of the boundary, for drag and lift on
+ * the body (Section 3.3, Eq. 42 and Table 6; their pressure and viscous parts, Fig. 13) and for the
+ * wall shear stress that locates the reattachment point behind the step (Section 3.2, Fig. 7).
+ * Each fine boundary edge e = (a, b) of the surface, with n its unit normal pointing into the fluid
+ * and the stress -p I + mu (grad u + grad u^T) of the P1 fields (pressure linear along e, velocity
+ * gradient constant on e's triangle), contributes -|e| (p_a + p_b)/2 n (pressure part) and
+ * |e| mu (grad u + grad u^T) n (viscous part). */
+/* Mark the surface by coarse boundary-edge indices (into cgp_mesh_desc.bedge; their children on
+ * every finer level inherit the mark).  count = 0 clears it.  Allocates on first use or growth. */
+cgp_status cgp_surface_set(cgp_mesh *mesh, int32_t count, const int32_t *coarse_bedge_ids);
+/* Per fine edge of the surface, rows of 8 doubles (dev [n_rows][8]): midpoint x, y, length, pressure
+ * force x, y, viscous force x, y, 0.  u dev [n_f][2], p_fine dev [n_f]; rows NULL only returns n_rows. */
+cgp_status cgp_surface_traction(cgp_mesh *mesh, const double *u, const double *p_fine, double *rows,
+                                int32_t *n_rows);
+/* Totals over the surface, host out[4]: pressure force x, y, viscous force x, y (zeros if none is
+ * marked).  Synchronises the mesh stream. */
+cgp_status cgp_surface_force(cgp_mesh *mesh, const double *u, const double *p_fine, double *out);
 
 /* Read or replace the Krylov launch shapes of a mesh (results do not depend on them beyond
  * rounding order).  Invalid knobs return CGP_E_ARG and leave the mesh unchanged. */

@@ -14,28 +14,33 @@ from pathlib import Path
 import numpy as np
 
 _DIR = Path(__file__).resolve().parent
-_LIB_PATH = _DIR / "liboracle.so"
-_SOURCES = ["mesh.c", "fem.c", "krylov.c", "cgp.c", "learn.c", "pod.c", "norms.c"]
+# CGP_ORACLE_OPENMP=1 selects the OpenMP build (multi-core CPU-baseline timing only; parity uses the
+# single-thread build)
+_OPENMP = os.environ.get("CGP_ORACLE_OPENMP", "") == "1"
+_LIB_PATH = _DIR / ("liboracle_omp.so" if _OPENMP else "liboracle.so")
+_SOURCES = ["mesh.c", "fem.c", "krylov.c", "cgp.c", "learn.c", "pod.c", "norms.c", "forces.c", "gmres.c"]
 _lib = None
 
 ERRORS = {0: "ok", 1: "bad argument", 2: "invalid mesh", 3: "no convergence", 4: "non-finite value"}
 
 
 def build(openmp: bool = False) -> Path:
-    """Compile the oracle with gcc (plain C99, -O2, no fast-math)."""
+    """Compile the oracle with gcc (plain C99, -O2, no fast-math); openmp=True builds liboracle_omp.so."""
     srcs = [str(_DIR / s) for s in _SOURCES if (_DIR / s).exists()]
+    out = _DIR / ("liboracle_omp.so" if openmp else "liboracle.so")
     cmd = ["gcc", "-O2", "-std=c99", "-D_POSIX_C_SOURCE=200809L", "-fPIC", "-shared", "-Wall",
-           "-Wno-unused-function", "-o", str(_LIB_PATH) + ".tmp"] + srcs + ["-lm"]
+           "-Wno-unused-function", "-Wno-unknown-pragmas"] + (["-fopenmp"] if openmp else []) + \
+          ["-o", str(out) + ".tmp"] + srcs + ["-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(str(_LIB_PATH) + ".tmp", _LIB_PATH)
-    return _LIB_PATH
+    os.replace(str(out) + ".tmp", out)
+    return out
 
 
 def lib():
     global _lib
     if _lib is None:
         if not _LIB_PATH.exists():
-            build()
+            build(openmp=_OPENMP)
         _lib = C.CDLL(str(_LIB_PATH))
         _declare(_lib)
     return _lib
@@ -111,6 +116,16 @@ def _declare(L):
     L.orc_jacobi_eigen.argtypes = [C.c_int, _dp, _dp]
     L.orc_pod.restype = C.c_int
     L.orc_pod.argtypes = [C.c_int, C.c_int, _dp, _dp, C.c_int, _dp, _dp]
+    L.orc_ilu0.restype = C.c_int
+    L.orc_ilu0.argtypes = [C.c_void_p, _dp, _dp]
+    L.orc_ilu0_apply.restype = None
+    L.orc_ilu0_apply.argtypes = [C.c_void_p, _dp, _dp, _dp]
+    L.orc_gmres.restype = C.c_int
+    L.orc_gmres.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, C.c_int, C.c_double, C.c_int, C.c_int, _ip, _dp]
+    L.orc_surface_traction.restype = C.c_int
+    L.orc_surface_traction.argtypes = [C.c_void_p, _ip, _dp, _dp, _dp, C.c_int]
+    L.orc_surface_force.restype = C.c_int
+    L.orc_surface_force.argtypes = [C.c_void_p, _ip, _dp, _dp, _dp]
     L.orc_quad_npts.restype = C.c_int
     L.orc_quad_points.restype = C.c_int
     L.orc_quad_points.argtypes = [C.c_void_p, C.c_int, _dp]
@@ -157,6 +172,38 @@ def pcg(rp, col, val, b, x0=None, tol=1e-12, maxit=100000, method="cg"):
     it, rr = C.c_int(), C.c_double()
     f = lib().orc_pcg if method == "cg" else lib().orc_bicgstab
     st = f(C.byref(s), _d(val), _d(b), _d(x), tol, maxit, C.byref(it), C.byref(rr))
+    return x, st, it.value, rr.value
+
+
+def ilu0(rp, col, val):
+    """ILU(0) factors of a CSR matrix on its own pattern (unit L below the diagonal, U on and above)."""
+    s, keep = _csr(rp, col)
+    val = np.ascontiguousarray(val, np.float64)
+    lu = np.zeros_like(val)
+    if lib().orc_ilu0(C.byref(s), _d(val), _d(lu)):
+        raise RuntimeError("zero pivot in ILU(0)")
+    return lu
+
+
+def ilu0_apply(rp, col, lu, r):
+    s, keep = _csr(rp, col)
+    z = np.zeros(len(rp) - 1)
+    lib().orc_ilu0_apply(C.byref(s), _d(np.ascontiguousarray(lu, np.float64)), _d(np.ascontiguousarray(r, np.float64)),
+                         _d(z))
+    return z
+
+
+def gmres(rp, col, val, b, x0=None, m=30, tol=1e-12, maxit=100000, ilu=True, orth="mgs"):
+    """ILU(0)-preconditioned (or plain) GMRES(m): solution, status, iterations, relative residual.
+    orth: "mgs" (modified Gram-Schmidt) or "cgs2" (classical Gram-Schmidt applied twice)."""
+    s, keep = _csr(rp, col)
+    val = np.ascontiguousarray(val, np.float64)
+    b = np.ascontiguousarray(b, np.float64)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, np.float64)
+    lu = ilu0(rp, col, val) if ilu else None
+    it, rr = C.c_int(), C.c_double()
+    st = lib().orc_gmres(C.byref(s), _d(val), _d(lu) if lu is not None else None, _d(b), _d(x), m, tol, maxit,
+                         {"mgs": 0, "cgs2": 1}[orth], C.byref(it), C.byref(rr))
     return x, st, it.value, rr.value
 
 
@@ -311,6 +358,27 @@ class Problem:
         if lib().orc_pressure_update(self._h, _d(np.ascontiguousarray(bc, np.float64)),
                                      _d(np.ascontiguousarray(phi, np.float64)), _d(out)):
             raise ValueError("not an incremental pressure mode")
+        return out
+
+    def surface_traction(self, mark, u, pf):
+        """Per fine edge of the marked coarse boundary edges: [x, y, length, Fp_x, Fp_y, Fv_x, Fv_y, 0]."""
+        mark = np.ascontiguousarray(mark, np.int32)
+        u = np.ascontiguousarray(u, np.float64)
+        pf = np.ascontiguousarray(pf, np.float64)
+        n = lib().orc_surface_traction(self._h, _i(mark), _d(u), _d(pf), None, 0)
+        if n < 0:
+            raise ValueError("bad surface")
+        out = np.zeros((n, 8))
+        lib().orc_surface_traction(self._h, _i(mark), _d(u), _d(pf), _d(out), n)
+        return out
+
+    def surface_force(self, mark, u, pf):
+        """Force of the fluid on the marked boundary: [pressure x, pressure y, viscous x, viscous y]."""
+        out = np.zeros(4)
+        if lib().orc_surface_force(self._h, _i(np.ascontiguousarray(mark, np.int32)),
+                                   _d(np.ascontiguousarray(u, np.float64)),
+                                   _d(np.ascontiguousarray(pf, np.float64)), _d(out)):
+            raise ValueError("bad surface")
         return out
 
     def quad_points(self, level=None):

@@ -4,6 +4,9 @@
  * Jacobi-preconditioned BiCGStab and a dense LU solve with partial pivoting.
  * TEST INFRASTRUCTURE ONLY.
  *
+ * The loop pragmas are read only by the OpenMP build of the oracle (liboracle_omp.so, -fopenmp), which
+ * serves the multi-core CPU baseline; the single-thread build, which judges the GPU path, ignores them.
+ *
  * Stopping rule for both Krylov methods: the (recursively updated,
  * unpreconditioned) residual satisfies ||r||_2 <= tol * ||b||_2; a zero right
  * hand side gives x = 0.  The textbook iterations are written out in full.
@@ -15,6 +18,7 @@
 #include "oracle.h"
 
 void orc_spmv(const orc_csr *A, const double *val, const double *x, double *y) {
+#pragma omp parallel for schedule(static)
   for (int i = 0; i < A->n; i++) {
     double s = 0.0;
     for (int k = A->rp[i]; k < A->rp[i + 1]; k++) s += val[k] * x[A->col[k]];
@@ -24,6 +28,7 @@ void orc_spmv(const orc_csr *A, const double *val, const double *x, double *y) {
 
 static double dot(int n, const double *a, const double *b) {
   double s = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : s)
   for (int i = 0; i < n; i++) s += a[i] * b[i];
   return s;
 }
@@ -61,9 +66,11 @@ int orc_pcg(const orc_csr *A, const double *val, const double *b, double *x, dou
     if (k >= maxit) { st = ORC_E_NOCONV; break; }
     orc_spmv(A, val, pv, q);
     double alpha = rz / dot(n, pv, q);
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < n; i++) { x[i] += alpha * pv[i]; r[i] -= alpha * q[i]; z[i] = dinv[i] * r[i]; }
     double rz_new = dot(n, r, z);
     double beta = rz_new / rz;
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < n; i++) pv[i] = z[i] + beta * pv[i];
     rz = rz_new;
     rn = sqrt(dot(n, r, r));
@@ -100,13 +107,16 @@ int orc_bicgstab(const orc_csr *A, const double *val, const double *b, double *x
     if (k >= maxit) { st = ORC_E_NOCONV; break; }
     double rho_new = dot(n, rh, r);
     double beta = (rho_new / rho) * (alpha / omega);
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < n; i++) { pv[i] = r[i] + beta * (pv[i] - omega * v[i]); ph[i] = dinv[i] * pv[i]; }
     orc_spmv(A, val, ph, v);
     alpha = rho_new / dot(n, rh, v);
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < n; i++) { s[i] = r[i] - alpha * v[i]; sh[i] = dinv[i] * s[i]; }
     orc_spmv(A, val, sh, t);
     double tt = dot(n, t, t);
     omega = tt > 0.0 ? dot(n, t, s) / tt : 0.0;
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < n; i++) { x[i] += alpha * ph[i] + omega * sh[i]; r[i] = s[i] - omega * t[i]; }
     rho = rho_new;
     rn = sqrt(dot(n, r, r));

@@ -135,4 +135,15 @@ int orc_quad_points(const orc_problem *p, int level, double *xyq);
 int orc_error_norms(const orc_problem *p, int level, int nc, const double *A, const double *aq, const double *an,
                     double *l2, double *linf);
 
+/* ---- the paper's solver: ILU(0)-preconditioned GMRES(m) (oracle/gmres.c) */
+int orc_ilu0(const orc_csr *A, const double *val, double *lu);
+void orc_ilu0_apply(const orc_csr *A, const double *lu, const double *r, double *z);
+int orc_gmres(const orc_csr *A, const double *val, const double *lu, const double *b, double *x, int m, double tol,
+              int maxit, int orth, int *iters, double *relres);
+
+/* ---- forces on a marked boundary (oracle/forces.c) */
+int orc_surface_traction(const orc_problem *p, const int *mark, const double *u, const double *pf, double *out,
+                         int cap);
+int orc_surface_force(const orc_problem *p, const int *mark, const double *u, const double *pf, double *out);
+
 #endif

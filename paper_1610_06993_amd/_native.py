@@ -20,12 +20,13 @@ PRESSURE_NONINCREMENTAL, PRESSURE_INCREMENTAL, PRESSURE_ROTATIONAL = 0, 1, 2
 PREC_FP64, PREC_FP32_IR = 0, 1
 X0_ZERO, X0_PREV, X0_LEARNED, X0_LEARNED_CORR, X0_POD_GALERKIN, X0_EXTRAP, X0_PROJECT = 0, 1, 2, 3, 4, 5, 6
 LAUNCH_AUTO, LAUNCH_LOOP, LAUNCH_PERSISTENT, LAUNCH_FUSED = 0, 1, 2, 3
+METHOD_DEFAULT, METHOD_ILU_GMRES = 0, 1
 OP_KBC_C, OP_M_F, OP_A_F, OP_KBC_C32 = 0, 1, 2, 3
 
 EXPORT = {"xy": 0, "tri": 1, "bedge": 2, "bkind": 3, "parent": 4, "edges": 5, "rowptr_f": 6, "col_f": 7,
           "slot_f": 8, "colour_f": 9, "rowptr_c": 10, "col_c": 11, "slot_c": 12, "colour_c": 13, "vdir": 14,
           "pdir": 15, "sizes": 16, "S_f": 20, "M_f": 21, "Dx_f": 22, "Dy_f": 23, "K_c": 24, "K_c_bc": 25,
-          "Dx_c": 26, "Dy_c": 27, "m_c": 28, "A_f": 29, "ml_f": 30}
+          "Dx_c": 26, "Dy_c": 27, "m_c": 28, "A_f": 29, "ml_f": 30, "ilu_c": 31}
 
 
 class CGPError(RuntimeError):
@@ -47,7 +48,7 @@ class _Params(C.Structure):
 
 class _SolverOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32), ("inner_tol", C.c_double),
-                ("x0_mode", C.c_int32), ("launch", C.c_int32)]
+                ("x0_mode", C.c_int32), ("launch", C.c_int32), ("method", C.c_int32), ("restart", C.c_int32)]
 
 
 class _StepOpts(C.Structure):
@@ -105,9 +106,12 @@ class SolverOpts:
     inner_tol: float = 1e-4
     x0_mode: int = X0_PREV
     launch: int = LAUNCH_AUTO
+    method: int = METHOD_DEFAULT
+    restart: int = 0
 
     def c(self):
-        return _SolverOpts(self.precision, self.tol, self.max_iter, self.inner_tol, self.x0_mode, self.launch)
+        return _SolverOpts(self.precision, self.tol, self.max_iter, self.inner_tol, self.x0_mode, self.launch,
+                           self.method, self.restart)
 
 
 @dataclass
@@ -149,6 +153,9 @@ def lib():
     L.cgp_prolong.argtypes = [vp, vp, vp]
     L.cgp_correct.argtypes = [vp, C.POINTER(_SolverOpts), vp, vp, vp, vp, C.POINTER(_Stats)]
     L.cgp_spmv.argtypes = [vp, C.c_int32, vp, vp]
+    L.cgp_surface_set.argtypes = [vp, C.c_int32, vp]
+    L.cgp_surface_traction.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_int32)]
+    L.cgp_surface_force.argtypes = [vp, vp, vp, vp]
     L.cgp_mesh_get_tuning.argtypes = [vp, C.POINTER(_Tuning)]
     L.cgp_mesh_set_tuning.argtypes = [vp, C.POINTER(_Tuning)]
     L.cgp_guess_create.argtypes = [vp, C.POINTER(_GuessDesc), C.POINTER(vp)]
@@ -179,7 +186,8 @@ def lib():
                  "cgp_guess_export_norm", "cgp_guess_set_online", "cgp_last_poisson_rhs", "cgp_mesh_get_tuning",
                  "cgp_mesh_set_tuning",
                  "cgp_mesh_create", "cgp_mesh_query", "cgp_mesh_export", "cgp_assemble", "cgp_step", "cgp_momentum",
-                 "cgp_restrict", "cgp_poisson_solve", "cgp_prolong", "cgp_correct", "cgp_spmv", "cgp_batch_create",
+                 "cgp_restrict", "cgp_poisson_solve", "cgp_prolong", "cgp_correct",
+                 "cgp_spmv", "cgp_surface_set", "cgp_surface_traction", "cgp_surface_force", "cgp_batch_create",
                  "cgp_batch_poisson_solve", "cgp_batch_step", "cgp_batch_get_tuning", "cgp_batch_set_tuning",
                  "cgp_batch_autotune"):
         getattr(L, name).restype = C.c_int32
@@ -266,7 +274,7 @@ class Mesh:
         nnzf, nnzc = inf["nnz_f"], inf["nnz_c"]
         for k in ("S_f", "M_f", "Dx_f", "Dy_f", "A_f"):
             shapes[k] = ((nnzf,), np.float64)
-        for k in ("K_c", "K_c_bc", "Dx_c", "Dy_c"):
+        for k in ("K_c", "K_c_bc", "Dx_c", "Dy_c", "ilu_c"):
             shapes[k] = ((nnzc,), np.float64)
         shapes["m_c"] = ((inf["n_c"],), np.float64)
         shapes["ml_f"] = ((inf["n_f"],), np.float64)
@@ -342,6 +350,27 @@ class Mesh:
 
     def last_poisson_rhs(self, dst):
         _check(lib().cgp_last_poisson_rhs(self._h, _ptr(dst)))
+
+    def surface_set(self, coarse_bedge_ids):
+        """Mark the measured surface by coarse boundary-edge indices (drag/lift body or a wall)."""
+        ids = np.ascontiguousarray(coarse_bedge_ids, np.int32)
+        _check(lib().cgp_surface_set(self._h, ids.size, ids.ctypes.data if ids.size else None))
+
+    def surface_traction(self, u, p_fine):
+        """Device tensor [n_edges][8]: midpoint x, y, length, pressure force x, y, viscous force x, y, 0."""
+        import torch
+        n = C.c_int32()
+        _check(lib().cgp_surface_traction(self._h, _ptr(u), _ptr(p_fine), None, C.byref(n)))
+        rows = torch.zeros((n.value, 8), dtype=torch.float64, device=u.device)
+        if n.value:
+            _check(lib().cgp_surface_traction(self._h, _ptr(u), _ptr(p_fine), _ptr(rows), C.byref(n)))
+        return rows
+
+    def surface_force(self, u, p_fine):
+        """Force of the fluid on the surface: [pressure x, pressure y, viscous x, viscous y] (host)."""
+        out = np.zeros(4)
+        _check(lib().cgp_surface_force(self._h, _ptr(u), _ptr(p_fine), out.ctypes.data))
+        return out
 
     def spmv(self, op: int, x, y):
         _check(lib().cgp_spmv(self._h, op, _ptr(x), _ptr(y)))

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <unordered_map>
 
 #include "internal.h"
 #include "kernels.h"
@@ -144,6 +145,10 @@ bool valid_opts(const cgp_solver_opts *o, bool poisson, bool allow_extrap = fals
     if (!(allow_extrap && !poisson && (o->x0_mode == CGP_X0_EXTRAP || o->x0_mode == CGP_X0_PROJECT))) return false;
   }
   if (o->launch < CGP_LAUNCH_AUTO || o->launch > CGP_LAUNCH_FUSED) return false;
+  if (o->method != CGP_METHOD_DEFAULT &&
+      !(poisson && o->method == CGP_METHOD_ILU_GMRES && o->precision == CGP_PREC_FP64))
+    return false;
+  if (o->restart < 0 || o->restart > 200) return false;
   return true;
 }
 
@@ -320,6 +325,14 @@ cgp_status cgp_mesh_export(const cgp_mesh *m, int32_t what, int32_t level, void 
     case CGP_X_MC: dsrc = m->d_mc; need = size_t(m->pc.n) * 8; break;
     case CGP_X_A_F: dsrc = m->d_A; need = m->pf.nnz * 8; break;
     case CGP_X_ML_F: dsrc = m->d_ml; need = size_t(m->pf.n) * 8; break;
+    case CGP_X_ILU_C:
+      if (!m->gm.factored) {
+        set_error("cgp_mesh_export: no ILU(0) factors yet (run a CGP_METHOD_ILU_GMRES solve first)");
+        return CGP_E_STATE;
+      }
+      dsrc = m->gm.d_lu;
+      need = m->pc.nnz * 8;
+      break;
     default: set_error("cgp_mesh_export: unknown selector"); return CGP_E_ARG;
   }
   if (bytes != need) {
@@ -346,6 +359,8 @@ void cgp_mesh_destroy(cgp_mesh *m) {
     (void)hipStreamSynchronize(m->stream);
     for (void *p : m->allocations) (void)hipFree(p);
     for (hipEvent_t e : m->kt_ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : m->step_ev)
+      if (e) (void)hipEventDestroy(e);
     if (m->h_state) (void)hipHostFree(m->h_state);
     if (m->h_scalar) (void)hipHostFree(m->h_scalar);
   }
@@ -370,6 +385,7 @@ cgp_status cgp_assemble(cgp_mesh *m, const cgp_params *p) {
   }
   m->params = *p;
   m->assembled = false;
+  m->gm.factored = false;  // the ILU(0) factors belong to the previous operators
   cgp_status s = drv_assemble(m);
   if (s == CGP_OK) m->assembled = true;
   return s;
@@ -450,10 +466,11 @@ cgp_status cgp_step(cgp_mesh *m, const cgp_step_opts *o, const double *g, const 
   cgp_stats local{};
   cgp_stats *S = st ? st : &local;
   *S = cgp_stats{};
-  hipEvent_t ev[7] = {};
+  hipEvent_t *ev = m->step_ev;  // created at the first timed step, kept until the mesh is destroyed
   const bool timing = o->timing != 0;
   if (timing) {
-    for (auto &e : ev) CGP_HIP(hipEventCreate(&e));
+    if (!ev[0])
+      for (int k = 0; k < 7; k++) CGP_HIP(hipEventCreate(&ev[k]));
     CGP_HIP(hipEventRecord(ev[0], m->stream));
   }
   cgp_status worst = CGP_OK;
@@ -534,11 +551,94 @@ cgp_status cgp_step(cgp_mesh *m, const cgp_step_opts *o, const double *g, const 
   if (s) g_err = msg;
 out:
   m->kt_on = false;
-  if (timing)
-    for (auto &e : ev)
-      if (e) (void)hipEventDestroy(e);
   if (st) CGP_HIP(hipStreamSynchronize(m->stream));
   return s;
+}
+
+cgp_status cgp_surface_set(cgp_mesh *m, int32_t count, const int32_t *ids) {
+  if (!m || count < 0 || (count > 0 && !ids)) {
+    set_error("cgp_surface_set: invalid argument");
+    return CGP_E_ARG;
+  }
+  if (m->host_only) {
+    set_error("cgp_surface_set: mesh was created host-only");
+    return CGP_E_STATE;
+  }
+  const HostLevel &C = m->lev[0], &F = m->lev[m->levels];
+  std::vector<char> mark(C.nb, 0);
+  for (int i = 0; i < count; i++) {
+    if (ids[i] < 0 || ids[i] >= C.nb) {
+      set_error("cgp_surface_set: boundary edge index " + std::to_string(ids[i]) + " out of range");
+      return CGP_E_ARG;
+    }
+    mark[ids[i]] = 1;
+  }
+  // fine boundary edge j descends from coarse edge j >> l (each subdivision splits edge k into 2k, 2k+1)
+  std::unordered_map<long long, int> slot;  // marked fine edge (min, max) -> row
+  std::vector<int> rows;
+  for (int j = 0; j < F.nb; j++) {
+    if (!mark[j >> m->levels]) continue;
+    const int a = F.bedge[2 * j], b = F.bedge[2 * j + 1];
+    slot[(long long)std::min(a, b) << 32 | std::max(a, b)] = int(rows.size() / 4);
+    rows.insert(rows.end(), {a, b, -1, 0});
+  }
+  for (int t = 0; t < F.t; t++)
+    for (int k = 0; k < 3; k++) {
+      const int a = F.tri[3 * t + k], b = F.tri[3 * t + (k + 1) % 3];
+      auto it = slot.find((long long)std::min(a, b) << 32 | std::max(a, b));
+      if (it != slot.end()) rows[4 * it->second + 2] = F.tri[3 * t + (k + 2) % 3];
+    }
+  const int ne = int(rows.size() / 4);
+  for (int i = 0; i < ne; i++)
+    if (rows[4 * i + 2] < 0) {
+      set_error("cgp_surface_set: a marked boundary edge lies on no triangle");
+      return CGP_E_MESH;
+    }
+  if (ne > m->n_surf_cap) {
+    void *p = nullptr;
+    if (hipMalloc(&p, rows.size() * sizeof(int)) != hipSuccess) {
+      set_error("cgp_surface_set: out of device memory");
+      return CGP_E_OOM;
+    }
+    m->allocations.push_back(p);
+    m->d_surf = static_cast<int *>(p);
+    m->n_surf_cap = ne;
+  }
+  if (ne) CGP_HIP(hipMemcpy(m->d_surf, rows.data(), rows.size() * sizeof(int), hipMemcpyHostToDevice));
+  m->n_surf = ne;
+  return CGP_OK;
+}
+
+cgp_status cgp_surface_traction(cgp_mesh *m, const double *u, const double *pf, double *rows, int32_t *n_rows) {
+  TRY(ready(m));
+  if (!u || !pf || !n_rows) {
+    set_error("cgp_surface_traction: null argument");
+    return CGP_E_ARG;
+  }
+  *n_rows = m->n_surf;
+  if (rows && m->n_surf) {
+    launch_surface(m, u, pf, rows);
+    CGP_HIP(hipGetLastError());
+  }
+  return CGP_OK;
+}
+
+cgp_status cgp_surface_force(cgp_mesh *m, const double *u, const double *pf, double *out) {
+  TRY(ready(m));
+  if (!u || !pf || !out) {
+    set_error("cgp_surface_force: null argument");
+    return CGP_E_ARG;
+  }
+  if (m->n_surf == 0) {
+    for (int k = 0; k < 4; k++) out[k] = 0.0;
+    return CGP_OK;
+  }
+  launch_surface(m, u, pf, nullptr);
+  CGP_HIP(hipGetLastError());
+  CGP_HIP(hipMemcpyAsync(m->h_scalar, m->d_scalar, 4 * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+  CGP_HIP(hipStreamSynchronize(m->stream));
+  for (int k = 0; k < 4; k++) out[k] = m->h_scalar[k];
+  return CGP_OK;
 }
 
 cgp_status cgp_mesh_get_tuning(const cgp_mesh *m, cgp_tuning *out) {

@@ -800,8 +800,9 @@ cgp_status cgp_batch_poisson_solve(cgp_batch *B, const double *const *rhs, doubl
                                    const cgp_solver_opts *o, cgp_stats *stats) {
   if (!B || !rhs || !x || !o || !(o->tol > 0.0) || o->max_iter < 1 ||
       (o->precision != CGP_PREC_FP64 && o->precision != CGP_PREC_FP32_IR) || o->x0_mode < CGP_X0_ZERO ||
-      o->x0_mode > CGP_X0_POD_GALERKIN) {
-    set_error("cgp_batch_poisson_solve: bad argument (FP64 or FP32_IR; x0 zero, previous, learned or POD-Galerkin)");
+      o->x0_mode > CGP_X0_POD_GALERKIN || o->method != CGP_METHOD_DEFAULT) {
+    set_error("cgp_batch_poisson_solve: bad argument (Jacobi-PCG in FP64 or FP32_IR; x0 zero, previous, learned or "
+              "POD-Galerkin)");
     return CGP_E_ARG;
   }
   for (int i = 0; i < B->ninst; i++)

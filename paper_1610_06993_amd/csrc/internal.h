@@ -76,6 +76,16 @@ struct KrylovState {
   int status;                       // 0, or CGP_E_NONFINITE / CGP_E_NOCONV / CGP_E_DEVICE
 };
 
+// ILU(0)-GMRES(m) of the coarse Poisson solve: level schedule (pattern only), factors, Krylov basis
+struct GmresState {
+  bool ready = false;              // levels and buffers set up
+  bool factored = false;           // d_lu holds ILU(0) of the current Kbar (cleared by cgp_assemble)
+  int cap = 0;                     // restart length the basis holds
+  std::vector<int> lptr, uptr;     // level pointers of the forward / backward substitution
+  int *d_diag = nullptr, *d_lrows = nullptr, *d_urows = nullptr;
+  double *d_lu = nullptr, *d_V = nullptr, *d_work = nullptr, *d_part = nullptr, *d_h = nullptr;
+};
+
 struct ReduceScratch {
   double *partials = nullptr;   // 4 regions of [8][red_grid] block partials
 };
@@ -131,9 +141,13 @@ struct cgp_mesh {
   double *d_pfn = nullptr;        // incremental pressure modes: prolonged P^n [n_f], allocated on first use
   double *d_phi = nullptr;        //   the last pressure increment [n_c] (its solve's initial guess)
   double *d_phif = nullptr;       //   the prolonged increment [n_f]
+  int n_surf = 0;                 // fine boundary edges of the marked surface (cgp_surface_set)
+  int *d_surf = nullptr;          // their {a, b, third vertex, 0} (int4)
+  int n_surf_cap = 0;             // rows d_surf holds
   cgp::KrylovState *d_state = nullptr;   // 4 solver states
   cgp::KrylovState *h_state = nullptr;   // pinned mirror
   cgp::ReduceScratch red;
+  cgp::GmresState gm;
   int cu_count = 0;
   int red_grid = 0;               // blocks of every reducing kernel (one partial per block)
   int coop_blocks = 0;            // blocks of the persistent PCG (0: not set up)
@@ -150,6 +164,7 @@ struct cgp_mesh {
   // kind; the FP32 inner solves keep one per refinement step, whose lengths differ
   int mom_chunk = 4, p_chunk = 32, p32_chunk[4] = {16, 16, 16, 16}, mass_chunk = 8;
   // HIP-event timing of every launch of the Poisson SpMV kernel (cgp_step_opts.timing == 2)
+  hipEvent_t step_ev[7] = {};      // per-phase events of cgp_step (timing >= 1)
   bool kt_on = false;
   std::vector<hipEvent_t> kt_ev;   // event pairs
   std::vector<int> kt_iter;        // Krylov iteration of each pair

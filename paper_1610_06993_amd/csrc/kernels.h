@@ -49,6 +49,9 @@ void dispatch_L(int L, F &&f) {
   }
 }
 
+// ILU(0)-GMRES(m) of the coarse Poisson equation (gmres.hip): b with boundary conditions, x the guess
+cgp_status gmres_solve(cgp_mesh *m, const double *b, double *x, const cgp_solver_opts *o, KrylovState *fin);
+
 // drivers (implemented in kernels.hip); all enqueue on mesh->stream
 cgp_status drv_assemble(cgp_mesh *m);
 // pn: prolonged previous pressure P_f^n (incremental pressure modes: the right-hand side gets -dt G P_f^n) or NULL
@@ -64,6 +67,8 @@ cgp_status drv_spmv(cgp_mesh *m, int op, const void *x, void *y);
 // launchers of kernels.hip used by the Krylov drivers (enqueue only)
 void launch_conv_assembly(cgp_mesh *m, const double *u);  // d_A = S + dt N(u), every entry
 void launch_mom_rhs(cgp_mesh *m, const double *g, const double *u, const double *f, const double *pn, double *rhs);
+// forces on the marked surface: per-edge rows (or NULL) and the four totals into d_scalar[0..3]
+void launch_surface(cgp_mesh *m, const double *u, const double *p, double *rows);
 // incremental pressure modes: pc <- pc + phi (- mu dt/rho ... rotational term), pressure-Dirichlet nodes 0
 void launch_pressure_update(cgp_mesh *m, double *pc, const double *phi, const double *bc);
 void launch_correct_rhs(cgp_mesh *m, const double *g, const double *ut, const double *pf, double *rhs);

@@ -484,6 +484,58 @@ __global__ void k_pressure_update(int n, const unsigned char *__restrict__ pdir,
   pc[i] = pdir[i] ? 0.0 : pc[i] + phi[i] + rot * bc[i] / mc[i];
 }
 
+// Force of the fluid on a marked boundary surface, one fine boundary edge e = (a, b) per thread, with
+// c the third vertex of its triangle: n the unit normal of e towards c (into the fluid), the stress
+// -p I + mu (grad u + grad u^T) of the P1 fields; the edge carries -|e| (p_a + p_b)/2 n (pressure) and
+// |e| mu (grad u + grad u^T) n (viscous).  One block: per-edge rows (x, y, |e|, pressure x, y,
+// viscous x, y, 0) when `rows` is set, and the four totals summed in a fixed order into `tot`.
+__global__ void __launch_bounds__(1024) k_surface(int ne, const int4 *__restrict__ e, const double2 *__restrict__ xy,
+                                                  const double2 *__restrict__ u, const double *__restrict__ p,
+                                                  double mu, double *__restrict__ rows, double *__restrict__ tot) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < ne; i += blockDim.x) {
+    const int4 v = e[i];
+    const double2 xa = xy[v.x], xb = xy[v.y], xc = xy[v.z];
+    const double ex = xb.x - xa.x, ey = xb.y - xa.y;
+    const double len = sqrt(ex * ex + ey * ey);
+    double nx = -ey / len, ny = ex / len;
+    if (nx * (xc.x - xa.x) + ny * (xc.y - xa.y) < 0.0) {
+      nx = -nx;
+      ny = -ny;
+    }
+    // P1 gradient on (a, b, c): grad phi_k = (y_j - y_l, x_l - x_j) / (2A) with (k, j, l) cyclic
+    const double a2 = (xb.x - xa.x) * (xc.y - xa.y) - (xc.x - xa.x) * (xb.y - xa.y);
+    const double2 ua = u[v.x], ub = u[v.y], uc = u[v.z];
+    const double ga_x = (xb.y - xc.y) / a2, ga_y = (xc.x - xb.x) / a2;
+    const double gb_x = (xc.y - xa.y) / a2, gb_y = (xa.x - xc.x) / a2;
+    const double gc_x = (xa.y - xb.y) / a2, gc_y = (xb.x - xa.x) / a2;
+    const double uxx = ua.x * ga_x + ub.x * gb_x + uc.x * gc_x, uxy = ua.x * ga_y + ub.x * gb_y + uc.x * gc_y;
+    const double uyx = ua.y * ga_x + ub.y * gb_x + uc.y * gc_x, uyy = ua.y * ga_y + ub.y * gb_y + uc.y * gc_y;
+    const double pm = 0.5 * (p[v.x] + p[v.y]);
+    const double sxx = 2.0 * uxx, syy = 2.0 * uyy, sxy = uxy + uyx;
+    const double fpx = -len * pm * nx, fpy = -len * pm * ny;
+    const double fvx = len * mu * (sxx * nx + sxy * ny), fvy = len * mu * (sxy * nx + syy * ny);
+    acc[0] += fpx;
+    acc[1] += fpy;
+    acc[2] += fvx;
+    acc[3] += fvy;
+    if (rows) {
+      double *o = rows + 8 * (size_t)i;
+      o[0] = 0.5 * (xa.x + xb.x);
+      o[1] = 0.5 * (xa.y + xb.y);
+      o[2] = len;
+      o[3] = fpx;
+      o[4] = fpy;
+      o[5] = fvx;
+      o[6] = fvy;
+      o[7] = 0.0;
+    }
+  }
+  double t[4];
+  block_sum<4>(acc, t);
+  if (threadIdx.x < 4) tot[threadIdx.x] = t[threadIdx.x];
+}
+
 __global__ void k_set_dirichlet(int n, const unsigned char *__restrict__ vdir, const double2 *__restrict__ g,
                                 double2 *__restrict__ u) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -514,6 +566,11 @@ void launch_mom_rhs(cgp_mesh *m, const double *g, const double *u, const double 
                      m->d_col_f, m->d_vdir,
                      m->d_M, m->d_A, (const double2 *)g, (const double2 *)u, (const double2 *)f,
                      (const double2 *)m->d_D, pn, m->params.rho, m->params.dt, (double2 *)rhs, m->d_dinvA);
+}
+
+void launch_surface(cgp_mesh *m, const double *u, const double *p, double *rows) {
+  hipLaunchKernelGGL(k_surface, dim3(1), dim3(1024), 0, m->stream, m->n_surf, (const int4 *)m->d_surf,
+                     (const double2 *)m->d_xy_f, (const double2 *)u, p, m->params.mu, rows, m->d_scalar);
 }
 
 void launch_pressure_update(cgp_mesh *m, double *pc, const double *phi, const double *bc) {

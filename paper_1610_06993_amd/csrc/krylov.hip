@@ -1622,7 +1622,12 @@ cgp_status drv_poisson(cgp_mesh *m, const double *b_in, double *x, const cgp_sol
   KrylovState fin{};
   cgp_status rs = CGP_OK;
   int total_iters = 0, outer = 1;
-  if (o->precision == CGP_PREC_FP64) {
+  if (o->method == CGP_METHOD_ILU_GMRES) {
+    cgp_status gs = gmres_solve(m, b, x, o, &fin);
+    if (gs) return gs;
+    rs = status_of(fin, SLOT_P);
+    total_iters = fin.iters;
+  } else if (o->precision == CGP_PREC_FP64) {
     if (persistent) {
       void *w[5] = {m->d_wc[1], m->d_wc[2], m->d_wc[3], m->d_wc[4], m->d_wc[5]};
       KrylovState *so = m->d_state + SLOT_P;

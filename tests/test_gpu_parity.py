@@ -317,6 +317,16 @@ def test_incremental_pressure_steps(env, which, restrict_mode, pressure_mode):
     _run_steps(env, case, 1, 8, opts, restrict_mode, 0, pressure_mode=pressure_mode, pc0=pc0)
 
 
+@pytest.mark.parametrize("which,restrict_mode", [("tg", 0), ("tg", 1), ("cyl", 0), ("cyl", 1)])
+def test_three_coarsening_levels(env, which, restrict_mode):
+    """l = 3 (the paper's deepest coarsening, Tables 1, 4, 5): chained prolongation and restriction over
+    three levels, every step against the oracle."""
+    torch, cgp, oracle = env
+    case = W.case_tg(6, levels=3) if which == "tg" else W.case_cylinder(700, seed=5, levels=3)
+    _say("three levels:", which, case.mesh.n_tris, "coarse triangles, restriction", restrict_mode)
+    _run_steps(env, case, 3, 5, tight_opts(cgp), restrict_mode, 0)
+
+
 @pytest.mark.parametrize("launch", [1, 2, 3])
 def test_cylinder_steps(env, launch):
     torch, cgp, oracle = env

@@ -114,3 +114,39 @@ def test_persistent_grid_and_spin_limits_validated(cgp):
     g.set_tuning(pcg_grid=256, pcg_spin_log2=1)
     t = g.get_tuning()
     assert t["pcg_grid"] == 256 and t["pcg_spin_log2"] == 1
+
+
+def test_paper_prolongation_loop_count_through_the_library(cgp):
+    """Section 3.2 / Table 5: the 102400:1600 backward-step resolution needs 68659 prolongation loops,
+    the nodes of the two intermediate and the finest meshes.  A step-shaped channel of 800 unit cells
+    (94 x 10 cells without a 20 x 7 corner: 1600 triangles, 905 nodes, like the paper's coarse mesh)
+    subdivided three times by the library gives the same counts."""
+    nx, ny, cx, cy = 94, 10, 20, 7
+    keep = np.ones((ny, nx), bool)
+    keep[:cy, :cx] = False  # the step's corner below the inlet section
+    ids = -np.ones((ny + 1, nx + 1), np.int64)
+    used = np.zeros_like(ids, bool)
+    for j in range(ny):
+        for i in range(nx):
+            if keep[j, i]:
+                used[j:j + 2, i:i + 2] = True
+    ids[used] = np.arange(used.sum())
+    J, I = np.nonzero(used)
+    xy = np.stack([I, J], 1).astype(np.float64)[np.argsort(ids[used])]
+    tris = []
+    for j in range(ny):
+        for i in range(nx):
+            if keep[j, i]:
+                a, b, c, d = ids[j, i], ids[j, i + 1], ids[j + 1, i + 1], ids[j + 1, i]
+                tris += [(a, b, c), (a, c, d)]
+    tri = np.array(tris, np.int32)
+    e = np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]])
+    key = np.sort(e, 1)
+    u, inv, cnt = np.unique(key[:, 0] * 100000 + key[:, 1], return_inverse=True, return_counts=True)
+    bedge = e[cnt[inv] == 1].astype(np.int32)
+    mesh = W.CoarseMesh(xy, tri, bedge, np.ones(len(bedge), np.int32))
+    assert mesh.n_nodes == 905 and mesh.n_tris == 1600
+    g = cgp.Mesh(mesh, 3, host_only=True)
+    sizes = [g.sizes(k) for k in range(4)]
+    assert sizes[3]["t"] == 102400
+    assert sum(s["n"] for s in sizes[1:]) == 68659
