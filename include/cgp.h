@@ -372,6 +372,17 @@ cgp_status cgp_mesh_set_tuning(cgp_mesh *mesh, const cgp_tuning *tuning);
 /* y = op x on device vectors (layouts listed with CGP_OP_*). */
 cgp_status cgp_spmv(cgp_mesh *mesh, int32_t op, const void *x, void *y);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): cgp_poisson_solve without any allocation.  Same arguments and
+ * results as cgp_poisson_solve (FP64 fused PCG; x0_mode CGP_X0_ZERO or CGP_X0_PREV; launch AUTO or
+ * FUSED; anything else is CGP_E_ARG).  The solve's working memory (right-hand side with boundary
+ * conditions, search direction, node records, partial sums, solver state) is one fixed device array of
+ * about 21 MB per GPU, held from the first cgp_mesh_create on that GPU until the process ends, instead
+ * of the mesh's buffers; coarse systems above 262144 rows are CGP_E_ARG.  Every call on one GPU uses
+ * the same array: calls that overlap on one GPU (other threads, other streams) race and must not be
+ * issued.  The mesh's attached learned guess is not used or updated.  Synchronises the mesh stream. */
+cgp_status cgp_poisson_solve_noalloc(cgp_mesh *mesh, const double *b, double *x, const cgp_solver_opts *opts,
+                                     cgp_stats *stats);
 
 #ifdef __cplusplus
 }

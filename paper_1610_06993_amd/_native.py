@@ -150,6 +150,7 @@ def lib():
     L.cgp_momentum.argtypes = [vp, C.POINTER(_SolverOpts), vp, vp, vp, vp, C.POINTER(_Stats)]
     L.cgp_restrict.argtypes = [vp, vp, vp]
     L.cgp_poisson_solve.argtypes = [vp, vp, vp, C.POINTER(_SolverOpts), C.POINTER(_Stats)]
+    L.cgp_poisson_solve_noalloc.argtypes = [vp, vp, vp, C.POINTER(_SolverOpts), C.POINTER(_Stats)]
     L.cgp_prolong.argtypes = [vp, vp, vp]
     L.cgp_correct.argtypes = [vp, C.POINTER(_SolverOpts), vp, vp, vp, vp, C.POINTER(_Stats)]
     L.cgp_spmv.argtypes = [vp, C.c_int32, vp, vp]
@@ -186,7 +187,7 @@ def lib():
                  "cgp_guess_export_norm", "cgp_guess_set_online", "cgp_last_poisson_rhs", "cgp_mesh_get_tuning",
                  "cgp_mesh_set_tuning",
                  "cgp_mesh_create", "cgp_mesh_query", "cgp_mesh_export", "cgp_assemble", "cgp_step", "cgp_momentum",
-                 "cgp_restrict", "cgp_poisson_solve", "cgp_prolong", "cgp_correct",
+                 "cgp_restrict", "cgp_poisson_solve", "cgp_poisson_solve_noalloc", "cgp_prolong", "cgp_correct",
                  "cgp_spmv", "cgp_surface_set", "cgp_surface_traction", "cgp_surface_force", "cgp_batch_create",
                  "cgp_batch_poisson_solve", "cgp_batch_step", "cgp_batch_get_tuning", "cgp_batch_set_tuning",
                  "cgp_batch_autotune"):
@@ -315,6 +316,16 @@ class Mesh:
         o = (opts or SolverOpts()).c()
         st = _Stats()
         s = lib().cgp_poisson_solve(self._h, _ptr(b), _ptr(x), C.byref(o), C.byref(st))
+        _check(s, (OK, E_NOCONV) if allow_noconv else (OK,))
+        d = st.asdict()
+        d["status"] = s
+        return d
+
+    def poisson_solve_noalloc(self, b, x, opts: SolverOpts | None = None, allow_noconv=False):
+        """cgp_poisson_solve with its working memory in the library's fixed device array (no allocation)."""
+        o = (opts or SolverOpts()).c()
+        st = _Stats()
+        s = lib().cgp_poisson_solve_noalloc(self._h, _ptr(b), _ptr(x), C.byref(o), C.byref(st))
         _check(s, (OK, E_NOCONV) if allow_noconv else (OK,))
         d = st.asdict()
         d["status"] = s

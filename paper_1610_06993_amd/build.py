@@ -10,7 +10,7 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 SRC = PKG / "csrc"
 OUT = PKG / "libcgp.so"
-SOURCES = ["kernels.hip", "krylov.hip", "persistent.hip", "learn.hip", "batch.hip", "gmres.hip", "api.cpp",
+SOURCES = ["kernels.hip", "krylov.hip", "persistent.hip", "learn.hip", "batch.hip", "gmres.hip", "noalloc.hip", "api.cpp",
            "topology.cpp"]
 ARCH = os.environ.get("CGP_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", f"-I{ROOT / 'include'}",

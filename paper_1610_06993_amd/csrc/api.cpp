@@ -51,6 +51,8 @@ cgp_status build_device(cgp_mesh *m) {
   int dev = 0;
   CGP_HIP(hipGetDevice(&dev));
   CGP_HIP(hipDeviceGetAttribute(&m->cu_count, hipDeviceAttributeMultiprocessorCount, dev));
+  m->device = dev;
+  TRY(noalloc_setup(dev));
   const HostLevel &F = m->lev[m->levels], &C = m->lev[0];
   // element arrays permuted by colour (contiguous range per colour)
   auto permute = [](const std::vector<int> &a, int w, const std::vector<int> &perm) {

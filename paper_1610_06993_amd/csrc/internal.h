@@ -149,6 +149,7 @@ struct cgp_mesh {
   cgp::ReduceScratch red;
   cgp::GmresState gm;
   int cu_count = 0;
+  int device = -1;                // HIP device the mesh's buffers live on
   int red_grid = 0;               // blocks of every reducing kernel (one partial per block)
   int coop_blocks = 0;            // blocks of the persistent PCG (0: not set up)
   int coop_max = 0;               // co-resident blocks reported by the runtime

@@ -49,6 +49,9 @@ void dispatch_L(int L, F &&f) {
   }
 }
 
+// with `device` current: the device address of the allocation-free solve's array (once per device)
+cgp_status noalloc_setup(int device);
+
 // ILU(0)-GMRES(m) of the coarse Poisson equation (gmres.hip): b with boundary conditions, x the guess
 cgp_status gmres_solve(cgp_mesh *m, const double *b, double *x, const cgp_solver_opts *o, KrylovState *fin);
 
