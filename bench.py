@@ -60,10 +60,15 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0))
 
 
+# sources that define the Poisson iteration kernels and what they compile against: a change to any of
+# them invalidates the HBM counters recorded for those kernels
+KERNEL_SOURCES = ("krylov.hip", "devutil.h", "internal.h", "kernels.h")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for p in sorted((ROOT / "paper_1610_06993_amd" / "csrc").glob("*")):
-        h.update(p.read_bytes())
+    for name in KERNEL_SOURCES:
+        h.update((ROOT / "paper_1610_06993_amd" / "csrc" / name).read_bytes())
     return h.hexdigest()[:16]
 
 
@@ -536,6 +541,44 @@ def run_steady(args, log):
     return dict(window=args.window, plain_steps_first=74, blocks=out)
 
 
+def run_batch_kernel(args, log):
+    """Only the batched PCG iteration with every instance active (the sweep's 64 instances, 64 iterations
+    from a random right-hand side, three times): the clean dispatches HBM counters are read on."""
+    import numpy as np
+    import torch
+
+    import paper_1610_06993_amd as cgp
+    import workloads as W
+    from paper_1610_06993_amd import SolverOpts
+    cases = W.batch_sweep(args.batch)
+    meshes = []
+    for c in cases:
+        m = cgp.Mesh(c.mesh, 1)
+        m.assemble(c.rho, c.mu, c.dt)
+        meshes.append(m)
+    rows = sum(m.info["n_c"] for m in meshes)
+    nnz = sum(m.info["nnz_c"] for m in meshes)
+    batch = cgp.Batch(meshes)
+    TUNING_CACHE.parent.mkdir(exist_ok=True)
+    tuned = batch.autotune(TUNING_CACHE)
+    rng = np.random.default_rng(0)
+    bs = [torch.from_numpy(rng.normal(size=m.info["n_c"])).cuda() for m in meshes]
+    xs = [torch.zeros_like(b) for b in bs]
+    out = []
+    for rep in range(3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        batch.poisson_solve(bs, xs, SolverOpts(tol=1e-300, max_iter=64, x0_mode=0), allow_noconv=True)
+        torch.cuda.synchronize()
+        out.append(1e6 * (time.perf_counter() - t) / 64)
+    kbytes = 12 * nnz + 92 * rows
+    log(f"batched PCG kernel, all {len(meshes)} instances active: {out} us per iteration, {kbytes / 1e6:.0f} MB, "
+        f"tuning {tuned}")
+    batch.close()
+    return dict(rows=rows, nnz=nnz, bytes_per_iteration=kbytes, us_per_iteration=[round(v, 2) for v in out],
+                tuning=tuned)
+
+
 def run_batch(args, log):
     """Config-4-style sweep: independent cylinder instances of uneven size stepped together."""
     import numpy as np
@@ -712,6 +755,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--batch-window", type=int, default=64, help="online POD window per batched instance (at most 64)")
     ap.add_argument("--only-batch", action="store_true", help="run only the batched sweep")
+    ap.add_argument("--only-batch-kernel", action="store_true",
+                    help="run only the batched PCG iteration with every instance active (for HBM counters)")
     ap.add_argument("--levels-sweep", type=int, default=1, help="run the l = 0..3 comparison on one fine mesh (0: skip)")
     ap.add_argument("--bfs", type=int, default=1, help="run the backward-facing step at l = 1 and l = 0 (0: skip)")
     ap.add_argument("--only-levels", action="store_true", help="run only the l = 0..3 comparison")
@@ -768,6 +813,9 @@ def main():
     X0 = cgp._native
     if args.only_batch:
         print(json.dumps({"batch": run_batch(args, log)}), flush=True)
+        return
+    if args.only_batch_kernel:
+        print(json.dumps({"batch_kernel": run_batch_kernel(args, log)}), flush=True)
         return
     if args.only_spmv:
         print(json.dumps({"spmv_sweep": run_spmv_sweep(args, log)}), flush=True)

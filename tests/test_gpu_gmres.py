@@ -98,7 +98,11 @@ def test_ilu_gmres_refactorised_after_assembly_and_in_a_step(env):
     pf = torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda")
     pc = torch.zeros(n, dtype=torch.float64, device="cuda")
     s = cgp.SolverOpts(tol=1e-13, max_iter=100000)
-    opts = cgp.StepOpts(momentum=s, poisson=cgp.SolverOpts(tol=1e-13, max_iter=20000, method=X0.METHOD_ILU_GMRES,
+    # GMRES stops on the true residual ||b - A x||, which on this right-hand side cannot go much below
+    # 1e-16 ||A|| ||x|| / ||b|| ~ 1e-11 (the ratio is about 1.3e5 at the first step: restarted GMRES
+    # stagnates at a true relative residual of 3e-13); 1e-12 is reached and puts the pressure within
+    # 2e-13 of the oracle's PCG solution
+    opts = cgp.StepOpts(momentum=s, poisson=cgp.SolverOpts(tol=1e-12, max_iter=20000, method=X0.METHOD_ILU_GMRES,
                                                            restart=60), mass=s)
     ur, pcr = u0.copy(), None
     for k in range(3):
