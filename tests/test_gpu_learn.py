@@ -122,6 +122,45 @@ def test_pod_basis_against_numpy(env, small_mesh):
     net.close()
 
 
+def test_pod_basis_against_oracle(env, small_mesh):
+    """cgp_guess_build_pod against the oracle's POD (snapshot Gram in FP64, cyclic Jacobi eigensolver):
+    eigenvalues and the M_c-orthogonal projector onto the basis, on snapshots of a real run's coarse
+    pressures as well as on a synthetic low-rank set."""
+    torch, cgp, oracle = env
+    case, g, o = small_mesh
+    n = g.info["n_c"]
+    mc = o.values("m_c")
+    # pressures of ten CGP steps from the oracle, plus a synthetic rank-24 set
+    xy = o.export("xy")
+    u = case.initial(xy, o.export("vdir"))
+    pc, ps = None, []
+    for k in range(10):
+        u, _, pc, code, _ = o.step(case.dirichlet(xy, (k + 1) * case.dt), u, pc, tol_mom=1e-12, tol_p=1e-12,
+                                   tol_mass=1e-12)
+        assert code == 0
+        ps.append(pc.copy())
+    sets = {"pressures": (np.array(ps), 4), "synthetic": (_snapshots(np.random.default_rng(5), n, 80, 24, mc), 16)}
+    for name, (snaps, nm) in sets.items():
+        _say(f"POD against the oracle: {name}, S={snaps.shape[0]}, modes={nm}")
+        net = cgp.Guess(g, n_modes=nm, hidden=32, seed=3)
+        energy = net.build_pod(dev(torch, snaps))
+        Phi = net.basis()
+        phi_o, e_o, rank = oracle.pod(snaps, mc, nm + 1)
+        assert rank >= nm + 1
+        phi_o, gap = phi_o[:, :nm], e_o[nm - 1] - e_o[nm]
+        e_o = e_o[:nm]
+        e_e = rel(energy, e_o)
+        P1 = Phi @ (Phi.T * mc)
+        P2 = phi_o @ (phi_o.T * mc)
+        e_p = np.linalg.norm(P1 - P2) / np.linalg.norm(P2)
+        # the spanned subspace moves by about (rounding of the Gram matrix) / (gap after the last mode kept):
+        # the Gram entries are sums of n products, rounded to well under 1e-12 of the largest eigenvalue
+        bar_p = max(1e-8, 1e-12 * e_o[0] / gap)
+        _say(f"  eigenvalues {e_e:.1e}, projector {e_p:.1e} (bar {bar_p:.1e})")
+        assert e_e <= 1e-10 and e_p <= bar_p
+        net.close()
+
+
 def _csr_matvec(o, x):
     import oracle
     return oracle.spmv(o.export("rowptr_c"), o.export("col_c"), o.values("K_c_bc"), x)

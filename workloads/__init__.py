@@ -341,10 +341,26 @@ def batch_sweep(n: int = 64, lo: int = 16_000, hi: int = 250_000, seed: int = 4,
     """Independent cylinder-flow instances for a batched run: coarse sizes log-uniform in [lo, hi]
     triangles, Re uniform in [60, 160] (mu = 0.1 / Re with rho = 1, mean inlet speed 1, D = 0.1), mesh
     seeds 1000 + i."""
+    return [batch_instance(i, n, lo, hi, seed, levels) for i in range(n)]
+
+
+def batch_sweep_sizes(n: int = 64, lo: int = 16_000, hi: int = 250_000, seed: int = 4) -> list:
+    """Target coarse triangle counts and Reynolds numbers of batch_sweep's instances, without building
+    the meshes."""
     u = uniform01(seed, 0, 2 * n).reshape(n, 2)
-    out = []
-    for i in range(n):
-        tris = int(round(math.exp(math.log(lo) + u[i, 0] * (math.log(hi) - math.log(lo)))))
-        re = 60.0 + 100.0 * u[i, 1]
-        out.append(case_cylinder(tris, seed=1000 + i, levels=levels, mu=0.1 / re))
-    return out
+    return [(int(round(math.exp(math.log(lo) + u[i, 0] * (math.log(hi) - math.log(lo))))), 60.0 + 100.0 * u[i, 1])
+            for i in range(n)]
+
+
+def batch_instance(i: int, n: int = 64, lo: int = 16_000, hi: int = 250_000, seed: int = 4, levels: int = 1) -> Case:
+    """Instance i of batch_sweep(n, lo, hi, seed, levels) alone."""
+    tris, re = batch_sweep_sizes(n, lo, hi, seed)[i]
+    return case_cylinder(tris, seed=1000 + i, levels=levels, mu=0.1 / re)
+
+
+def batch_deciles(n: int = 64, lo: int = 16_000, hi: int = 250_000, seed: int = 4) -> list:
+    """Indices of one batch_sweep instance per size decile: the instance at the middle of each tenth of
+    the instances sorted by size."""
+    sizes = batch_sweep_sizes(n, lo, hi, seed)
+    order = sorted(range(n), key=lambda i: sizes[i][0])
+    return [order[min(n - 1, int((d + 0.5) * n / 10))] for d in range(10)]
