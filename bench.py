@@ -388,11 +388,14 @@ def run_functionals(args, log):
 
 def run_learned(args, log):
     """The learned initial guess at the shape of the configuration it is specified for: pressure
-    snapshots from plain CGP runs of the cylinder at Re drawn uniformly in [60, 160] (seeded), 64 POD
-    modes, MLPs 64-256-256-64 (GELU, BF16 on the matrix cores) trained on the GPU with Adam (lr 1e-3,
-    batch 256); Poisson iterations and solve times on held-out Re from x0 = 0, the previous pressure,
-    the POD-Galerkin correction, the absolute network and the incremental network (whose basis spans
-    the pressure increments), in FP64 and with FP32 inner solves."""
+    snapshots from CGP runs of the cylinder at Re drawn uniformly in [60, 160] (seeded), every
+    `learn_stride`-th step after `learn_settle` steps, 64 POD modes, MLPs 64-256-256-64 (GELU, BF16 on
+    the matrix cores) trained on the GPU with Adam (lr 1e-3, batch 256); Poisson iterations and solve
+    times on held-out Re from x0 = 0, the previous pressure, the POD-Galerkin correction, the absolute
+    network and the incremental network (whose basis spans the pressure increments), in FP64 and with
+    FP32 inner solves.  The recording runs start each Poisson solve from an online POD basis of the
+    run's last 64 solutions (the solutions are the method's to the solver tolerance; only the start
+    differs), so that 2000-step runs fit the time budget."""
     import numpy as np
     import torch
 
@@ -401,6 +404,7 @@ def run_learned(args, log):
     from paper_1610_06993_amd import SolverOpts, StepOpts
     X0 = cgp._native
     n_re, n_test, settle, rec = args.learn_re, args.learn_test_re, args.learn_settle, args.learn_record
+    stride, rmode = args.learn_stride, args.learn_restrict
     res = 60.0 + 100.0 * W.uniform01(7, 0, n_re)
     case = W.case_cylinder(args.target_tris)
     mesh = cgp.Mesh(case.mesh, 1)
@@ -411,23 +415,37 @@ def run_learned(args, log):
     B = torch.zeros((S, n), dtype=torch.float64, device="cuda")
     P = torch.zeros_like(B)
     Pp = torch.zeros_like(B)
+    window = args.learn_online_window
     o = StepOpts(momentum=SolverOpts(tol=args.mom_tol, max_iter=5000, x0_mode=X0.X0_PROJECT),
-                 poisson=SolverOpts(tol=1e-8, max_iter=100000), mass=SolverOpts(tol=args.mass_tol, max_iter=2000))
+                 poisson=SolverOpts(tol=1e-8, max_iter=100000, x0_mode=X0.X0_POD_GALERKIN if window else X0.X0_PREV),
+                 mass=SolverOpts(tol=args.mass_tol, max_iter=2000))
     t0 = time.perf_counter()
+    max_u = []
     for r, re in enumerate(res):
-        mesh.assemble(case.rho, 0.1 / re, case.dt)
+        mesh.assemble(case.rho, 0.1 / re, case.dt, rmode)
+        online = None
+        if window:
+            online = cgp.Guess(mesh, n_modes=window, hidden=16, seed=5)
+            online.set_online(window, 1)
+            online.attach()
         u = torch.from_numpy(case.initial(xy, vd)).cuda()
         pf = torch.zeros(mesh.info["n_f"], dtype=torch.float64, device="cuda")
         pc = torch.zeros(n, dtype=torch.float64, device="cuda")
-        for k in range(settle + rec):
-            if k >= settle:
-                Pp[r * rec + k - settle].copy_(pc)
+        for k in range(settle + rec * stride):
+            j = (k - settle) // stride if k >= settle and (k - settle) % stride == stride - 1 else -1
+            if j >= 0:
+                Pp[r * rec + j].copy_(pc)
             mesh.step(g, u, pf, pc, opts=o)
-            if k >= settle:
-                mesh.last_poisson_rhs(B[r * rec + k - settle])
-                P[r * rec + k - settle].copy_(pc)
+            if j >= 0:
+                mesh.last_poisson_rhs(B[r * rec + j])
+                P[r * rec + j].copy_(pc)
+        if online:
+            online.detach()
+            online.close()
         torch.cuda.synchronize()
-        log(f"learned study: Re {re:.1f} recorded ({r + 1}/{n_re}), {time.perf_counter() - t0:.0f}s")
+        max_u.append(round(float(u.abs().max()), 4))
+        log(f"learned study: Re {re:.1f} recorded ({r + 1}/{n_re}), max|u| at the end {max_u[-1]}, "
+            f"{time.perf_counter() - t0:.0f}s")
     ntr = (n_re - n_test) * rec
     tr = slice(0, ntr)
     models, train = {}, {}
@@ -450,7 +468,7 @@ def run_learned(args, log):
              "pod_galerkin": (X0.X0_POD_GALERKIN, "abs", 0), "learned": (X0.X0_LEARNED, "abs", 0),
              "learned_corr": (X0.X0_LEARNED_CORR, "incr", 0), "mixed+prev": (X0.X0_PREV, None, 1),
              "mixed+learned_corr": (X0.X0_LEARNED_CORR, "incr", 1)}
-    mesh.assemble(case.rho, 0.1 / res[ntr // rec], case.dt)
+    mesh.assemble(case.rho, 0.1 / res[ntr // rec], case.dt, rmode)
     out = {}
     for name, (mode, model, prec) in modes.items():
         if model:
@@ -459,7 +477,7 @@ def run_learned(args, log):
         for i in test_idx:
             re_i = res[i // rec]
             if abs(mesh.params["mu"] - 0.1 / re_i) > 0:
-                mesh.assemble(case.rho, 0.1 / re_i, case.dt)  # K does not depend on mu; b does, and is recorded
+                mesh.assemble(case.rho, 0.1 / re_i, case.dt, rmode)  # K does not depend on mu; b is recorded
             x = Pp[i].clone() if mode != X0.X0_ZERO else torch.zeros(n, dtype=torch.float64, device="cuda")
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -478,9 +496,11 @@ def run_learned(args, log):
     for net in models.values():
         net.close()
     mesh.close()
-    return dict(workload=f"cylinder channel, coarse {case.mesh.n_tris} / fine {4 * case.mesh.n_tris} triangles, dt=1e-3; "
-                         f"{n_re} Re values in [60,160] (seed 7), steps {settle + 1}-{settle + rec} of each recorded "
+    return dict(workload=f"cylinder channel, coarse {case.mesh.n_tris} / fine {4 * case.mesh.n_tris} triangles, dt=1e-3, "
+                         f"restriction {'Galerkin' if rmode else 'injection'}; {n_re} Re values in [60,160] (seed 7), "
+                         f"every {stride}th of steps {settle + 1}-{settle + rec * stride} of each recorded "
                          f"({S} snapshots); the last {n_test} Re held out; Poisson tol 1e-8",
+                max_abs_u_end_per_re=max_u,
                 train_re=[round(float(v), 2) for v in res[:n_re - n_test]],
                 test_re=[round(float(v), 2) for v in res[n_re - n_test:]], samples_evaluated=len(test_idx),
                 training=train, guesses=out)
@@ -575,8 +595,15 @@ def run_batch_kernel(args, log):
     log(f"batched PCG kernel, all {len(meshes)} instances active: {out} us per iteration, {kbytes / 1e6:.0f} MB, "
         f"tuning {tuned}")
     batch.close()
+    cands = []
+    try:
+        for key, entry in json.loads(TUNING_CACHE.read_text()).items():
+            if key.endswith(f"_inst{len(meshes)}") and "candidates" in entry:
+                cands = entry["candidates"]
+    except (OSError, ValueError):
+        pass
     return dict(rows=rows, nnz=nnz, bytes_per_iteration=kbytes, us_per_iteration=[round(v, 2) for v in out],
-                tuning=tuned)
+                tuning=tuned, autotune_candidates=cands)
 
 
 def run_batch(args, log):
@@ -739,6 +766,9 @@ def main():
     ap.add_argument("--refresh", type=int, default=1, help="Poisson solves between online basis rebuilds")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps timed for the CPU baseline (0: skip)")
     ap.add_argument("--no-instrumented", action="store_true", help="skip the event-timed kernel pass")
+    ap.add_argument("--pcg-graph", type=int, default=0,
+                    help="1: fused Poisson PCG iterations launched as captured graphs of 8 (0, one launch each, is "
+                         "the library default)")
     ap.add_argument("--launch", choices=["loop", "persistent", "fused"], default="fused",
                     help="Poisson Krylov launch strategy")
     ap.add_argument("--mom-x0", choices=["prev", "extrap", "project"], default="project",
@@ -764,8 +794,12 @@ def main():
                     help="run only the learned-guess study (Re sweep, 64 modes, 64-256-256-64, held-out Re)")
     ap.add_argument("--learn-re", type=int, default=20, help="Re values of the learned-guess study")
     ap.add_argument("--learn-test-re", type=int, default=4, help="of them held out for evaluation")
-    ap.add_argument("--learn-settle", type=int, default=100, help="unrecorded steps per Re")
+    ap.add_argument("--learn-settle", type=int, default=1000, help="unrecorded steps per Re")
     ap.add_argument("--learn-record", type=int, default=100, help="recorded steps per Re")
+    ap.add_argument("--learn-stride", type=int, default=10, help="steps per recorded step after the settling steps")
+    ap.add_argument("--learn-restrict", type=int, default=1, help="restriction of the study's runs (0 injection, 1 Galerkin)")
+    ap.add_argument("--learn-online-window", type=int, default=64,
+                    help="online POD window of the recording runs' Poisson starts (0: previous pressure)")
     ap.add_argument("--learn-epochs", type=int, default=200, help="training epochs")
     ap.add_argument("--learn-eval-every", type=int, default=5, help="held-out recorded steps between evaluations")
     ap.add_argument("--only-functionals", action="store_true",
@@ -847,6 +881,7 @@ def main():
     case = W.case_cylinder(args.target_tris)
     mesh = cgp.Mesh(case.mesh, 1)
     mesh.assemble(case.rho, case.mu, case.dt)
+    mesh.set_tuning(pcg_graph=args.pcg_graph)
     info = mesh.info
     nnz_c, n_c = info["nnz_c"], info["n_c"]
     log(f"mesh: coarse {info['t_c']} tris / {n_c} nodes, fine {info['t_f']} tris / {info['n_f']} nodes, "

@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define CGP_ABI_VERSION 2
+#define CGP_ABI_VERSION 3
 
 typedef enum {
   CGP_OK = 0,
@@ -211,6 +211,10 @@ typedef struct {
                                two blocks per CU was not all resident and never passed its first barrier */
   int32_t pcg_spin_log2;    /* persistent Poisson kernel: a grid-barrier wait gives up after 2^pcg_spin_log2 polls
                                and the solve returns CGP_E_DEVICE (0 = 2^24; 1..30) */
+  int32_t pcg_graph;        /* fused Poisson PCG: 1 = runs of 8 iterations go out as one launch of a captured HIP
+                               graph (kept per buffer set, at most 8 sets per mesh); 0 (the default) = every
+                               iteration its own launch, which measured faster on gfx950 (10.4 against 10.9 us
+                               per FP64 iteration at 125k rows).  Ignored while kernel events are timed. */
 } cgp_tuning;
 
 int32_t cgp_abi_version(void);
@@ -321,7 +325,10 @@ cgp_status cgp_last_poisson_rhs(const cgp_mesh *mesh, double *dst);
  * the meshes must not be used elsewhere during the call.  Pointer arrays are host arrays of n
  * device pointers. */
 typedef struct cgp_batch cgp_batch;
-typedef struct { int32_t lanes, block, passes, use_graph, chunk; } cgp_batch_tuning;
+/* ahead = 1 or 2 selects the iteration kernel that issues a tile's loads before the instance's scalars
+ * are formed (lanes 4 or 8, passes 1, 2 or 4; 2: the columns of all of a lane group's rows before its
+ * first gather); ahead = 0 the row loop. */
+typedef struct { int32_t lanes, block, passes, use_graph, chunk, ahead; } cgp_batch_tuning;
 cgp_status cgp_batch_create(cgp_mesh *const *meshes, int32_t n, cgp_batch **out);
 void cgp_batch_destroy(cgp_batch *batch);
 /* rhs[i], x[i]: instance i's coarse right-hand side and solution (x: initial guess when x0_mode =
@@ -340,9 +347,9 @@ cgp_status cgp_batch_step(cgp_batch *batch, const cgp_step_opts *opts, const dou
                           const double *const *f, double *const *u, double *const *p_fine, double *const *p_coarse,
                           cgp_stats *stats);
 cgp_status cgp_batch_get_tuning(const cgp_batch *batch, cgp_batch_tuning *out);
-/* lanes 2/4/8/16 per row, block a power of two in 64..1024, passes 1..64, chunk even in 2..256. */
+/* lanes 2/4/8/16 per row, block a power of two in 64..1024, passes 1..64, chunk even in 2..256, ahead 0/1/2. */
 cgp_status cgp_batch_set_tuning(cgp_batch *batch, const cgp_batch_tuning *tuning);
-/* Time 12 launch shapes on the batch's own system and keep the fastest; the choice is cached in the JSON
+/* Time 63 launch shapes on the batch's own system and keep the fastest; the choice is cached in the JSON
  * file cache_path (NULL: no cache) under the batch's size class and reused without timing. */
 cgp_status cgp_batch_autotune(cgp_batch *batch, const char *cache_path, cgp_batch_tuning *chosen);
 

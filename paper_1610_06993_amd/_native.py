@@ -72,7 +72,7 @@ class _Knobs(C.Structure):
 
 class _Tuning(C.Structure):
     _fields_ = [("fine", _Knobs), ("coarse", _Knobs), ("pcg_barrier", C.c_int32), ("pcg_grid", C.c_int32),
-                ("pcg_spin_log2", C.c_int32)]
+                ("pcg_spin_log2", C.c_int32), ("pcg_graph", C.c_int32)]
 
 
 class _GuessDesc(C.Structure):
@@ -90,7 +90,7 @@ class _TrainStats(C.Structure):
 
 class _BatchTuning(C.Structure):
     _fields_ = [("lanes", C.c_int32), ("block", C.c_int32), ("passes", C.c_int32), ("use_graph", C.c_int32),
-                ("chunk", C.c_int32)]
+                ("chunk", C.c_int32), ("ahead", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -347,16 +347,19 @@ class Mesh:
         d["pcg_barrier"] = t.pcg_barrier
         d["pcg_grid"] = t.pcg_grid
         d["pcg_spin_log2"] = t.pcg_spin_log2
+        d["pcg_graph"] = t.pcg_graph
         return d
 
-    def set_tuning(self, fine=None, coarse=None, pcg_barrier=None, pcg_grid=None, pcg_spin_log2=None):
+    def set_tuning(self, fine=None, coarse=None, pcg_barrier=None, pcg_grid=None, pcg_spin_log2=None,
+                   pcg_graph=None):
         cur = self.get_tuning()
         f = fine or cur["fine"]
         c = coarse or cur["coarse"]
         b = cur["pcg_barrier"] if pcg_barrier is None else pcg_barrier
         g = cur["pcg_grid"] if pcg_grid is None else pcg_grid
         sp = cur["pcg_spin_log2"] if pcg_spin_log2 is None else pcg_spin_log2
-        t = _Tuning(_Knobs(*f), _Knobs(*c), b, g, sp)
+        gr = cur["pcg_graph"] if pcg_graph is None else pcg_graph
+        t = _Tuning(_Knobs(*f), _Knobs(*c), b, g, sp, gr)
         _check(lib().cgp_mesh_set_tuning(self._h, C.byref(t)))
 
     def last_poisson_rhs(self, dst):

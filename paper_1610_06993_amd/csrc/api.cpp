@@ -363,6 +363,10 @@ void cgp_mesh_destroy(cgp_mesh *m) {
     for (hipEvent_t e : m->kt_ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : m->step_ev)
       if (e) (void)hipEventDestroy(e);
+    for (cgp::Cg1Graph &g : m->cg1_graphs)
+      for (hipGraphExec_t x : g.gx)
+        if (x) (void)hipGraphExecDestroy(x);
+    if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
     if (m->h_state) (void)hipHostFree(m->h_state);
     if (m->h_scalar) (void)hipHostFree(m->h_scalar);
   }
@@ -666,8 +670,9 @@ cgp_status cgp_mesh_set_tuning(cgp_mesh *m, const cgp_tuning *t) {
     }
   }
   if ((t->pcg_barrier != 0 && t->pcg_barrier != 1) || t->pcg_grid < 0 || t->pcg_spin_log2 < 0 ||
-      t->pcg_spin_log2 > 30) {
-    set_error("cgp_mesh_set_tuning: pcg_barrier must be 0 or 1, pcg_grid >= 0 and pcg_spin_log2 in 0..30");
+      t->pcg_spin_log2 > 30 || (t->pcg_graph != 0 && t->pcg_graph != 1)) {
+    set_error("cgp_mesh_set_tuning: pcg_barrier must be 0 or 1, pcg_grid >= 0, pcg_spin_log2 in 0..30 and "
+              "pcg_graph 0 or 1");
     return CGP_E_ARG;
   }
   // one block per compute unit at most: the persistent kernel needs every block resident at once

@@ -58,7 +58,7 @@ struct cgp_batch {
   double *d_r64 = nullptr;
   double4 *d_rec[2] = {};             // records {r, w, s, D^-1}, double-buffered
   // tiles
-  cgp_batch_tuning tune{4, 512, 1, 1, 16};
+  cgp_batch_tuning tune{4, 512, 1, 1, 16, 0};
   int ntiles = 0;
   int4 *d_tiles = nullptr;            // {instance, first row, end row, -}
   int4 *d_tinfo = nullptr;            // per tile: {first tile, tile count} of its instance
@@ -261,6 +261,139 @@ __global__ void __launch_bounds__(kMaxBlock)
   put_at_last<3>(acc, Pout, G, t);
 }
 
+// The same iteration with every load of the tile issued before the instance's scalars are known
+// (cgp_batch_tuning.ahead = 1).  The gathered column's next u_j = D^-1_j (r_j - alpha (w_j + beta s_j))
+// is linear in (1, alpha, alpha beta), so a row's SpMV splits into three sums that need no scalars,
+//   sum_k A_jk u_j = S_r - alpha S_w - alpha beta S_s,  S_f = sum_k A_jk D^-1_j f_j,
+// which each lane accumulates as its gathered records arrive, while the instance's partials of the
+// previous iteration are still being summed.  A tile is P passes of blockDim/L rows: every lane group
+// streams P rows one after the other (only three accumulators per row stay live), and lane q of the
+// group holds row q's own record, x and p for the update.  The sums are combined in FP64; the result
+// differs from the single-mesh kernel's only in rounding.
+template <int L> constexpr int bt_ahead() { return (10 + L - 1) / L; }  // entries per lane issued together
+
+template <typename T, int L, int P, bool JOINT>
+__global__ void __launch_bounds__(kMaxBlock)
+    k_bt_iter_ahead(int it, int G, const int4 *__restrict__ tiles, const int4 *__restrict__ tinfo,
+                    const int *__restrict__ rp, const int *__restrict__ col, const T *__restrict__ A,
+                    T *__restrict__ x, T *__restrict__ p, const rec_t<T> *__restrict__ Rc,
+                    rec_t<T> *__restrict__ Rn, const double *__restrict__ Pin, double *__restrict__ Pout,
+                    KrylovState *__restrict__ st) {
+  static_assert(P <= L, "one row update per lane of a group");
+  using R4 = rec_t<T>;
+  constexpr int E = bt_ahead<L>();
+  const int t = xcd_block();
+  const int4 Tl = tiles[t], I = tinfo[t];
+  KrylovState *S = st + Tl.x;
+  if (S->status || S->done[0]) return;
+  const int lane = threadIdx.x & (L - 1), rpb = blockDim.x / L, gid = threadIdx.x / L;
+  const int my_row = Tl.y + lane * rpb + gid;  // the row this lane updates (lane < P)
+  const bool mine = lane < P && my_row < Tl.z;
+  R4 own{};
+  T xo = T(0), po = T(0);
+  if (mine) {
+    own = Rc[my_row];
+    xo = x[my_row];
+    po = p[my_row];
+  }
+  int k0[P], k1[P];
+#pragma unroll
+  for (int q = 0; q < P; q++) {
+    const int row = Tl.y + q * rpb + gid;
+    k0[q] = row < Tl.z ? rp[row] : 0;
+    k1[q] = row < Tl.z ? rp[row + 1] : 0;
+  }
+  double sr[P], sw[P], ss[P];
+  // JOINT: the columns and values of all P rows are loaded before the first gather (more loads in
+  // flight, more registers); otherwise row by row
+  int jj[JOINT ? P : 1][E];
+  T aa[JOINT ? P : 1][E];
+  auto load_cols = [&](int q, int slot) {
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      const int k = k0[q] + lane + e * L;
+      jj[slot][e] = k < k1[q] ? col[k] : -1;
+      aa[slot][e] = k < k1[q] ? A[k] : T(0);
+    }
+  };
+  if (JOINT) {
+#pragma unroll
+    for (int q = 0; q < P; q++) load_cols(q, q);
+  }
+#pragma unroll
+  for (int q = 0; q < P; q++) {
+    // the row's first E entries per lane: columns and values, then the gathered records, together
+    const int slot = JOINT ? q : 0;
+    if (!JOINT) load_cols(q, 0);
+    double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; e++)
+      if (jj[slot][e] >= 0) {
+        const R4 g = Rc[jj[slot][e]];
+        const T ad = aa[slot][e] * g.w;
+        a += (double)(ad * g.x);
+        b += (double)(ad * g.y);
+        c += (double)(ad * g.z);
+      }
+    for (int k = k0[q] + lane + E * L; k < k1[q]; k += L) {  // longer rows
+      const R4 g = Rc[col[k]];
+      const T ad = A[k] * g.w;
+      a += (double)(ad * g.x);
+      b += (double)(ad * g.y);
+      c += (double)(ad * g.z);
+    }
+    sr[q] = a;
+    sw[q] = b;
+    ss[q] = c;
+  }
+  double t3[3];
+  inst_sum<3>(Pin, G, I.x, I.y, t3);
+  const double gam = t3[0], del = t3[1], rr = t3[2];
+  const double bb = S->bnorm[0] * S->bnorm[0];
+  const bool done = bb == 0.0 || sqrt(rr) <= S->tol * sqrt(bb);
+  double beta = 0.0, alpha = 0.0;
+  if (it == 0) {
+    alpha = gam / del;
+  } else {
+    beta = gam / S->rz[(it - 1) & 1][0];
+    alpha = gam / (del - beta * gam / S->alpha[(it - 1) & 1][0]);
+  }
+  const bool bad = !is_finite(rr) || (!done && (!is_finite(alpha) || !is_finite(beta)));
+  if (t == I.x && threadIdx.x == 0) {
+    S->rz[it & 1][0] = gam;
+    S->alpha[it & 1][0] = alpha;
+    S->rnorm[0] = sqrt(rr);
+    if (done) S->done[0] = 1;
+    if (bad) S->status = CGP_E_NONFINITE;
+    if (!done && !bad) S->iters += 1;
+  }
+  if (done || bad) return;
+  const T al = (T)alpha, bt = (T)beta;
+  const double ab = (double)al * (double)bt;
+  double my_sum = 0.0;
+#pragma unroll
+  for (int q = 0; q < P; q++) {
+    const double sum = group_sum<L>(sr[q] - (double)al * sw[q] - ab * ss[q]);
+    if (lane == q) my_sum = sum;
+  }
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (mine) {
+    const T d = own.w, rc = own.x, wc = own.y, sc = own.z;
+    const T si = wc + bt * sc;
+    const T pi = d * rc + bt * po;
+    const T rn = rc - al * si;
+    const T un = d * (rc - al * (wc + bt * sc));
+    const T wn = (T)my_sum;
+    x[my_row] = xo + al * pi;
+    p[my_row] = pi;
+    store_rws(&Rn[my_row], rn, wn, si);
+    acc[0] = (double)rn * (double)un;
+    acc[1] = (double)wn * (double)un;
+    acc[2] = (double)rn * (double)rn;
+  }
+  put_at_last<3>(acc, Pout, G, t);
+}
+
 // ---- FP32 inner solves inside FP64 iterative refinement, per instance (as the single-mesh solve)
 // r64 = b - A x in FP64; partials (r.r, b.b) per tile
 template <int L>
@@ -453,6 +586,25 @@ cgp_status build_tiles(cgp_batch *B) {
   return CGP_OK;
 }
 
+// the loads-ahead kernel's instantiations: lanes 4 or 8 per row, passes 1, 2 or 4 rows per lane group,
+// columns row by row or of all rows first
+template <typename F>
+void dispatch_ahead(int L, int P, bool joint, F &&f) {
+  auto with_LP = [&](auto LC, auto PC) {
+    if (joint) f(LC, PC, std::true_type{});
+    else f(LC, PC, std::false_type{});
+  };
+  auto with_L = [&](auto LC) {
+    switch (P) {
+      case 1: with_LP(LC, std::integral_constant<int, 1>{}); break;
+      case 2: with_LP(LC, std::integral_constant<int, 2>{}); break;
+      default: with_LP(LC, std::integral_constant<int, 4>{}); break;
+    }
+  };
+  if (L == 8) with_L(std::integral_constant<int, 8>{});
+  else with_L(std::integral_constant<int, 4>{});
+}
+
 // enqueue `count` iterations starting at `it0`, then the chunk's convergence check: the FP64 solve
 // (fp32 = false) or the FP32 inner solves of the refinement (states si = d_state + ninst)
 void enqueue_chunk(cgp_batch *B, int it0, int count, bool fp32 = false) {
@@ -460,6 +612,26 @@ void enqueue_chunk(cgp_batch *B, int it0, int count, bool fp32 = false) {
   hipStream_t s = B->stream;
   KrylovState *st = fp32 ? B->d_state + B->ninst : B->d_state;
   float4 *R32[2] = {reinterpret_cast<float4 *>(B->d_rec[0]), reinterpret_cast<float4 *>(B->d_rec[0]) + B->rows};
+  if (B->tune.ahead) {
+    dispatch_ahead(B->tune.lanes, B->tune.passes, B->tune.ahead == 2, [&](auto LC, auto PC, auto JC) {
+      constexpr int LL = decltype(LC)::value, PP = decltype(PC)::value;
+      constexpr bool JJ = decltype(JC)::value;
+      for (int it = it0; it < it0 + count; it++) {
+        const int cur = it & 1, nxt = cur ^ 1;
+        if (fp32)
+          hipLaunchKernelGGL((k_bt_iter_ahead<float, LL, PP, JJ>), dim3(G), dim3(blk), 0, s, it, G,
+                             (const int4 *)B->d_tiles, (const int4 *)B->d_tinfo, (const int *)B->d_rp,
+                             (const int *)B->d_col, (const float *)B->d_A32, B->d_d32, B->d_p32,
+                             (const float4 *)R32[cur], R32[nxt], (const double *)bpin(B, it), bpout(B, it), st);
+        else
+          hipLaunchKernelGGL((k_bt_iter_ahead<double, LL, PP, JJ>), dim3(G), dim3(blk), 0, s, it, G,
+                             (const int4 *)B->d_tiles, (const int4 *)B->d_tinfo, (const int *)B->d_rp,
+                             (const int *)B->d_col, (const double *)B->d_A, B->d_x, B->d_p,
+                             (const double4 *)B->d_rec[cur], B->d_rec[nxt], (const double *)bpin(B, it),
+                             bpout(B, it), st);
+      }
+    });
+  } else
   dispatch_L(B->tune.lanes, [&](auto LC) {
     constexpr int LL = decltype(LC)::value;
     for (int it = it0; it < it0 + count; it++) {
@@ -783,13 +955,14 @@ cgp_status cgp_batch_get_tuning(const cgp_batch *B, cgp_batch_tuning *out) {
 cgp_status cgp_batch_set_tuning(cgp_batch *B, const cgp_batch_tuning *t) {
   if (!B || !t || (t->lanes != 2 && t->lanes != 4 && t->lanes != 8 && t->lanes != 16) || t->block < 64 || t->block > 1024 ||
       (t->block & (t->block - 1)) || t->passes < 1 || t->passes > 64 || t->chunk < 2 || t->chunk > 256 ||
-      (t->chunk & 1) || (t->use_graph != 0 && t->use_graph != 1)) {
+      (t->chunk & 1) || (t->use_graph != 0 && t->use_graph != 1) || t->ahead < 0 || t->ahead > 2 ||
+      (t->ahead && ((t->lanes != 4 && t->lanes != 8) || (t->passes != 1 && t->passes != 2 && t->passes != 4)))) {
     set_error("cgp_batch_set_tuning: lanes 2/4/8/16, block a power of two in 64..1024, passes 1..64, "
-              "chunk even in 2..256, use_graph 0/1");
+              "chunk even in 2..256, use_graph 0/1, ahead 0/1/2 (ahead 1, 2: lanes 4/8, passes 1/2/4)");
     return CGP_E_ARG;
   }
   const bool shape = t->lanes != B->tune.lanes || t->block != B->tune.block || t->passes != B->tune.passes;
-  const bool chunk = t->chunk != B->tune.chunk || t->use_graph != B->tune.use_graph;
+  const bool chunk = t->chunk != B->tune.chunk || t->use_graph != B->tune.use_graph || t->ahead != B->tune.ahead;
   B->tune = *t;
   if (shape) return build_tiles(B);
   if (chunk) drop_graphs(B);
@@ -975,7 +1148,7 @@ cgp_status cgp_batch_autotune(cgp_batch *B, const char *cache_path, cgp_batch_tu
     return (v + p / 2) / p * p;
   };
   char key[96];
-  std::snprintf(key, sizeof(key), "rows%ld_nnz%ld_inst%d", round2(B->rows), round2(B->nnz), B->ninst);
+  std::snprintf(key, sizeof(key), "v2_rows%ld_nnz%ld_inst%d", round2(B->rows), round2(B->nnz), B->ninst);
   // cache lookup: lines of the form  "key": {"lanes": L, "block": B, "passes": P, ...}
   std::string text;
   if (cache_path) {
@@ -987,8 +1160,9 @@ cgp_status cgp_batch_autotune(cgp_batch *B, const char *cache_path, cgp_batch_tu
     const size_t at = text.find(needle);
     if (at != std::string::npos) {
       cgp_batch_tuning t = B->tune;
-      if (std::sscanf(text.c_str() + at + needle.size(), ": {\"lanes\": %d, \"block\": %d, \"passes\": %d", &t.lanes,
-                      &t.block, &t.passes) == 3) {
+      if (std::sscanf(text.c_str() + at + needle.size(),
+                      ": {\"lanes\": %d, \"block\": %d, \"passes\": %d, \"ahead\": %d", &t.lanes, &t.block,
+                      &t.passes, &t.ahead) == 4) {
         BTRY(cgp_batch_set_tuning(B, &t));
         if (chosen) *chosen = B->tune;
         return CGP_OK;
@@ -996,20 +1170,23 @@ cgp_status cgp_batch_autotune(cgp_batch *B, const char *cache_path, cgp_batch_tu
     }
   }
   const cgp_batch_tuning keep = B->tune;
-  const int lanes[2] = {4, 8}, blocks[3] = {256, 512, 1024}, passes[2] = {1, 2};
+  const int lanes[3] = {2, 4, 8}, blocks[3] = {256, 512, 1024}, passes[3] = {1, 2, 4};
   cgp_batch_tuning best = keep;
   double best_us = 1e30;
   std::string table;
   hipEvent_t e0, e1;
   CGP_HIP(hipEventCreate(&e0));
   CGP_HIP(hipEventCreate(&e1));
+  for (int ah = 0; ah < 3; ah++)
   for (int L : lanes)
     for (int blk : blocks)
       for (int ps : passes) {
+        if (ah && L == 2) continue;  // the loads-ahead kernels are built for 4 and 8 lanes
         cgp_batch_tuning t = keep;
         t.lanes = L;
         t.block = blk;
         t.passes = ps;
+        t.ahead = ah;
         t.use_graph = 1;
         t.chunk = 16;
         BTRY(cgp_batch_set_tuning(B, &t));
@@ -1028,8 +1205,9 @@ cgp_status cgp_batch_autotune(cgp_batch *B, const char *cache_path, cgp_batch_tu
           us = 1e3 * ms / launched;
         }
         char line[160];
-        std::snprintf(line, sizeof(line), "%s{\"lanes\": %d, \"block\": %d, \"passes\": %d, \"us_per_iteration\": %.3f}",
-                      table.empty() ? "" : ", ", L, blk, ps, us);
+        std::snprintf(line, sizeof(line),
+                      "%s{\"lanes\": %d, \"block\": %d, \"passes\": %d, \"ahead\": %d, \"us_per_iteration\": %.3f}",
+                      table.empty() ? "" : ", ", L, blk, ps, ah, us);
         table += line;
         if (us < best_us) {
           best_us = us;
@@ -1044,8 +1222,9 @@ cgp_status cgp_batch_autotune(cgp_batch *B, const char *cache_path, cgp_batch_tu
   if (chosen) *chosen = B->tune;
   if (cache_path) {
     char head[256];
-    std::snprintf(head, sizeof(head), "\"%s\": {\"lanes\": %d, \"block\": %d, \"passes\": %d, \"us_per_iteration\": %.3f, ",
-                  key, best.lanes, best.block, best.passes, best_us);
+    std::snprintf(head, sizeof(head),
+                  "\"%s\": {\"lanes\": %d, \"block\": %d, \"passes\": %d, \"ahead\": %d, \"us_per_iteration\": %.3f, ",
+                  key, best.lanes, best.block, best.passes, best.ahead, best_us);
     const std::string entry = std::string(head) + "\"candidates\": [" + table + "]}";
     // append the entry to the JSON object (the file holds one object of entries and a log of timings)
     std::string body = text;

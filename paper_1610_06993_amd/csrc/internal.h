@@ -76,6 +76,15 @@ struct KrylovState {
   int status;                       // 0, or CGP_E_NONFINITE / CGP_E_NOCONV / CGP_E_DEVICE
 };
 
+// A captured run of kCg1GraphChunk fused PCG iterations: gx[0] starts at iteration 0, gx[1] at
+// iteration kCg1GraphChunk (replayed at every later even iteration); key = the launches' arguments.
+constexpr int kCg1GraphChunk = 8;
+struct Cg1Graph {
+  static constexpr int kKey = 14;
+  uintptr_t key[kKey] = {};
+  hipGraphExec_t gx[2] = {nullptr, nullptr};
+};
+
 // ILU(0)-GMRES(m) of the coarse Poisson solve: level schedule (pattern only), factors, Krylov basis
 struct GmresState {
   bool ready = false;              // levels and buffers set up
@@ -160,7 +169,10 @@ struct cgp_mesh {
   std::vector<void *> allocations;
   double *d_scalar = nullptr;     // device scalar for sums (means)
   double *h_scalar = nullptr;     // pinned [4]
-  cgp_tuning tune{{4, 512, 4}, {2, 1024, 1}, 0, 0};  // Krylov launch shapes (fine, coarse), persistent kernel
+  cgp_tuning tune{{4, 512, 4}, {2, 1024, 1}, 0, 0, 0, 0};  // Krylov launch shapes (fine, coarse), persistent kernel
+  // captured chunks of the fused Poisson PCG (per argument set) and the stream they are captured on
+  std::vector<cgp::Cg1Graph> cg1_graphs;
+  hipStream_t cap_stream = nullptr;
   // Krylov iterations queued before the first poll of a solve (the last solve's count), per solve
   // kind; the FP32 inner solves keep one per refinement step, whose lengths differ
   int mom_chunk = 4, p_chunk = 32, p32_chunk[4] = {16, 16, 16, 16}, mass_chunk = 8;

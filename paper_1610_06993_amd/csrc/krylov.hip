@@ -453,7 +453,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg1_iter(int Gin, int it, int n, 
     st->rz[it & 1][0] = gam;
     st->alpha[it & 1][0] = alpha;
     st->rnorm[0] = sqrt(rr);
-    st->iters = it;
+    // counted, not copied from `it`: a captured chunk replayed later carries its capture-time `it`
+    // (same parity, so the slots above are right), and the count stays that of the launches that updated
+    if (!done && !bad) st->iters += 1;
     if (done) st->done[0] = 1;
     if (bad) st->status = CGP_E_NONFINITE;
   }
@@ -507,8 +509,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg1_total(int G, const double *__
   if (threadIdx.x < 3) Ptot[threadIdx.x] = t3[threadIdx.x];
 }
 
-// after a chunk: convergence and iteration count from the last iteration's partials
-__global__ void __launch_bounds__(kMaxBlock) k_cg1_finish(int it_end, int G, const double *__restrict__ Pin,
+// after a chunk: convergence from the last iteration's partials (the iterations count themselves)
+__global__ void __launch_bounds__(kMaxBlock) k_cg1_finish(int G, const double *__restrict__ Pin,
                                                          KrylovState *__restrict__ st) {
   if (st->status || st->done[0]) return;
   double t3[3];
@@ -516,7 +518,6 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg1_finish(int it_end, int G, con
   if (threadIdx.x != 0) return;
   const double rn = sqrt(t3[2]);
   st->rnorm[0] = rn;
-  st->iters = it_end;
   if (!is_finite(rn)) st->status = CGP_E_NONFINITE;
   else if (rn <= st->tol * st->bnorm[0]) st->done[0] = 1;
 }
@@ -1323,6 +1324,27 @@ void dispatch_cg1(int lanes, int passes, int grid, bool tree, F &&f) {
   }
 }
 
+// The graph entry of this argument set, created empty (captured on first use); at most 8 are kept, the
+// oldest replaced after the stream has drained (one of its graphs may still be queued).
+cgp_status cg1_graph_for(cgp_mesh *m, const uintptr_t (&key)[Cg1Graph::kKey], Cg1Graph **out) {
+  for (Cg1Graph &g : m->cg1_graphs)
+    if (std::equal(key, key + Cg1Graph::kKey, g.key)) {
+      *out = &g;
+      return CGP_OK;
+    }
+  if (!m->cap_stream) CGP_HIP(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking));
+  if (m->cg1_graphs.size() >= 8) {
+    CGP_HIP(hipStreamSynchronize(m->stream));
+    for (hipGraphExec_t &x : m->cg1_graphs.front().gx)
+      if (x) (void)hipGraphExecDestroy(x);
+    m->cg1_graphs.erase(m->cg1_graphs.begin());
+  }
+  m->cg1_graphs.emplace_back();
+  std::copy(key, key + Cg1Graph::kKey, m->cg1_graphs.back().key);
+  *out = &m->cg1_graphs.back();
+  return CGP_OK;
+}
+
 template <typename T>
 cgp_status cg1_loop(cgp_mesh *m, int slot, int n, const int *rp, const int *col, const T *A, T *x, T *p,
                     rec_t<T> *const R[2], const cgp_tuning_knobs &tk, int g_first, int maxit, int *chunk_hint,
@@ -1346,26 +1368,67 @@ cgp_status cg1_loop(cgp_mesh *m, int slot, int n, const int *rp, const int *col,
                        (const double *)region(m, R_INIT), Pw, st);
   });
   if (tree) hipLaunchKernelGGL(k_cg1_total, dim3(1), dim3(1024), 0, s, sh.grid, (const double *)Pw, Ptot, st);
-  int it = 0, chunk = std::max(1, std::min(*chunk_hint, maxit));
-  for (;;) {
+  // one iteration (and its total when the grid is large) enqueued on stream q; e0/e1: event pair
+  auto launch_one = [&](hipStream_t q, int i, hipEvent_t e0, hipEvent_t e1) {
     dispatch_cg1(tk.lanes, tk.passes, sh.grid, tree, [&](auto LC, auto PC, auto UC, auto EC) {
       constexpr int LL = decltype(LC)::value, PP = decltype(PC)::value, UU = decltype(UC)::value;
       constexpr int EE = decltype(EC)::value;
-      for (int c = 0; c < chunk && it < maxit; c++, it++) {
-        const int cur = it & 1, nxt = cur ^ 1;
-        hipEvent_t e0, e1;
-        if (timed && kt_slot(m, it, &e0, &e1))
-          hipExtLaunchKernelGGL((k_cg1_iter<T, LL, PP, UU, EE>), dim3(sh.grid), dim3(sh.block), 0, s, e0, e1, 0, gin, it,
-                                n, rp, col, A, x, p, (const rec_t<T> *)R[cur], R[nxt], (const double *)pin(it),
-                                pout(it), st);
-        else
-          hipLaunchKernelGGL((k_cg1_iter<T, LL, PP, UU, EE>), dim3(sh.grid), dim3(sh.block), 0, s, gin, it, n, rp, col,
-                             A, x, p, (const rec_t<T> *)R[cur], R[nxt], (const double *)pin(it), pout(it), st);
-        if (tree)
-          hipLaunchKernelGGL(k_cg1_total, dim3(1), dim3(1024), 0, s, sh.grid, (const double *)pout(it), Ptot, st);
-      }
+      const int cur = i & 1, nxt = cur ^ 1;
+      if (e0)
+        hipExtLaunchKernelGGL((k_cg1_iter<T, LL, PP, UU, EE>), dim3(sh.grid), dim3(sh.block), 0, q, e0, e1, 0, gin, i,
+                              n, rp, col, A, x, p, (const rec_t<T> *)R[cur], R[nxt], (const double *)pin(i),
+                              pout(i), st);
+      else
+        hipLaunchKernelGGL((k_cg1_iter<T, LL, PP, UU, EE>), dim3(sh.grid), dim3(sh.block), 0, q, gin, i, n, rp, col,
+                           A, x, p, (const rec_t<T> *)R[cur], R[nxt], (const double *)pin(i), pout(i), st);
     });
-    hipLaunchKernelGGL(k_cg1_finish, dim3(1), dim3(256), 0, s, it, gin, (const double *)pin(it), st);
+    if (tree) hipLaunchKernelGGL(k_cg1_total, dim3(1), dim3(1024), 0, q, sh.grid, (const double *)pout(i), Ptot, st);
+  };
+  // Without event timing, runs of kCg1GraphChunk iterations go out as one launch of a captured graph:
+  // the chunk from iteration 0, or the one captured at iterations kCg1GraphChunk.. (even length, so a
+  // replay at any even iteration reads and writes the same slots).  Graphs are kept per argument set.
+  Cg1Graph *gr = nullptr;
+  if (m->tune.pcg_graph && !(timed && m->kt_on)) {
+    const uintptr_t key[Cg1Graph::kKey] = {sizeof(T), (uintptr_t)n, (uintptr_t)rp, (uintptr_t)col, (uintptr_t)A,
+                                           (uintptr_t)x, (uintptr_t)p, (uintptr_t)R[0], (uintptr_t)R[1],
+                                           (uintptr_t)st, (uintptr_t)Pw, (uintptr_t)sh.grid, (uintptr_t)sh.block,
+                                           (uintptr_t)(tk.lanes * 64 + tk.passes)};
+    cgp_status gs = cg1_graph_for(m, key, &gr);
+    if (gs) return gs;
+  }
+  auto graph_exec = [&](int which) -> hipGraphExec_t {
+    if (!gr->gx[which]) {
+      hipGraph_t g = nullptr;
+      hipStream_t q = m->cap_stream;
+      if (hipStreamBeginCapture(q, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+      const int i0 = which == 0 ? 0 : kCg1GraphChunk;
+      for (int c = 0; c < kCg1GraphChunk; c++) launch_one(q, i0 + c, nullptr, nullptr);
+      if (hipStreamEndCapture(q, &g) != hipSuccess || !g) return nullptr;
+      if (hipGraphInstantiate(&gr->gx[which], g, nullptr, nullptr, 0) != hipSuccess) gr->gx[which] = nullptr;
+      (void)hipGraphDestroy(g);
+    }
+    return gr->gx[which];
+  };
+  int it = 0, chunk = std::max(1, std::min(*chunk_hint, maxit));
+  for (;;) {
+    const int end = std::min(maxit, it + chunk);
+    while (it < end) {
+      if (gr && end - it >= kCg1GraphChunk && (it & 1) == 0) {
+        hipGraphExec_t gx = graph_exec(it == 0 ? 0 : 1);
+        if (!gx) {
+          set_error("cg1_loop: capturing the PCG iteration graph failed");
+          return CGP_E_DEVICE;
+        }
+        CGP_HIP(hipGraphLaunch(gx, s));
+        it += kCg1GraphChunk;
+        continue;
+      }
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (timed) kt_slot(m, it, &e0, &e1);
+      launch_one(s, it, e0, e1);
+      it++;
+    }
+    hipLaunchKernelGGL(k_cg1_finish, dim3(1), dim3(256), 0, s, gin, (const double *)pin(it), st);
     CGP_HIP(hipGetLastError());
     cgp_status ps = poll(m, slot);
     if (ps) return ps;

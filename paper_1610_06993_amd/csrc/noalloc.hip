@@ -89,11 +89,13 @@ extern "C" cgp_status cgp_poisson_solve_noalloc(cgp_mesh *m, const double *b, do
   unsigned char *s = static_cast<unsigned char *>(base);
   // the solve's own buffers point into the array for this call; the mesh's are put back on every
   // return.  The attached guess is set aside: the call records no solution and starts no rebuild.
+  // Graph capture is off for the call: instantiating a graph may allocate.
   struct Swap {
     cgp_mesh *m;
     double *wc0, *wc7, *rec, *part;
     KrylovState *state;
     cgp_guess *guess;
+    int32_t graph;
     ~Swap() {
       m->d_wc[0] = wc0;
       m->d_wc[7] = wc7;
@@ -101,8 +103,10 @@ extern "C" cgp_status cgp_poisson_solve_noalloc(cgp_mesh *m, const double *b, do
       m->red.partials = part;
       m->d_state = state;
       m->guess = guess;
+      m->tune.pcg_graph = graph;
     }
-  } keep{m, m->d_wc[0], m->d_wc[7], m->d_rec, m->red.partials, m->d_state, m->guess};
+  } keep{m, m->d_wc[0], m->d_wc[7], m->d_rec, m->red.partials, m->d_state, m->guess, m->tune.pcg_graph};
+  m->tune.pcg_graph = 0;
   m->d_wc[0] = reinterpret_cast<double *>(s + noalloc::kOffB);
   m->d_wc[7] = reinterpret_cast<double *>(s + noalloc::kOffP);
   m->d_rec = reinterpret_cast<double *>(s + noalloc::kOffRec);

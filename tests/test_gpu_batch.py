@@ -117,6 +117,31 @@ def test_batch_fp32_refinement(env, instances):
     batch.close()
 
 
+@pytest.mark.parametrize("lanes,block,passes,ahead", [(4, 512, 2, 0), (2, 512, 2, 0), (4, 512, 2, 1), (8, 256, 4, 1),
+                                                      (4, 1024, 1, 1), (4, 256, 4, 2), (8, 512, 2, 2)])
+def test_batch_kernel_forms(env, instances, lanes, block, passes, ahead):
+    """Both forms of the batched iteration (the row loop and the loads-ahead kernel) at several launch
+    shapes: per-instance solutions <= 1e-10 from the oracle in FP64, <= 1e-6 with the FP32 inner solves."""
+    torch, cgp, oracle = env
+    X0 = cgp._native
+    batch = cgp.Batch([g for _, g, _ in instances])
+    batch.set_tuning(lanes=lanes, block=block, passes=passes, ahead=ahead)
+    bs = _rhs(instances, 9)
+    for prec, tol, bar in ((X0.PREC_FP64, TIGHT, 1e-10), (X0.PREC_FP32_IR, 1e-10, 1e-6)):
+        xs = [torch.zeros(len(b), dtype=torch.float64, device="cuda") for b in bs]
+        st = batch.poisson_solve([dev(torch, b) for b in bs], xs, cgp.SolverOpts(tol=tol, max_iter=100000, precision=prec,
+                                                                                 x0_mode=X0.X0_ZERO))
+        errs = []
+        for (case, g, o), b, x, s in zip(instances, bs, xs, st):
+            ref, code, its, rr = o.poisson_solve(b, tol=1e-14)
+            errs.append(rel(x.cpu().numpy(), ref))
+            assert code == 0
+        _say(f"  shape {lanes}/{block}/{passes} ahead {ahead} precision {prec}: worst rel err {max(errs):.2e}, "
+             f"iterations {[s['p_iters'] for s in st]}")
+        assert max(errs) <= bar
+    batch.close()
+
+
 def test_graph_replays_equal_eager(env, instances):
     torch, cgp, oracle = env
     batch = cgp.Batch([g for _, g, _ in instances])
@@ -232,11 +257,12 @@ def test_autotune_cache(env, instances, tmp_path):
     data = json.loads(cache.read_text())
     assert len(data) == 1
     entry = next(iter(data.values()))
-    assert {"lanes", "block", "passes", "candidates"} <= set(entry) and len(entry["candidates"]) == 12
-    assert (entry["lanes"], entry["block"], entry["passes"]) == (chosen["lanes"], chosen["block"], chosen["passes"])
-    batch.set_tuning(lanes=16, block=64, passes=3)
+    assert {"lanes", "block", "passes", "ahead", "candidates"} <= set(entry) and len(entry["candidates"]) == 63
+    assert (entry["lanes"], entry["block"], entry["passes"], entry["ahead"]) == (chosen["lanes"], chosen["block"], chosen["passes"], chosen["ahead"])
+    batch.set_tuning(lanes=16, block=64, passes=3, ahead=0)
     again = batch.autotune(cache)   # from the cache: same choice, no timing
-    assert (again["lanes"], again["block"], again["passes"]) == (chosen["lanes"], chosen["block"], chosen["passes"])
+    assert (again["lanes"], again["block"], again["passes"], again["ahead"]) == \
+        (chosen["lanes"], chosen["block"], chosen["passes"], chosen["ahead"])
     # the tuned batch still solves correctly
     bs = _rhs(instances, 4)
     xs = [torch.zeros(len(b), dtype=torch.float64, device="cuda") for b in bs]
@@ -246,3 +272,86 @@ def test_autotune_cache(env, instances, tmp_path):
         ref, code, its, rr = o.poisson_solve(b, tol=1e-14)
         assert rel(x.cpu().numpy(), ref) <= 1e-10
     batch.close()
+
+
+DECILE_STEPS = 6
+
+
+@pytest.fixture(scope="module")
+def deciles(env):
+    """One instance per size decile of the 64-instance sweep (coarse 19k to 201k triangles, Re in
+    [60, 160]) and the oracle's trajectory of each over the first steps, computed once on host threads
+    (one per instance) and shared by the batched paths."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    torch, cgp, oracle = env
+    idx = W.batch_deciles()
+    cases = [W.batch_instance(i) for i in idx]
+    meshes, probs = [], []
+    for case in cases:
+        g = cgp.Mesh(case.mesh, 1)
+        g.assemble(case.rho, case.mu, case.dt)
+        o = oracle.Problem(case.mesh, 1)
+        o.assemble(case.rho, case.mu, case.dt, 0, 0)
+        meshes.append(g)
+        probs.append(o)
+    _say(f"batch deciles: instances {idx}, coarse nodes {[g.info['n_c'] for g in meshes]}; oracle trajectories")
+    xys = [g.export("xy") for g in meshes]
+
+    def trajectory(j):
+        case, o, xy = cases[j], probs[j], xys[j]
+        u, pc, out = case.initial(xy, meshes[j].export("vdir")), None, []
+        for k in range(DECILE_STEPS):
+            gd = case.dirichlet(xy, (k + 1) * case.dt)
+            un, pf, pcn, code, _ = o.step(gd, u, pc, tol_mom=1e-13, tol_p=1e-14, tol_mass=1e-13)
+            assert code == 0
+            out.append(dict(gd=gd, u=u, pc=pc, u_next=un, pf_next=pf))
+            u, pc = un, pcn
+        return out
+
+    with ThreadPoolExecutor(max_workers=len(cases)) as pool:
+        trajs = list(pool.map(trajectory, range(len(cases))))
+    return cases, meshes, trajs
+
+
+@pytest.mark.parametrize("path", ["online", "mixed+online"])
+def test_batch_size_deciles_against_oracle(env, deciles, path):
+    """The ten decile instances stepped together in one batch with per-instance online POD guesses
+    (window 4), FP64 or with the batched FP32 inner solves inside each instance's FP64 refinement.
+    Every step starts all instances from the oracle's state of the step before, so each comparison is
+    one step's local error: <= 1e-10 for FP64, <= 1e-6 for the FP32 refinement (its tolerance 1e-10
+    times the condition of the coarse Laplacian)."""
+    torch, cgp, oracle = env
+    X0 = cgp._native
+    cases, meshes, trajs = deciles
+    mixed = path.startswith("mixed")
+    poisson = cgp.SolverOpts(tol=1e-10 if mixed else 1e-13, max_iter=100000, x0_mode=X0.X0_POD_GALERKIN,
+                             precision=X0.PREC_FP32_IR if mixed else X0.PREC_FP64)
+    tight = cgp.SolverOpts(tol=1e-13, max_iter=100000)
+    opts = cgp.StepOpts(momentum=tight, poisson=poisson, mass=tight)
+    bar = 1e-6 if mixed else 1e-10
+    guesses = []
+    for g in meshes:
+        gs = cgp.Guess(g, n_modes=4, hidden=16, seed=3)
+        gs.set_online(4, 1)
+        gs.attach()
+        guesses.append(gs)
+    batch = cgp.Batch(meshes)
+    try:
+        for k in range(DECILE_STEPS):
+            rows = [t[k] for t in trajs]
+            us = [dev(torch, r["u"].copy()) for r in rows]
+            pcs = [dev(torch, r["pc"].copy()) if r["pc"] is not None else
+                   torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda") for r, g in zip(rows, meshes)]
+            pfs = [torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda") for g in meshes]
+            st = batch.step([dev(torch, r["gd"]) for r in rows], us, pfs, pcs, opts=opts)
+            errs = [max(rel(u.cpu().numpy(), r["u_next"]), rel(pf.cpu().numpy(), r["pf_next"]))
+                    for u, pf, r in zip(us, pfs, rows)]
+            _say(f"  {path} step {k + 1}: worst rel err {max(errs):.2e}, Poisson iterations "
+                 f"{[s['p_iters'] for s in st]}")
+            assert max(errs) <= bar
+    finally:
+        batch.close()
+        for gs in guesses:
+            gs.detach()
+            gs.close()

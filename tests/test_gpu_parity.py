@@ -176,6 +176,45 @@ def test_poisson_solve(env, which, precision, launch):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_graph_chunks_equal_single_launches(env, precision):
+    """The fused PCG with runs of 8 iterations launched as captured graphs (pcg_graph = 1) against one
+    launch per iteration: bitwise equal solutions and equal iteration counts, over solves into two
+    different output buffers (two graph sets), with eager work between them; an iteration limit that
+    is not a multiple of 8 is met exactly."""
+    torch, cgp, oracle = env
+    X0 = cgp._native
+    case = W.case_cylinder(3000, seed=5)
+    g = cgp.Mesh(case.mesh, 1)
+    g.assemble(case.rho, case.mu, case.dt)
+    n = g.info["n_c"]
+    rng = np.random.default_rng(11)
+    bs = [dev(torch, rng.normal(size=n)) for _ in range(3)]
+    opts = cgp.SolverOpts(tol=1e-11, max_iter=100000, x0_mode=X0.X0_ZERO, precision=precision)
+    res = {}
+    for graph in (0, 1):
+        g.set_tuning(pcg_graph=graph)
+        outs = []
+        xa, xb = torch.zeros(n, dtype=torch.float64, device="cuda"), torch.zeros(n, dtype=torch.float64, device="cuda")
+        for k, b in enumerate(bs * 2):
+            x = xa if k % 2 == 0 else xb
+            st = g.poisson_solve(b, x, opts)
+            _ = torch.ones(1000, device="cuda").sum().item()  # eager work between solves
+            outs.append((x.cpu().numpy().copy(), st["p_iters"], st["p_outer"]))
+        res[graph] = outs
+    for (a, ia, oa), (b, ib, ob) in zip(res[0], res[1]):
+        assert ia == ib and oa == ob
+        assert np.array_equal(a, b)
+    _say(f"  precision {precision}: iterations {[r[1] for r in res[1]]}, bitwise equal with and without graphs")
+    if precision == 0:
+        for graph in (0, 1):
+            g.set_tuning(pcg_graph=graph)
+            x = torch.zeros(n, dtype=torch.float64, device="cuda")
+            st = g.poisson_solve(bs[0], x, cgp.SolverOpts(tol=1e-300, max_iter=37, x0_mode=X0.X0_ZERO),
+                                 allow_noconv=True)
+            assert st["p_iters"] == 37 and st["status"] == X0.E_NOCONV
+    g.close()
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_persistent_barrier_give_up_is_reported(env, precision):
     """The persistent kernel's grid-barrier wait is bounded.  With the bound forced down to two polls from
     the host, blocks give up waiting; every block then leaves at its next barrier and the solve reports
@@ -482,23 +521,30 @@ def test_failure_paths(env):
     assert torch.isfinite(u).all()
 
 
-def test_full_size_cylinder_step_against_oracle(env):
-    """One FP64 step at the 1M-fine-triangle size, in the benchmark's launch
-    configuration, compared with the oracle from the same state."""
+@pytest.mark.parametrize("which,steps", [("cylinder", 3), ("backward_step", 5)])
+def test_full_size_steps_against_oracle(env, which, steps):
+    """The first steps at the full benchmark sizes (cylinder: 248920 coarse / 995680 fine triangles;
+    backward-facing step: 51408 / 205632), FP64, in the benchmark's launch configuration.  Each step
+    starts the GPU from the oracle's state of the step before, so every comparison is one step's
+    local error and the errors do not compound."""
     torch, cgp, oracle = env
-    case = W.case_cylinder()
-    _say("full-size cylinder", case.mesh.n_tris, "coarse triangles")
+    case = W.case_cylinder() if which == "cylinder" else W.case_bfs()
+    _say(f"full-size {which}", case.mesh.n_tris, "coarse triangles,", steps, "steps")
     g, o = make_pair(env, case.mesh, 1, case.rho, case.mu, case.dt)
-    assert g.info["t_f"] >= 950_000
+    assert g.info["t_f"] >= (950_000 if which == "cylinder" else 200_000)
     xy = g.export("xy")
-    u0 = case.initial(xy, g.export("vdir"))
-    gd = case.dirichlet(xy, case.dt)
-    u = dev(torch, u0.copy())
-    pf = torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda")
-    pc = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
-    st = g.step(dev(torch, gd), u, pf, pc, opts=tight_opts(cgp))
-    ur, pfr, pcr, code, ost = o.step(gd, u0, None, tol_mom=TIGHT, tol_p=TIGHT_P, tol_mass=TIGHT)
-    assert code == 0
-    eu, ep = rel(u.cpu().numpy(), ur), rel(pf.cpu().numpy(), pfr)
-    _say("full-size rel err u", eu, "p", ep, "gpu stats", st, "oracle stats", ost)
-    assert eu <= 1e-10 and ep <= 1e-10
+    ur = case.initial(xy, g.export("vdir"))
+    pcr = None
+    for k in range(steps):
+        gd = case.dirichlet(xy, (k + 1) * case.dt)
+        u = dev(torch, ur.copy())
+        pf = torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda")
+        pc = dev(torch, pcr.copy()) if pcr is not None else torch.zeros(g.info["n_c"], dtype=torch.float64,
+                                                                        device="cuda")
+        st = g.step(dev(torch, gd), u, pf, pc, opts=tight_opts(cgp))
+        ur, pfr, pcr, code, ost = o.step(gd, ur, pcr, tol_mom=TIGHT, tol_p=TIGHT_P, tol_mass=TIGHT)
+        assert code == 0
+        eu, ep = rel(u.cpu().numpy(), ur), rel(pf.cpu().numpy(), pfr)
+        _say(f"  step {k + 1}: rel err u {eu:.2e}, p {ep:.2e}; Poisson iterations GPU {st['p_iters']}, "
+             f"oracle {ost['p_iters']}")
+        assert eu <= 1e-10 and ep <= 1e-10

@@ -104,11 +104,12 @@ def test_host_only_mesh_refuses_device_calls(cgp):
 def test_persistent_grid_and_spin_limits_validated(cgp):
     """The persistent Poisson kernel needs every block resident at once: more than one block per compute
     unit (at most 256 on a gfx950 part; a host-only mesh has no device to ask) is rejected, as is a
-    barrier spin limit outside 2^1..2^30."""
+    barrier spin limit outside 2^1..2^30.  The graph switch of the fused PCG is 0 or 1, off by default."""
     g = cgp.Mesh(W.unit_square_tg(4), 1, host_only=True)
     before = g.get_tuning()
+    assert before["pcg_graph"] == 0
     for kw in ({"pcg_grid": 257}, {"pcg_grid": 512}, {"pcg_grid": -1}, {"pcg_spin_log2": 31},
-               {"pcg_spin_log2": -2}):
+               {"pcg_spin_log2": -2}, {"pcg_graph": 2}, {"pcg_graph": -1}):
         _expect(cgp, 1, lambda: g.set_tuning(**kw))
         assert g.get_tuning() == before
     g.set_tuning(pcg_grid=256, pcg_spin_log2=1)
