@@ -638,7 +638,7 @@ def run_batch(args, log):
     X0 = cgp._native
     mom = SolverOpts(tol=args.mom_tol, max_iter=5000,
                      x0_mode={"prev": X0.X0_PREV, "extrap": X0.X0_EXTRAP, "project": X0.X0_PROJECT}[args.mom_x0])
-    opts = StepOpts(momentum=mom, poisson=SolverOpts(tol=tol, max_iter=100000),
+    opts = StepOpts(timing=1, momentum=mom, poisson=SolverOpts(tol=tol, max_iter=100000),
                     mass=SolverOpts(tol=args.mass_tol, max_iter=2000))
     for k in range(2):
         batch.step(g, u, pf, pc, opts=opts)
@@ -665,11 +665,16 @@ def run_batch(args, log):
     st = batch.step(g, u, pf, pc, opts=opts)
     err = max(max(rel(a.cpu().numpy(), r[0]), rel(b.cpu().numpy(), r[1])) for a, b, r in zip(u, pf, ref))
     restore()
+    phases = lambda sts: {k: round(float(np.mean([s[0][k] for s in sts])), 2)
+                          for k in ("ms_momentum", "ms_poisson", "ms_correct")}
     t1 = time.perf_counter()
+    sts = []
     for k in range(args.batch_steps):
         st = batch.step(g, u, pf, pc, opts=opts)
+        sts.append(st)
     torch.cuda.synchronize()
     el = time.perf_counter() - t1
+    ph_plain = phases(sts)
     iters = [s["p_iters"] for s in st]
     launches = st[0]["n_dominant"]
     # the batched PCG kernel with every instance active: 64 iterations from a random right-hand side
@@ -691,29 +696,35 @@ def run_batch(args, log):
         gs.set_online(args.batch_window, 1)
         gs.attach()
         guesses.append(gs)
-    oopts = StepOpts(momentum=mom, poisson=SolverOpts(tol=tol, max_iter=100000, x0_mode=X0.X0_POD_GALERKIN),
+    oopts = StepOpts(timing=1, momentum=mom, poisson=SolverOpts(tol=tol, max_iter=100000, x0_mode=X0.X0_POD_GALERKIN),
                      mass=SolverOpts(tol=args.mass_tol, max_iter=2000))
     restore()
     for k in range(args.batch_window + 1):
         batch.step(g, u, pf, pc, opts=oopts)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    sts = []
     for k in range(args.batch_steps):
         st_on = batch.step(g, u, pf, pc, opts=oopts)
+        sts.append(st_on)
     torch.cuda.synchronize()
     el_on = time.perf_counter() - t1
+    ph_on = phases(sts)
     iters_on = [s["p_iters"] for s in st_on]
     # the same with every instance's FP32 inner solves batched inside its FP64 refinement
-    mopts = StepOpts(momentum=mom, poisson=SolverOpts(tol=tol, max_iter=100000, precision=cgp._native.PREC_FP32_IR,
+    mopts = StepOpts(timing=1, momentum=mom, poisson=SolverOpts(tol=tol, max_iter=100000, precision=cgp._native.PREC_FP32_IR,
                                                       inner_tol=args.inner_tol, x0_mode=X0.X0_POD_GALERKIN),
                      mass=SolverOpts(tol=args.mass_tol, max_iter=2000))
     batch.step(g, u, pf, pc, opts=mopts)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    sts = []
     for k in range(args.batch_steps):
         st_mx = batch.step(g, u, pf, pc, opts=mopts)
+        sts.append(st_mx)
     torch.cuda.synchronize()
     el_mx = time.perf_counter() - t1
+    ph_mx = phases(sts)
     iters_mx = [s["p_iters"] for s in st_mx]
     for gs in guesses:
         gs.detach()
@@ -725,6 +736,7 @@ def run_batch(args, log):
                sequential_instance_steps_per_s=round(len(meshes) / seq_s, 3),
                speedup_vs_sequential=round(len(meshes) * args.batch_steps / el / (len(meshes) / seq_s), 3),
                poisson_iters_min_max=[min(iters), max(iters)], batched_launches_per_step=launches,
+               phase_ms_mean=ph_plain,
                rel_err_vs_single_instance_gpu=err,
                tuning=tuned, batched_kernel_us_per_iteration_all_active=round(us_it, 2),
                batched_kernel_bytes_per_iteration=kbytes,
@@ -733,17 +745,17 @@ def run_batch(args, log):
                online_pod=dict(window=args.batch_window,
                                instance_steps_per_s=round(len(meshes) * args.batch_steps / el_on, 3),
                                ms_per_batch_step=round(1e3 * el_on / args.batch_steps, 2),
-                               poisson_iters_min_max=[min(iters_on), max(iters_on)]),
+                               poisson_iters_min_max=[min(iters_on), max(iters_on)], phase_ms_mean=ph_on),
                mixed_online_pod=dict(instance_steps_per_s=round(len(meshes) * args.batch_steps / el_mx, 3),
                                      ms_per_batch_step=round(1e3 * el_mx / args.batch_steps, 2),
-                                     inner_iters_min_max=[min(iters_mx), max(iters_mx)]))
+                                     inner_iters_min_max=[min(iters_mx), max(iters_mx)], phase_ms_mean=ph_mx))
     log(f"batch: {out['instance_steps_per_s']} instance-steps/s ({out['ms_per_batch_step']} ms per batch step) vs "
         f"{out['sequential_instance_steps_per_s']} sequential; Poisson iterations {min(iters)}..{max(iters)}; "
         f"batched PCG kernel {us_it:.1f} us/iteration for {kbytes / 1e6:.0f} MB -> {out['batched_kernel_gbs']} GB/s; "
-        f"rel err vs single-instance {err:.1e}")
+        f"rel err vs single-instance {err:.1e}; phases (ms) {ph_plain}")
     log(f"batch with per-instance online POD guesses (window {args.batch_window}): "
         f"{out['online_pod']['instance_steps_per_s']} instance-steps/s ({out['online_pod']['ms_per_batch_step']} ms "
-        f"per batch step); Poisson iterations {min(iters_on)}..{max(iters_on)}")
+        f"per batch step); Poisson iterations {min(iters_on)}..{max(iters_on)}; phases (ms) {ph_on}")
     log(f"batch with online POD guesses and batched FP32 refinement: {out['mixed_online_pod']['instance_steps_per_s']} "
         f"instance-steps/s ({out['mixed_online_pod']['ms_per_batch_step']} ms per batch step); inner iterations "
         f"{min(iters_mx)}..{max(iters_mx)}")

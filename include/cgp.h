@@ -342,7 +342,10 @@ void cgp_batch_destroy(cgp_batch *batch);
  * instance converged. */
 cgp_status cgp_batch_poisson_solve(cgp_batch *batch, const double *const *rhs, double *const *x,
                                    const cgp_solver_opts *opts, cgp_stats *stats);
-/* One IFE-CGP step of every instance (arguments as cgp_step, one pointer per instance; f may be NULL). */
+/* One IFE-CGP step of every instance (arguments as cgp_step, one pointer per instance; f may be NULL).
+ * With opts->timing >= 1 every instance's ms_momentum, ms_poisson and ms_correct hold the batch's host
+ * wall time of that phase for all instances (momentum with restriction, the batched Poisson solve,
+ * prolongation with correction). */
 cgp_status cgp_batch_step(cgp_batch *batch, const cgp_step_opts *opts, const double *const *g,
                           const double *const *f, double *const *u, double *const *p_fine, double *const *p_coarse,
                           cgp_stats *stats);

@@ -1102,6 +1102,13 @@ cgp_status cgp_batch_step(cgp_batch *B, const cgp_step_opts *o, const double *co
     if (s == CGP_E_NOCONV && worst == CGP_OK) worst = s;
     return s == CGP_OK || s == CGP_E_NOCONV;
   };
+  // phase times (timing >= 1): host wall clock around each phase, whose calls return after their polls
+  using clk = std::chrono::steady_clock;
+  auto ms_since = [](clk::time_point t0) {
+    return (float)std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+  };
+  clk::time_point t0 = clk::now();
+  float ms_mom = 0.0f, ms_p = 0.0f, ms_cor = 0.0f;
   // steps 1-2 (Eqs. 19-21) per instance
   cgp_status s = per_instance([&](int i, cgp_mesh *m) {
     cgp_status r = drv_momentum(m, &o->momentum, g[i], f ? f[i] : nullptr, u[i], m->d_ut, &S[i]);
@@ -1110,11 +1117,21 @@ cgp_status cgp_batch_step(cgp_batch *B, const cgp_step_opts *o, const double *co
     return r2 != CGP_OK ? r2 : r;
   });
   if (!note(s)) return s;
+  if (o->timing >= 1) {
+    CGP_HIP(hipStreamSynchronize(B->mstream));
+    ms_mom = ms_since(t0);
+    t0 = clk::now();
+  }
   for (int i = 0; i < n; i++) bc[i] = B->meshes[i]->d_bc;
   // step 3 (Eq. 21): every instance's Poisson solve in one PCG
   std::vector<cgp_stats> P(n);
   s = cgp_batch_poisson_solve(B, bc.data(), pc, &o->poisson, P.data());
   if (!note(s)) return s;
+  if (o->timing >= 1) {
+    CGP_HIP(hipStreamSynchronize(B->mstream));
+    ms_p = ms_since(t0);
+    t0 = clk::now();
+  }
   // steps 4-5 (Eqs. 22-23) per instance
   s = per_instance([&](int i, cgp_mesh *m) {
     const cgp_status r = drv_prolong(m, pc[i], pf[i]);
@@ -1122,12 +1139,21 @@ cgp_status cgp_batch_step(cgp_batch *B, const cgp_step_opts *o, const double *co
     return drv_correct(m, &o->mass, g[i], m->d_ut, pf[i], u[i], &S[i]);
   });
   if (!note(s)) return s;
+  if (o->timing >= 1) {
+    CGP_HIP(hipStreamSynchronize(B->mstream));
+    ms_cor = ms_since(t0);
+  }
   for (int i = 0; i < n; i++) {
     S[i].p_iters = P[i].p_iters;
     S[i].p_outer = P[i].p_outer;
     S[i].p_relres = P[i].p_relres;
     S[i].ms_poisson = P[i].ms_poisson;
     S[i].n_dominant = P[i].n_dominant;
+    if (o->timing >= 1) {  // the batch's phase wall times, the same for every instance
+      S[i].ms_momentum = ms_mom;  // momentum and restriction of all instances
+      S[i].ms_poisson = ms_p;
+      S[i].ms_correct = ms_cor;   // prolongation and correction of all instances
+    }
   }
   CGP_HIP(hipStreamSynchronize(B->mstream));
   if (stats) std::copy(S.begin(), S.end(), stats);
