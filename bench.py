@@ -293,6 +293,60 @@ def strouhal(times, lift, diameter=0.1, speed=1.0):
     return float((len(ups) - 1) / (ups[-1] - ups[0]) * diameter / speed)
 
 
+def run_gmres(args, log):
+    """The paper's Poisson solver against the fused Jacobi-PCG on the benchmark's pressure systems:
+    ILU(0)-GMRES(m) with level-scheduled triangular solves (one launch per level) and the fused
+    PCG, on the Poisson right-hand side of step 20 of plain CGP, for the full cylinder and a
+    16k-triangle one; iterations, ms per solve and ms per iteration (GMRES capped at
+    `gmres_max_iter` iterations at the full size)."""
+    import torch
+
+    import paper_1610_06993_amd as cgp
+    import workloads as W
+    from paper_1610_06993_amd import SolverOpts, StepOpts
+    X0 = cgp._native
+    out = []
+    for tris, cap in ((16_000, 20000), (args.target_tris, args.gmres_max_iter)):
+        case = W.case_cylinder(tris)
+        mesh = cgp.Mesh(case.mesh, 1)
+        mesh.assemble(case.rho, case.mu, case.dt)
+        xy, vd = mesh.export("xy"), mesh.export("vdir")
+        g = torch.from_numpy(case.dirichlet(xy, 0.0)).cuda()
+        u = torch.from_numpy(case.initial(xy, vd)).cuda()
+        n = mesh.info["n_c"]
+        pf = torch.zeros(mesh.info["n_f"], dtype=torch.float64, device="cuda")
+        pc = torch.zeros(n, dtype=torch.float64, device="cuda")
+        o = StepOpts(momentum=SolverOpts(tol=args.mom_tol, max_iter=5000), poisson=SolverOpts(tol=1e-8, max_iter=100000),
+                     mass=SolverOpts(tol=args.mass_tol, max_iter=2000))
+        for k in range(20):
+            mesh.step(g, u, pf, pc, opts=o)
+        b = torch.zeros(n, dtype=torch.float64, device="cuda")
+        mesh.last_poisson_rhs(b)
+        row = dict(coarse_triangles=case.mesh.n_tris, coarse_nodes=n)
+        for name, so in (("jacobi_pcg", SolverOpts(tol=1e-8, max_iter=100000, x0_mode=X0.X0_ZERO)),
+                         ("ilu0_gmres30", SolverOpts(tol=1e-8, max_iter=cap, x0_mode=X0.X0_ZERO,
+                                                     method=X0.METHOD_ILU_GMRES, restart=30)),
+                         ("ilu0_gmres60", SolverOpts(tol=1e-8, max_iter=cap, x0_mode=X0.X0_ZERO,
+                                                     method=X0.METHOD_ILU_GMRES, restart=60))):
+            x = torch.zeros(n, dtype=torch.float64, device="cuda")
+            mesh.poisson_solve(b, x, so, allow_noconv=True)  # first solve: factorisation, warm-up
+            x.zero_()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st = mesh.poisson_solve(b, x, so, allow_noconv=True)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t1)
+            row[name] = dict(iterations=st["p_iters"], converged=st["status"] == 0,
+                             relres=float(st["p_relres"]), ms=round(ms, 2),
+                             ms_per_iteration=round(ms / max(1, st["p_iters"]), 4))
+            log(f"Poisson solvers, {case.mesh.n_tris} coarse triangles: {name}: {st['p_iters']} iterations "
+                f"({'converged' if st['status'] == 0 else 'capped'}, relres {st['p_relres']:.1e}), {ms:.1f} ms")
+        mesh.close()
+        out.append(row)
+    return dict(workload="Poisson right-hand side of step 20 of plain CGP on cylinder channels (Re 100, l = 1), "
+                         "tolerance 1e-8 relative, x0 = 0", points=out)
+
+
 def run_functionals(args, log):
     """Flow functionals from long runs (Section 3.3, Eq. 42, Table 6, Fig. 13; Section 3.2, Fig. 7):
     drag and lift coefficients (pressure and viscous parts) and the Strouhal number of the cylinder
@@ -778,6 +832,11 @@ def main():
     ap.add_argument("--refresh", type=int, default=1, help="Poisson solves between online basis rebuilds")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps timed for the CPU baseline (0: skip)")
     ap.add_argument("--no-instrumented", action="store_true", help="skip the event-timed kernel pass")
+    ap.add_argument("--only-gmres", action="store_true",
+                    help="run only the ILU(0)-GMRES against Jacobi-PCG comparison on the Poisson systems")
+    ap.add_argument("--gmres-max-iter", type=int, default=300,
+                    help="iteration cap of ILU(0)-GMRES at the full size (each iteration is two level-scheduled "
+                         "triangular solves)")
     ap.add_argument("--pcg-graph", type=int, default=0,
                     help="1: fused Poisson PCG iterations launched as captured graphs of 8 (0, one launch each, is "
                          "the library default)")
@@ -871,6 +930,9 @@ def main():
         return
     if args.only_learned:
         print(json.dumps({"learned": run_learned(args, log)}), flush=True)
+        return
+    if args.only_gmres:
+        print(json.dumps({"poisson_solvers": run_gmres(args, log)}), flush=True)
         return
     if args.only_functionals:
         print(json.dumps({"functionals": run_functionals(args, log)}), flush=True)
