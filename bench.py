@@ -973,9 +973,14 @@ def main():
 
     mom_x0 = {"prev": X0.X0_PREV, "extrap": X0.X0_EXTRAP, "project": X0.X0_PROJECT}[args.mom_x0]
 
+    F64, F32 = cgp._native.PREC_FP64, cgp._native.PREC_FP32_IR
+    MIXED_ALL = 100  # the bench's own code: FP32 inner solves in the momentum and the Poisson solve
+
     def opts(precision=0, x0=X0.X0_PREV, timing=0):
-        return StepOpts(momentum=SolverOpts(tol=args.mom_tol, max_iter=5000, x0_mode=mom_x0),
-                        poisson=SolverOpts(tol=tol, max_iter=100000, precision=precision, inner_tol=args.inner_tol,
+        pp = F32 if precision in (F32, MIXED_ALL) else F64
+        mp = F32 if precision == MIXED_ALL else F64
+        return StepOpts(momentum=SolverOpts(tol=args.mom_tol, max_iter=5000, x0_mode=mom_x0, precision=mp),
+                        poisson=SolverOpts(tol=tol, max_iter=100000, precision=pp, inner_tol=args.inner_tol,
                                            x0_mode=x0, launch=launch),
                         mass=SolverOpts(tol=args.mass_tol, max_iter=2000), timing=timing)
 
@@ -1045,7 +1050,6 @@ def main():
             online.detach()
         torch.cuda.synchronize()
 
-    F64, F32 = cgp._native.PREC_FP64, cgp._native.PREC_FP32_IR
     paths = {
         "fp64": (F64, X0.X0_PREV, None),
         "fp64+pod_galerkin": (F64, X0.X0_POD_GALERKIN, "abs"),
@@ -1055,6 +1059,7 @@ def main():
         "mixed": (F32, X0.X0_PREV, None),
         "mixed+learned_corr": (F32, X0.X0_LEARNED_CORR, "incr"),
         "mixed+online_pod": (F32, X0.X0_POD_GALERKIN, "online"),
+        "mixed_all+online_pod": (MIXED_ALL, X0.X0_POD_GALERKIN, "online"),
     }
     if args.paths != "all":
         keep = set(args.paths.split(",")) | {"fp64"}
@@ -1143,7 +1148,8 @@ def main():
             cnt += s["n_dominant"]
             its += s["dominant_iters"]
         restore()
-        kname, bytes_per_iter = dominant_kernel("f32" if bprec == F32 else "f64", args.launch, nnz_c, n_c)
+        kname, bytes_per_iter = dominant_kernel("f32" if bprec in (F32, MIXED_ALL) else "f64", args.launch, nnz_c,
+                                                n_c)
         achieved = bytes_per_iter * its / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
         traffic = None
         tf = ROOT / "profiles" / "traffic_dominant.json"
@@ -1225,7 +1231,7 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": res["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64+f32-ir" if bprec == F32 else "f64", "data": "synthetic",
+        "dtype": "f64+f32-ir" if bprec in (F32, MIXED_ALL) else "f64", "data": "synthetic",
         "config": {"workload": f"cylinder channel Re=100, coarse {info['t_c']} / fine {info['t_f']} P1 triangles, "
                                f"l=1, injection restriction, consistent-mass correction, dt=1e-3, Poisson PCG tol 1e-8 "
                                f"(momentum {args.mom_tol:g}, mass {args.mass_tol:g}), momentum x0 {args.mom_x0}, "

@@ -128,7 +128,9 @@ typedef struct {
 } cgp_params;
 
 typedef struct {
-  int32_t precision;          /* CGP_PREC_*; only the Poisson solve honours FP32_IR */
+  int32_t precision;          /* CGP_PREC_*; FP32_IR: the Poisson solve (FP32 Jacobi-PCG) and the momentum
+                                 solve (FP32 Jacobi-BiCGStab on both components, inner_tol 0 = 1e-5)
+                                 inside FP64 iterative refinement; the mass solve is FP64 only */
   double tol;                 /* stop when ||b - A x||_2 <= tol ||b||_2 (unpreconditioned) */
   int32_t max_iter;           /* Krylov iterations (inner iterations summed for FP32_IR) */
   double inner_tol;           /* FP32_IR: relative reduction asked of each inner FP32 solve; an inner

@@ -128,21 +128,23 @@ cgp_status build_device(cgp_mesh *m) {
   TRY(dalloc(m, &m->d_ut_prev2, 2 * Nf));
   TRY(dalloc(m, &m->d_rec, 8 * Nc));
   TRY(dalloc(m, &m->d_bc, Nc));
-  TRY(dalloc(m, &m->d_state, 4));
+  TRY(dalloc(m, &m->d_state, 5));
   m->red_grid = std::max(8, m->cu_count);
   TRY(dalloc(m, &m->red.partials, size_t(4) * 8 * kMaxRedGrid));
   TRY(dalloc(m, &m->d_scalar, 4));
-  CGP_HIP(hipMemsetAsync(m->d_state, 0, 4 * sizeof(KrylovState), m->stream));
-  CGP_HIP(hipHostMalloc((void **)&m->h_state, 4 * sizeof(KrylovState), hipHostMallocDefault));
+  CGP_HIP(hipMemsetAsync(m->d_state, 0, 5 * sizeof(KrylovState), m->stream));
+  CGP_HIP(hipHostMalloc((void **)&m->h_state, 5 * sizeof(KrylovState), hipHostMallocDefault));
   CGP_HIP(hipHostMalloc((void **)&m->h_scalar, 4 * sizeof(double), hipHostMallocDefault));
   CGP_HIP(hipStreamSynchronize(m->stream));
   return CGP_OK;
 }
 
-bool valid_opts(const cgp_solver_opts *o, bool poisson, bool allow_extrap = false) {
+// poisson: the coarse Poisson solve; allow_extrap: the momentum solve of cgp_step (history-based
+// guesses); allow_fp32: the momentum solve (FP32 inner BiCGStab inside FP64 refinement)
+bool valid_opts(const cgp_solver_opts *o, bool poisson, bool allow_extrap = false, bool allow_fp32 = false) {
   if (!o) return false;
   if (!(o->tol > 0.0) || o->max_iter < 1) return false;
-  if (o->precision != CGP_PREC_FP64 && !(poisson && o->precision == CGP_PREC_FP32_IR)) return false;
+  if (o->precision != CGP_PREC_FP64 && !((poisson || allow_fp32) && o->precision == CGP_PREC_FP32_IR)) return false;
   if (o->x0_mode < CGP_X0_ZERO || o->x0_mode > (poisson ? CGP_X0_POD_GALERKIN : CGP_X0_PREV)) {
     if (!(allow_extrap && !poisson && (o->x0_mode == CGP_X0_EXTRAP || o->x0_mode == CGP_X0_PROJECT))) return false;
   }
@@ -400,7 +402,7 @@ cgp_status cgp_assemble(cgp_mesh *m, const cgp_params *p) {
 cgp_status cgp_momentum(cgp_mesh *m, const cgp_solver_opts *o, const double *g, const double *f, const double *u,
                         double *ut, cgp_stats *st) {
   TRY(ready(m));
-  if (!valid_opts(o, false) || !g || !u || !ut) {
+  if (!valid_opts(o, false, false, true) || !g || !u || !ut) {
     set_error("cgp_momentum: invalid argument");
     return CGP_E_ARG;
   }
@@ -464,7 +466,7 @@ static cgp_status incremental_buffers(cgp_mesh *m) {
 cgp_status cgp_step(cgp_mesh *m, const cgp_step_opts *o, const double *g, const double *f, double *u, double *pf,
                     double *pc, cgp_stats *st) {
   TRY(ready(m));
-  if (!o || !valid_opts(&o->momentum, false, true) || !valid_opts(&o->poisson, true) || !valid_opts(&o->mass, false) ||
+  if (!o || !valid_opts(&o->momentum, false, true, true) || !valid_opts(&o->poisson, true) || !valid_opts(&o->mass, false) ||
       !g || !u || !pf || !pc) {
     set_error("cgp_step: invalid argument");
     return CGP_E_ARG;

@@ -130,6 +130,8 @@ struct cgp_mesh {
   // device operators
   double *d_S = nullptr, *d_M = nullptr, *d_D = nullptr, *d_Mbc = nullptr, *d_dinvM = nullptr, *d_ml = nullptr;
   double *d_A = nullptr, *d_dinvA = nullptr;
+  float *d_A32 = nullptr, *d_dinvA32 = nullptr;  // FP32 momentum matrix and Jacobi inverse (first FP32-refined solve)
+  float2 *d_wf32 = nullptr;                      // 7 fine FP32 2-vectors of the inner BiCGStab (same)
   double *d_K = nullptr, *d_Kbc = nullptr, *d_Dc = nullptr, *d_mc = nullptr, *d_dinvK = nullptr;
   float *d_Kbc32 = nullptr, *d_dinvK32 = nullptr;
   double mc_sum = 0.0;
@@ -153,7 +155,7 @@ struct cgp_mesh {
   int n_surf = 0;                 // fine boundary edges of the marked surface (cgp_surface_set)
   int *d_surf = nullptr;          // their {a, b, third vertex, 0} (int4)
   int n_surf_cap = 0;             // rows d_surf holds
-  cgp::KrylovState *d_state = nullptr;   // 4 solver states
+  cgp::KrylovState *d_state = nullptr;   // 5 solver states
   cgp::KrylovState *h_state = nullptr;   // pinned mirror
   cgp::ReduceScratch red;
   cgp::GmresState gm;
@@ -175,7 +177,7 @@ struct cgp_mesh {
   hipStream_t cap_stream = nullptr;
   // Krylov iterations queued before the first poll of a solve (the last solve's count), per solve
   // kind; the FP32 inner solves keep one per refinement step, whose lengths differ
-  int mom_chunk = 4, p_chunk = 32, p32_chunk[4] = {16, 16, 16, 16}, mass_chunk = 8;
+  int mom_chunk = 4, mom32_chunk = 4, p_chunk = 32, p32_chunk[4] = {16, 16, 16, 16}, mass_chunk = 8;
   // HIP-event timing of every launch of the Poisson SpMV kernel (cgp_step_opts.timing == 2)
   hipEvent_t step_ev[7] = {};      // per-phase events of cgp_step (timing >= 1)
   bool kt_on = false;

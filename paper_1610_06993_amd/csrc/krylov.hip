@@ -634,13 +634,26 @@ __global__ void __launch_bounds__(kMaxBlock) k_bi_init(int n, const int *__restr
   put_partials<4>(acc, Pout);
 }
 
+// Vector and matrix precision of a BiCGStab solve: T = double (the FP64 solve) or float (the inner
+// solve of FP32 iterative refinement); scalars, dot products and the arithmetic are FP64 either way.
+template <typename T> struct v2_of;
+template <> struct v2_of<double> { using type = double2; };
+template <> struct v2_of<float> { using type = float2; };
+template <typename T>
+__device__ __forceinline__ typename v2_of<T>::type mk2(double a, double b) {
+  return typename v2_of<T>::type{(T)a, (T)b};
+}
+
 // Iteration `it` start: reduce (r.r, r^.r) of the previous iteration (or the
 // init partials), test convergence, rho_it = r^.r, beta = (rho_it /
 // rho_{it-1}) (alpha_{it-1} / omega_{it-1}); p = r + beta (p - omega v), p^ = D^-1 p.
-__global__ void __launch_bounds__(kMaxBlock) k_bi_p(int Gin, int it, int n, const double2 *__restrict__ r,
-                                                   double2 *__restrict__ p, const double2 *__restrict__ v,
-                                                   const double *__restrict__ dinv, double2 *__restrict__ ph,
+template <typename T>
+__global__ void __launch_bounds__(kMaxBlock) k_bi_p(int Gin, int it, int n, const typename v2_of<T>::type *__restrict__ r,
+                                                   typename v2_of<T>::type *__restrict__ p,
+                                                   const typename v2_of<T>::type *__restrict__ v,
+                                                   const T *__restrict__ dinv, typename v2_of<T>::type *__restrict__ ph,
                                                    const double *__restrict__ Pin, KrylovState *__restrict__ st) {
+  using V2 = typename v2_of<T>::type;
   if (st->status || all_done<2>(st)) return;
   double t4[4];
   sum_partials<4>(Pin, Gin, t4);
@@ -686,22 +699,24 @@ __global__ void __launch_bounds__(kMaxBlock) k_bi_p(int Gin, int it, int n, cons
   const bool a0 = !done[0], a1 = !done[1];
   const int stride = gridDim.x * blockDim.x;
   for (int i = xcd_block() * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const double2 rr2 = r[i], vv = v[i];
-    double2 pp = p[i];
-    if (a0) pp.x = rr2.x + beta[0] * (pp.x - om[0] * vv.x);
-    if (a1) pp.y = rr2.y + beta[1] * (pp.y - om[1] * vv.y);
+    const V2 rr2 = r[i], vv = v[i];
+    V2 pp = p[i];
+    if (a0) pp.x = (T)((double)rr2.x + beta[0] * ((double)pp.x - om[0] * (double)vv.x));
+    if (a1) pp.y = (T)((double)rr2.y + beta[1] * ((double)pp.y - om[1] * (double)vv.y));
     p[i] = pp;
     const double d = dinv[i];
-    ph[i] = make_double2(d * pp.x, d * pp.y);
+    ph[i] = mk2<T>(d * (double)pp.x, d * (double)pp.y);
   }
 }
 
 // v = A p^; partials r^.v
-template <int L>
+template <typename T, int L>
 __global__ void __launch_bounds__(kMaxBlock) k_bi_v(int n, const int *__restrict__ rp, const int *__restrict__ col,
-                                                   const double *__restrict__ A, const double2 *__restrict__ ph,
-                                                   double2 *__restrict__ v, const double2 *__restrict__ rh,
+                                                   const T *__restrict__ A, const typename v2_of<T>::type *__restrict__ ph,
+                                                   typename v2_of<T>::type *__restrict__ v,
+                                                   const typename v2_of<T>::type *__restrict__ rh,
                                                    double *__restrict__ Pout, const KrylovState *__restrict__ st) {
+  using V2 = typename v2_of<T>::type;
   if (st->status || all_done<2>(st)) return;
   const int lane = threadIdx.x & (L - 1);
   const int rows_per_grid = gridDim.x * blockDim.x / L;
@@ -710,30 +725,33 @@ __global__ void __launch_bounds__(kMaxBlock) k_bi_v(int n, const int *__restrict
     double sx = 0.0, sy = 0.0;
     for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
       const double a = A[k];
-      const double2 xc = ph[col[k]];
-      sx += a * xc.x;
-      sy += a * xc.y;
+      const V2 xc = ph[col[k]];
+      sx += a * (double)xc.x;
+      sy += a * (double)xc.y;
     }
     sx = group_sum<L>(sx);
     sy = group_sum<L>(sy);
     if (lane == 0) {
-      v[row] = make_double2(sx, sy);
-      const double2 h = rh[row];
-      acc[0] += h.x * sx;
-      acc[1] += h.y * sy;
+      const V2 vw = mk2<T>(sx, sy);
+      v[row] = vw;
+      const V2 h = rh[row];
+      acc[0] += (double)h.x * (double)vw.x;
+      acc[1] += (double)h.y * (double)vw.y;
     }
   }
   put_partials<2>(acc, Pout);
 }
 
 // alpha = rho / (r^.v); s = r - alpha v formed on the fly; t = A (D^-1 s); partials (t.s, t.t)
-template <int L>
+template <typename T, int L>
 __global__ void __launch_bounds__(kMaxBlock) k_bi_t(int Gin, int it, int n, const int *__restrict__ rp,
-                                                   const int *__restrict__ col, const double *__restrict__ A,
-                                                   const double2 *__restrict__ r, const double2 *__restrict__ v,
-                                                   const double *__restrict__ dinv, double2 *__restrict__ t,
+                                                   const int *__restrict__ col, const T *__restrict__ A,
+                                                   const typename v2_of<T>::type *__restrict__ r,
+                                                   const typename v2_of<T>::type *__restrict__ v,
+                                                   const T *__restrict__ dinv, typename v2_of<T>::type *__restrict__ t,
                                                    const double *__restrict__ Pin, double *__restrict__ Pout,
                                                    KrylovState *__restrict__ st) {
+  using V2 = typename v2_of<T>::type;
   if (st->status || all_done<2>(st)) return;
   double rv[2];
   sum_partials<2>(Pin, Gin, rv);
@@ -756,32 +774,39 @@ __global__ void __launch_bounds__(kMaxBlock) k_bi_t(int Gin, int it, int n, cons
     double sx = 0.0, sy = 0.0;
     for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
       const int j = col[k];
-      const double a = A[k] * dinv[j];
-      const double2 rr = r[j], vv = v[j];
-      sx += a * (rr.x - al[0] * vv.x);
-      sy += a * (rr.y - al[1] * vv.y);
+      const double a = (double)A[k] * (double)dinv[j];
+      const V2 rr = r[j], vv = v[j];
+      sx += a * ((double)rr.x - al[0] * (double)vv.x);
+      sy += a * ((double)rr.y - al[1] * (double)vv.y);
     }
     sx = group_sum<L>(sx);
     sy = group_sum<L>(sy);
     if (lane == 0) {
-      t[row] = make_double2(sx, sy);
-      const double2 rr = r[row], vv = v[row];
-      const double s0 = rr.x - al[0] * vv.x, s1 = rr.y - al[1] * vv.y;
-      acc[0] += sx * s0;
-      acc[1] += sy * s1;
-      acc[2] += sx * sx;
-      acc[3] += sy * sy;
+      const V2 tw = mk2<T>(sx, sy);
+      t[row] = tw;
+      const V2 rr = r[row], vv = v[row];
+      const double s0 = (double)rr.x - al[0] * (double)vv.x, s1 = (double)rr.y - al[1] * (double)vv.y;
+      const double tx = tw.x, ty = tw.y;
+      acc[0] += tx * s0;
+      acc[1] += ty * s1;
+      acc[2] += tx * tx;
+      acc[3] += ty * ty;
     }
   }
   put_partials<4>(acc, Pout);
 }
 
 // omega = (t.s)/(t.t); x += alpha p^ + omega D^-1 s, r = s - omega t; partials (r.r, r^.r)
-__global__ void __launch_bounds__(kMaxBlock) k_bi_x(int Gin, int it, int n, double2 *__restrict__ x, double2 *__restrict__ r,
-                                                   const double2 *__restrict__ v, const double2 *__restrict__ t,
-                                                   const double *__restrict__ dinv, const double2 *__restrict__ ph,
-                                                   const double2 *__restrict__ rh, const double *__restrict__ Pin,
-                                                   double *__restrict__ Pout, KrylovState *__restrict__ st) {
+template <typename T>
+__global__ void __launch_bounds__(kMaxBlock) k_bi_x(int Gin, int it, int n, typename v2_of<T>::type *__restrict__ x,
+                                                   typename v2_of<T>::type *__restrict__ r,
+                                                   const typename v2_of<T>::type *__restrict__ v,
+                                                   const typename v2_of<T>::type *__restrict__ t,
+                                                   const T *__restrict__ dinv, const typename v2_of<T>::type *__restrict__ ph,
+                                                   const typename v2_of<T>::type *__restrict__ rh,
+                                                   const double *__restrict__ Pin, double *__restrict__ Pout,
+                                                   KrylovState *__restrict__ st) {
+  using V2 = typename v2_of<T>::type;
   if (st->status || all_done<2>(st)) return;
   double t4[4];
   sum_partials<4>(Pin, Gin, t4);
@@ -799,25 +824,26 @@ __global__ void __launch_bounds__(kMaxBlock) k_bi_x(int Gin, int it, int n, doub
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   const int stride = gridDim.x * blockDim.x;
   for (int i = xcd_block() * blockDim.x + threadIdx.x; i < n; i += stride) {
-    double2 xx = x[i], rr = r[i];
-    const double2 vv = v[i], tt = t[i], pp = ph[i], hh = rh[i];
+    V2 xx = x[i], rr = r[i];
+    const V2 vv = v[i], tt = t[i], pp = ph[i], hh = rh[i];
     const double d = dinv[i];
     if (act[0]) {
-      const double s = rr.x - al[0] * vv.x;
-      xx.x += al[0] * pp.x + w[0] * (d * s);
-      rr.x = s - w[0] * tt.x;
+      const double s = (double)rr.x - al[0] * (double)vv.x;
+      xx.x = (T)((double)xx.x + (al[0] * (double)pp.x + w[0] * (d * s)));
+      rr.x = (T)(s - w[0] * (double)tt.x);
     }
     if (act[1]) {
-      const double s = rr.y - al[1] * vv.y;
-      xx.y += al[1] * pp.y + w[1] * (d * s);
-      rr.y = s - w[1] * tt.y;
+      const double s = (double)rr.y - al[1] * (double)vv.y;
+      xx.y = (T)((double)xx.y + (al[1] * (double)pp.y + w[1] * (d * s)));
+      rr.y = (T)(s - w[1] * (double)tt.y);
     }
     x[i] = xx;
     r[i] = rr;
-    acc[0] += rr.x * rr.x;
-    acc[1] += rr.y * rr.y;
-    acc[2] += hh.x * rr.x;
-    acc[3] += hh.y * rr.y;
+    const double rx = rr.x, ry = rr.y;
+    acc[0] += rx * rx;
+    acc[1] += ry * ry;
+    acc[2] += (double)hh.x * rx;
+    acc[3] += (double)hh.y * ry;
   }
   put_partials<4>(acc, Pout);
 }
@@ -837,6 +863,120 @@ __global__ void __launch_bounds__(kMaxBlock) k_bi_finish(int it_end, int G, cons
   }
   st->iters = it_end;
   if (bad) st->status = CGP_E_NONFINITE;
+}
+
+// ---- FP32 inner BiCGStab inside FP64 iterative refinement of the momentum solve (both components)
+// FP32 copies of the eliminated momentum matrix and its Jacobi inverse (once per solve).
+__global__ void k_mir_convert(long nnz, int n, const double *__restrict__ A, const double *__restrict__ dinv,
+                              float *__restrict__ A32, float *__restrict__ dinv32) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += stride) {
+    A32[k] = (float)A[k];
+    if (k < n) dinv32[k] = (float)dinv[k];
+  }
+}
+
+// r64 = b - A x in FP64 (both components); partials (r.r, b.b) per component.
+template <int L>
+__global__ void __launch_bounds__(kMaxBlock) k_mir_residual(int n, const int *__restrict__ rp,
+                                                           const int *__restrict__ col, const double *__restrict__ A,
+                                                           const double2 *__restrict__ b, const double2 *__restrict__ x,
+                                                           double2 *__restrict__ r64, double *__restrict__ Pout) {
+  const int lane = threadIdx.x & (L - 1);
+  const int rows_per_grid = gridDim.x * blockDim.x / L;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int row = (xcd_block() * blockDim.x + threadIdx.x) / L; row < n; row += rows_per_grid) {
+    double sx = 0.0, sy = 0.0;
+    for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
+      const double a = A[k];
+      const double2 xc = x[col[k]];
+      sx += a * xc.x;
+      sy += a * xc.y;
+    }
+    sx = group_sum<L>(sx);
+    sy = group_sum<L>(sy);
+    if (lane == 0) {
+      const double2 bb = b[row];
+      const double2 rr = make_double2(bb.x - sx, bb.y - sy);
+      r64[row] = rr;
+      acc[0] += rr.x * rr.x;
+      acc[1] += rr.y * rr.y;
+      acc[2] += bb.x * bb.x;
+      acc[3] += bb.y * bb.y;
+    }
+  }
+  put_partials<4>(acc, Pout);
+}
+
+// Outer test on the FP64 residual (per component: done when ||r|| <= tol ||b||), then the inner
+// solve's start: r = r^ = r64 / ||r64|| in FP32 for the components still refining (zero for the
+// others, which the inner solve then marks done at once), d = p = v = 0; inner tolerance = what the
+// outer tolerance still needs (the smaller over the refining components), at least inner_tol.
+// Partials (r.r, r.r) per component in the layout of the FP64 init, so that the first iteration
+// reads them the same way.
+__global__ void __launch_bounds__(kMaxBlock) k_mir_init(int Gin, int n, double inner_tol,
+                                                       const double2 *__restrict__ r64, float2 *__restrict__ r,
+                                                       float2 *__restrict__ rh, float2 *__restrict__ p,
+                                                       float2 *__restrict__ v, float2 *__restrict__ d,
+                                                       const double *__restrict__ Pin, double *__restrict__ Pout,
+                                                       KrylovState *__restrict__ so, KrylovState *__restrict__ si) {
+  double t4[4];
+  sum_partials<4>(Pin, Gin, t4);
+  double rn[2], bn[2], sc[2];
+  bool act[2], bad = false;
+  double need = 1.0;
+  for (int c = 0; c < 2; c++) {
+    rn[c] = sqrt(t4[c]);
+    bn[c] = sqrt(t4[2 + c]);
+    bad = bad || !is_finite(rn[c]);
+    act[c] = !(bn[c] == 0.0 || rn[c] <= so->tol * bn[c]);
+    sc[c] = act[c] && rn[c] > 0.0 ? 1.0 / rn[c] : 0.0;
+    if (act[c]) need = fmin(need, inner_tol_for(inner_tol, so->tol, rn[c], bn[c]));
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int c = 0; c < 2; c++) {
+      so->bnorm[c] = bn[c];
+      so->rnorm[c] = rn[c];
+      so->zero_b[c] = (bn[c] == 0.0);
+      so->done[c] = !act[c];
+    }
+    if (bad) so->status = CGP_E_NONFINITE;
+    KrylovState t{};
+    t.tol = need;
+    t.maxit = si->maxit;
+    t.ncomp = 2;
+    for (int c = 0; c < 2; c++) t.done[c] = !act[c] || bad;
+    *si = t;
+  }
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int stride = gridDim.x * blockDim.x;
+  for (int i = xcd_block() * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double2 q = r64[i];
+    const float2 z = make_float2((float)(q.x * sc[0]), (float)(q.y * sc[1]));
+    r[i] = z;
+    rh[i] = z;
+    p[i] = make_float2(0.0f, 0.0f);
+    v[i] = make_float2(0.0f, 0.0f);
+    d[i] = make_float2(0.0f, 0.0f);
+    const double zx = z.x, zy = z.y;
+    acc[0] += zx * zx;
+    acc[1] += zy * zy;
+    acc[2] += zx * zx;
+    acc[3] += zy * zy;
+  }
+  put_partials<4>(acc, Pout);
+}
+
+// x += ||r64|| d on the components that refined (FP64).
+__global__ void k_mir_update(int n, double2 *__restrict__ x, const float2 *__restrict__ d,
+                             const KrylovState *__restrict__ so) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float2 dd = d[i];
+  double2 xx = x[i];
+  if (!so->done[0]) xx.x += so->rnorm[0] * (double)dd.x;
+  if (!so->done[1]) xx.y += so->rnorm[1] * (double)dd.y;
+  x[i] = xx;
 }
 
 // ------------------------------------------------------------------ projected momentum guess
@@ -1135,7 +1275,7 @@ using namespace dev;
 
 namespace {
 
-enum { SLOT_MOM = 0, SLOT_P = 1, SLOT_PIN = 2, SLOT_MASS = 3 };
+enum { SLOT_MOM = 0, SLOT_P = 1, SLOT_PIN = 2, SLOT_MASS = 3, SLOT_MOMIN = 4 };
 // partial-sum regions (each holds up to 8 arrays of kMaxRedGrid doubles)
 enum { R_INIT = 0, R_A = 1, R_B = 2, R_C = 3 };
 
@@ -1444,6 +1584,124 @@ cgp_status cg1_loop(cgp_mesh *m, int slot, int n, const int *rp, const int *col,
 
 }  // namespace
 
+// BiCGStab iterations (both components) from the state and partials an init kernel left: T = double
+// (the FP64 solve; x is the solution) or float (the inner solve of the refinement; x is its
+// correction).  Chunks of iterations, each followed by a state poll; *chunk_hint is the next solve's
+// first chunk (its count + 1: momentum counts are stable, so usually one poll per solve).
+template <typename T>
+cgp_status bicg_loop(cgp_mesh *m, int slot, int n, const T *A, const T *dinv, typename v2_of<T>::type *x,
+                     typename v2_of<T>::type *r, typename v2_of<T>::type *rh, typename v2_of<T>::type *p,
+                     typename v2_of<T>::type *v, typename v2_of<T>::type *t, typename v2_of<T>::type *ph,
+                     int g_init, int maxit, int *chunk_hint) {
+  using V2 = typename v2_of<T>::type;
+  hipStream_t s = m->stream;
+  KrylovState *st = m->d_state + slot;
+  const cgp_tuning_knobs &tk = m->tune.fine;
+  const LoopShapes sh = loop_shapes(tk, n);
+  const int *rp = m->d_rp_f, *col = m->d_col_f;
+  double *Pinit = region(m, R_INIT), *Pv = region(m, R_A), *Pt = region(m, R_B), *Px = region(m, R_C);
+  int it = 0, chunk = std::max(1, std::min(*chunk_hint, maxit));
+  for (;;) {
+    dispatch_L(tk.lanes, [&](auto LC) {
+      constexpr int LL = decltype(LC)::value;
+      for (int c = 0; c < chunk && it < maxit; c++, it++) {
+        hipLaunchKernelGGL(k_bi_p<T>, dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, it == 0 ? g_init : sh.elem.grid,
+                           it, n, (const V2 *)r, p, (const V2 *)v, dinv, ph, (const double *)(it == 0 ? Pinit : Px),
+                           st);
+        hipLaunchKernelGGL((k_bi_v<T, LL>), dim3(sh.rows.grid), dim3(sh.rows.block), 0, s, n, rp, col, A,
+                           (const V2 *)ph, v, (const V2 *)rh, Pv, (const KrylovState *)st);
+        hipLaunchKernelGGL((k_bi_t<T, LL>), dim3(sh.rows.grid), dim3(sh.rows.block), 0, s, sh.rows.grid, it, n, rp,
+                           col, A, (const V2 *)r, (const V2 *)v, dinv, t, (const double *)Pv, Pt, st);
+        hipLaunchKernelGGL(k_bi_x<T>, dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, sh.rows.grid, it, n, x, r,
+                           (const V2 *)v, (const V2 *)t, dinv, (const V2 *)ph, (const V2 *)rh, (const double *)Pt,
+                           Px, st);
+      }
+    });
+    hipLaunchKernelGGL(k_bi_finish, dim3(1), dim3(256), 0, s, it, it == 0 ? g_init : sh.elem.grid,
+                       (const double *)(it == 0 ? Pinit : Px), st);
+    CGP_HIP(hipGetLastError());
+    cgp_status ps = poll(m, slot);
+    if (ps) return ps;
+    const KrylovState &h = m->h_state[slot];
+    if (h.status || host_all_done(h) || it >= maxit) break;
+    chunk = 2;
+  }
+  *chunk_hint = std::max(1, m->h_state[slot].iters + 1);
+  return CGP_OK;
+}
+
+// FP32 inner BiCGStab inside FP64 iterative refinement (outer state SLOT_MOM, inner SLOT_MOMIN):
+// r64 = b - A x, outer test, inner solve of A d = r64 / ||r64|| in FP32 to the reduction still
+// needed, x += ||r64|| d, until both components meet the tolerance.  The FP32 matrix and vectors
+// are allocated at the first such solve.
+cgp_status momentum_ir(cgp_mesh *m, const cgp_solver_opts *o, const double2 *b, double2 *x, int *inner_total) {
+  hipStream_t s = m->stream;
+  const int n = m->pf.n;
+  const long nnz = m->pf.nnz;
+  if (!m->d_A32) {
+    void *q = nullptr;
+    CGP_HIP(hipMalloc(&q, sizeof(float) * ((size_t)nnz + (size_t)n)));
+    m->allocations.push_back(q);
+    m->d_A32 = (float *)q;
+    m->d_dinvA32 = m->d_A32 + nnz;
+    CGP_HIP(hipMalloc(&q, sizeof(float2) * 7 * (size_t)n));
+    m->allocations.push_back(q);
+    m->d_wf32 = (float2 *)q;
+  }
+  const cgp_tuning_knobs &tk = m->tune.fine;
+  const LoopShapes sh = loop_shapes(tk, n);
+  hipLaunchKernelGGL(k_mir_convert, dim3(std::min<long>(4096, (nnz + 255) / 256)), dim3(256), 0, s, nnz, n,
+                     (const double *)m->d_A, (const double *)m->d_dinvA, m->d_A32, m->d_dinvA32);
+  float2 *w = m->d_wf32;
+  float2 *r = w, *rh = w + n, *p = w + 2 * (size_t)n, *v = w + 3 * (size_t)n, *t = w + 4 * (size_t)n,
+         *ph = w + 5 * (size_t)n, *d = w + 6 * (size_t)n;
+  double2 *r64 = (double2 *)m->d_wf[1];
+  KrylovState *so = m->d_state + SLOT_MOM, *si = m->d_state + SLOT_MOMIN;
+  const double inner_tol = o->inner_tol > 0 ? o->inner_tol : 1e-5;
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, si, inner_tol, o->max_iter, 2);
+  *inner_total = 0;
+  for (int outer = 0; outer < 50; outer++) {
+    dispatch_L(tk.lanes, [&](auto LC) {
+      constexpr int LL = decltype(LC)::value;
+      hipLaunchKernelGGL((k_mir_residual<LL>), dim3(sh.rows.grid), dim3(sh.rows.block), 0, s, n, m->d_rp_f,
+                         m->d_col_f, (const double *)m->d_A, b, (const double2 *)x, r64, region(m, R_C));
+    });
+    hipLaunchKernelGGL(k_mir_init, dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, sh.rows.grid, n, inner_tol,
+                       (const double2 *)r64, r, rh, p, v, d, (const double *)region(m, R_C), region(m, R_INIT), so,
+                       si);
+    const int budget = std::max(1, o->max_iter - *inner_total);
+    cgp_status ls = bicg_loop<float>(m, SLOT_MOMIN, n, m->d_A32, m->d_dinvA32, d, r, rh, p, v, t, ph, sh.elem.grid,
+                                     budget, &m->mom32_chunk);
+    if (ls) return ls;
+    cgp_status ps = poll(m, SLOT_MOM);
+    if (ps) return ps;
+    const KrylovState ho = m->h_state[SLOT_MOM], hi = m->h_state[SLOT_MOMIN];
+    if (ho.status || host_all_done(ho)) break;
+    if (hi.status) {
+      m->h_state[SLOT_MOM].status = hi.status;
+      break;
+    }
+    *inner_total += hi.iters;
+    hipLaunchKernelGGL(k_mir_update, dim3(blocks_1d(n)), dim3(256), 0, s, n, x, (const float2 *)d,
+                       (const KrylovState *)so);
+    if (*inner_total >= o->max_iter) {  // the residual of the last iterate, for the report
+      dispatch_L(tk.lanes, [&](auto LC) {
+        constexpr int LL = decltype(LC)::value;
+        hipLaunchKernelGGL((k_mir_residual<LL>), dim3(sh.rows.grid), dim3(sh.rows.block), 0, s, n, m->d_rp_f,
+                           m->d_col_f, (const double *)m->d_A, b, (const double2 *)x, r64, region(m, R_C));
+      });
+      hipLaunchKernelGGL(k_mir_init, dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, sh.rows.grid, n, inner_tol,
+                         (const double2 *)r64, r, rh, p, v, d, (const double *)region(m, R_C), region(m, R_INIT),
+                         so, si);
+      if ((ps = poll(m, SLOT_MOM))) return ps;
+      if (!host_all_done(m->h_state[SLOT_MOM])) m->h_state[SLOT_MOM].status = CGP_E_NOCONV;
+      break;
+    }
+  }
+  CGP_HIP(hipGetLastError());
+  return CGP_OK;
+}
+
 // ------------------------------------------------------------------ step 1
 cgp_status drv_momentum(cgp_mesh *m, const cgp_solver_opts *o, const double *g, const double *f, const double *u,
                         double *ut, cgp_stats *stats, const double *pn) {
@@ -1502,50 +1760,32 @@ cgp_status drv_momentum(cgp_mesh *m, const cgp_solver_opts *o, const double *g, 
   m->ut_hist = extrap ? std::min(m->ut_hist + 1, 3) : 0;
   // known values in the initial guess: the eliminated Dirichlet rows then start (and stay) exact
   launch_set_dirichlet(m, g, ut);
-  double2 *r = (double2 *)m->d_wf[1], *rh = (double2 *)m->d_wf[2], *p = (double2 *)m->d_wf[3];
-  double2 *v = (double2 *)m->d_wf[4], *t = (double2 *)m->d_wf[5], *ph = (double2 *)m->d_wf[6];
   KrylovState *st = m->d_state + SLOT_MOM;
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, st, o->tol, o->max_iter, 2);
   const cgp_tuning_knobs &tk = m->tune.fine;
   const LoopShapes sh = loop_shapes(tk, n);
-  const int *rp = m->d_rp_f, *col = m->d_col_f;
-  const double *A = m->d_A, *dinv = m->d_dinvA;
   double2 *x = (double2 *)ut;
-  double *Pinit = region(m, R_INIT), *Pv = region(m, R_A), *Pt = region(m, R_B), *Px = region(m, R_C);
-  dispatch_L(tk.lanes, [&](auto LC) {
-    constexpr int LL = decltype(LC)::value;
-    hipLaunchKernelGGL((k_bi_init<LL>), dim3(sh.rows.grid), dim3(sh.rows.block), 0, s, n, rp, col, A,
-                       (const double2 *)rhs, (const double2 *)x, r, rh, p, v, Pinit);
-  });
-  int it = 0, chunk = std::max(1, std::min(m->mom_chunk, o->max_iter));
-  for (;;) {
+  int mom_iters = 0;
+  if (o->precision == CGP_PREC_FP32_IR) {
+    cgp_status ls = momentum_ir(m, o, (const double2 *)rhs, x, &mom_iters);
+    if (ls) return ls;
+  } else {
+    double2 *r = (double2 *)m->d_wf[1], *rh = (double2 *)m->d_wf[2], *p = (double2 *)m->d_wf[3];
+    double2 *v = (double2 *)m->d_wf[4], *t = (double2 *)m->d_wf[5], *ph = (double2 *)m->d_wf[6];
+    double *Pinit = region(m, R_INIT);
     dispatch_L(tk.lanes, [&](auto LC) {
       constexpr int LL = decltype(LC)::value;
-      for (int c = 0; c < chunk && it < o->max_iter; c++, it++) {
-        hipLaunchKernelGGL(k_bi_p, dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, it == 0 ? sh.rows.grid : sh.elem.grid,
-                           it, n, (const double2 *)r, p, (const double2 *)v, dinv, ph,
-                           (const double *)(it == 0 ? Pinit : Px), st);
-        hipLaunchKernelGGL((k_bi_v<LL>), dim3(sh.rows.grid), dim3(sh.rows.block), 0, s, n, rp, col, A,
-                           (const double2 *)ph, v, (const double2 *)rh, Pv, (const KrylovState *)st);
-        hipLaunchKernelGGL((k_bi_t<LL>), dim3(sh.rows.grid), dim3(sh.rows.block), 0, s, sh.rows.grid, it, n, rp, col,
-                           A, (const double2 *)r, (const double2 *)v, dinv, t, (const double *)Pv, Pt, st);
-        hipLaunchKernelGGL(k_bi_x, dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, sh.rows.grid, it, n, x, r,
-                           (const double2 *)v, (const double2 *)t, dinv, (const double2 *)ph, (const double2 *)rh,
-                           (const double *)Pt, Px, st);
-      }
+      hipLaunchKernelGGL((k_bi_init<LL>), dim3(sh.rows.grid), dim3(sh.rows.block), 0, s, n, m->d_rp_f, m->d_col_f,
+                         (const double *)m->d_A, (const double2 *)rhs, (const double2 *)x, r, rh, p, v, Pinit);
     });
-    hipLaunchKernelGGL(k_bi_finish, dim3(1), dim3(256), 0, s, it, it == 0 ? sh.rows.grid : sh.elem.grid,
-                       (const double *)(it == 0 ? Pinit : Px), st);
-    CGP_HIP(hipGetLastError());
-    cgp_status ps = poll(m, SLOT_MOM);
-    if (ps) return ps;
-    const KrylovState &h = m->h_state[SLOT_MOM];
-    if (h.status || host_all_done(h) || it >= o->max_iter) break;
-    chunk = 2;
+    cgp_status ls = bicg_loop<double>(m, SLOT_MOM, n, m->d_A, m->d_dinvA, x, r, rh, p, v, t, ph, sh.rows.grid,
+                                      o->max_iter, &m->mom_chunk);
+    if (ls) return ls;
+    mom_iters = m->h_state[SLOT_MOM].iters;
   }
   hipLaunchKernelGGL((k_zero_b_fix<2>), dim3(blocks_1d(n)), dim3(256), 0, s, n, ut, (const KrylovState *)st);
-  const KrylovState h = m->h_state[SLOT_MOM];
-  m->mom_chunk = std::max(1, h.iters + 1);  // one iteration of slack: usually a single poll per solve
+  KrylovState h = m->h_state[SLOT_MOM];
+  h.iters = mom_iters;
   if (project && status_of(h, SLOT_MOM) == CGP_OK) {
     hipLaunchKernelGGL(k_proj_push, dim3(blocks_1d(n)), dim3(256), 0, s, n, (const double2 *)ut,
                        (double2 *)m->d_uhist, m->uh_head);
@@ -1555,7 +1795,7 @@ cgp_status drv_momentum(cgp_mesh *m, const cgp_solver_opts *o, const double *g, 
     m->uh_count = m->uh_head = 0;
   }
   if (stats) {
-    stats->mom_iters = h.iters;
+    stats->mom_iters = mom_iters;
     stats->mom_relres = 0.0;
     for (int c = 0; c < 2; c++)
       stats->mom_relres = std::max(stats->mom_relres, h.bnorm[c] > 0 ? h.rnorm[c] / h.bnorm[c] : 0.0);

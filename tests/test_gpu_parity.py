@@ -124,6 +124,49 @@ def test_momentum_solve(env):
     assert rel(ut.cpu().numpy(), ref) <= 1e-10, (st, ost)
 
 
+@pytest.mark.parametrize("which,x0", [("bfs", 0), ("cylinder", 0), ("cylinder", 1)])
+def test_momentum_fp32_refinement(env, which, x0):
+    """The momentum solve with FP32 inner BiCGStab inside FP64 refinement (both components) against
+    the oracle's FP64 solve: the outer test is on the FP64 residual, so the solution meets the FP64
+    tolerance (<= 1e-10 relative at tol 1e-12); from U^n and from zero (the zero start needs several
+    refinement steps, each asking the inner solve for what is still missing)."""
+    torch, cgp, oracle = env
+    X0 = cgp._native
+    case = W.case_bfs(nx=80, ny=10) if which == "bfs" else W.case_cylinder(5000, seed=4)
+    g, o = make_pair(env, case.mesh, 1, case.rho, case.mu, case.dt)
+    xy = g.export("xy")
+    rng = np.random.default_rng(3)
+    u = case.initial(xy, g.export("vdir")) + 0.1 * rng.normal(size=(g.info["n_f"], 2))
+    gd = case.dirichlet(xy, case.dt)
+    ut = torch.zeros(g.info["n_f"], 2, dtype=torch.float64, device="cuda")
+    st = g.momentum(dev(torch, gd), dev(torch, u), ut,
+                    opts=cgp.SolverOpts(tol=1e-12, max_iter=20000, precision=X0.PREC_FP32_IR,
+                                        x0_mode=X0.X0_ZERO if x0 else X0.X0_PREV))
+    ref, code, ost = o.momentum(gd, u, tol=1e-14)
+    assert code == 0
+    e = rel(ut.cpu().numpy(), ref)
+    _say(f"  momentum FP32 refinement {which} x0 {'zero' if x0 else 'U^n'}: rel err {e:.2e}, inner iterations "
+         f"{st['mom_iters']} (oracle FP64 {ost['mom_iters']}), residual {st['mom_relres']:.1e}")
+    assert e <= 1e-10 and st["mom_relres"] <= 1e-12
+
+
+def test_step_with_fp32_momentum_and_poisson(env):
+    """Whole steps with FP32 inner solves in both the momentum and the Poisson solve (each inside FP64
+    refinement): per-step local error against the oracle <= 1e-10 with the momentum alone in FP32
+    refinement (tolerances 1e-13), and <= 1e-6 with the Poisson solve's refinement at 1e-10 as well."""
+    torch, cgp, oracle = env
+    X0 = cgp._native
+    case = W.case_cylinder(12000, seed=3)
+    s64 = cgp.SolverOpts(tol=TIGHT, max_iter=100000)
+    m32 = cgp.SolverOpts(tol=TIGHT, max_iter=100000, precision=X0.PREC_FP32_IR)
+    _say("cylinder 12k, FP32-refined momentum, FP64 Poisson")
+    _run_steps(env, case, 1, 3, cgp.StepOpts(momentum=m32, poisson=cgp.SolverOpts(tol=TIGHT_P, max_iter=100000),
+                                              mass=s64), check_every=False)
+    _say("cylinder 12k, FP32-refined momentum and Poisson")
+    p32 = cgp.SolverOpts(tol=1e-10, max_iter=100000, precision=X0.PREC_FP32_IR, inner_tol=1e-4)
+    _run_steps(env, case, 1, 3, cgp.StepOpts(momentum=m32, poisson=p32, mass=s64), check_every=False, bar=1e-6)
+
+
 def test_momentum_matrix(env):
     """The momentum matrix a step forms (A = rho M + dt mu K + dt N(U^n) with the velocity-Dirichlet
     rows reduced to their diagonal and the Dirichlet columns of the other rows cleared, Eq. 19)
@@ -519,6 +562,63 @@ def test_failure_paths(env):
     # the library keeps working after errors
     g.step(gd, u, pf, pc)
     assert torch.isfinite(u).all()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_poisson_at_two_million_rows_by_residual(env, precision):
+    """At 2M rows (the 4M-triangle cylinder at l = 0, past what the oracle solves in seconds; the fused
+    PCG then sums each iteration's partials in a tree): a property that holds at any size, the
+    relative residual ||b - Kbar x|| / ||b|| of the eliminated system recomputed in FP64 on the CPU
+    from the exported operator, at the tolerance (FP64) or the refinement's outer tolerance (FP32
+    inner solves); and the operator's rows at sampled nodes against the oracle's element formulas on
+    the same mesh (K of a P1 triangle, Eq. 17)."""
+    import scipy.sparse as sp
+
+    torch, cgp, oracle = env
+    X0 = cgp._native
+    mesh = W.cylinder_channel(4_000_000, seed=3)
+    g = cgp.Mesh(mesh, 0)
+    g.assemble(1.0, 1e-3, 1e-3)
+    n = g.info["n_c"]
+    assert n > 2_000_000
+    rng = np.random.default_rng(21)
+    b = rng.normal(size=n)
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    tol = 1e-10 if precision == 0 else 1e-8  # FP32 inner solves gain ~20x per refinement step at this size
+    st = g.poisson_solve(dev(torch, b), x, cgp.SolverOpts(tol=tol, max_iter=200000, x0_mode=X0.X0_ZERO,
+                                                          precision=precision))
+    rp, col, K = g.export("rowptr_c"), g.export("col_c"), g.export("K_c_bc")
+    A = sp.csr_matrix((K, col, rp), shape=(n, n))
+    bb = b.copy()
+    bb[g.export("pdir").astype(bool)] = 0.0
+    xs = x.cpu().numpy()
+    relres = float(np.linalg.norm(bb - A @ xs) / np.linalg.norm(bb))
+    _say(f"  {n} rows, precision {precision}: {st['p_iters']} iterations, residual recomputed on the CPU "
+         f"{relres:.2e} (solver's own {st['p_relres']:.2e})")
+    # the FP64 PCG stops on its recursively updated residual, which after 1e4 iterations drifts from the
+    # true b - Kbar x by rounding (measured: 9.9e-11 against 1.11e-10); the refinement's outer test is on
+    # the explicitly formed FP64 residual
+    assert relres <= (1.5 if precision == 0 else 1.05) * tol
+    # sampled rows of the unconstrained operator against an element-by-element sum of P1 stiffness
+    Kraw = g.export("K_c")
+    xy, tri = mesh.xy, mesh.tri
+    rows = rng.choice(n, 50, replace=False)
+    for r in rows:
+        ref = {}
+        for t in np.nonzero((tri == r).any(1))[0]:
+            v = tri[t]
+            p = xy[v]
+            area2 = (p[1, 0] - p[0, 0]) * (p[2, 1] - p[0, 1]) - (p[2, 0] - p[0, 0]) * (p[1, 1] - p[0, 1])
+            bgrad = np.array([p[1, 1] - p[2, 1], p[2, 1] - p[0, 1], p[0, 1] - p[1, 1]])
+            cgrad = np.array([p[2, 0] - p[1, 0], p[0, 0] - p[2, 0], p[1, 0] - p[0, 0]])
+            i = list(v).index(r)
+            for j in range(3):
+                ref[int(v[j])] = ref.get(int(v[j]), 0.0) + (bgrad[i] * bgrad[j] + cgrad[i] * cgrad[j]) / (2.0 * area2)
+        got = {int(col[k]): Kraw[k] for k in range(rp[r], rp[r + 1])}
+        assert set(got) == set(ref)
+        for j in ref:
+            assert abs(got[j] - ref[j]) <= 1e-12 * max(1.0, abs(ref[r]))
+    g.close()
 
 
 @pytest.mark.parametrize("which,steps", [("cylinder", 3), ("backward_step", 5)])
