@@ -837,6 +837,9 @@ def main():
     ap.add_argument("--gmres-max-iter", type=int, default=300,
                     help="iteration cap of ILU(0)-GMRES at the full size (each iteration is two level-scheduled "
                          "triangular solves)")
+    ap.add_argument("--mass-x0", default="lumped", choices=["lumped", "extrap"],
+                    help="mass solve start: the lumped correction, or that plus the last step's consistent-minus-"
+                         "lumped difference")
     ap.add_argument("--pcg-graph", type=int, default=0,
                     help="1: fused Poisson PCG iterations launched as captured graphs of 8 (0, one launch each, is "
                          "the library default)")
@@ -972,6 +975,7 @@ def main():
     launch = {"loop": 1, "persistent": 2, "fused": 3}[args.launch]
 
     mom_x0 = {"prev": X0.X0_PREV, "extrap": X0.X0_EXTRAP, "project": X0.X0_PROJECT}[args.mom_x0]
+    mass_x0 = {"lumped": X0.X0_PREV, "extrap": X0.X0_EXTRAP}[args.mass_x0]
 
     F64, F32 = cgp._native.PREC_FP64, cgp._native.PREC_FP32_IR
     MIXED_ALL = 100  # the bench's own code: FP32 inner solves in the momentum and the Poisson solve
@@ -982,7 +986,7 @@ def main():
         return StepOpts(momentum=SolverOpts(tol=args.mom_tol, max_iter=5000, x0_mode=mom_x0, precision=mp),
                         poisson=SolverOpts(tol=tol, max_iter=100000, precision=pp, inner_tol=args.inner_tol,
                                            x0_mode=x0, launch=launch),
-                        mass=SolverOpts(tol=args.mass_tol, max_iter=2000), timing=timing)
+                        mass=SolverOpts(tol=args.mass_tol, max_iter=2000, x0_mode=mass_x0), timing=timing)
 
     SETTLE = 10  # plain steps from the impulsive start before the training data is recorded
     for k in range(SETTLE):
@@ -1102,12 +1106,13 @@ def main():
         for k in range(args.warmup):  # untimed: solver chunk sizes adapt, guess windows turn over
             mesh.step(g, u, pf, pc, opts=opts(prec, x0))
         torch.cuda.synchronize()
-        iters, miters, phases, flow = [], [], {k: 0.0 for k in phase_keys}, []
+        iters, miters, mass_its, phases, flow = [], [], [], {k: 0.0 for k in phase_keys}, []
         t1 = time.perf_counter()
         for k in range(args.steps):
             st = mesh.step(g, u, pf, pc, opts=opts(prec, x0, timing=1))
             iters.append(st["p_iters"])
             miters.append(st["mom_iters"])
+            mass_its.append(st["mass_iters"])
             for key in phase_keys:
                 phases[key] += st[key]
             if k == 0:
@@ -1119,6 +1124,7 @@ def main():
         err_end = one_step_error(prec, x0, model)
         results[name] = dict(steps_per_s=round(args.steps / el, 3), ms_per_step=round(1e3 * el / args.steps, 3),
                              poisson_iters_mean=float(np.mean(iters)), momentum_iters_mean=float(np.mean(miters)),
+                             mass_iters_mean=float(np.mean(mass_its)),
                              rel_err_vs_fp64=max(err_start, err_end), rel_err_vs_fp64_at_restart=err_start,
                              rel_err_vs_fp64_after_timed_steps=err_end,
                              trajectory_diff_vs_fp64=err_traj,

@@ -83,7 +83,7 @@ enum { CGP_X0_ZERO = 0,            /* Krylov initial guess zero */
        CGP_X0_LEARNED = 2,         /* Poisson only: x0 = Phi c, c from the attached POD/MLP model */
        CGP_X0_LEARNED_CORR = 3,    /* Poisson only: x0 = x + Phi dc, dc from the incremental model and b - K x */
        CGP_X0_POD_GALERKIN = 4,    /* Poisson only: previous pressure plus the Galerkin correction in span(Phi) */
-       CGP_X0_EXTRAP = 5,          /* cgp_step momentum only: x0 = 3 U~^n - 3 U~^(n-1) + U~^(n-2), the quadratic
+       CGP_X0_EXTRAP = 5,          /* cgp_step momentum (and mass, see cgp_step_opts) only: x0 = 3 U~^n - 3 U~^(n-1) + U~^(n-2), the quadratic
                                       extrapolation of this mesh's three previous intermediate velocities
                                       (U^n after no such step, linear 2 U~^n - U~^(n-1) after one); the solve
                                       still meets its tolerance */
@@ -146,7 +146,10 @@ typedef struct {
   cgp_solver_opts momentum;   /* step 1, Eq. (19): Jacobi-BiCGStab, both components together */
   cgp_solver_opts poisson;    /* step 3, Eq. (21): Jacobi-PCG on the coarse mesh */
   cgp_solver_opts mass;       /* step 5, Eq. (23): Jacobi-PCG with the consistent mass matrix, started
-                                 from the lumped-mass correction (from 0 when x0_mode = CGP_X0_ZERO) */
+                                 from the lumped-mass correction (from 0 when x0_mode = CGP_X0_ZERO; with
+                                 CGP_X0_EXTRAP, from the lumped correction plus the previous cgp_step's
+                                 consistent-minus-lumped difference, kept per mesh, 16 bytes a fine node
+                                 allocated at first use) */
   int32_t timing;             /* 1: per-phase HIP-event times in cgp_stats; 2: also bracket every launch of
                                  the Poisson Krylov kernel with HIP events (slows the step; for measurement) */
 } cgp_step_opts;

@@ -466,7 +466,9 @@ static cgp_status incremental_buffers(cgp_mesh *m) {
 cgp_status cgp_step(cgp_mesh *m, const cgp_step_opts *o, const double *g, const double *f, double *u, double *pf,
                     double *pc, cgp_stats *st) {
   TRY(ready(m));
-  if (!o || !valid_opts(&o->momentum, false, true, true) || !valid_opts(&o->poisson, true) || !valid_opts(&o->mass, false) ||
+  const bool mass_ok = o && (valid_opts(&o->mass, false) ||
+                             (valid_opts(&o->mass, false, true) && o->mass.x0_mode == CGP_X0_EXTRAP));
+  if (!o || !valid_opts(&o->momentum, false, true, true) || !valid_opts(&o->poisson, true) || !mass_ok ||
       !g || !u || !pf || !pc) {
     set_error("cgp_step: invalid argument");
     return CGP_E_ARG;

@@ -145,6 +145,8 @@ struct cgp_mesh {
   double *d_ut_prev2 = nullptr;   // and the one before that
   int ut_hist = 0;                // consecutive cgp_step momentum solves kept in d_ut / d_ut_prev / d_ut_prev2
   double *d_uhist = nullptr;      // [n_f][8] double2 ring of momentum solutions (projected guess; on first use)
+  double *d_mdelta = nullptr;     // [n_f][2] last consistent-minus-lumped correction (mass x0 EXTRAP; first use)
+  bool mdelta_ok = false;         // d_mdelta holds the previous cgp_step's difference
   double *d_proj = nullptr;       // projected guess: Gram block partials, coefficients [2][8], entry sums
   int uh_count = 0, uh_head = 0;  // filled ring slots (consecutive cgp_step solves) and the next slot to write
   double *d_rec = nullptr;        // 2 x [n_c] records {r, w, s, D^-1} of the fused Poisson PCG (double4 or float4)

@@ -967,6 +967,13 @@ __global__ void __launch_bounds__(kMaxBlock) k_mir_init(int Gin, int n, double i
   put_partials<4>(acc, Pout);
 }
 
+// out = a + s b over `count` values (the mass solve's extrapolated start and its difference update)
+__global__ void k_axpy_into(long count, const double *__restrict__ a, double sb, const double *__restrict__ b,
+                            double *__restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = a[i] + sb * b[i];
+}
+
 // x += ||r64|| d on the components that refined (FP64).
 __global__ void k_mir_update(int n, double2 *__restrict__ x, const float2 *__restrict__ d,
                              const KrylovState *__restrict__ so) {
@@ -2007,19 +2014,43 @@ cgp_status drv_correct(cgp_mesh *m, const cgp_solver_opts *o, const double *g, c
   }
   double *rhs = m->d_wf[0];
   launch_correct_rhs(m, g, ut, pf, rhs);
+  // CGP_X0_EXTRAP inside cgp_step: the lumped correction plus the last step's consistent-minus-lumped
+  // difference, which changes slowly from step to step
+  const bool extrap = (o->x0_mode == CGP_X0_EXTRAP && ut == m->d_ut);
+  double *ul = m->d_wf[6];  // the lumped correction (free here: the momentum solve is done)
+  const long cnt = 2L * n;
+  if (extrap && !m->d_mdelta) {
+    void *q = nullptr;
+    CGP_HIP(hipMalloc(&q, sizeof(double) * cnt));
+    m->allocations.push_back(q);
+    m->d_mdelta = (double *)q;
+    m->mdelta_ok = false;
+  }
+  if (!extrap) m->mdelta_ok = false;
   if (o->x0_mode == CGP_X0_ZERO) {
     CGP_HIP(hipMemsetAsync(u, 0, 2 * n * sizeof(double), s));
+    launch_set_dirichlet(m, g, u);
+  } else if (extrap && m->mdelta_ok) {
+    launch_correct_lumped(m, g, ut, pf, ul);
+    hipLaunchKernelGGL(k_axpy_into, dim3((cnt + 255) / 256), dim3(256), 0, s, cnt, (const double *)ul, 1.0,
+                       (const double *)m->d_mdelta, u);
     launch_set_dirichlet(m, g, u);
   } else {
     // start from the lumped-mass correction (g on the Dirichlet rows): the consistent solve then
     // only removes the difference between the two mass matrices
-    launch_correct_lumped(m, g, ut, pf, u);
+    launch_correct_lumped(m, g, ut, pf, extrap ? ul : u);
+    if (extrap) CGP_HIP(hipMemcpyAsync(u, ul, sizeof(double) * cnt, hipMemcpyDeviceToDevice, s));
   }
   double *w[5] = {m->d_wf[1], m->d_wf[2], m->d_wf[3], m->d_wf[4], m->d_wf[5]};
   KrylovState fin{};
   cgp_status rs = run_pcg64<2>(m, SLOT_MASS, n, m->d_rp_f, m->d_col_f, m->d_Mbc, m->d_dinvM, rhs, u, w, m->tune.fine,
                                o->tol, o->max_iter, &m->mass_chunk, false, &fin);
   launch_set_dirichlet(m, g, u);
+  if (extrap) {
+    hipLaunchKernelGGL(k_axpy_into, dim3((cnt + 255) / 256), dim3(256), 0, s, cnt, (const double *)u, -1.0,
+                       (const double *)ul, m->d_mdelta);
+    m->mdelta_ok = (rs == CGP_OK);
+  }
   CGP_HIP(hipGetLastError());
   if (stats) {
     stats->mass_iters = fin.iters;

@@ -419,6 +419,39 @@ def test_cylinder_steps(env, launch):
     _run_steps(env, case, 1, 5, opts)
 
 
+def test_extrapolated_mass_start(env):
+    """The mass solve started from the lumped correction plus the previous step's consistent-minus-
+    lumped difference (CGP_X0_EXTRAP in cgp_step): every step's solution against the oracle <= 1e-10
+    (only the start changes), and fewer mass iterations than from the lumped correction alone once the
+    difference is known."""
+    torch, cgp, oracle = env
+    X0 = cgp._native
+    case = W.case_cylinder(5000, seed=4)
+    s64 = cgp.SolverOpts(tol=TIGHT, max_iter=100000)
+    iters = {}
+    for mode in ("lumped", "extrap"):
+        mass = cgp.SolverOpts(tol=TIGHT, max_iter=100000, x0_mode=X0.X0_EXTRAP if mode == "extrap" else X0.X0_PREV)
+        opts = cgp.StepOpts(momentum=s64, poisson=cgp.SolverOpts(tol=TIGHT_P, max_iter=100000), mass=mass)
+        g, o = make_pair(env, case.mesh, 1, case.rho, case.mu, case.dt)
+        xy = g.export("xy")
+        u0 = case.initial(xy, g.export("vdir"))
+        u = dev(torch, u0.copy())
+        pf = torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda")
+        pc = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
+        ur, pcr, its = u0.copy(), None, []
+        for k in range(6):
+            gd = case.dirichlet(xy, (k + 1) * case.dt)
+            st = g.step(dev(torch, gd), u, pf, pc, opts=opts)
+            its.append(st["mass_iters"][0] if isinstance(st["mass_iters"], list) else st["mass_iters"])
+            ur, pfr, pcr, code, _ = o.step(gd, ur, pcr, tol_mom=TIGHT, tol_p=TIGHT_P, tol_mass=TIGHT)
+            assert code == 0
+            eu, ep = rel(u.cpu().numpy(), ur), rel(pf.cpu().numpy(), pfr)
+            assert eu <= 1e-10 and ep <= 1e-10, (mode, k, eu, ep)
+        iters[mode] = its
+    _say(f"  mass iterations per step: lumped start {iters['lumped']}, extrapolated {iters['extrap']}")
+    assert sum(iters["extrap"][2:]) < sum(iters["lumped"][2:])
+
+
 def test_extrapolated_momentum_guess(env):
     """x0 = 2 U~^n - U~^(n-1) for the momentum solve changes only the start of the Krylov iteration.
     A different start moves the converged momentum result by up to cond(A) * tol, which the pressure
