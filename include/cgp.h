@@ -331,7 +331,7 @@ cgp_status cgp_last_poisson_rhs(const cgp_mesh *mesh, double *dst);
  * device pointers. */
 typedef struct cgp_batch cgp_batch;
 /* ahead = 1 or 2 selects the iteration kernel that issues a tile's loads before the instance's scalars
- * are formed (lanes 4 or 8, passes 1, 2 or 4; 2: the columns of all of a lane group's rows before its
+ * are formed (lanes 4 or 8, passes 1, 2 or 4, or 8 with 8 lanes; 2: the columns of all of a lane group's rows before its
  * first gather); ahead = 0 the row loop. */
 typedef struct { int32_t lanes, block, passes, use_graph, chunk, ahead; } cgp_batch_tuning;
 cgp_status cgp_batch_create(cgp_mesh *const *meshes, int32_t n, cgp_batch **out);
@@ -357,7 +357,7 @@ cgp_status cgp_batch_step(cgp_batch *batch, const cgp_step_opts *opts, const dou
 cgp_status cgp_batch_get_tuning(const cgp_batch *batch, cgp_batch_tuning *out);
 /* lanes 2/4/8/16 per row, block a power of two in 64..1024, passes 1..64, chunk even in 2..256, ahead 0/1/2. */
 cgp_status cgp_batch_set_tuning(cgp_batch *batch, const cgp_batch_tuning *tuning);
-/* Time 63 launch shapes on the batch's own system and keep the fastest; the choice is cached in the JSON
+/* Time 69 launch shapes on the batch's own system and keep the fastest; the choice is cached in the JSON
  * file cache_path (NULL: no cache) under the batch's size class and reused without timing. */
 cgp_status cgp_batch_autotune(cgp_batch *batch, const char *cache_path, cgp_batch_tuning *chosen);
 

@@ -586,7 +586,8 @@ cgp_status build_tiles(cgp_batch *B) {
   return CGP_OK;
 }
 
-// the loads-ahead kernel's instantiations: lanes 4 or 8 per row, passes 1, 2 or 4 rows per lane group,
+// the loads-ahead kernel's instantiations: lanes 4 or 8 per row, passes 1, 2 or 4 rows per lane group
+// (8 with 8 lanes),
 // columns row by row or of all rows first
 template <typename F>
 void dispatch_ahead(int L, int P, bool joint, F &&f) {
@@ -601,7 +602,8 @@ void dispatch_ahead(int L, int P, bool joint, F &&f) {
       default: with_LP(LC, std::integral_constant<int, 4>{}); break;
     }
   };
-  if (L == 8) with_L(std::integral_constant<int, 8>{});
+  if (L == 8 && P == 8) with_LP(std::integral_constant<int, 8>{}, std::integral_constant<int, 8>{});
+  else if (L == 8) with_L(std::integral_constant<int, 8>{});
   else with_L(std::integral_constant<int, 4>{});
 }
 
@@ -956,9 +958,10 @@ cgp_status cgp_batch_set_tuning(cgp_batch *B, const cgp_batch_tuning *t) {
   if (!B || !t || (t->lanes != 2 && t->lanes != 4 && t->lanes != 8 && t->lanes != 16) || t->block < 64 || t->block > 1024 ||
       (t->block & (t->block - 1)) || t->passes < 1 || t->passes > 64 || t->chunk < 2 || t->chunk > 256 ||
       (t->chunk & 1) || (t->use_graph != 0 && t->use_graph != 1) || t->ahead < 0 || t->ahead > 2 ||
-      (t->ahead && ((t->lanes != 4 && t->lanes != 8) || (t->passes != 1 && t->passes != 2 && t->passes != 4)))) {
+      (t->ahead && ((t->lanes != 4 && t->lanes != 8) ||
+                    (t->passes != 1 && t->passes != 2 && t->passes != 4 && !(t->passes == 8 && t->lanes == 8))))) {
     set_error("cgp_batch_set_tuning: lanes 2/4/8/16, block a power of two in 64..1024, passes 1..64, "
-              "chunk even in 2..256, use_graph 0/1, ahead 0/1/2 (ahead 1, 2: lanes 4/8, passes 1/2/4)");
+              "chunk even in 2..256, use_graph 0/1, ahead 0/1/2 (ahead 1, 2: lanes 4/8, passes 1/2/4, or 8 with 8 lanes)");
     return CGP_E_ARG;
   }
   const bool shape = t->lanes != B->tune.lanes || t->block != B->tune.block || t->passes != B->tune.passes;
@@ -1196,7 +1199,7 @@ cgp_status cgp_batch_autotune(cgp_batch *B, const char *cache_path, cgp_batch_tu
     }
   }
   const cgp_batch_tuning keep = B->tune;
-  const int lanes[3] = {2, 4, 8}, blocks[3] = {256, 512, 1024}, passes[3] = {1, 2, 4};
+  const int lanes[3] = {2, 4, 8}, blocks[3] = {256, 512, 1024}, passes[4] = {1, 2, 4, 8};
   cgp_batch_tuning best = keep;
   double best_us = 1e30;
   std::string table;
@@ -1208,6 +1211,7 @@ cgp_status cgp_batch_autotune(cgp_batch *B, const char *cache_path, cgp_batch_tu
     for (int blk : blocks)
       for (int ps : passes) {
         if (ah && L == 2) continue;  // the loads-ahead kernels are built for 4 and 8 lanes
+        if (ps == 8 && !(ah && L == 8)) continue;  // 8 rows per lane group: loads ahead with 8 lanes only
         cgp_batch_tuning t = keep;
         t.lanes = L;
         t.block = blk;

@@ -118,7 +118,8 @@ def test_batch_fp32_refinement(env, instances):
 
 
 @pytest.mark.parametrize("lanes,block,passes,ahead", [(4, 512, 2, 0), (2, 512, 2, 0), (4, 512, 2, 1), (8, 256, 4, 1),
-                                                      (4, 1024, 1, 1), (4, 256, 4, 2), (8, 512, 2, 2)])
+                                                      (4, 1024, 1, 1), (4, 256, 4, 2), (8, 512, 2, 2),
+                                                      (8, 256, 8, 1), (8, 1024, 8, 2)])
 def test_batch_kernel_forms(env, instances, lanes, block, passes, ahead):
     """Both forms of the batched iteration (the row loop and the loads-ahead kernel) at several launch
     shapes: per-instance solutions <= 1e-10 from the oracle in FP64, <= 1e-6 with the FP32 inner solves."""
@@ -195,6 +196,42 @@ def test_batch_step_matches_single_steps(env, instances):
         assert rel(ub, us_) <= 1e-10 and rel(pb, ps) <= 1e-10
 
 
+def test_batch_step_solver_options_match_single_steps(env, instances):
+    """The per-instance phases of a batch step honour the momentum and mass options as a single step
+    does: FP32 inner BiCGStab inside FP64 refinement for the momentum solve and the extrapolated mass
+    start, three steps, batched against single-instance steps (the batched Poisson solve differs only
+    in its reduction order)."""
+    torch, cgp, oracle = env
+    X0 = cgp._native
+    sub = [instances[0], instances[2], instances[4]]
+    opts = cgp.StepOpts(momentum=cgp.SolverOpts(tol=TIGHT, max_iter=100000, precision=X0.PREC_FP32_IR),
+                        poisson=cgp.SolverOpts(tol=1e-13, max_iter=100000),
+                        mass=cgp.SolverOpts(tol=TIGHT, max_iter=100000, x0_mode=X0.X0_EXTRAP))
+    states = {}
+    for mode in ("batch", "single"):
+        us, pfs, pcs = [], [], []
+        for case, g, o in sub:
+            us.append(dev(torch, case.initial(g.export("xy"), g.export("vdir"))))
+            pfs.append(torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda"))
+            pcs.append(torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda"))
+        batch = cgp.Batch([g for _, g, _ in sub]) if mode == "batch" else None
+        try:
+            for k in range(3):
+                gds = [dev(torch, case.dirichlet(g.export("xy"), (k + 1) * case.dt)) for case, g, _ in sub]
+                if batch:
+                    batch.step(gds, us, pfs, pcs, opts=opts)
+                else:
+                    for (case, g, o), gd, u, pf, pc in zip(sub, gds, us, pfs, pcs):
+                        g.step(gd, u, pf, pc, opts=opts)
+        finally:
+            if batch:
+                batch.close()
+        states[mode] = [(u.cpu().numpy(), pf.cpu().numpy()) for u, pf in zip(us, pfs)]
+    errs = [max(rel(ub, us_), rel(pb, ps)) for (ub, pb), (us_, ps) in zip(states["batch"], states["single"])]
+    _say(f"  FP32-refined momentum, extrapolated mass start: batch vs single worst rel err {max(errs):.1e}")
+    assert max(errs) <= 1e-9
+
+
 def test_batch_step_online_guess_matches_single_steps(env, instances):
     """Every instance keeps its own online POD basis (window 4); inside the batched solve each instance's
     initial guess comes from it exactly as in its single solve.  After the windows fill, the batched
@@ -257,7 +294,7 @@ def test_autotune_cache(env, instances, tmp_path):
     data = json.loads(cache.read_text())
     assert len(data) == 1
     entry = next(iter(data.values()))
-    assert {"lanes", "block", "passes", "ahead", "candidates"} <= set(entry) and len(entry["candidates"]) == 63
+    assert {"lanes", "block", "passes", "ahead", "candidates"} <= set(entry) and len(entry["candidates"]) == 69
     assert (entry["lanes"], entry["block"], entry["passes"], entry["ahead"]) == (chosen["lanes"], chosen["block"], chosen["passes"], chosen["ahead"])
     batch.set_tuning(lanes=16, block=64, passes=3, ahead=0)
     again = batch.autotune(cache)   # from the cache: same choice, no timing
