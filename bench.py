@@ -660,6 +660,102 @@ def run_batch_kernel(args, log):
                 tuning=tuned, autotune_candidates=cands)
 
 
+def run_batch_long(args, log):
+    """The batched sweep as the configuration states it: 64 instances stepped together for
+    `batch_long` steps each from the impulsive start, with per-instance online POD guesses and FP32
+    inner solves inside FP64 refinement; aggregate steps/s over all the steps, max |u| of every
+    instance along the way, and at the end each size-decile instance's one-step error against the FP64
+    oracle from the same state (the oracle steps the ten instances on host threads)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1610_06993_amd as cgp
+    import workloads as W
+    from paper_1610_06993_amd import SolverOpts, StepOpts
+    X0 = cgp._native
+    t0 = time.perf_counter()
+    cases = W.batch_sweep(args.batch)
+    meshes, g, u, pf, pc = [], [], [], [], []
+    for c in cases:
+        m = cgp.Mesh(c.mesh, 1)
+        m.assemble(c.rho, c.mu, c.dt)
+        xy = m.export("xy")
+        meshes.append(m)
+        g.append(torch.from_numpy(c.dirichlet(xy, 0.0)).cuda())
+        u.append(torch.from_numpy(c.initial(xy, m.export("vdir"))).cuda())
+        pf.append(torch.zeros(m.info["n_f"], dtype=torch.float64, device="cuda"))
+        pc.append(torch.zeros(m.info["n_c"], dtype=torch.float64, device="cuda"))
+    batch = cgp.Batch(meshes)
+    TUNING_CACHE.parent.mkdir(exist_ok=True)
+    tuned = batch.autotune(TUNING_CACHE)
+    guesses = []
+    for m in meshes:
+        gs = cgp.Guess(m, n_modes=args.batch_window, hidden=16, seed=5)
+        gs.set_online(args.batch_window, 1)
+        gs.attach()
+        guesses.append(gs)
+    mom = SolverOpts(tol=args.mom_tol, max_iter=5000, x0_mode=X0.X0_PROJECT)
+    opts = StepOpts(momentum=mom, poisson=SolverOpts(tol=1e-8, max_iter=100000, precision=X0.PREC_FP32_IR,
+                                                     inner_tol=args.inner_tol, x0_mode=X0.X0_POD_GALERKIN),
+                    mass=SolverOpts(tol=args.mass_tol, max_iter=2000))
+    log(f"batch long run: {len(meshes)} instances, setup {time.perf_counter() - t0:.1f}s, tuning {tuned}")
+    n_steps = args.batch_long
+    maxu_hist, iters_hist = [], []
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(n_steps):
+        st = batch.step(g, u, pf, pc, opts=opts)
+        if (k + 1) % 100 == 0 or k + 1 == n_steps:
+            torch.cuda.synchronize()
+            mu = [float(x.abs().max()) for x in u]
+            maxu_hist.append([k + 1, round(min(mu), 4), round(max(mu), 4)])
+            iters_hist.append([k + 1, min(s["p_iters"] for s in st), max(s["p_iters"] for s in st)])
+            log(f"batch long run: step {k + 1}, {len(meshes) * (k + 1) / (time.perf_counter() - t1):.1f} "
+                f"instance-steps/s so far, max|u| over instances {min(mu):.3f}..{max(mu):.3f}, Poisson inner "
+                f"iterations {iters_hist[-1][1]}..{iters_hist[-1][2]}")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    # one more step of every instance beside the oracle's step from the same state, for the deciles
+    idx = W.batch_deciles(args.batch)
+    probs = []
+    for i in idx:
+        o = oracle.Problem(cases[i].mesh, 1)
+        o.assemble(cases[i].rho, cases[i].mu, cases[i].dt, 0, 0)
+        probs.append(o)
+    state = [(u[i].cpu().numpy().copy(), pc[i].cpu().numpy().copy(), g[i].cpu().numpy()) for i in idx]
+    batch.step(g, u, pf, pc, opts=opts)
+    torch.cuda.synchronize()
+
+    def oracle_step(j):
+        uu, pcc, gd = state[j]
+        return probs[j].step(gd, uu, pcc, tol_mom=1e-13, tol_p=1e-13, tol_mass=1e-13)
+
+    with ThreadPoolExecutor(max_workers=len(idx)) as pool:
+        res = list(pool.map(oracle_step, range(len(idx))))
+    errs = []
+    for j, i in enumerate(idx):
+        ur, pfr, _, code, _ = res[j]
+        errs.append(dict(instance=i, coarse_triangles=cases[i].mesh.n_tris, oracle_code=code,
+                         rel_err_u=rel(u[i].cpu().numpy(), ur), rel_err_p=rel(pf[i].cpu().numpy(), pfr)))
+    for gs in guesses:
+        gs.detach()
+        gs.close()
+    batch.close()
+    worst = max(max(e["rel_err_u"], e["rel_err_p"]) for e in errs)
+    log(f"batch long run: {n_steps} steps of {len(meshes)} instances in {el:.1f}s = "
+        f"{len(meshes) * n_steps / el:.1f} instance-steps/s; size-decile one-step error against the FP64 oracle "
+        f"at step {n_steps + 1}: worst {worst:.1e}")
+    return dict(workload=f"{len(meshes)} cylinder instances (coarse 15.8k-228k triangles, Re uniform in [60,160]), "
+                         f"impulsive start, {n_steps} steps each, per-instance online POD guesses (window "
+                         f"{args.batch_window}), FP32 inner Poisson solves inside FP64 refinement to 1e-8",
+                steps=n_steps, seconds=round(el, 2), instance_steps_per_s=round(len(meshes) * n_steps / el, 3),
+                max_abs_u_min_max_every_100=maxu_hist, poisson_inner_iters_min_max_every_100=iters_hist,
+                decile_one_step_error_vs_oracle=errs, worst_rel_err=worst, tuning=tuned)
+
+
 def run_batch(args, log):
     """Config-4-style sweep: independent cylinder instances of uneven size stepped together."""
     import numpy as np
@@ -832,6 +928,9 @@ def main():
     ap.add_argument("--refresh", type=int, default=1, help="Poisson solves between online basis rebuilds")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps timed for the CPU baseline (0: skip)")
     ap.add_argument("--no-instrumented", action="store_true", help="skip the event-timed kernel pass")
+    ap.add_argument("--only-batch-long", action="store_true",
+                    help="run only the long batched run (64 instances, --batch-long steps each) with the oracle check")
+    ap.add_argument("--batch-long", type=int, default=500, help="steps of the long batched run")
     ap.add_argument("--only-gmres", action="store_true",
                     help="run only the ILU(0)-GMRES against Jacobi-PCG comparison on the Poisson systems")
     ap.add_argument("--gmres-max-iter", type=int, default=300,
@@ -933,6 +1032,9 @@ def main():
         return
     if args.only_learned:
         print(json.dumps({"learned": run_learned(args, log)}), flush=True)
+        return
+    if args.only_batch_long:
+        print(json.dumps({"batch_long": run_batch_long(args, log)}), flush=True)
         return
     if args.only_gmres:
         print(json.dumps({"poisson_solvers": run_gmres(args, log)}), flush=True)
