@@ -285,6 +285,76 @@ def test_batch_step_online_guess_matches_single_steps(env, instances):
     assert iters["batch"].sum() < iters["batch_prev"].sum()
 
 
+def test_batch_step_learned_guess_per_instance_matches_single_steps(env, instances):
+    """Every instance with its own trained network (a POD basis of its own recorded pressures and an
+    MLP trained on the GPU from its recorded right-hand sides): inside the batched solve each instance
+    forms its initial guess from its own model (CGP_X0_LEARNED) as in its single step; three batched
+    steps agree with three single-instance steps, and the guess changes where the solves start (the
+    Poisson counts differ from the previous-pressure start)."""
+    torch, cgp, oracle = env
+    X0 = cgp._native
+    sub = [instances[0], instances[4]]
+    rec_opts = cgp.StepOpts(momentum=cgp.SolverOpts(tol=TIGHT, max_iter=100000),
+                            poisson=cgp.SolverOpts(tol=1e-12, max_iter=100000),
+                            mass=cgp.SolverOpts(tol=TIGHT, max_iter=100000))
+    models, starts = [], []
+    for case, g, o in sub:
+        xy = g.export("xy")
+        u = dev(torch, case.initial(xy, g.export("vdir")))
+        pf = torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda")
+        pc = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
+        n = g.info["n_c"]
+        B = torch.zeros((24, n), dtype=torch.float64, device="cuda")
+        P = torch.zeros_like(B)
+        for k in range(24):
+            g.step(dev(torch, case.dirichlet(xy, (k + 1) * case.dt)), u, pf, pc, opts=rec_opts)
+            g.last_poisson_rhs(B[k])
+            P[k].copy_(pc)
+        net = cgp.Guess(g, n_modes=8, hidden=32, seed=7)
+        net.build_pod(P.contiguous())
+        net.train(B.contiguous(), P.contiguous(), epochs=40, batch=8)
+        models.append(net)
+        starts.append((u.clone(), pc.clone()))
+    opts = {x0: cgp.StepOpts(momentum=cgp.SolverOpts(tol=TIGHT, max_iter=100000),
+                             poisson=cgp.SolverOpts(tol=1e-12, max_iter=100000, x0_mode=x0),
+                             mass=cgp.SolverOpts(tol=TIGHT, max_iter=100000)) for x0 in (X0.X0_LEARNED, X0.X0_PREV)}
+    states, iters = {}, {}
+    try:
+        for mode, x0 in (("batch", X0.X0_LEARNED), ("single", X0.X0_LEARNED), ("batch_prev", X0.X0_PREV)):
+            for net in models:
+                net.attach()
+            us = [st[0].clone() for st in starts]
+            pcs = [st[1].clone() for st in starts]
+            pfs = [torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda") for _, g, _ in sub]
+            batch = cgp.Batch([g for _, g, _ in sub]) if mode != "single" else None
+            its = []
+            try:
+                for k in range(24, 27):
+                    gds = [dev(torch, case.dirichlet(g.export("xy"), (k + 1) * case.dt)) for case, g, _ in sub]
+                    if batch:
+                        st = batch.step(gds, us, pfs, pcs, opts=opts[x0])
+                    else:
+                        st = [g.step(gd, u, pf, pc, opts=opts[x0]) for (case, g, o), gd, u, pf, pc in
+                              zip(sub, gds, us, pfs, pcs)]
+                    its.append([s_["p_iters"] for s_ in st])
+            finally:
+                if batch:
+                    batch.close()
+                for net in models:
+                    net.detach()
+            states[mode] = [(u.cpu().numpy(), pf.cpu().numpy()) for u, pf in zip(us, pfs)]
+            iters[mode] = its
+    finally:
+        for net in models:
+            net.close()
+    _say(f"  Poisson iterations, learned start batch {iters['batch']}, single {iters['single']}, previous "
+         f"pressure {iters['batch_prev']}")
+    for (ub, pb), (us_, ps) in zip(states["batch"], states["single"]):
+        assert rel(ub, us_) <= 1e-9 and rel(pb, ps) <= 1e-9
+    assert np.all(np.abs(np.array(iters["batch"]) - np.array(iters["single"])) <= 6)
+    assert iters["batch"] != iters["batch_prev"]
+
+
 def test_autotune_cache(env, instances, tmp_path):
     torch, cgp, oracle = env
     batch = cgp.Batch([g for _, g, _ in instances])

@@ -654,6 +654,39 @@ def test_poisson_at_two_million_rows_by_residual(env, precision):
     g.close()
 
 
+def test_under_resolved_injection_run_fails_loudly(env):
+    """The under-resolved cylinder (1500 coarse triangles, l = 1) with injection restriction grows a
+    fine-scale velocity mode (the oblique projection; the oracle reaches max |u| 5e3 and stops
+    converging at step 116): the library must report it through a status, never return a silently
+    wrong field, and the Galerkin restriction on the same mesh stays bounded over the same steps."""
+    torch, cgp, oracle = env
+    X0 = cgp._native
+    case = W.case_cylinder(1500, seed=5)
+    opts = cgp.StepOpts(momentum=cgp.SolverOpts(tol=1e-10, max_iter=2000),
+                        poisson=cgp.SolverOpts(tol=1e-10, max_iter=20000),
+                        mass=cgp.SolverOpts(tol=1e-10, max_iter=2000))
+    out = {}
+    for mode in (0, 1):
+        g = cgp.Mesh(case.mesh, 1)
+        g.assemble(case.rho, case.mu, case.dt, mode)
+        xy = g.export("xy")
+        u = dev(torch, case.initial(xy, g.export("vdir")))
+        pf = torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda")
+        pc = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
+        status, step, msg = 0, None, ""
+        for k in range(200):
+            try:
+                g.step(dev(torch, case.dirichlet(xy, (k + 1) * case.dt)), u, pf, pc, opts=opts)
+            except cgp.CGPError as e:
+                status, step, msg = e.status, k + 1, str(e)
+                break
+        out[mode] = (status, step, msg, float(u.abs().max()) if torch.isfinite(u).all() else float("inf"))
+        g.close()
+    _say(f"  injection: status {out[0][0]} at step {out[0][1]} ({out[0][2][:90]}); Galerkin: status {out[1][0]}, "
+         f"max|u| {out[1][3]:.3f} after 200 steps")
+    assert out[0][0] in (X0.E_NOCONV, X0.E_NONFINITE) and out[0][1] is not None and out[0][1] < 200
+    assert out[1][0] == 0 and out[1][3] < 3.0
+
 @pytest.mark.parametrize("which,steps", [("cylinder", 3), ("backward_step", 5)])
 def test_full_size_steps_against_oracle(env, which, steps):
     """The first steps at the full benchmark sizes (cylinder: 248920 coarse / 995680 fine triangles;
