@@ -324,9 +324,9 @@ __global__ void k_zero_b_fix(int n, double *__restrict__ x, const KrylovState *_
 // so the kernel is laid out to overlap its dependent loads: every load that does
 // not need this iteration's scalars (the row pointers, columns and values of the
 // block's first chunk of rows, the gathered records, the own records, x and p) is
-// issued before the scalars are formed, each wave reduces the previous
-// iteration's block partials itself (no barrier before the row work), and the
-// block's partials leave after a single barrier.
+// issued before the scalars are formed; wave 0 reduces the previous iteration's
+// block partials while those loads are in flight and hands the totals to the
+// block through LDS, and the block's own partials leave after one more barrier.
 
 template <typename T>
 __device__ __forceinline__ T cg1_u_next(T dinv, T r, T w, T s, T alpha, T beta) {
@@ -390,7 +390,23 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg1_iter(int Gin, int it, int n, 
   const double rz_prev = it ? st->rz[(it - 1) & 1][0] : 1.0;
   const double al_prev = it ? st->alpha[(it - 1) & 1][0] : 1.0;
   double t3[3];
-  wave_partials<3, U>(Pin, Gin, t3);
+  // Direct partials (E > 0): wave 0 alone loads them here and sums them once the row loads below are in
+  // flight, and the block takes the totals from LDS; every wave summing them itself put its own partial
+  // loads ahead of its row loads.  Summed partials (E = 0, 3 values): each wave reads them.
+  __shared__ double tot_sh[3];
+  double pa[3][U];
+  const bool wave0 = (threadIdx.x >> 6) == 0;
+  if constexpr (E > 0) {
+    if (wave0) {
+      const int l = threadIdx.x & 63;
+#pragma unroll
+      for (int u = 0; u < U; u++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) pa[k][u] = l + 64 * u < Gin ? Pin[k * Gin + l + 64 * u] : 0.0;
+    }
+  } else {
+    wave_partials<3, U>(Pin, Gin, t3);
+  }
 
   const int lane = threadIdx.x & (L - 1);
   const int rpb = blockDim.x / L;  // rows per block and pass
@@ -436,6 +452,24 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg1_iter(int Gin, int it, int n, 
   };
   int c = xcd_block();
   load_chunk(c);
+  if constexpr (E > 0) {
+    if (wave0) {
+      const int l = threadIdx.x & 63;
+#pragma unroll
+      for (int k = 0; k < 3; k++) {
+        double sum = 0.0;
+#pragma unroll
+        for (int u = 0; u < U; u++) sum += pa[k][u];
+        for (int b = l + 64 * U; b < Gin; b += 64) sum += Pin[k * Gin + b];
+        sum = wave_sum(sum);
+        if (l == 0) tot_sh[k] = sum;
+      }
+    }
+    __syncthreads();
+    t3[0] = tot_sh[0];
+    t3[1] = tot_sh[1];
+    t3[2] = tot_sh[2];
+  }
   if (stopped) return;
 
   const double gam = t3[0], del = t3[1], rr = t3[2];
