@@ -681,6 +681,7 @@ __device__ __forceinline__ typename v2_of<T>::type mk2(double a, double b) {
 // Iteration `it` start: reduce (r.r, r^.r) of the previous iteration (or the
 // init partials), test convergence, rho_it = r^.r, beta = (rho_it /
 // rho_{it-1}) (alpha_{it-1} / omega_{it-1}); p = r + beta (p - omega v), p^ = D^-1 p.
+// The loop launches it for iteration 0 only (p = r0); k_bi_xp forms the later directions.
 template <typename T>
 __global__ void __launch_bounds__(kMaxBlock) k_bi_p(int Gin, int it, int n, const typename v2_of<T>::type *__restrict__ r,
                                                    typename v2_of<T>::type *__restrict__ p,
@@ -743,15 +744,47 @@ __global__ void __launch_bounds__(kMaxBlock) k_bi_p(int Gin, int it, int n, cons
   }
 }
 
-// v = A p^; partials r^.v
+// Iterations after the first run as three kernels instead of four: the update of x and r and the
+// next search direction share one pass over the nodes.  The direction needs rho_{i+1} = r^.r_{i+1},
+// and with r_{i+1} = s - omega t that is r^.s - omega r^.t, both of which the t kernel can sum on
+// its own rows; the convergence test of r_{i+1} (its r.r summed directly) moves to the start of the
+// next v kernel.  A direction formed for a component that then tests converged is never used.
+
+// Iteration `it` start: for it > 0 reduce r.r of r_it (from k_bi_xp of it - 1) and test each
+// component, as k_bi_p does at it = 0; then v = A p^ with partials r^.v.
 template <typename T, int L>
-__global__ void __launch_bounds__(kMaxBlock) k_bi_v(int n, const int *__restrict__ rp, const int *__restrict__ col,
-                                                   const T *__restrict__ A, const typename v2_of<T>::type *__restrict__ ph,
-                                                   typename v2_of<T>::type *__restrict__ v,
-                                                   const typename v2_of<T>::type *__restrict__ rh,
-                                                   double *__restrict__ Pout, const KrylovState *__restrict__ st) {
+__global__ void __launch_bounds__(kMaxBlock) k_bi_vc(int Gin, int it, int n, const int *__restrict__ rp,
+                                                    const int *__restrict__ col, const T *__restrict__ A,
+                                                    const typename v2_of<T>::type *__restrict__ ph,
+                                                    typename v2_of<T>::type *__restrict__ v,
+                                                    const typename v2_of<T>::type *__restrict__ rh,
+                                                    const double *__restrict__ Pin, double *__restrict__ Pout,
+                                                    KrylovState *__restrict__ st) {
   using V2 = typename v2_of<T>::type;
   if (st->status || all_done<2>(st)) return;
+  if (it > 0) {
+    double rr[2];
+    sum_partials<2>(Pin, Gin, rr);
+    bool done[2], all = true, bad = false, brk = false;
+    const double tol = st->tol;
+    for (int c = 0; c < 2; c++) {
+      const double bb = st->bnorm[c] * st->bnorm[c];
+      done[c] = st->done[c] || bb == 0.0 || sqrt(rr[c]) <= tol * sqrt(bb);
+      all = all && done[c];
+      bad = bad || !is_finite(rr[c]);
+      if (!done[c] && st->omega[(it - 1) & 1][c] == 0.0) brk = true;  // breakdown
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      for (int c = 0; c < 2; c++) {
+        st->done[c] = done[c];
+        st->rnorm[c] = sqrt(rr[c]);
+      }
+      st->iters = it;
+      if (bad) st->status = CGP_E_NONFINITE;
+      else if (brk && !all) st->status = CGP_E_NOCONV;
+    }
+    if (all || bad || brk) return;
+  }
   const int lane = threadIdx.x & (L - 1);
   const int rows_per_grid = gridDim.x * blockDim.x / L;
   double acc[2] = {0.0, 0.0};
@@ -776,12 +809,14 @@ __global__ void __launch_bounds__(kMaxBlock) k_bi_v(int n, const int *__restrict
   put_partials<2>(acc, Pout);
 }
 
-// alpha = rho / (r^.v); s = r - alpha v formed on the fly; t = A (D^-1 s); partials (t.s, t.t)
+// alpha = rho / (r^.v); s = r - alpha v formed on the fly; t = A (D^-1 s); partials (t.s, t.t, r^.s,
+// r^.t) per component
 template <typename T, int L>
 __global__ void __launch_bounds__(kMaxBlock) k_bi_t(int Gin, int it, int n, const int *__restrict__ rp,
                                                    const int *__restrict__ col, const T *__restrict__ A,
                                                    const typename v2_of<T>::type *__restrict__ r,
                                                    const typename v2_of<T>::type *__restrict__ v,
+                                                   const typename v2_of<T>::type *__restrict__ rh,
                                                    const T *__restrict__ dinv, typename v2_of<T>::type *__restrict__ t,
                                                    const double *__restrict__ Pin, double *__restrict__ Pout,
                                                    KrylovState *__restrict__ st) {
@@ -803,7 +838,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_bi_t(int Gin, int it, int n, cons
   if (bad) return;
   const int lane = threadIdx.x & (L - 1);
   const int rows_per_grid = gridDim.x * blockDim.x / L;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int row = (xcd_block() * blockDim.x + threadIdx.x) / L; row < n; row += rows_per_grid) {
     double sx = 0.0, sy = 0.0;
     for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
@@ -818,79 +853,91 @@ __global__ void __launch_bounds__(kMaxBlock) k_bi_t(int Gin, int it, int n, cons
     if (lane == 0) {
       const V2 tw = mk2<T>(sx, sy);
       t[row] = tw;
-      const V2 rr = r[row], vv = v[row];
+      const V2 rr = r[row], vv = v[row], h = rh[row];
       const double s0 = (double)rr.x - al[0] * (double)vv.x, s1 = (double)rr.y - al[1] * (double)vv.y;
       const double tx = tw.x, ty = tw.y;
       acc[0] += tx * s0;
       acc[1] += ty * s1;
       acc[2] += tx * tx;
       acc[3] += ty * ty;
+      acc[4] += (double)h.x * s0;
+      acc[5] += (double)h.y * s1;
+      acc[6] += (double)h.x * tx;
+      acc[7] += (double)h.y * ty;
     }
   }
-  put_partials<4>(acc, Pout);
+  put_partials<8>(acc, Pout);
 }
 
-// omega = (t.s)/(t.t); x += alpha p^ + omega D^-1 s, r = s - omega t; partials (r.r, r^.r)
+// omega = (t.s)/(t.t); x += alpha p^ + omega D^-1 s, r = s - omega t; rho_{it+1} = r^.s - omega r^.t,
+// beta = (rho_{it+1} / rho_it)(alpha / omega); p = r + beta (p - omega v), p^ = D^-1 p; partials r.r
 template <typename T>
-__global__ void __launch_bounds__(kMaxBlock) k_bi_x(int Gin, int it, int n, typename v2_of<T>::type *__restrict__ x,
-                                                   typename v2_of<T>::type *__restrict__ r,
-                                                   const typename v2_of<T>::type *__restrict__ v,
-                                                   const typename v2_of<T>::type *__restrict__ t,
-                                                   const T *__restrict__ dinv, const typename v2_of<T>::type *__restrict__ ph,
-                                                   const typename v2_of<T>::type *__restrict__ rh,
-                                                   const double *__restrict__ Pin, double *__restrict__ Pout,
-                                                   KrylovState *__restrict__ st) {
+__global__ void __launch_bounds__(kMaxBlock) k_bi_xp(int Gin, int it, int n, typename v2_of<T>::type *__restrict__ x,
+                                                    typename v2_of<T>::type *__restrict__ r,
+                                                    typename v2_of<T>::type *__restrict__ p,
+                                                    const typename v2_of<T>::type *__restrict__ v,
+                                                    const typename v2_of<T>::type *__restrict__ t,
+                                                    const T *__restrict__ dinv, typename v2_of<T>::type *__restrict__ ph,
+                                                    const double *__restrict__ Pin, double *__restrict__ Pout,
+                                                    KrylovState *__restrict__ st) {
   using V2 = typename v2_of<T>::type;
   if (st->status || all_done<2>(st)) return;
-  double t4[4];
-  sum_partials<4>(Pin, Gin, t4);
-  double w[2], al[2];
+  double t8[8];
+  sum_partials<8>(Pin, Gin, t8);
+  double w[2], al[2], be[2], rho_next[2];
   bool act[2];
   for (int c = 0; c < 2; c++) {
     act[c] = !st->done[c];
-    w[c] = (act[c] && t4[2 + c] > 0.0) ? t4[c] / t4[2 + c] : 0.0;
+    w[c] = (act[c] && t8[2 + c] > 0.0) ? t8[c] / t8[2 + c] : 0.0;
     al[c] = st->alpha[it & 1][c];
+    rho_next[c] = t8[4 + c] - w[c] * t8[6 + c];
+    // omega = 0 is a breakdown, reported by the next v kernel unless the component has converged
+    be[c] = (act[c] && w[c] != 0.0) ? (rho_next[c] / st->rho[it & 1][c]) * (al[c] / w[c]) : 0.0;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->omega[it & 1][0] = w[0];
-    st->omega[it & 1][1] = w[1];
+    for (int c = 0; c < 2; c++) {
+      st->omega[it & 1][c] = w[c];
+      st->rho[(it + 1) & 1][c] = rho_next[c];
+    }
   }
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double acc[2] = {0.0, 0.0};
   const int stride = gridDim.x * blockDim.x;
   for (int i = xcd_block() * blockDim.x + threadIdx.x; i < n; i += stride) {
-    V2 xx = x[i], rr = r[i];
-    const V2 vv = v[i], tt = t[i], pp = ph[i], hh = rh[i];
+    V2 xx = x[i], rr = r[i], pp = p[i];
+    const V2 vv = v[i], tt = t[i];
     const double d = dinv[i];
     if (act[0]) {
       const double s = (double)rr.x - al[0] * (double)vv.x;
-      xx.x = (T)((double)xx.x + (al[0] * (double)pp.x + w[0] * (d * s)));
+      xx.x = (T)((double)xx.x + (al[0] * (d * (double)pp.x) + w[0] * (d * s)));
       rr.x = (T)(s - w[0] * (double)tt.x);
+      pp.x = (T)((double)rr.x + be[0] * ((double)pp.x - w[0] * (double)vv.x));
     }
     if (act[1]) {
       const double s = (double)rr.y - al[1] * (double)vv.y;
-      xx.y = (T)((double)xx.y + (al[1] * (double)pp.y + w[1] * (d * s)));
+      xx.y = (T)((double)xx.y + (al[1] * (d * (double)pp.y) + w[1] * (d * s)));
       rr.y = (T)(s - w[1] * (double)tt.y);
+      pp.y = (T)((double)rr.y + be[1] * ((double)pp.y - w[1] * (double)vv.y));
     }
     x[i] = xx;
     r[i] = rr;
+    p[i] = pp;
+    ph[i] = mk2<T>(d * (double)pp.x, d * (double)pp.y);
     const double rx = rr.x, ry = rr.y;
     acc[0] += rx * rx;
     acc[1] += ry * ry;
-    acc[2] += (double)hh.x * rx;
-    acc[3] += (double)hh.y * ry;
   }
-  put_partials<4>(acc, Pout);
+  put_partials<2>(acc, Pout);
 }
 
 __global__ void __launch_bounds__(kMaxBlock) k_bi_finish(int it_end, int G, const double *__restrict__ Pin,
                                                         KrylovState *__restrict__ st) {
   if (st->status || all_done<2>(st)) return;
-  double t4[4];
-  sum_partials<4>(Pin, G, t4);
+  double t2[2];
+  sum_partials<2>(Pin, G, t2);  // r.r per component (the first two arrays of the init partials too)
   if (threadIdx.x != 0) return;
   bool bad = false;
   for (int c = 0; c < 2; c++) {
-    const double rn = sqrt(t4[c]);
+    const double rn = sqrt(t2[c]);
     st->rnorm[c] = rn;
     bad = bad || !is_finite(rn);
     if (!st->done[c] && rn <= st->tol * st->bnorm[c]) st->done[c] = 1;
@@ -1646,16 +1693,17 @@ cgp_status bicg_loop(cgp_mesh *m, int slot, int n, const T *A, const T *dinv, ty
     dispatch_L(tk.lanes, [&](auto LC) {
       constexpr int LL = decltype(LC)::value;
       for (int c = 0; c < chunk && it < maxit; c++, it++) {
-        hipLaunchKernelGGL(k_bi_p<T>, dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, it == 0 ? g_init : sh.elem.grid,
-                           it, n, (const V2 *)r, p, (const V2 *)v, dinv, ph, (const double *)(it == 0 ? Pinit : Px),
-                           st);
-        hipLaunchKernelGGL((k_bi_v<T, LL>), dim3(sh.rows.grid), dim3(sh.rows.block), 0, s, n, rp, col, A,
-                           (const V2 *)ph, v, (const V2 *)rh, Pv, (const KrylovState *)st);
+        // the first direction p = r0 (and the first convergence test); later ones come with the update
+        if (it == 0)
+          hipLaunchKernelGGL(k_bi_p<T>, dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, g_init, 0, n, (const V2 *)r,
+                             p, (const V2 *)v, dinv, ph, (const double *)Pinit, st);
+        hipLaunchKernelGGL((k_bi_vc<T, LL>), dim3(sh.rows.grid), dim3(sh.rows.block), 0, s, sh.elem.grid, it, n, rp,
+                           col, A, (const V2 *)ph, v, (const V2 *)rh, (const double *)Px, Pv, st);
         hipLaunchKernelGGL((k_bi_t<T, LL>), dim3(sh.rows.grid), dim3(sh.rows.block), 0, s, sh.rows.grid, it, n, rp,
-                           col, A, (const V2 *)r, (const V2 *)v, dinv, t, (const double *)Pv, Pt, st);
-        hipLaunchKernelGGL(k_bi_x<T>, dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, sh.rows.grid, it, n, x, r,
-                           (const V2 *)v, (const V2 *)t, dinv, (const V2 *)ph, (const V2 *)rh, (const double *)Pt,
-                           Px, st);
+                           col, A, (const V2 *)r, (const V2 *)v, (const V2 *)rh, dinv, t, (const double *)Pv, Pt,
+                           st);
+        hipLaunchKernelGGL(k_bi_xp<T>, dim3(sh.elem.grid), dim3(sh.elem.block), 0, s, sh.rows.grid, it, n, x, r, p,
+                           (const V2 *)v, (const V2 *)t, dinv, ph, (const double *)Pt, Px, st);
       }
     });
     hipLaunchKernelGGL(k_bi_finish, dim3(1), dim3(256), 0, s, it, it == 0 ? g_init : sh.elem.grid,
