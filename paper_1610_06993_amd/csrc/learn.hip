@@ -22,6 +22,7 @@
 #include "devutil.h"
 #include "kernels.h"
 #include "learn.h"
+#include "symeig.h"
 
 namespace cgp {
 // blocks of the POD projection (one partial per block and mode) and of the expansion
@@ -167,6 +168,8 @@ __global__ void k_gather_batch(int rows, int cols, const int *__restrict__ idx, 
 // ---- basis kernels (FP64)
 // Cpart[z][a][b] = sum over i in chunk z of P(a,i) w_i Y(i,b), with P(a,i) = P[a*spa + i*spi],
 // Y(i,b) = Y[i*syi + b*syb]; 64x64 tile per block, each thread a 4x4 sub-tile, 32-row LDS stages.
+// An operand stored along i (stride 1 in i, as the snapshot rows of a Gram matrix are) is staged by
+// lanes walking i, so that a wave reads whole 256-byte runs; otherwise lanes walk the tile's columns.
 __global__ void __launch_bounds__(256) k_gemm64(int M, int N, int K, int kchunk, const double *__restrict__ P,
                                                 long spa, long spi, const double *__restrict__ w,
                                                 const double *__restrict__ Y, long syi, long syb,
@@ -174,15 +177,22 @@ __global__ void __launch_bounds__(256) k_gemm64(int M, int N, int K, int kchunk,
   __shared__ double sp[32][65], sy[32][65];
   const int ta = blockIdx.y * 64, tb = blockIdx.x * 64;
   const int i_beg = blockIdx.z * kchunk, i_end = min(K, i_beg + kchunk);
-  const int tr = (threadIdx.x >> 4) * 4, tc = (threadIdx.x & 15) * 4;
+  // a thread's 4x4 outputs are rows tr + 16u and columns tc + 16v: the 16 column groups of a wave
+  // then read 16 consecutive LDS words (no bank conflicts), where contiguous 4x4 blocks hit 4 banks
+  const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
   double acc[4][4] = {};
   for (int i0 = i_beg; i0 < i_end; i0 += 32) {
     for (int e = threadIdx.x; e < 32 * 64; e += 256) {
-      const int ii = e >> 6, cc = e & 63, i = i0 + ii;
-      const int aa = ta + cc, bb = tb + cc;
-      const bool iv = i < i_end;
-      sp[ii][cc] = (iv && aa < M) ? P[aa * spa + (long)i * spi] * (w ? w[i] : 1.0) : 0.0;
-      sy[ii][cc] = (iv && bb < N) ? Y[(long)i * syi + bb * syb] : 0.0;
+      {
+        const int ii = spi == 1 ? (e & 31) : (e >> 6), cc = spi == 1 ? (e >> 5) : (e & 63), i = i0 + ii;
+        const int aa = ta + cc;
+        sp[ii][cc] = (i < i_end && aa < M) ? P[aa * spa + (long)i * spi] * (w ? w[i] : 1.0) : 0.0;
+      }
+      {
+        const int ii = syi == 1 ? (e & 31) : (e >> 6), cc = syi == 1 ? (e >> 5) : (e & 63), i = i0 + ii;
+        const int bb = tb + cc;
+        sy[ii][cc] = (i < i_end && bb < N) ? Y[(long)i * syi + bb * syb] : 0.0;
+      }
     }
     __syncthreads();
 #pragma unroll 4
@@ -190,8 +200,8 @@ __global__ void __launch_bounds__(256) k_gemm64(int M, int N, int K, int kchunk,
       double pa[4], yb[4];
 #pragma unroll
       for (int u = 0; u < 4; u++) {
-        pa[u] = sp[ii][tr + u];
-        yb[u] = sy[ii][tc + u];
+        pa[u] = sp[ii][tr + 16 * u];
+        yb[u] = sy[ii][tc + 16 * u];
       }
 #pragma unroll
       for (int u = 0; u < 4; u++)
@@ -204,7 +214,7 @@ __global__ void __launch_bounds__(256) k_gemm64(int M, int N, int K, int kchunk,
   for (int u = 0; u < 4; u++)
 #pragma unroll
     for (int v = 0; v < 4; v++) {
-      const int aa = ta + tr + u, bb = tb + tc + v;
+      const int aa = ta + tr + 16 * u, bb = tb + tc + 16 * v;
       if (aa < M && bb < N) Cpart[((long)blockIdx.z * M + aa) * N + bb] = acc[u][v];
     }
 }
@@ -502,45 +512,6 @@ void backward(cgp_guess *g, hipStream_t s, int B) {
   // layer 1
   gemm<0>(s, h, m, B, g->d_dz1b, 1, h, g->d_xb, m, 1, nullptr, gr + L.w1, m);
   hipLaunchKernelGGL(k_colsum, dim3((h + 255) / 256), dim3(256), 0, s, B, h, (const float *)g->d_dz1, gr + L.b1);
-}
-
-// 64x64-or-smaller symmetric eigen-decomposition by cyclic Jacobi rotations (host)
-void jacobi_eigen(int q, std::vector<double> &A, std::vector<double> &V) {
-  V.assign((size_t)q * q, 0.0);
-  for (int i = 0; i < q; i++) V[(size_t)i * q + i] = 1.0;
-  double dmax = 0.0;
-  for (int i = 0; i < q; i++) dmax = std::max(dmax, std::fabs(A[(size_t)i * q + i]));
-  for (int sweep = 0; sweep < 60; sweep++) {
-    int rotations = 0;
-    for (int p = 0; p < q - 1; p++)
-      for (int r = p + 1; r < q; r++) {
-        const double apr = A[(size_t)p * q + r];
-        const double app = A[(size_t)p * q + p], arr = A[(size_t)r * q + r];
-        // an off-diagonal entry below the rounding level of its diagonal pair, or of the whole matrix,
-        // changes nothing that the input resolves
-        if (std::fabs(apr) <= std::max(1e-18 * std::sqrt(std::fabs(app * arr)), 1e-16 * dmax)) continue;
-        rotations++;
-        const double theta = (arr - app) / (2.0 * apr);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
-        for (int k = 0; k < q; k++) {  // rotate columns p, r
-          const double akp = A[(size_t)k * q + p], akr = A[(size_t)k * q + r];
-          A[(size_t)k * q + p] = c * akp - sn * akr;
-          A[(size_t)k * q + r] = sn * akp + c * akr;
-        }
-        for (int k = 0; k < q; k++) {  // rotate rows p, r
-          const double apk = A[(size_t)p * q + k], ark = A[(size_t)r * q + k];
-          A[(size_t)p * q + k] = c * apk - sn * ark;
-          A[(size_t)r * q + k] = sn * apk + c * ark;
-        }
-        for (int k = 0; k < q; k++) {
-          const double vkp = V[(size_t)k * q + p], vkr = V[(size_t)k * q + r];
-          V[(size_t)k * q + p] = c * vkp - sn * vkr;
-          V[(size_t)k * q + r] = sn * vkp + c * vkr;
-        }
-      }
-    if (rotations == 0) break;
-  }
 }
 
 // columns of Y [S][q] made orthonormal (modified Gram-Schmidt, twice)
@@ -857,14 +828,21 @@ cgp_status pod_stage_basis(cgp_guess *g, hipStream_t st) {
   }
   for (int i = 0; i < q; i++)  // symmetrise
     for (int j = i + 1; j < q; j++) Bm[(size_t)i * q + j] = Bm[(size_t)j * q + i] = 0.5 * (Bm[(size_t)i * q + j] + Bm[(size_t)j * q + i]);
-  jacobi_eigen(q, Bm, U);
+  if (!sym_eigen(q, Bm, U)) {
+    set_error("cgp_guess_build_pod: the eigen-decomposition of the snapshot Gram matrix did not converge");
+    return CGP_E_NOCONV;
+  }
   std::vector<int> order(q);
   for (int i = 0; i < q; i++) order[i] = i;
-  std::sort(order.begin(), order.end(), [&](int a, int b) { return Bm[(size_t)a * q + a] > Bm[(size_t)b * q + b]; });
-  // modes with an eigenvalue at the rounding level of the largest (below 1e-20 of it, or not positive)
-  // are left out: their basis columns are zero and the guesses ignore them.  Small but resolved
-  // eigenvalues stay: their modes carry the slowly converging components the Krylov solver left in
-  // the snapshots, which is what a Galerkin initial guess removes best.
+  // by magnitude: the Gram matrix is semi-definite, and an eigenvalue computed below zero is one at the
+  // rounding level whose sign the decomposition does not resolve
+  std::sort(order.begin(), order.end(),
+            [&](int a, int b) { return std::fabs(Bm[(size_t)a * q + a]) > std::fabs(Bm[(size_t)b * q + b]); });
+  // modes with an eigenvalue below 1e-20 of the largest in magnitude are left out: their basis columns
+  // are zero and the guesses ignore them.  Small eigenvalues stay, also those at the rounding level of
+  // the largest: their modes carry the slowly converging components the Krylov solver left in the
+  // snapshots, which is what a Galerkin initial guess removes best, and each is scaled by 1/sqrt|lambda|
+  // (the Galerkin guess does not depend on the scaling of a basis column).
   std::vector<double> Vs((size_t)S * nm, 0.0);
   g->energy.assign(nm, 0.0);
   const double lam0 = Bm[(size_t)order[0] * q + order[0]];
@@ -875,7 +853,7 @@ cgp_status pod_stage_basis(cgp_guess *g, hipStream_t st) {
   int rank = 0;
   for (int k = 0; k < nm; k++) {
     const int c = order[k];
-    const double lam = Bm[(size_t)c * q + c];
+    const double lam = std::fabs(Bm[(size_t)c * q + c]);
     if (!(lam > 1e-20 * lam0)) break;
     rank = k + 1;
     g->energy[k] = lam;
