@@ -979,19 +979,23 @@ cgp_status pod_finish(cgp_guess *g) {
 
 void guess_progress(cgp_mesh *m) {
   cgp_guess *g = m->guess;
-  if (!g || g->stage != 1 || g->stage_err) return;
+  if (!g || (g->stage != 1 && g->stage != 2) || g->stage_err) return;
   const bool clean = hipPeekAtLastError() == hipSuccess;
-  if (hipEventQuery(g->ev_gram) != hipSuccess) {  // not there yet: a later poll or the next guess
-    if (clean) (void)hipGetLastError();            // "not ready" is no error of the caller's launches
+  // the stage's input not there yet: a later poll or the next guess ("not ready" is no error of the
+  // caller's launches)
+  if (hipEventQuery(g->stage == 1 ? g->ev_gram : g->ev_basis) != hipSuccess) {
+    if (clean) (void)hipGetLastError();
     return;
   }
-  const cgp_status st = pod_stage_basis(g, g->side);
+  // stage 1 -> 2: eigen-decomposition and basis; stage 2 -> done: the inverse of Phi^T K Phi (the
+  // mesh's stream then waits for its upload, so every later guess sees the new basis whole)
+  const cgp_status st = g->stage == 1 ? pod_stage_basis(g, g->side) : pod_stage_inverse(g, g->side);
   if (st) {
     g->stage_err = st;
     g->stage_msg = cgp_last_error();
     return;
   }
-  g->stage = 2;
+  g->stage = g->stage == 1 ? 2 : 0;
 }
 
 }  // namespace cgp
