@@ -282,10 +282,11 @@ typedef struct { double loss_first, loss_last; int32_t steps; float ms; } cgp_tr
 cgp_status cgp_guess_create(cgp_mesh *mesh, const cgp_guess_desc *desc, cgp_guess **out);
 void cgp_guess_destroy(cgp_guess *g);
 /* Basis from snapshots (device [S][n_c], rows = snapshots): eigenvectors of S M_c S^T for the n_modes
- * largest eigenvalues (randomised subspace iteration on the host when S > n_modes + 16, else the whole
- * S x S Gram matrix; Householder tridiagonalisation and shifted QR), Phi = S^T V Lambda^-1/2.  Modes with
- * an eigenvalue below 1e-20 of the largest are left out (zero columns, energy 0).
- * energy: host [n_modes] eigenvalues or NULL.  CGP_E_NOCONV if the QR iteration does not converge. */
+ * eigenvalues largest in magnitude (randomised subspace iteration on the host when S > n_modes + 16,
+ * else the whole S x S Gram matrix; Householder tridiagonalisation and shifted QR),
+ * Phi = S^T V |Lambda|^-1/2.  Modes below 1e-20 of the largest magnitude are left out (zero columns,
+ * energy 0); a rounding-level eigenvalue that comes out negative keeps its mode.
+ * energy: host [n_modes] |eigenvalues| or NULL.  CGP_E_NOCONV if the QR iteration does not converge. */
 cgp_status cgp_guess_build_pod(cgp_guess *g, const double *snaps, int32_t S, double *energy);
 /* Train on S (2..65536) samples: device [S][n_c] right-hand sides after boundary conditions and the
  * [S][n_c] pressures solving them.  Mini-batch Adam on FP32 master weights; the basis must be built
