@@ -124,6 +124,36 @@ def test_momentum_solve(env):
     assert rel(ut.cpu().numpy(), ref) <= 1e-10, (st, ost)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_momentum_one_component_at_rest(env, precision):
+    """Both velocity components go through one BiCGStab, each with its own convergence test: with
+    v = 0 in U^n and in the boundary data the second component's right-hand side is zero, so it is
+    done before the first iteration while the first component iterates on (x, r and the next search
+    direction are updated for the active component only).  Against the oracle's FP64 solve; the
+    resting component must come out exactly zero (FP64, and FP32 inner solves inside refinement)."""
+    torch, cgp, oracle = env
+    X0 = cgp._native
+    case = W.case_bfs(nx=80, ny=10)
+    g, o = make_pair(env, case.mesh, 1, case.rho, case.mu, case.dt)
+    xy = g.export("xy")
+    rng = np.random.default_rng(11)
+    u = case.initial(xy, g.export("vdir")) + 0.1 * rng.normal(size=(g.info["n_f"], 2))
+    u[:, 1] = 0.0
+    gd = case.dirichlet(xy, case.dt)
+    gd[:, 1] = 0.0
+    ut = torch.zeros(g.info["n_f"], 2, dtype=torch.float64, device="cuda")
+    prec = X0.PREC_FP32_IR if precision else X0.PREC_FP64
+    st = g.momentum(dev(torch, gd), dev(torch, u), ut, opts=cgp.SolverOpts(tol=1e-12, max_iter=20000, precision=prec))
+    ref, code, ost = o.momentum(gd, u, tol=1e-14)
+    assert code == 0
+    out = ut.cpu().numpy()
+    e = rel(out[:, 0], ref[:, 0])
+    _say(f"  momentum with v at rest, precision {precision}: rel err {e:.2e}, iterations {st['mom_iters']} "
+         f"(oracle {ost['mom_iters']})")
+    assert np.count_nonzero(out[:, 1]) == 0 and np.count_nonzero(ref[:, 1]) == 0
+    assert e <= 1e-10 and st["mom_relres"] <= 1e-12
+
+
 @pytest.mark.parametrize("which,x0", [("bfs", 0), ("cylinder", 0), ("cylinder", 1)])
 def test_momentum_fp32_refinement(env, which, x0):
     """The momentum solve with FP32 inner BiCGStab inside FP64 refinement (both components) against
