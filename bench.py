@@ -953,6 +953,8 @@ def main():
     ap.add_argument("--mom-tol", type=float, default=3e-11, help="momentum solve tolerance (relative residual)")
     ap.add_argument("--mass-tol", type=float, default=1e-10, help="mass solve tolerance of the correction")
     ap.add_argument("--inner-tol", type=float, default=1e-4, help="FP32 inner solve tolerance of the refinement")
+    ap.add_argument("--mass-method", default="pcg", choices=["pcg", "cheb"],
+                    help="mass solve of the correction: Jacobi-PCG or the Chebyshev iteration on [1/2, 2]")
     ap.add_argument("--paths", default="all", help="comma-separated subset of the timed paths")
     ap.add_argument("--batch", type=int, default=64, help="instances of the batched sweep (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
@@ -1078,6 +1080,7 @@ def main():
 
     mom_x0 = {"prev": X0.X0_PREV, "extrap": X0.X0_EXTRAP, "project": X0.X0_PROJECT}[args.mom_x0]
     mass_x0 = {"lumped": X0.X0_PREV, "extrap": X0.X0_EXTRAP}[args.mass_x0]
+    mass_method = {"pcg": X0.METHOD_DEFAULT, "cheb": X0.METHOD_CHEBYSHEV}[args.mass_method]
 
     F64, F32 = cgp._native.PREC_FP64, cgp._native.PREC_FP32_IR
     MIXED_ALL = 100  # the bench's own code: FP32 inner solves in the momentum and the Poisson solve
@@ -1088,7 +1091,8 @@ def main():
         return StepOpts(momentum=SolverOpts(tol=args.mom_tol, max_iter=5000, x0_mode=mom_x0, precision=mp),
                         poisson=SolverOpts(tol=tol, max_iter=100000, precision=pp, inner_tol=args.inner_tol,
                                            x0_mode=x0, launch=launch),
-                        mass=SolverOpts(tol=args.mass_tol, max_iter=2000, x0_mode=mass_x0), timing=timing)
+                        mass=SolverOpts(tol=args.mass_tol, max_iter=2000, x0_mode=mass_x0, method=mass_method),
+                        timing=timing)
 
     SETTLE = 10  # plain steps from the impulsive start before the training data is recorded
     for k in range(SETTLE):

@@ -97,9 +97,15 @@ enum { CGP_X0_ZERO = 0,            /* Krylov initial guess zero */
                                       The first use allocates 128 bytes per fine node for the history. */
 
 enum { CGP_METHOD_DEFAULT = 0,     /* Jacobi-PCG (Poisson, mass), Jacobi-BiCGStab (momentum) */
-       CGP_METHOD_ILU_GMRES = 1 };  /* Poisson only: GMRES(restart) preconditioned by ILU(0) of Kbar, the paper's solver
+       CGP_METHOD_ILU_GMRES = 1,    /* Poisson only: GMRES(restart) preconditioned by ILU(0) of Kbar, the paper's solver
                                        (Section 2.3); FP64; factorised on the device at the first such solve
                                        after cgp_assemble */
+       CGP_METHOD_CHEBYSHEV = 2 };  /* mass solve only (step 5, consistent mass): Jacobi-preconditioned Chebyshev
+                                       iteration on the bounds [1/2, 2] that hold for the P1 mass matrix on any
+                                       triangulation (Wathen 1987): no inner products, one kernel per step; runs
+                                       as many steps as the last solve needed, then checks the true residual
+                                       against tol and continues if it must; FP64.  Refused for the momentum
+                                       and Poisson solves (CGP_E_ARG) */
 
 enum { CGP_LAUNCH_AUTO = 0,        /* library choice (FUSED for the Poisson solve) */
        CGP_LAUNCH_LOOP = 1,        /* two kernels per PCG iteration (textbook recurrences), host polls every chunk */

@@ -20,7 +20,7 @@ PRESSURE_NONINCREMENTAL, PRESSURE_INCREMENTAL, PRESSURE_ROTATIONAL = 0, 1, 2
 PREC_FP64, PREC_FP32_IR = 0, 1
 X0_ZERO, X0_PREV, X0_LEARNED, X0_LEARNED_CORR, X0_POD_GALERKIN, X0_EXTRAP, X0_PROJECT = 0, 1, 2, 3, 4, 5, 6
 LAUNCH_AUTO, LAUNCH_LOOP, LAUNCH_PERSISTENT, LAUNCH_FUSED = 0, 1, 2, 3
-METHOD_DEFAULT, METHOD_ILU_GMRES = 0, 1
+METHOD_DEFAULT, METHOD_ILU_GMRES, METHOD_CHEBYSHEV = 0, 1, 2
 OP_KBC_C, OP_M_F, OP_A_F, OP_KBC_C32 = 0, 1, 2, 3
 
 EXPORT = {"xy": 0, "tri": 1, "bedge": 2, "bkind": 3, "parent": 4, "edges": 5, "rowptr_f": 6, "col_f": 7,

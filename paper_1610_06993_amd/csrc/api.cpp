@@ -140,8 +140,10 @@ cgp_status build_device(cgp_mesh *m) {
 }
 
 // poisson: the coarse Poisson solve; allow_extrap: the momentum solve of cgp_step (history-based
-// guesses); allow_fp32: the momentum solve (FP32 inner BiCGStab inside FP64 refinement)
-bool valid_opts(const cgp_solver_opts *o, bool poisson, bool allow_extrap = false, bool allow_fp32 = false) {
+// guesses); allow_fp32: the momentum solve (FP32 inner BiCGStab inside FP64 refinement); mass: the
+// velocity correction's mass solve (may use the Chebyshev iteration)
+bool valid_opts(const cgp_solver_opts *o, bool poisson, bool allow_extrap = false, bool allow_fp32 = false,
+                bool mass = false) {
   if (!o) return false;
   if (!(o->tol > 0.0) || o->max_iter < 1) return false;
   if (o->precision != CGP_PREC_FP64 && !((poisson || allow_fp32) && o->precision == CGP_PREC_FP32_IR)) return false;
@@ -150,7 +152,8 @@ bool valid_opts(const cgp_solver_opts *o, bool poisson, bool allow_extrap = fals
   }
   if (o->launch < CGP_LAUNCH_AUTO || o->launch > CGP_LAUNCH_FUSED) return false;
   if (o->method != CGP_METHOD_DEFAULT &&
-      !(poisson && o->method == CGP_METHOD_ILU_GMRES && o->precision == CGP_PREC_FP64))
+      !(poisson && o->method == CGP_METHOD_ILU_GMRES && o->precision == CGP_PREC_FP64) &&
+      !(mass && o->method == CGP_METHOD_CHEBYSHEV))
     return false;
   if (o->restart < 0 || o->restart > 200) return false;
   return true;
@@ -439,7 +442,7 @@ cgp_status cgp_prolong(cgp_mesh *m, const double *pc, double *pf) {
 cgp_status cgp_correct(cgp_mesh *m, const cgp_solver_opts *o, const double *g, const double *ut, const double *pf,
                        double *u, cgp_stats *st) {
   TRY(ready(m));
-  if (!valid_opts(o, false) || !g || !ut || !pf || !u) {
+  if (!valid_opts(o, false, false, false, true) || !g || !ut || !pf || !u) {
     set_error("cgp_correct: invalid argument");
     return CGP_E_ARG;
   }
@@ -466,8 +469,8 @@ static cgp_status incremental_buffers(cgp_mesh *m) {
 cgp_status cgp_step(cgp_mesh *m, const cgp_step_opts *o, const double *g, const double *f, double *u, double *pf,
                     double *pc, cgp_stats *st) {
   TRY(ready(m));
-  const bool mass_ok = o && (valid_opts(&o->mass, false) ||
-                             (valid_opts(&o->mass, false, true) && o->mass.x0_mode == CGP_X0_EXTRAP));
+  const bool mass_ok = o && (valid_opts(&o->mass, false, false, false, true) ||
+                             (valid_opts(&o->mass, false, true, false, true) && o->mass.x0_mode == CGP_X0_EXTRAP));
   if (!o || !valid_opts(&o->momentum, false, true, true) || !valid_opts(&o->poisson, true) || !mass_ok ||
       !g || !u || !pf || !pc) {
     set_error("cgp_step: invalid argument");

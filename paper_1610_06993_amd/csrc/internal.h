@@ -180,6 +180,7 @@ struct cgp_mesh {
   // Krylov iterations queued before the first poll of a solve (the last solve's count), per solve
   // kind; the FP32 inner solves keep one per refinement step, whose lengths differ
   int mom_chunk = 4, mom32_chunk = 4, p_chunk = 32, p32_chunk[4] = {16, 16, 16, 16}, mass_chunk = 8;
+  int cheb_steps = 16;  // Chebyshev steps of the first cycle of a mass solve (the last solve's count)
   // HIP-event timing of every launch of the Poisson SpMV kernel (cgp_step_opts.timing == 2)
   hipEvent_t step_ev[7] = {};      // per-phase events of cgp_step (timing >= 1)
   bool kt_on = false;

@@ -1348,6 +1348,98 @@ __global__ void k_ir_update(int n, double *__restrict__ x, const float *__restri
   x[i] += s * (double)d[i];
 }
 
+// ------------------------------------------------------------------ Chebyshev iteration (mass solve)
+// For P1 triangles the Jacobi-scaled consistent mass matrix has its spectrum in [1/2, 2] on every mesh
+// (Wathen 1987: each element's D_e^-1 M_e has the eigenvalues 1/2, 1/2 and 2, and the assembled
+// Rayleigh quotient x^T M x / x^T D x lies between the elements' extremes); an eliminated Dirichlet
+// row keeps only its diagonal (eigenvalue 1).  With those bounds the Chebyshev iteration needs no
+// inner products: one SpMV and a three-term update per step (Saad, Iterative Methods for Sparse
+// Linear Systems, 2nd ed., Algorithm 12.1).
+constexpr double kChebLo = 0.5, kChebHi = 2.0;
+
+// r = b - M x (the true residual), d = D^-1 r / theta; partials (r.r, b.b) per component
+template <int L>
+__global__ void __launch_bounds__(kMaxBlock) k_cheb_init(int n, const int *__restrict__ rp,
+                                                        const int *__restrict__ col, const double *__restrict__ A,
+                                                        const double *__restrict__ dinv, const double2 *__restrict__ b,
+                                                        const double2 *__restrict__ x, double2 *__restrict__ r,
+                                                        double2 *__restrict__ d, double inv_theta,
+                                                        double *__restrict__ Pout) {
+  const int lane = threadIdx.x & (L - 1);
+  const int rows_per_grid = gridDim.x * blockDim.x / L;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int row = (xcd_block() * blockDim.x + threadIdx.x) / L; row < n; row += rows_per_grid) {
+    double sx = 0.0, sy = 0.0;
+    for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
+      const double a = A[k];
+      const double2 xc = x[col[k]];
+      sx += a * xc.x;
+      sy += a * xc.y;
+    }
+    sx = group_sum<L>(sx);
+    sy = group_sum<L>(sy);
+    if (lane == 0) {
+      const double2 bb = b[row];
+      const double rx = bb.x - sx, ry = bb.y - sy, di = dinv[row] * inv_theta;
+      r[row] = make_double2(rx, ry);
+      d[row] = make_double2(di * rx, di * ry);
+      acc[0] += rx * rx;
+      acc[1] += ry * ry;
+      acc[2] += bb.x * bb.x;
+      acc[3] += bb.y * bb.y;
+    }
+  }
+  put_partials<4>(acc, Pout);
+}
+
+// one step: x += d_k, r -= M d_k, d_{k+1} = c1 d_k + c2 D^-1 r
+template <int L>
+__global__ void __launch_bounds__(kMaxBlock) k_cheb_step(int n, const int *__restrict__ rp,
+                                                        const int *__restrict__ col, const double *__restrict__ A,
+                                                        const double *__restrict__ dinv, double2 *__restrict__ x,
+                                                        double2 *__restrict__ r, const double2 *__restrict__ dk,
+                                                        double2 *__restrict__ dk1, double c1, double c2) {
+  const int lane = threadIdx.x & (L - 1);
+  const int rows_per_grid = gridDim.x * blockDim.x / L;
+  for (int row = (xcd_block() * blockDim.x + threadIdx.x) / L; row < n; row += rows_per_grid) {
+    double sx = 0.0, sy = 0.0;
+    for (int k = rp[row] + lane; k < rp[row + 1]; k += L) {
+      const double a = A[k];
+      const double2 dc = dk[col[k]];
+      sx += a * dc.x;
+      sy += a * dc.y;
+    }
+    sx = group_sum<L>(sx);
+    sy = group_sum<L>(sy);
+    if (lane == 0) {
+      const double2 dd = dk[row], xx = x[row], rr = r[row];
+      const double di = dinv[row];
+      const double rx = rr.x - sx, ry = rr.y - sy;
+      x[row] = make_double2(xx.x + dd.x, xx.y + dd.y);
+      r[row] = make_double2(rx, ry);
+      dk1[row] = make_double2(c1 * dd.x + c2 * (di * rx), c1 * dd.y + c2 * (di * ry));
+    }
+  }
+}
+
+// the init partials into the state: norms, zero right-hand sides (first call), convergence per component
+__global__ void __launch_bounds__(256) k_cheb_state(int G, const double *__restrict__ Pin,
+                                                   KrylovState *__restrict__ st, int first) {
+  double t4[4];
+  sum_partials<4>(Pin, G, t4);
+  if (threadIdx.x != 0) return;
+  for (int c = 0; c < 2; c++) {
+    if (first) {
+      st->bnorm[c] = sqrt(t4[2 + c]);
+      st->zero_b[c] = (t4[2 + c] == 0.0);
+    }
+    const double rn = sqrt(t4[c]);
+    st->rnorm[c] = rn;
+    if (!is_finite(rn)) st->status = CGP_E_NONFINITE;
+    st->done[c] = st->zero_b[c] || rn <= st->tol * st->bnorm[c];
+  }
+}
+
 __global__ void k_state_init(KrylovState *st, double tol, int maxit, int ncomp) {
   KrylovState s{};
   s.tol = tol;
@@ -2081,6 +2173,63 @@ cgp_status drv_poisson(cgp_mesh *m, const double *b_in, double *x, const cgp_sol
 }
 
 // ------------------------------------------------------------------ step 5
+// Chebyshev iteration for the consistent mass matrix (two components), from x: cycles of steps,
+// each closed by the true residual and one poll.  The first cycle runs as many steps as the last solve
+// needed (*hint); a later one as many as the bound 2 q^k on the M-norm error (q = 1/3 for kappa = 4)
+// asks for the remaining reduction, plus two for the residual's 2-norm.
+cgp_status cheb_mass(cgp_mesh *m, int n, const double *b, double *x, double **w, const cgp_tuning_knobs &tk,
+                     double tol, int maxit, int *hint, KrylovState *out) {
+  KrylovState *st = m->d_state + SLOT_MASS;
+  hipStream_t s = m->stream;
+  double2 *r = reinterpret_cast<double2 *>(w[0]);
+  double2 *d[2] = {reinterpret_cast<double2 *>(w[1]), reinterpret_cast<double2 *>(w[2])};
+  const Shape sh = shape_rows(tk, n, tk.lanes);
+  const double theta = 0.5 * (kChebHi + kChebLo), delta = 0.5 * (kChebHi - kChebLo), sigma = theta / delta;
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, st, tol, maxit, 2);
+  auto check = [&](bool first) {
+    dispatch_L(tk.lanes, [&](auto LC) {
+      constexpr int LL = decltype(LC)::value;
+      hipLaunchKernelGGL((k_cheb_init<LL>), dim3(sh.grid), dim3(sh.block), 0, s, n, m->d_rp_f, m->d_col_f,
+                         (const double *)m->d_Mbc, (const double *)m->d_dinvM, (const double2 *)b,
+                         (const double2 *)x, r, d[0], 1.0 / theta, region(m, R_INIT));
+    });
+    hipLaunchKernelGGL(k_cheb_state, dim3(1), dim3(256), 0, s, sh.grid, (const double *)region(m, R_INIT), st,
+                       first ? 1 : 0);
+  };
+  check(true);
+  int used = 0, k = std::max(1, std::min(*hint, maxit));
+  for (;;) {
+    double rho = 1.0 / sigma;
+    for (int j = 0; j < k; j++) {
+      const double rho1 = 1.0 / (2.0 * sigma - rho);
+      const double c1 = rho1 * rho, c2 = 2.0 * rho1 / delta;
+      dispatch_L(tk.lanes, [&](auto LC) {
+        constexpr int LL = decltype(LC)::value;
+        hipLaunchKernelGGL((k_cheb_step<LL>), dim3(sh.grid), dim3(sh.block), 0, s, n, m->d_rp_f, m->d_col_f,
+                           (const double *)m->d_Mbc, (const double *)m->d_dinvM, reinterpret_cast<double2 *>(x), r,
+                           (const double2 *)d[j & 1], d[(j + 1) & 1], c1, c2);
+      });
+      rho = rho1;
+    }
+    used += k;
+    check(false);
+    CGP_HIP(hipGetLastError());
+    cgp_status ps = poll(m, SLOT_MASS);
+    if (ps) return ps;
+    const KrylovState &h = m->h_state[SLOT_MASS];
+    if (h.status || host_all_done(h) || used >= maxit) break;
+    double need = 1.0;
+    for (int c = 0; c < 2; c++)
+      if (!h.done[c]) need = std::max(need, h.rnorm[c] / (tol * h.bnorm[c]));
+    k = std::max(1, std::min(maxit - used, (int)std::ceil(std::log(2.0 * need) / std::log(3.0)) + 2));
+  }
+  *out = m->h_state[SLOT_MASS];
+  out->iters = used;
+  *hint = std::max(1, used);
+  hipLaunchKernelGGL((k_zero_b_fix<2>), dim3(blocks_1d(n)), dim3(256), 0, s, n, x, (const KrylovState *)st);
+  return status_of(*out, SLOT_MASS);
+}
+
 cgp_status drv_correct(cgp_mesh *m, const cgp_solver_opts *o, const double *g, const double *ut, const double *pf,
                        double *u, cgp_stats *stats) {
   hipStream_t s = m->stream;
@@ -2125,8 +2274,10 @@ cgp_status drv_correct(cgp_mesh *m, const cgp_solver_opts *o, const double *g, c
   }
   double *w[5] = {m->d_wf[1], m->d_wf[2], m->d_wf[3], m->d_wf[4], m->d_wf[5]};
   KrylovState fin{};
-  cgp_status rs = run_pcg64<2>(m, SLOT_MASS, n, m->d_rp_f, m->d_col_f, m->d_Mbc, m->d_dinvM, rhs, u, w, m->tune.fine,
-                               o->tol, o->max_iter, &m->mass_chunk, false, &fin);
+  cgp_status rs = o->method == CGP_METHOD_CHEBYSHEV
+                       ? cheb_mass(m, n, rhs, u, w, m->tune.fine, o->tol, o->max_iter, &m->cheb_steps, &fin)
+                       : run_pcg64<2>(m, SLOT_MASS, n, m->d_rp_f, m->d_col_f, m->d_Mbc, m->d_dinvM, rhs, u, w,
+                                      m->tune.fine, o->tol, o->max_iter, &m->mass_chunk, false, &fin);
   launch_set_dirichlet(m, g, u);
   if (extrap) {
     hipLaunchKernelGGL(k_axpy_into, dim3((cnt + 255) / 256), dim3(256), 0, s, cnt, (const double *)u, -1.0,

@@ -482,6 +482,67 @@ def test_extrapolated_mass_start(env):
     assert sum(iters["extrap"][2:]) < sum(iters["lumped"][2:])
 
 
+@pytest.mark.parametrize("x0", ["lumped", "extrap", "zero"])
+def test_chebyshev_mass_solve(env, x0):
+    """The mass solve by the Chebyshev iteration on the Wathen bounds [1/2, 2] (CGP_METHOD_CHEBYSHEV)
+    against the oracle's PCG steps, from each start, on the cylinder (graded, nonuniform triangles):
+    velocity <= 1e-10 every step, and the reported mass residual meets the tolerance.  The pressure
+    bar is 1e-9 for both methods here: each method stops somewhere inside the mass tolerance (1e-13),
+    and the next step's pressure, driven by the divergence of a nearly divergence-free velocity,
+    magnifies such a difference about a thousandfold (1.5e-10 measured after the Chebyshev step,
+    velocity 3.5e-13).  Iterations: CG adapts to the actual spectrum and Chebyshev only knows the
+    bounds, so it takes more steps (29 against 23-25 at 1e-13 from the lumped start), each one kernel
+    against PCG's two; asserted within 1.4 times the PCG count plus two."""
+    torch, cgp, oracle = env
+    X0 = cgp._native
+    case = W.case_cylinder(5000, seed=4)
+    s64 = cgp.SolverOpts(tol=TIGHT, max_iter=100000)
+    mx0 = {"lumped": X0.X0_PREV, "extrap": X0.X0_EXTRAP, "zero": X0.X0_ZERO}[x0]
+    its = {}
+    for method in (X0.METHOD_DEFAULT, X0.METHOD_CHEBYSHEV):
+        mass = cgp.SolverOpts(tol=TIGHT, max_iter=100000, x0_mode=mx0, method=method)
+        opts = cgp.StepOpts(momentum=s64, poisson=cgp.SolverOpts(tol=TIGHT_P, max_iter=100000), mass=mass)
+        g, o = make_pair(env, case.mesh, 1, case.rho, case.mu, case.dt)
+        xy = g.export("xy")
+        u0 = case.initial(xy, g.export("vdir"))
+        u = dev(torch, u0.copy())
+        pf = torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda")
+        pc = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
+        ur, pcr, its[method] = u0.copy(), None, []
+        for k in range(4):
+            gd = case.dirichlet(xy, (k + 1) * case.dt)
+            st = g.step(dev(torch, gd), u, pf, pc, opts=opts)
+            its[method].append(st["mass_iters"])
+            assert st["mass_relres"] <= TIGHT, (method, k, st["mass_relres"])
+            ur, pfr, pcr, code, _ = o.step(gd, ur, pcr, tol_mom=TIGHT, tol_p=TIGHT_P, tol_mass=TIGHT)
+            assert code == 0
+            eu, ep = rel(u.cpu().numpy(), ur), rel(pf.cpu().numpy(), pfr)
+            assert eu <= 1e-10 and ep <= 1e-9, (method, k, eu, ep)
+    _say(f"  mass iterations ({x0} start): PCG {its[X0.METHOD_DEFAULT]}, Chebyshev {its[X0.METHOD_CHEBYSHEV]}")
+    if x0 == "lumped":
+        assert max(its[X0.METHOD_CHEBYSHEV][1:]) <= 1.4 * max(its[X0.METHOD_DEFAULT][1:]) + 2
+
+
+def test_chebyshev_only_for_the_mass_solve(env):
+    """CGP_METHOD_CHEBYSHEV is refused for the momentum and the Poisson solve (its bounds hold for the
+    P1 mass matrix only)."""
+    torch, cgp, oracle = env
+    X0 = cgp._native
+    case = W.case_cylinder(5000, seed=4)
+    g = cgp.Mesh(case.mesh, 1)
+    g.assemble(case.rho, case.mu, case.dt)
+    n_c = g.info["n_c"]
+    b = torch.ones(n_c, dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    with pytest.raises(cgp.CGPError):
+        g.poisson_solve(b, x, cgp.SolverOpts(tol=1e-8, method=X0.METHOD_CHEBYSHEV))
+    n_f = g.info["n_f"]
+    u = torch.zeros(n_f, 2, dtype=torch.float64, device="cuda")
+    with pytest.raises(cgp.CGPError):
+        g.momentum(u, u.clone(), u.clone(), opts=cgp.SolverOpts(tol=1e-8, method=X0.METHOD_CHEBYSHEV))
+    g.close()
+
+
 def test_extrapolated_momentum_guess(env):
     """x0 = 2 U~^n - U~^(n-1) for the momentum solve changes only the start of the Krylov iteration.
     A different start moves the converged momentum result by up to cond(A) * tol, which the pressure

@@ -309,6 +309,25 @@ def test_mass_pcg_iterations_within_wathen_bound(tg_problem):
     assert max(st["mass_iters"]) <= bound
 
 
+def test_jacobi_scaled_mass_spectrum_in_wathen_interval(orc):
+    """The bounds the Chebyshev mass solve is built on: every eigenvalue of D^-1 M for the P1 mass
+    matrix lies in [1/2, 2] (Wathen 1987), here on a graded cylinder mesh refined once (triangles of
+    very different sizes and shapes), also for the principal submatrix of the free rows that the
+    Dirichlet elimination leaves; the extremes are attained closely, so the interval is not loose."""
+    c = W.case_cylinder(1500, seed=2)
+    P = orc.Problem(c.mesh, 1)
+    P.assemble(c.rho, c.mu, c.dt)
+    M = _csr_mat(P, P.values("M_f")).toarray()
+    d = np.diag(M)
+    S = M / np.sqrt(np.outer(d, d))  # D^-1/2 M D^-1/2: same spectrum as D^-1 M, symmetric
+    lam = np.linalg.eigvalsh(S)
+    assert lam.min() >= 0.5 - 1e-12 and lam.max() <= 2.0 + 1e-12, (lam.min(), lam.max())
+    assert lam.min() <= 0.55 and lam.max() >= 1.9
+    free = P.export("vdir") == 0
+    lf = np.linalg.eigvalsh(S[np.ix_(free, free)])
+    assert lf.min() >= 0.5 - 1e-12 and lf.max() <= 2.0 + 1e-12, (lf.min(), lf.max())
+
+
 def _manufactured_error(orc, n, neumann):
     m = W.unit_square_tg(n, seed=11)
     if not neumann:
