@@ -543,6 +543,38 @@ def test_chebyshev_only_for_the_mass_solve(env):
     g.close()
 
 
+def test_chebyshev_mass_solve_stops_at_max_iter(env):
+    """An unreachable mass tolerance (1e-300): the Chebyshev solve stops after exactly max_iter steps
+    and the step reports CGP_E_NOCONV with a finite velocity, both when the first cycle is cut (5) and
+    when a later cycle is (23: a first cycle as long as the last solve, then the rest).  The next solve
+    with a reachable tolerance converges as usual."""
+    torch, cgp, oracle = env
+    X0 = cgp._native
+    case = W.case_cylinder(5000, seed=4)
+    g = cgp.Mesh(case.mesh, 1)
+    g.assemble(case.rho, case.mu, case.dt)
+    xy = g.export("xy")
+    u0 = case.initial(xy, g.export("vdir"))
+    gd = dev(torch, case.dirichlet(xy, case.dt))
+    s64 = cgp.SolverOpts(tol=TIGHT, max_iter=100000)
+    for maxit, tol, want in ((5, 1e-300, X0.E_NOCONV), (23, 1e-300, X0.E_NOCONV), (100000, TIGHT, X0.OK)):
+        mass = cgp.SolverOpts(tol=tol, max_iter=maxit, x0_mode=X0.X0_PREV, method=X0.METHOD_CHEBYSHEV)
+        opts = cgp.StepOpts(momentum=s64, poisson=cgp.SolverOpts(tol=TIGHT_P, max_iter=100000), mass=mass)
+        u = dev(torch, u0.copy())
+        pf = torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda")
+        pc = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
+        st = g.step(gd, u, pf, pc, opts=opts, allow_noconv=True)
+        _say(f"  max_iter {maxit}, tol {tol:g}: status {st['status']}, {st['mass_iters']} steps, "
+             f"relres {st['mass_relres']:.2e}")
+        assert st["status"] == want
+        assert bool(torch.isfinite(u).all())
+        if want == X0.E_NOCONV:
+            assert st["mass_iters"] == maxit
+        else:
+            assert st["mass_relres"] <= TIGHT
+    g.close()
+
+
 def test_extrapolated_momentum_guess(env):
     """x0 = 2 U~^n - U~^(n-1) for the momentum solve changes only the start of the Krylov iteration.
     A different start moves the converged momentum result by up to cond(A) * tol, which the pressure
