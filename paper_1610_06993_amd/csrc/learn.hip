@@ -514,7 +514,12 @@ void backward(cgp_guess *g, hipStream_t s, int B) {
   hipLaunchKernelGGL(k_colsum, dim3((h + 255) / 256), dim3(256), 0, s, B, h, (const float *)g->d_dz1, gr + L.b1);
 }
 
-// columns of Y [S][q] made orthonormal (modified Gram-Schmidt, twice)
+// columns of Y [S][q] made orthonormal (modified Gram-Schmidt, twice).  A column that enters the second
+// pass with unit norm keeps most of it unless it lies in the span of the columns before it; one left
+// with less than 1e-6 has no direction of its own (G of rank below q, e.g. snapshots that repeat bit for
+// bit, whose products are exact multiples of one vector, so that their residuals normalise to that
+// vector again) and is set to zero: Q^T G Q then has a zero row and column for it instead of counting an
+// eigenvalue twice.
 void orthonormalise(int S, int q, std::vector<double> &Y) {
   for (int pass = 0; pass < 2; pass++)
     for (int j = 0; j < q; j++) {
@@ -526,7 +531,8 @@ void orthonormalise(int S, int q, std::vector<double> &Y) {
       double nrm = 0.0;
       for (int a = 0; a < S; a++) nrm += Y[(size_t)a * q + j] * Y[(size_t)a * q + j];
       nrm = std::sqrt(nrm);
-      for (int a = 0; a < S; a++) Y[(size_t)a * q + j] = nrm > 0 ? Y[(size_t)a * q + j] / nrm : 0.0;
+      const bool keep = pass == 0 ? nrm > 0 : nrm > 1e-6;
+      for (int a = 0; a < S; a++) Y[(size_t)a * q + j] = keep ? Y[(size_t)a * q + j] / nrm : 0.0;
     }
 }
 
@@ -901,16 +907,23 @@ cgp_status pod_stage_inverse(cgp_guess *g, hipStream_t st) {
   double *hK = g->h_pin + (size_t)S * S + (size_t)S * nm, *hI = hK + (size_t)nm * nm;
   std::vector<double> Kc(hK, hK + (size_t)nm * nm);
   // inverse of the leading rank x rank block by Gauss-Jordan with partial pivoting (SPD and tiny);
-  // rows and columns of the unused modes stay zero
+  // rows and columns of the unused modes stay zero.  A pivot at the rounding level of the largest
+  // diagonal entry means that some modes are linearly dependent (snapshots that span fewer directions
+  // than modes were kept): then the inverse is taken over an independent subset instead.
+  double dmax = 0.0;
+  for (int i = 0; i < rank; i++) dmax = std::max(dmax, std::fabs(Kc[(size_t)i * nm + i]));
   std::vector<double> inv((size_t)nm * nm, 0.0);
   for (int i = 0; i < rank; i++) inv[(size_t)i * nm + i] = 1.0;
   for (int col = 0; col < rank; col++) {
     int piv = col;
     for (int r = col + 1; r < rank; r++)
       if (std::fabs(Kc[(size_t)r * nm + col]) > std::fabs(Kc[(size_t)piv * nm + col])) piv = r;
-    if (Kc[(size_t)piv * nm + col] == 0.0) {
-      set_error("cgp_guess_build_pod: Phi^T K Phi is singular");
-      return CGP_E_ARG;
+    if (!(std::fabs(Kc[(size_t)piv * nm + col]) > 1e-13 * dmax)) {
+      if (!independent_inverse(nm, rank, hK, inv)) {
+        set_error("cgp_guess_build_pod: Phi^T K Phi has no positive diagonal entry");
+        return CGP_E_ARG;
+      }
+      break;
     }
     for (int k = 0; k < rank; k++) {
       std::swap(Kc[(size_t)col * nm + k], Kc[(size_t)piv * nm + k]);

@@ -1,4 +1,5 @@
-// Dense symmetric eigen-decomposition on the host (the POD basis builds up to a few hundred modes).
+// Dense symmetric eigen-decomposition on the host (the POD basis builds up to a few hundred modes), and
+// the inverse of the POD-Galerkin matrix over its independent modes.
 //
 // Householder reduction to tridiagonal form T = Q^T A Q, then implicit symmetric QR steps with the
 // Wilkinson shift on T, the Givens rotations accumulated into Q (Golub & Van Loan, Matrix
@@ -6,6 +7,7 @@
 // the nine or so cyclic Jacobi sweeps a 64 x 64 snapshot Gram matrix needs.
 #pragma once
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -104,6 +106,55 @@ inline bool sym_eigen(int n, std::vector<double> &A, std::vector<double> &Z) {
   for (int i = 0; i < n; i++)
     for (int j = 0; j < n; j++) a(i, j) = i == j ? d[i] : 0.0;
   return m == 0;
+}
+
+
+// Inverse of Phi^T K Phi (symmetric positive semi-definite, leading rank x rank block of the nm x nm
+// row-major Kc) over the modes that are independent of the ones before them: symmetric elimination in
+// mode order (most energetic first) keeps a mode when its diagonal entry, reduced by the modes kept
+// before it, is above 1e-12 of its own (the sine of its angle to their span, in the K inner product,
+// above 1e-6); the kept block is inverted by Gauss-Jordan without exchanges (positive definite) and
+// the rows and columns of the other modes are zero.  False when no mode is kept.
+inline bool independent_inverse(int nm, int rank, const double *Kc, std::vector<double> &inv) {
+  std::vector<double> A(Kc, Kc + (size_t)nm * nm);
+  std::vector<int> keep;
+  for (int j = 0; j < rank; j++) {
+    const double d = A[(size_t)j * nm + j], d0 = Kc[(size_t)j * nm + j];
+    if (!(d0 > 0.0) || !(d > 1e-12 * d0)) continue;
+    keep.push_back(j);
+    for (int r = j + 1; r < rank; r++) {
+      const double f = A[(size_t)r * nm + j] / d;
+      if (f == 0.0) continue;
+      for (int c = j + 1; c < rank; c++) A[(size_t)r * nm + c] -= f * A[(size_t)j * nm + c];
+    }
+  }
+  const int k = (int)keep.size();
+  std::fill(inv.begin(), inv.end(), 0.0);
+  if (k == 0) return false;
+  std::vector<double> B((size_t)k * k), I((size_t)k * k, 0.0);
+  for (int a = 0; a < k; a++) {
+    I[(size_t)a * k + a] = 1.0;
+    for (int b = 0; b < k; b++) B[(size_t)a * k + b] = Kc[(size_t)keep[a] * nm + keep[b]];
+  }
+  for (int col = 0; col < k; col++) {
+    const double d = B[(size_t)col * k + col];
+    for (int c = 0; c < k; c++) {
+      B[(size_t)col * k + c] /= d;
+      I[(size_t)col * k + c] /= d;
+    }
+    for (int r = 0; r < k; r++) {
+      if (r == col) continue;
+      const double f = B[(size_t)r * k + col];
+      if (f == 0.0) continue;
+      for (int c = 0; c < k; c++) {
+        B[(size_t)r * k + c] -= f * B[(size_t)col * k + c];
+        I[(size_t)r * k + c] -= f * I[(size_t)col * k + c];
+      }
+    }
+  }
+  for (int a = 0; a < k; a++)
+    for (int b = 0; b < k; b++) inv[(size_t)keep[a] * nm + keep[b]] = I[(size_t)a * k + b];
+  return true;
 }
 
 }  // namespace cgp
