@@ -410,6 +410,43 @@ def test_online_window_basis(env):
     assert out["online"][2] < 0.7 * out["plain"][2]
 
 
+def test_online_window_on_a_repeated_step(env):
+    """The same step taken again and again from the same state (the limit of a steady flow): the window
+    fills with pressures that agree to the Krylov tolerance, then bit for bit once the guess meets the
+    tolerance by itself, so every rebuilt basis has rank one or close to it.  Every step succeeds, every
+    result agrees with the first to the tolerance, and the guess needs no more iterations than the first
+    solve took."""
+    torch, cgp, oracle = env
+    case = W.case_cylinder(6000, seed=5)
+    g = cgp.Mesh(case.mesh, 1)
+    g.assemble(case.rho, case.mu, case.dt)
+    X0 = cgp._native
+    xy = g.export("xy")
+    u0 = case.initial(xy, g.export("vdir"))
+    gd = dev(torch, case.dirichlet(xy, case.dt))
+    window = 8
+    net = cgp.Guess(g, n_modes=window, hidden=16, seed=1)
+    net.set_online(window, 1)
+    net.attach()
+    opts = cgp.StepOpts(poisson=cgp.SolverOpts(tol=1e-10, x0_mode=X0.X0_POD_GALERKIN))
+    pf = torch.zeros(g.info["n_f"], dtype=torch.float64, device="cuda")
+    pc = torch.zeros(g.info["n_c"], dtype=torch.float64, device="cuda")
+    its, first = [], None
+    for k in range(3 * window + 4):
+        u = dev(torch, u0.copy())
+        st = g.step(gd, u, pf, pc, opts=opts)
+        its.append(st["p_iters"])
+        if first is None:
+            first = (u.cpu().numpy(), pf.cpu().numpy())
+        else:
+            eu, ep = rel(u.cpu().numpy(), first[0]), rel(pf.cpu().numpy(), first[1])
+            assert eu <= 1e-8 and ep <= 1e-8, (k, eu, ep)
+    net.detach()
+    net.close()
+    _say(f"  repeated step, window {window}: Poisson iterations {its}")
+    assert max(its[1:]) <= its[0]
+
+
 def test_guess_errors(env, small_mesh):
     torch, cgp, oracle = env
     case, g, o = small_mesh
